@@ -1,0 +1,197 @@
+"""Seeded synthetic inputs: grain packings, inlet profiles, test states.
+
+This module holds input generation only -- none of the lattice Boltzmann
+arithmetic.  Both the GPU path and the CPU oracle consume what it produces,
+as plain arrays.
+
+Stand-ins for the paper's data: the paper's 2D packings and its CT scan of
+Hamburg sand (Section 3.3) are not available, so packings of the same kind
+are drawn here from explicit, seeded recipes:
+
+* ``rsa_disks``: non-overlapping circular grains by random sequential
+  addition, a throat of at least ``gap`` nodes between grains, kept clear of
+  ``x_margin`` nodes at the inlet and outlet faces (2D media, Section 3.1.1);
+* ``boolean_spheres``: overlapping spheres (Boolean model), periodic on the
+  chosen axes, for porosities below the jamming limit of hard spheres (3D
+  media, Section 3.3);
+* ``fourier_profile``: a smooth per-node inlet field built from a handful of
+  Fourier modes (a smooth non-uniform inlet pressure, Section 3.1.2).
+
+A node is solid iff its squared distance to a grain centre is at most r^2.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+try:
+    from scipy import ndimage as _ndi
+except Exception:  # pragma: no cover - scipy is present in this image
+    _ndi = None
+
+
+def porosity(solid: np.ndarray) -> float:
+    return float(1.0 - np.count_nonzero(solid) / solid.size)
+
+
+def percolates(solid: np.ndarray) -> bool:
+    """True if fluid nodes of the x = 0 face connect to fluid nodes of the
+    x = nx-1 face through face-adjacent fluid nodes (x is the last axis)."""
+    fluid = solid == 0
+    if _ndi is not None:
+        lab, _ = _ndi.label(fluid)
+        a = set(np.unique(lab[..., 0])) - {0}
+        b = set(np.unique(lab[..., -1])) - {0}
+        return bool(a & b)
+    # plain BFS fallback
+    from collections import deque
+    seen = np.zeros_like(fluid)
+    dq = deque()
+    for idx in zip(*np.nonzero(fluid[..., 0])):
+        full = tuple(idx) + (0,)
+        seen[full] = True
+        dq.append(full)
+    nd = fluid.ndim
+    while dq:
+        p = dq.popleft()
+        if p[-1] == fluid.shape[-1] - 1:
+            return True
+        for a in range(nd):
+            for d in (-1, 1):
+                q = list(p)
+                q[a] += d
+                if 0 <= q[a] < fluid.shape[a]:
+                    q = tuple(q)
+                    if fluid[q] and not seen[q]:
+                        seen[q] = True
+                        dq.append(q)
+    return False
+
+
+def _paint_disk(solid, cx, cy, r):
+    ny, nx = solid.shape
+    x0, x1 = max(int(np.floor(cx - r)), 0), min(int(np.ceil(cx + r)), nx - 1)
+    y0, y1 = max(int(np.floor(cy - r)), 0), min(int(np.ceil(cy + r)), ny - 1)
+    if x1 < x0 or y1 < y0:
+        return
+    yy, xx = np.mgrid[y0:y1 + 1, x0:x1 + 1]
+    m = (xx - cx) ** 2 + (yy - cy) ** 2 <= r * r
+    solid[y0:y1 + 1, x0:x1 + 1] |= m.astype(np.uint8)
+
+
+def rsa_disks(nx: int, ny: int, r_range=(6.0, 14.0), target_porosity=0.7, seed=0,
+              x_margin=4, gap=2.0, max_reject=100_000, max_reseed=20):
+    """2D solid mask (ny, nx) uint8 of non-overlapping disks.
+
+    Disks are drawn with radius ~ U[r_range] and a real-valued centre such
+    that the disk lies inside y in [0, ny-1] and x in [x_margin,
+    nx-1-x_margin]; a candidate is rejected if its centre distance to any
+    placed disk is below r1 + r2 + gap.  Disks are added until the porosity
+    is at most target_porosity.  After max_reject consecutive rejections the
+    non-overlap rule is dropped (overlapping placement).  The mask must let
+    fluid percolate from inlet to outlet; otherwise the next seed of the
+    stream is used."""
+    rng = np.random.default_rng(seed)
+    for _ in range(max_reseed):
+        solid = np.zeros((ny, nx), np.uint8)
+        cs = []
+        rejects = 0
+        overlap_ok = False
+        while porosity(solid) > target_porosity:
+            r = rng.uniform(*r_range)
+            lo_x, hi_x = x_margin + r, nx - 1 - x_margin - r
+            lo_y, hi_y = r, ny - 1 - r
+            if hi_x < lo_x or hi_y < lo_y:
+                raise ValueError("lattice too small for the grain radius")
+            cx, cy = rng.uniform(lo_x, hi_x), rng.uniform(lo_y, hi_y)
+            if not overlap_ok and cs:
+                arr = np.asarray(cs)
+                d2 = (arr[:, 0] - cx) ** 2 + (arr[:, 1] - cy) ** 2
+                if np.any(d2 < (arr[:, 2] + r + gap) ** 2):
+                    rejects += 1
+                    if rejects >= max_reject:
+                        overlap_ok = True
+                    continue
+            rejects = 0
+            cs.append((cx, cy, r))
+            _paint_disk(solid, cx, cy, r)
+        if percolates(solid):
+            return solid
+    raise RuntimeError("no percolating packing found")
+
+
+def boolean_spheres(n, r_range=(6.0, 10.0), target_porosity=0.4, seed=0,
+                    periodic=(False, True, True), x_margin=4, max_reseed=20):
+    """3D solid mask (nz, ny, nx) uint8 of overlapping spheres.
+
+    n = (nx, ny, nz).  Centres are uniform with x in [x_margin + r,
+    nx-1-x_margin-r] (sphere-free inlet/outlet buffers) and uniform over the
+    whole extent of periodic axes (spheres wrap around).  Spheres are added
+    until the porosity is at most target_porosity; the pore space must
+    percolate from inlet to outlet."""
+    nx, ny, nz = n
+    rng = np.random.default_rng(seed)
+    ext = (nx, ny, nz)
+    for _ in range(max_reseed):
+        solid = np.zeros((nz, ny, nx), np.uint8)
+        while porosity(solid) > target_porosity:
+            r = rng.uniform(*r_range)
+            c = [rng.uniform(x_margin + r, nx - 1 - x_margin - r)]
+            for a in (1, 2):
+                c.append(rng.uniform(0, ext[a]) if periodic[a] else rng.uniform(r, ext[a] - 1 - r))
+            _paint_sphere(solid, c, r, periodic)
+        if percolates(solid):
+            return solid
+    raise RuntimeError("no percolating packing found")
+
+
+def _paint_sphere(solid, c, r, periodic):
+    nz, ny, nx = solid.shape
+    ext = (nx, ny, nz)
+    rng_ax = []
+    for a in range(3):
+        lo, hi = int(np.floor(c[a] - r)), int(np.ceil(c[a] + r))
+        idx = np.arange(lo, hi + 1)
+        d = idx - c[a]
+        if periodic[a]:
+            idx = np.mod(idx, ext[a])
+        else:
+            keep = (idx >= 0) & (idx < ext[a])
+            idx, d = idx[keep], d[keep]
+        rng_ax.append((idx, d))
+    (ix, dx), (iy, dy), (iz, dz) = rng_ax
+    d2 = dz[:, None, None] ** 2 + dy[None, :, None] ** 2 + dx[None, None, :] ** 2
+    m = (d2 <= r * r).astype(np.uint8)
+    solid[np.ix_(iz, iy, ix)] |= m
+
+
+def fourier_profile(ny: int, nz: int, n_modes=8, seed=0, kmax=3):
+    """Smooth field phi(z, y) in [0, 1] from n_modes Fourier modes:
+    psi = sum_k a_k cos(2 pi (m_k y / ny + n_k z / nz) + theta_k) with
+    (m_k, n_k) integers in [-kmax, kmax]^2 minus the origin, a_k ~ N(0, 1),
+    theta_k ~ U[0, 2 pi); phi = (psi - min) / (max - min)."""
+    rng = np.random.default_rng(seed)
+    yy, zz = np.meshgrid(np.arange(ny), np.arange(nz), indexing="xy")
+    psi = np.zeros((nz, ny))
+    for _ in range(n_modes):
+        while True:
+            m, nn = rng.integers(-kmax, kmax + 1, size=2)
+            if m != 0 or nn != 0:
+                break
+        a = rng.normal()
+        th = rng.uniform(0, 2 * np.pi)
+        psi += a * np.cos(2 * np.pi * (m * yy / ny + nn * zz / nz) + th)
+    lo, hi = psi.min(), psi.max()
+    return (psi - lo) / (hi - lo) if hi > lo else np.zeros_like(psi)
+
+
+def random_perturbation(shape, q, amplitude, seed=0):
+    """Seeded uniform perturbation in [-amplitude, amplitude] of shape
+    shape + (q,) -- used as non-equilibrium test states (added to the
+    lattice weights by the caller)."""
+    rng = np.random.default_rng(seed)
+    return rng.uniform(-amplitude, amplitude, size=tuple(shape) + (q,))
+
+
+def random_field(shape, scale, seed=0):
+    rng = np.random.default_rng(seed)
+    return rng.normal(0.0, scale, size=shape)

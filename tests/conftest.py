@@ -1,0 +1,63 @@
+import os
+import sys
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU")
+    config.addinivalue_line("markers", "slow: long-running check")
+
+
+def pytest_collection_modifyitems(config, items):
+    try:
+        import torch
+        have_gpu = torch.cuda.is_available()
+    except Exception:
+        have_gpu = False
+    if have_gpu:
+        return
+    skip = pytest.mark.skip(reason="no GPU in this environment")
+    for it in items:
+        if "gpu" in it.keywords:
+            it.add_marker(skip)
+
+
+@pytest.fixture(scope="session")
+def oracle_mod():
+    import oracle
+    oracle.lib()
+    return oracle
+
+
+def tiny_lattices():
+    """Small lattices that exercise every boundary kind: Zou-He faces, walls,
+    periodic axes, grain nodes next to the faces and in the interior."""
+    import oracle as O
+    out = []
+    s2 = np.zeros((1, 6, 8), np.uint8)
+    s2[0, 2, 3] = 1
+    s2[0, 3, 4] = 1
+    s2[0, 0, 1] = 1           # grain node touching the wall, next to the inlet
+    out.append(("d2q9_wall_grains", O.Lattice(9, 8, 6, 1, (O.BC_PRESSURE, O.BC_WALL, O.BC_PERIODIC), s2)))
+    s2p = np.zeros((1, 5, 7), np.uint8)
+    s2p[0, 1, 2] = 1
+    s2p[0, 4, 0] = 1          # solid node on the inlet face
+    out.append(("d2q9_periodic_y", O.Lattice(9, 7, 5, 1, (O.BC_PRESSURE, O.BC_PERIODIC, O.BC_PERIODIC), s2p)))
+    s3 = np.zeros((4, 5, 6), np.uint8)
+    s3[1, 2, 2] = 1
+    s3[2, 2, 3] = 1
+    s3[0, 4, 5] = 1           # solid node on the outlet face
+    out.append(("d3q19_periodic_yz", O.Lattice(19, 6, 5, 4, (O.BC_PRESSURE, O.BC_PERIODIC, O.BC_PERIODIC), s3)))
+    s3w = np.zeros((4, 5, 6), np.uint8)
+    s3w[2, 1, 3] = 1
+    out.append(("d3q19_wall_y", O.Lattice(19, 6, 5, 4, (O.BC_PRESSURE, O.BC_WALL, O.BC_PERIODIC), s3w)))
+    s3ww = np.zeros((3, 4, 5), np.uint8)
+    s3ww[1, 1, 2] = 1
+    out.append(("d3q19_wall_yz", O.Lattice(19, 5, 4, 3, (O.BC_PRESSURE, O.BC_WALL, O.BC_WALL), s3ww)))
+    return out

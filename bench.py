@@ -1,0 +1,219 @@
+"""Benchmark of the differentiable LBM hot path on one MI355X.
+
+One benchmark step is one full gradient evaluation of the 3D inverse
+problem (inlet pressure profile + viscosity in a packed-sphere box):
+taped forward over T steps with checkpoints every K, loss, reverse sweep
+(segment recompute + adjoint steps), gradient reductions.
+
+Workload (synthetic stand-in for the paper's 3D granular media): D3Q19,
+128^3 nodes, overlapping spheres with radii U[6, 10] to porosity 0.40
+(seed 3), periodic y and z, Zou-He inlet profile rho_in = 1 + 0.004 phi
+(phi: 8 Fourier modes, seed 33), rho_out = 1, tau = 0.75, T = 8000, K = 400,
+VEC loss against the velocity of a second run at tau = 0.9, mean over
+fluid nodes.
+
+Prints ONE JSON line.  value = forward+adjoint MLUPS (all lattice nodes x T
+per second of the whole gradient evaluation).
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS fwd & fwd+adjoint (D3Q19 grains) vs HBM roofline; warm vs cold solve sec"
+HBM_PEAK_GBS = 8000.0
+Q = 19
+BYTES_FWD = 2 * Q * 4        # read + write one population set per fluid node
+BYTES_ADJ = 3 * Q * 4        # gather F^{k-1}, gather nu^{k+1}, write nu^k
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def workload(n=128, T=8000, K=400):
+    from paper_2310_00810_amd import geometry as G
+    solid = G.boolean_spheres((n, n, n), (6.0, 10.0), 0.40, seed=3, periodic=(False, True, True), x_margin=4)
+    phi = G.fourier_profile(n, n, n_modes=8, seed=33)
+    return dict(n=n, T=T, K=K, solid=solid, din=(0.004 * phi).astype(np.float32), tau=0.75, tau_target=0.9)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("lbm_device.hpp", "lbm_kernels.hip"):
+        with open(os.path.join(ROOT, "paper_2310_00810_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel):
+    """HBM bytes per launch from the committed rocprofv3 --pmc summary of this
+    kernel, if it was taken on the current kernel source; else None."""
+    p = os.path.join(PROFILES, "pmc_traffic.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        d = json.load(open(p))
+    except Exception:
+        return None
+    e = d.get(kernel)
+    if not e or e.get("source_hash") != kernel_source_hash():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def copy_peak_gbs(torch, nbytes=4 << 30, reps=10):
+    """Measured device-to-device copy bandwidth (read + write bytes / s)."""
+    x = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    x.fill_(1.0)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        y.copy_(x)
+    b.record()
+    torch.cuda.synchronize()
+    gbs = 2 * nbytes * reps / (a.elapsed_time(b) * 1e-3) / 1e9
+    del x, y
+    torch.cuda.empty_cache()
+    return gbs
+
+
+def cpu_baseline(w, budget_steps=3):
+    """The FP64 oracle's gradient evaluation (forward + reverse) on the same
+    128^3 problem for a bounded number of steps, timed on the host cores."""
+    import oracle as O
+    n = w["n"]
+    lat = O.Lattice(19, n, n, n, (O.BC_PRESSURE, O.BC_PERIODIC, O.BC_PERIODIC), w["solid"])
+    f0 = O.init_eq(lat, 1.0, 0.0)
+    tgt = np.zeros(lat.shape + (3,))
+    rin = 1.0 + w["din"].astype(np.float64)
+    nfl = int(lat.fluid().sum())
+    t0 = time.perf_counter()
+    O.grad(lat, w["tau"], rin, 1.0, f0, budget_steps, tgt, scale=1.0 / nfl, K=budget_steps)
+    dt = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": n ** 3 * budget_steps / dt / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
+            "sample": f"FP64 oracle forward+reverse gradient of the same 128^3 D3Q19 sphere-box problem, "
+                      f"{budget_steps} steps (K={budget_steps}), {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--size", type=int, default=128)
+    ap.add_argument("--T", type=int, default=8000)
+    ap.add_argument("--K", type=int, default=400)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-copy", action="store_true", help="skip the copy-bandwidth calibration")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+    from paper_2310_00810_amd import lbm
+
+    w = workload(args.size, args.T, args.K)
+    n, T, K = w["n"], w["T"], w["K"]
+    fluid_frac = float((w["solid"] == 0).mean())
+    n_fluid = int((w["solid"] == 0).sum())
+    print(f"[bench] workload D3Q19 {n}^3 porosity {fluid_frac:.3f} T={T} K={K}", file=sys.stderr, flush=True)
+
+    # target velocity from a run at another tau (the inverse problem recovers tau and the profile)
+    ins0 = lbm.Instance(n, n, n, solid=w["solid"])
+    s0 = lbm.Solver(19, [ins0], bc=("pressure", "periodic", "periodic"), steps=T, inlet_mode="profile")
+    s0.forward(w["tau_target"], w["din"].ravel(), 0.0, want_loss=False)
+    _, ut = s0.macro()
+    target = ut.cpu().numpy().reshape(n, n, n, 3)
+    del s0, ut
+    torch.cuda.empty_cache()
+
+    ins = lbm.Instance(n, n, n, solid=w["solid"], target_u=target)
+    s = lbm.Solver(19, [ins], bc=("pressure", "periodic", "periodic"), steps=T, ckpt_interval=K, tape=True,
+                   loss_scale="mean", inlet_mode="profile")
+    print(f"[bench] workspace {s.workspace_bytes / 2**30:.1f} GiB", file=sys.stderr, flush=True)
+
+    def one():
+        s.forward(w["tau"], w["din"].ravel(), 0.0, record_tape=True)
+        s.adjoint()
+        return s.grad()
+
+    for i in range(args.warmup):
+        one()
+        print(f"[bench] warmup {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    s.set_timing(True, reset=True)
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        g = one()
+        print(f"[bench] step {i + 1}/{args.steps} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    tm = s.timing()
+    s.set_timing(False)
+
+    ms_step = dt / args.steps * 1e3
+    value = n ** 3 * T / (ms_step * 1e-3) / 1e6
+    fwd_ms = tm["forward_ms"] / max(tm["forward_launches"], 1)
+    adj_ms = tm["adjoint_ms"] / max(tm["adjoint_launches"], 1)
+    rec_ms = tm["recompute_ms"] / max(tm["recompute_launches"], 1)
+    adj_bytes = BYTES_ADJ * n_fluid
+    fwd_bytes = BYTES_FWD * n_fluid
+    adj_gbs = adj_bytes / (adj_ms * 1e-3) / 1e9
+    fwd_gbs = fwd_bytes / (fwd_ms * 1e-3) / 1e9
+    traffic = load_traffic("k_adj_step<19>")
+    fwd_mlups = n ** 3 / (fwd_ms * 1e-3) / 1e6
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"D3Q19 {n}^3 packed spheres r~U[6,10] porosity 0.40, periodic y/z, "
+                               f"Zou-He profile inlet (8 Fourier modes) + tau gradient, T={T}, K={K}, "
+                               f"one step = taped forward + reverse sweep",
+                   "lattice": "D3Q19", "nodes": n ** 3, "fluid_nodes": n_fluid, "T": T, "K": K},
+        "roofline": {"bound": "hbm", "achieved": round(adj_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(adj_gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "kernel": "k_adj_step<19>", "bytes_per_launch": adj_bytes,
+                     "avg_launch_ms": round(adj_ms, 5)},
+        "fwd_mlups": round(fwd_mlups, 1),
+        "fwd_fluid_mlups": round(n_fluid / (fwd_ms * 1e-3) / 1e6, 1),
+        "fwd_roofline": {"kernel": "k_step<19>", "achieved": round(fwd_gbs, 1), "unit": "GB/s",
+                         "frac": round(fwd_gbs / HBM_PEAK_GBS, 4), "avg_launch_ms": round(fwd_ms, 5),
+                         "bytes_per_launch": fwd_bytes},
+        "recompute_avg_launch_ms": round(rec_ms, 5),
+        "gradient_norms": {"drho_in": float(np.linalg.norm(g["drho_in"])), "dtau": float(g["dtau"][0])},
+        "warm_vs_cold": None,
+    }
+    if not args.no_copy:
+        del s
+        torch.cuda.empty_cache()
+        out["copy_peak_gbs"] = round(copy_peak_gbs(torch), 1)
+    if not args.no_cpu:
+        print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(w)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

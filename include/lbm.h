@@ -1,0 +1,186 @@
+/*
+ * lbm.h -- C ABI of the MI355X differentiable lattice Boltzmann library
+ * (liblbm.so).
+ *
+ * The library computes the forward map of a BGK lattice Boltzmann solver
+ * (D2Q9 or D3Q19, Section 2.1, Eq. 1-5 of Wang & Kumar, "An inverse analysis
+ * of fluid flow through granular media using differentiable lattice
+ * Boltzmann method") and the exact reverse-mode derivative of a final-time
+ * velocity-mismatch loss (Section 2.2 and its loss listing; Eq. 7 and Eq. 15)
+ * with respect to the inlet density (constant head or per-node profile,
+ * Section 3.1), the outlet density and the relaxation time tau (viscosity,
+ * Eq. 9; Section 3.4).
+ *
+ * Boundary conditions: halfway bounce-back on walls and solid nodes (grains,
+ * spheres); Zou-He density boundaries on the x faces (inlet x = 0, outlet
+ * x = nx-1) when bc_x = LBM_BC_PRESSURE; periodic or wall y and z axes.
+ *
+ * Conventions
+ *   - Populations are stored on the device as shifted values f_i - w_i in
+ *     FP32 (structure of arrays, x rows padded to a multiple of 32).  Where
+ *     the ABI exchanges populations it uses the dense shifted layout
+ *     [inst][i][nz][ny][nx], float.
+ *   - Velocity ordering:
+ *       D2Q9 : (0,0) (1,0) (0,1) (-1,0) (0,-1) (1,1) (-1,1) (-1,-1) (1,-1)
+ *       D3Q19: rest, +x -x +y -y +z -z, (1,1,0) (-1,-1,0) (1,-1,0) (-1,1,0),
+ *              (1,0,1) (-1,0,-1) (1,0,-1) (-1,0,1),
+ *              (0,1,1) (0,-1,-1) (0,1,-1) (0,-1,1)
+ *   - Densities cross the ABI as deviations drho = rho - 1 (FP64 parameters,
+ *     FP32 fields); velocities as D = 2 (D2Q9) or D = 3 (D3Q19) components,
+ *     node-major: u[inst][nz][ny][nx][D].
+ *   - Per-node arrays of several instances are concatenated instance after
+ *     instance.
+ *
+ * Ownership and streams
+ *   - The caller owns all device memory.  lbm_workspace_bytes() sizes one
+ *     workspace, which the caller allocates and passes to lbm_init(); the
+ *     library never allocates device memory and the handle owns only host
+ *     metadata.
+ *   - All device work is enqueued on the stream given to lbm_init().  Calls
+ *     that return host values (loss, gradients, residuals) synchronise that
+ *     stream; the others are asynchronous.
+ *   - A handle is not thread-safe: use one handle per stream.
+ *
+ * Errors: every call returns 0 (LBM_OK) or a negative LBM_E* code; nothing
+ * aborts or throws across the ABI.  lbm_strerror() names a code and
+ * lbm_last_error() gives the detail of the most recent failure on the
+ * calling thread (including the HIP error string for LBM_EDEVICE).
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBM_OK 0
+#define LBM_EINVAL (-1)    /* bad argument: dims, tau <= 0.5, NULL pointer, solid inlet in profile mode */
+#define LBM_ENOMEM (-2)    /* workspace smaller than lbm_workspace_bytes() */
+#define LBM_ESTATE (-3)    /* call out of order (adjoint without a taped forward, grad without adjoint) */
+#define LBM_EUNSTABLE (-4) /* non-finite loss, residual or state */
+#define LBM_ECORRUPT (-5)  /* a recomputed segment does not reproduce its checkpoint bit for bit */
+#define LBM_EDEVICE (-6)   /* a HIP runtime call failed */
+
+enum lbm_lattice { LBM_D2Q9 = 9, LBM_D3Q19 = 19 };
+enum lbm_bc { LBM_BC_PRESSURE = 0, LBM_BC_PERIODIC = 1, LBM_BC_WALL = 2 };
+enum lbm_loss_kind { LBM_LOSS_VEC = 0, LBM_LOSS_NORM = 1 };
+enum lbm_loss_scale { LBM_SCALE_SUM = 0, LBM_SCALE_MEAN_FLUID = 1 };
+enum lbm_inlet_mode { LBM_INLET_CONST = 0, LBM_INLET_PROFILE = 1 };
+enum lbm_population_kind { LBM_POP_STATE = 0, LBM_POP_ADJOINT = 1 };
+
+/* One lattice instance.  Host arrays are copied into the workspace by
+ * lbm_init(); the caller may free them afterwards. */
+typedef struct lbm_instance {
+    int nx, ny, nz;          /* nz = 1 for D2Q9; nx >= 2 with a pressure x axis */
+    const uint8_t *solid;    /* [nz][ny][nx], nonzero = solid node; NULL = all fluid */
+    const float *roi;        /* [nz][ny][nx] loss weights (Eq. 7 region of interest); NULL = 1 */
+    const float *target_u;   /* [nz][ny][nx][D] target velocity; NULL = 0 */
+} lbm_instance;
+
+/* The problem: lattice, instances, boundary kinds, horizon and loss. */
+typedef struct lbm_problem {
+    int lattice;             /* LBM_D2Q9 or LBM_D3Q19 */
+    int n_inst;              /* number of independent instances (>= 1) */
+    const lbm_instance *inst;
+    int bc_x, bc_y, bc_z;    /* lbm_bc per axis; LBM_BC_PRESSURE only on x */
+    int steps;               /* T, number of time steps of lbm_forward() (>= 1) */
+    int ckpt_interval;       /* K, checkpoint interval of the taped forward; 0 = ceil(sqrt(T)) */
+    int tape;                /* nonzero: reserve checkpoints and a segment store for lbm_adjoint() */
+    int loss_kind;           /* lbm_loss_kind: VEC |u - u_t|^2 or NORM (|u| - |u_t|)^2 */
+    int loss_scale;          /* lbm_loss_scale: SUM, or MEAN_FLUID = 1 / (number of fluid nodes) (Eq. 15) */
+    int inlet_mode;          /* lbm_inlet_mode: one inlet density per instance, or one per inlet node */
+} lbm_problem;
+
+/* Parameters of one forward evaluation (host arrays, read during the call). */
+typedef struct lbm_params {
+    const double *tau;       /* [n_inst] relaxation times, > 0.5 */
+    const double *drho_in;   /* CONST: [n_inst]; PROFILE: per instance [nz][ny], concatenated */
+    const double *drho_out;  /* [n_inst] outlet density deviations */
+} lbm_params;
+
+/* Elapsed device time per phase of the most recent calls (HIP events on the
+ * library stream), filled when timing was enabled with lbm_set_timing(). */
+typedef struct lbm_timing {
+    double forward_ms;       /* lbm_forward step launches */
+    long forward_launches;
+    double recompute_ms;     /* segment recompute launches inside lbm_adjoint */
+    long recompute_launches;
+    double adjoint_ms;       /* adjoint step launches inside lbm_adjoint */
+    long adjoint_launches;
+} lbm_timing;
+
+typedef struct lbm_handle lbm_handle;
+
+/* Bytes of device workspace lbm_init() needs for problem p (pure query). */
+int lbm_workspace_bytes(const lbm_problem *p, size_t *bytes);
+
+/* Validates p, lays the workspace out, copies masks, weights and targets to
+ * the device and sets the initial state to rest (rho = 1, u = 0).
+ * d_workspace: device pointer of at least lbm_workspace_bytes() bytes, 256-B
+ * aligned; hip_stream: hipStream_t (NULL = default stream). */
+int lbm_init(lbm_handle **h, const lbm_problem *p, void *d_workspace, size_t bytes,
+             void *hip_stream);
+
+/* Releases the host metadata of h (the workspace stays the caller's). */
+int lbm_destroy(lbm_handle *h);
+
+/* Initial state f = f_eq(1 + drho, u) at fluid nodes (Eq. 5).  d_drho:
+ * device [nodes] float, d_u: device [nodes][D] float; both NULL = rest. */
+int lbm_set_initial(lbm_handle *h, const float *d_drho, const float *d_u);
+
+/* Initial state from explicit populations: device dense shifted
+ * [inst][i][nz][ny][nx] float (values at solid nodes are ignored). */
+int lbm_set_populations(lbm_handle *h, const float *d_fbar);
+
+/* Copies populations to device d_out in the dense shifted layout:
+ * LBM_POP_STATE   -> the state after the last forward / run (post-collision);
+ * LBM_POP_ADJOINT -> dL/d(initial state) after lbm_adjoint().
+ * Solid nodes read as 0. */
+int lbm_get_populations(lbm_handle *h, int which, float *d_out);
+
+/* Runs T steps from the initial state (fused pull streaming, bounce-back,
+ * Zou-He and BGK collision per step) and evaluates the loss on the final
+ * state.  With record_tape nonzero (requires problem.tape) the states needed
+ * by lbm_adjoint() are kept.  loss_out (host, nullable): [n_inst] losses;
+ * LBM_EUNSTABLE if any is not finite. */
+int lbm_forward(lbm_handle *h, const lbm_params *prm, int record_tape, double *loss_out);
+
+/* Reverse sweep over the taped forward.  d_seed_du NULL: the built-in loss;
+ * otherwise a device array [nodes][D] float of dL/du(T) supplied by the
+ * caller (any differentiable loss of the final velocity). */
+int lbm_adjoint(lbm_handle *h, const float *d_seed_du);
+
+/* Host outputs of the last lbm_adjoint(), each nullable:
+ * d_rho_in  CONST: [n_inst]; PROFILE: per instance [nz][ny] (0 at solid nodes);
+ * d_tau     [n_inst];
+ * d_rho_out [n_inst]. */
+int lbm_grad(lbm_handle *h, double *d_rho_in, double *d_tau, double *d_rho_out);
+
+/* Steps from the initial state until the two-step-mean velocity residual
+ * r = ||u(t) - u(t-2)|| / ||u(t) + u(t-1)|| (every instance) is <= tol, testing
+ * every check_every steps, or until max_steps.  steps_out / r_out (host,
+ * nullable) receive the step count and the largest instance residual. */
+int lbm_run_to_residual(lbm_handle *h, const lbm_params *prm, double tol, int max_steps,
+                        int check_every, int *steps_out, double *r_out);
+
+/* Macroscopic fields of the current state to device arrays: d_drho [nodes],
+ * d_u [nodes][D] (zeros at solid nodes).  mean2 nonzero: the mean of the
+ * last two states (cancels the undamped period-2 staggered mode; needs a
+ * state produced by at least two steps). */
+int lbm_get_macro(lbm_handle *h, float *d_drho, float *d_u, int mean2);
+
+/* Enables (nonzero) or disables per-phase event timing; reset clears it. */
+int lbm_set_timing(lbm_handle *h, int enable, int reset);
+int lbm_get_timing(lbm_handle *h, lbm_timing *out);
+
+const char *lbm_strerror(int code);
+const char *lbm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

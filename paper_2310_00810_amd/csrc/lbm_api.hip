@@ -1,0 +1,613 @@
+// Host side of liblbm.so: workspace planning, tape (checkpoint + segment
+// recompute) scheduling, parameter upload and the C ABI declared in lbm.h.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "lbm.h"
+#include "lbm_kernels.hpp"
+
+using lbm::InstDev;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(LBM_EDEVICE, "%s failed: %s (%d)", #expr, hipGetErrorString(e_), (int)e_); \
+    } while (0)
+
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Device workspace layout of one problem.
+struct Layout {
+    int q = 9, D = 2, n_inst = 0;
+    int T = 1, K = 1, n_seg = 1, tape = 0;
+    int n_tiles = 0;
+    long long total_poff = 0, total_nodes = 0, total_face = 0, total_words = 0;
+    long long S = 0;          // floats per state buffer
+    int n_states = 0;
+    size_t off_inst = 0, off_mask = 0, off_roi = 0, off_target = 0, off_face_in = 0, off_face_out = 0,
+           off_grad_in = 0, off_grad_out = 0, off_part_loss = 0, off_part_dtau = 0, off_part_res = 0,
+           off_red = 0, off_u2 = 0, off_states = 0, state_bytes = 0, total = 0;
+    std::vector<InstDev> inst;
+};
+
+int validate_problem(const lbm_problem *p) {
+    if (!p) return fail(LBM_EINVAL, "problem is NULL");
+    if (p->lattice != LBM_D2Q9 && p->lattice != LBM_D3Q19)
+        return fail(LBM_EINVAL, "lattice must be LBM_D2Q9 or LBM_D3Q19 (got %d)", p->lattice);
+    if (p->n_inst < 1 || !p->inst) return fail(LBM_EINVAL, "n_inst must be >= 1 with a descriptor array");
+    const int bcs[3] = {p->bc_x, p->bc_y, p->bc_z};
+    for (int a = 0; a < 3; ++a)
+        if (bcs[a] < LBM_BC_PRESSURE || bcs[a] > LBM_BC_WALL)
+            return fail(LBM_EINVAL, "boundary kind of axis %d is invalid (%d)", a, bcs[a]);
+    if (p->bc_y == LBM_BC_PRESSURE || p->bc_z == LBM_BC_PRESSURE)
+        return fail(LBM_EINVAL, "pressure (Zou-He) faces are supported on the x axis only");
+    if (p->steps < 1) return fail(LBM_EINVAL, "steps must be >= 1 (got %d)", p->steps);
+    if (p->ckpt_interval < 0) return fail(LBM_EINVAL, "ckpt_interval must be >= 0");
+    if (p->loss_kind != LBM_LOSS_VEC && p->loss_kind != LBM_LOSS_NORM) return fail(LBM_EINVAL, "bad loss_kind");
+    if (p->loss_scale != LBM_SCALE_SUM && p->loss_scale != LBM_SCALE_MEAN_FLUID)
+        return fail(LBM_EINVAL, "bad loss_scale");
+    if (p->inlet_mode != LBM_INLET_CONST && p->inlet_mode != LBM_INLET_PROFILE)
+        return fail(LBM_EINVAL, "bad inlet_mode");
+    for (int b = 0; b < p->n_inst; ++b) {
+        const lbm_instance &I = p->inst[b];
+        if (I.nx < 1 || I.ny < 1 || I.nz < 1)
+            return fail(LBM_EINVAL, "instance %d: dimensions must be positive (%d x %d x %d)", b, I.nx, I.ny, I.nz);
+        if (p->lattice == LBM_D2Q9 && I.nz != 1) return fail(LBM_EINVAL, "instance %d: D2Q9 needs nz = 1", b);
+        if (p->bc_x == LBM_BC_PRESSURE && I.nx < 2)
+            return fail(LBM_EINVAL, "instance %d: a pressure x axis needs nx >= 2", b);
+        if ((long long)I.nx * I.ny * I.nz > (1LL << 31))
+            return fail(LBM_EINVAL, "instance %d: more than 2^31 nodes", b);
+        if (p->inlet_mode == LBM_INLET_PROFILE && p->bc_x == LBM_BC_PRESSURE && I.solid) {
+            for (long long zy = 0; zy < (long long)I.ny * I.nz; ++zy)
+                if (I.solid[zy * I.nx])
+                    return fail(LBM_EINVAL, "instance %d: solid node on the inlet face in profile mode", b);
+        }
+    }
+    return LBM_OK;
+}
+
+void plan(const lbm_problem *p, Layout &L) {
+    L.q = p->lattice;
+    L.D = L.q == 9 ? 2 : 3;
+    L.n_inst = p->n_inst;
+    L.T = p->steps;
+    L.K = p->ckpt_interval > 0 ? p->ckpt_interval : (int)ceil(sqrt((double)p->steps));
+    if (L.K > L.T) L.K = L.T;
+    L.n_seg = (L.T + L.K - 1) / L.K;
+    L.tape = p->tape ? 1 : 0;
+    L.inst.assign(p->n_inst, InstDev{});
+    long long poff = 0, node = 0, face = 0, words = 0;
+    int tile = 0;
+    for (int b = 0; b < p->n_inst; ++b) {
+        const lbm_instance &S = p->inst[b];
+        InstDev &I = L.inst[b];
+        I.nx = S.nx; I.ny = S.ny; I.nz = S.nz;
+        I.pitch = (int)align_up(S.nx, 32);
+        I.words = I.pitch / 32;
+        I.tiles_x = (S.nx + lbm::TILE_X - 1) / lbm::TILE_X;
+        I.tiles_y = (S.ny + lbm::TILE_Y - 1) / lbm::TILE_Y;
+        I.n_tiles = I.tiles_x * I.tiles_y * S.nz;
+        I.tile_begin = tile;
+        tile += I.n_tiles;
+        I.plane = (long long)S.nz * S.ny * I.pitch;
+        I.poff = poff;
+        I.st_off = (long long)L.q * poff;
+        poff += (long long)align_up((size_t)I.plane, 64);
+        I.node_off = node;
+        node += (long long)S.nx * S.ny * S.nz;
+        I.face_off = face;
+        face += (long long)S.ny * S.nz;
+        I.mask_off = words;
+        words += (long long)S.nz * S.ny * I.words;
+        I.omega = 1.0f;
+        I.inv_tau2 = 1.0f;
+        I.loss_scale = 1.0f;
+    }
+    L.n_tiles = tile;
+    L.total_poff = poff;
+    L.total_nodes = node;
+    L.total_face = face;
+    L.total_words = words;
+    L.S = (long long)L.q * poff;
+    L.n_states = 3 + (L.tape ? (L.n_seg - 1) + (L.K - 1) + 2 : 0);
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + bytes, 256); return r; };
+    L.off_inst = take(sizeof(InstDev) * p->n_inst);
+    L.off_mask = take(sizeof(uint32_t) * words);
+    L.off_roi = take(sizeof(float) * poff);
+    L.off_target = take(sizeof(float) * poff * L.D);
+    L.off_face_in = take(sizeof(float) * face);
+    L.off_face_out = take(sizeof(float) * face);
+    L.off_grad_in = take(sizeof(double) * face);
+    L.off_grad_out = take(sizeof(double) * face);
+    L.off_part_loss = take(sizeof(double) * L.n_tiles);
+    L.off_part_dtau = take(sizeof(double) * L.n_tiles);
+    L.off_part_res = take(sizeof(double) * 2 * L.n_tiles);
+    L.off_red = take(sizeof(double) * 2 * p->n_inst);
+    L.off_u2 = take(sizeof(float) * node * L.D);
+    L.state_bytes = align_up(sizeof(float) * (size_t)L.S, 256);
+    L.off_states = o;
+    L.total = L.off_states + L.state_bytes * (size_t)L.n_states;
+}
+
+}  // namespace
+
+struct lbm_handle {
+    Layout L;
+    lbm_problem P;
+    hipStream_t stream = nullptr;
+    char *ws = nullptr;
+    lbm::Geo G{};
+    std::vector<InstDev> hinst;
+    std::vector<float> h_face_in, h_face_out;
+    std::vector<double> h_red, h_grad;
+    // state bookkeeping
+    float *cur = nullptr, *prev = nullptr;
+    long long cur_steps = 0;          // steps taken since the initial state
+    bool fwd_taped = false, adjoint_done = false, seg_holds_last = false;
+    float *nu_last = nullptr;         // nu^1 after the adjoint
+    std::vector<double> tau;          // parameters of the taped forward
+    // timing
+    bool timing = false;
+    lbm_timing tm{};
+    std::vector<hipEvent_t> ev;
+
+    float *state(int k) const { return (float *)(ws + L.off_states + L.state_bytes * (size_t)k); }
+    float *init() const { return state(0); }
+    float *pp(int k) const { return state(1 + k); }
+    float *ckpt(int c) const { return c == 0 ? init() : state(3 + (c - 1)); }
+    float *seg(int j) const { return state(3 + (L.n_seg - 1) + (j - 1)); }
+    float *nu(int k) const { return state(3 + (L.n_seg - 1) + (L.K - 1) + k); }
+    template <class T> T *at(size_t off) const { return (T *)(ws + off); }
+};
+
+namespace {
+
+int upload_params(lbm_handle *h, const lbm_params *prm) {
+    if (!prm || !prm->tau || !prm->drho_in || !prm->drho_out)
+        return fail(LBM_EINVAL, "params and their tau, drho_in, drho_out arrays must be non-NULL");
+    const Layout &L = h->L;
+    h->h_face_in.assign(L.total_face, 0.f);
+    h->h_face_out.assign(L.total_face, 0.f);
+    long long prof = 0;
+    for (int b = 0; b < L.n_inst; ++b) {
+        InstDev &I = h->hinst[b];
+        const double tau = prm->tau[b];
+        if (!(tau > 0.5) || !isfinite(tau)) return fail(LBM_EINVAL, "instance %d: tau must be > 0.5 (got %g)", b, tau);
+        I.omega = (float)(1.0 / tau);
+        I.inv_tau2 = (float)(1.0 / (tau * tau));
+        const long long nf = (long long)I.ny * I.nz;
+        const double dout = prm->drho_out[b];
+        if (!isfinite(dout) || dout <= -1.0) return fail(LBM_EINVAL, "instance %d: drho_out must be finite and > -1", b);
+        for (long long k = 0; k < nf; ++k) {
+            double din = h->P.inlet_mode == LBM_INLET_PROFILE ? prm->drho_in[prof + k] : prm->drho_in[b];
+            if (!isfinite(din) || din <= -1.0) return fail(LBM_EINVAL, "instance %d: drho_in must be finite and > -1", b);
+            h->h_face_in[I.face_off + k] = (float)din;
+            h->h_face_out[I.face_off + k] = (float)dout;
+        }
+        prof += nf;
+    }
+    HIP_TRY(hipMemcpyAsync(h->at<InstDev>(L.off_inst), h->hinst.data(), sizeof(InstDev) * L.n_inst,
+                           hipMemcpyHostToDevice, h->stream));
+    if (L.total_face) {
+        HIP_TRY(hipMemcpyAsync(h->at<float>(L.off_face_in), h->h_face_in.data(), sizeof(float) * L.total_face,
+                               hipMemcpyHostToDevice, h->stream));
+        HIP_TRY(hipMemcpyAsync(h->at<float>(L.off_face_out), h->h_face_out.data(),
+                               sizeof(float) * L.total_face, hipMemcpyHostToDevice, h->stream));
+    }
+    return LBM_OK;
+}
+
+int record(lbm_handle *h, int idx) {
+    if (!h->timing) return LBM_OK;
+    while ((int)h->ev.size() <= idx) {
+        hipEvent_t e;
+        HIP_TRY(hipEventCreate(&e));
+        h->ev.push_back(e);
+    }
+    HIP_TRY(hipEventRecord(h->ev[idx], h->stream));
+    return LBM_OK;
+}
+
+double elapsed(lbm_handle *h, int a, int b) {
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, h->ev[a], h->ev[b]);
+    return ms;
+}
+
+int step(lbm_handle *h, const float *src, float *dst) {
+    HIP_TRY(lbm::launch_step(h->L.q, h->G, src, dst, h->at<float>(h->L.off_face_in),
+                             h->at<float>(h->L.off_face_out), h->stream));
+    return LBM_OK;
+}
+
+int reduce_to_host(lbm_handle *h, size_t part_off, int stride) {
+    const Layout &L = h->L;
+    HIP_TRY(lbm::launch_reduce(h->at<InstDev>(L.off_inst), L.n_inst, h->at<double>(part_off), stride,
+                               h->at<double>(L.off_red), h->stream));
+    h->h_red.assign((size_t)L.n_inst * stride, 0.0);
+    HIP_TRY(hipMemcpyAsync(h->h_red.data(), h->at<double>(L.off_red), sizeof(double) * L.n_inst * stride,
+                           hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *lbm_strerror(int code) {
+    switch (code) {
+        case LBM_OK: return "ok";
+        case LBM_EINVAL: return "invalid argument";
+        case LBM_ENOMEM: return "workspace too small";
+        case LBM_ESTATE: return "call out of order";
+        case LBM_EUNSTABLE: return "non-finite value (unstable run)";
+        case LBM_ECORRUPT: return "recomputed state does not match its checkpoint";
+        case LBM_EDEVICE: return "HIP runtime error";
+        default: return "unknown error";
+    }
+}
+
+const char *lbm_last_error(void) { return g_err.c_str(); }
+
+int lbm_workspace_bytes(const lbm_problem *p, size_t *bytes) {
+    int rc = validate_problem(p);
+    if (rc) return rc;
+    if (!bytes) return fail(LBM_EINVAL, "bytes is NULL");
+    Layout L;
+    plan(p, L);
+    *bytes = L.total;
+    return LBM_OK;
+}
+
+int lbm_init(lbm_handle **out, const lbm_problem *p, void *d_workspace, size_t bytes, void *hip_stream) {
+    if (!out) return fail(LBM_EINVAL, "handle pointer is NULL");
+    *out = nullptr;
+    int rc = validate_problem(p);
+    if (rc) return rc;
+    if (!d_workspace) return fail(LBM_EINVAL, "workspace is NULL");
+    if (((uintptr_t)d_workspace) & 255) return fail(LBM_EINVAL, "workspace must be 256-byte aligned");
+    lbm_handle *h = new lbm_handle();
+    plan(p, h->L);
+    if (bytes < h->L.total) {
+        size_t need = h->L.total;
+        delete h;
+        return fail(LBM_ENOMEM, "workspace of %zu bytes, %zu needed", bytes, need);
+    }
+    h->P = *p;
+    h->P.inst = nullptr;
+    h->stream = (hipStream_t)hip_stream;
+    h->ws = (char *)d_workspace;
+    h->hinst = h->L.inst;
+    const Layout &L = h->L;
+    // host copies of masks, weights and targets in the device layouts
+    std::vector<uint32_t> mask(L.total_words, 0u);
+    std::vector<float> roi(L.total_poff, 0.f), target((size_t)L.total_poff * L.D, 0.f);
+    for (int b = 0; b < L.n_inst; ++b) {
+        const lbm_instance &S = p->inst[b];
+        InstDev &I = h->hinst[b];
+        long long nfluid = 0;
+        for (int z = 0; z < S.nz; ++z)
+            for (int y = 0; y < S.ny; ++y)
+                for (int x = 0; x < S.nx; ++x) {
+                    const long long dn = ((long long)z * S.ny + y) * S.nx + x;
+                    const bool sol = S.solid && S.solid[dn];
+                    const long long pr = ((long long)z * S.ny + y) * I.pitch + x;
+                    if (sol) {
+                        mask[I.mask_off + ((long long)z * S.ny + y) * I.words + (x >> 5)] |= 1u << (x & 31);
+                        continue;
+                    }
+                    ++nfluid;
+                    roi[I.poff + pr] = S.roi ? S.roi[dn] : 1.0f;
+                    if (S.target_u)
+                        for (int a = 0; a < L.D; ++a)
+                            target[I.poff * L.D + a * I.plane + pr] = S.target_u[dn * L.D + a];
+                }
+        I.n_fluid = (int)nfluid;
+        I.loss_scale = p->loss_scale == LBM_SCALE_MEAN_FLUID ? (nfluid ? (float)(1.0 / (double)nfluid) : 0.f) : 1.0f;
+    }
+    auto cp = [&](size_t off, const void *src, size_t n) -> int {
+        if (!n) return LBM_OK;
+        HIP_TRY(hipMemcpyAsync(h->ws + off, src, n, hipMemcpyHostToDevice, h->stream));
+        return LBM_OK;
+    };
+    int e = 0;
+    if ((e = cp(L.off_inst, h->hinst.data(), sizeof(InstDev) * L.n_inst)) ||
+        (e = cp(L.off_mask, mask.data(), sizeof(uint32_t) * mask.size())) ||
+        (e = cp(L.off_roi, roi.data(), sizeof(float) * roi.size())) ||
+        (e = cp(L.off_target, target.data(), sizeof(float) * target.size()))) {
+        delete h;
+        return e;
+    }
+    h->G.inst = h->at<InstDev>(L.off_inst);
+    h->G.n_inst = L.n_inst;
+    h->G.n_tiles = L.n_tiles;
+    h->G.bcx = p->bc_x; h->G.bcy = p->bc_y; h->G.bcz = p->bc_z;
+    h->G.mask = h->at<uint32_t>(L.off_mask);
+    hipError_t he = lbm::launch_init_eq(L.q, h->G, h->init(), nullptr, nullptr, h->stream);
+    if (he == hipSuccess) he = hipStreamSynchronize(h->stream);
+    if (he != hipSuccess) {
+        delete h;
+        return fail(LBM_EDEVICE, "initial state: %s", hipGetErrorString(he));
+    }
+    h->cur = h->init();
+    h->prev = nullptr;
+    h->cur_steps = 0;
+    *out = h;
+    return LBM_OK;
+}
+
+int lbm_destroy(lbm_handle *h) {
+    if (!h) return LBM_OK;
+    for (auto e : h->ev) (void)hipEventDestroy(e);
+    delete h;
+    return LBM_OK;
+}
+
+static void reset_state(lbm_handle *h) {
+    h->cur = h->init();
+    h->prev = nullptr;
+    h->cur_steps = 0;
+    h->fwd_taped = h->adjoint_done = h->seg_holds_last = false;
+}
+
+int lbm_set_initial(lbm_handle *h, const float *d_drho, const float *d_u) {
+    if (!h) return fail(LBM_EINVAL, "handle is NULL");
+    HIP_TRY(lbm::launch_init_eq(h->L.q, h->G, h->init(), d_drho, d_u, h->stream));
+    reset_state(h);
+    return LBM_OK;
+}
+
+int lbm_set_populations(lbm_handle *h, const float *d_fbar) {
+    if (!h || !d_fbar) return fail(LBM_EINVAL, "handle and populations must be non-NULL");
+    HIP_TRY(lbm::launch_convert(h->L.q, h->G, h->init(), (float *)d_fbar, 1, h->stream));
+    reset_state(h);
+    return LBM_OK;
+}
+
+int lbm_get_populations(lbm_handle *h, int which, float *d_out) {
+    if (!h || !d_out) return fail(LBM_EINVAL, "handle and output must be non-NULL");
+    if (which == LBM_POP_STATE) {
+        HIP_TRY(lbm::launch_convert(h->L.q, h->G, h->cur, d_out, 0, h->stream));
+        return LBM_OK;
+    }
+    if (which == LBM_POP_ADJOINT) {
+        if (!h->adjoint_done) return fail(LBM_ESTATE, "no adjoint has been computed");
+        HIP_TRY(lbm::launch_adj_final(h->L.q, h->G, h->nu_last, d_out, h->stream));
+        return LBM_OK;
+    }
+    return fail(LBM_EINVAL, "unknown population kind %d", which);
+}
+
+int lbm_forward(lbm_handle *h, const lbm_params *prm, int record_tape, double *loss_out) {
+    if (!h) return fail(LBM_EINVAL, "handle is NULL");
+    const Layout &L = h->L;
+    if (record_tape && !L.tape) return fail(LBM_ESTATE, "the problem was planned without a tape");
+    int rc = upload_params(h, prm);
+    if (rc) return rc;
+    h->fwd_taped = h->adjoint_done = false;
+    const int T = L.T, K = L.K, last = L.n_seg - 1;
+    if ((rc = record(h, 0))) return rc;
+    const float *src = h->init();
+    float *dst = nullptr;
+    for (int t = 1; t <= T; ++t) {
+        if (record_tape && t < T) {
+            const int c = t / K, j = t % K;
+            dst = j == 0 ? h->ckpt(c) : (c == last ? h->seg(j) : h->pp(t & 1));
+        } else {
+            dst = h->pp(t & 1);
+        }
+        if ((rc = step(h, src, dst))) return rc;
+        h->prev = (float *)src;
+        src = dst;
+    }
+    if ((rc = record(h, 1))) return rc;
+    h->cur = dst;
+    h->cur_steps = T;
+    if (record_tape) {
+        h->fwd_taped = true;
+        h->seg_holds_last = true;
+        h->tau.assign(prm->tau, prm->tau + L.n_inst);
+    }
+    if (loss_out) {
+        HIP_TRY(lbm::launch_loss(L.q, h->G, h->cur, h->at<float>(L.off_roi), h->at<float>(L.off_target),
+                                 h->P.loss_kind, h->at<double>(L.off_part_loss), h->stream));
+        if ((rc = reduce_to_host(h, L.off_part_loss, 1))) return rc;
+        bool finite = true;
+        for (int b = 0; b < L.n_inst; ++b) {
+            loss_out[b] = h->h_red[b];
+            finite = finite && isfinite(h->h_red[b]);
+        }
+        if (!finite) return fail(LBM_EUNSTABLE, "non-finite loss after %d steps", T);
+    }
+    if (h->timing) {
+        HIP_TRY(hipEventSynchronize(h->ev[1]));
+        h->tm.forward_ms += elapsed(h, 0, 1);
+        h->tm.forward_launches += T;
+    }
+    return LBM_OK;
+}
+
+int lbm_adjoint(lbm_handle *h, const float *d_seed_du) {
+    if (!h) return fail(LBM_EINVAL, "handle is NULL");
+    if (!h->fwd_taped) return fail(LBM_ESTATE, "lbm_adjoint needs a preceding lbm_forward with record_tape");
+    const Layout &L = h->L;
+    const int q = L.q, T = L.T, K = L.K;
+    int rc;
+    HIP_TRY(lbm::launch_fill_f64(h->at<double>(L.off_grad_in), L.total_face, 0.0, h->stream));
+    HIP_TRY(lbm::launch_fill_f64(h->at<double>(L.off_grad_out), L.total_face, 0.0, h->stream));
+    HIP_TRY(lbm::launch_fill_f64(h->at<double>(L.off_part_dtau), L.n_tiles, 0.0, h->stream));
+    const float *fin = h->at<float>(L.off_face_in), *fout = h->at<float>(L.off_face_out);
+    double *gin = h->at<double>(L.off_grad_in), *gout = h->at<double>(L.off_grad_out);
+    double *dpart = h->at<double>(L.off_part_dtau);
+    int ev = 0;
+    std::vector<int> evmark;
+    for (int c = L.n_seg - 1; c >= 0; --c) {
+        const int t0 = c * K, t1 = std::min(t0 + K, T);
+        auto F = [&](int j) -> const float * { return j == 0 ? h->ckpt(c) : h->seg(j); };
+        if ((rc = record(h, ev))) return rc;
+        evmark.push_back(ev++);
+        if (!(c == L.n_seg - 1 && h->seg_holds_last)) {
+            for (int j = 1; j < t1 - t0; ++j)
+                if ((rc = step(h, F(j - 1), h->seg(j)))) return rc;
+            h->seg_holds_last = false;
+            if (h->timing) h->tm.recompute_launches += t1 - t0 - 1;
+        }
+        if ((rc = record(h, ev))) return rc;
+        evmark.push_back(ev++);
+        for (int k = t1; k > t0; --k) {
+            const float *Fprev = F(k - 1 - t0);
+            float *nu_out = h->nu(k & 1);
+            if (k == T) {
+                HIP_TRY(lbm::launch_adj_seed(q, h->G, Fprev, nu_out, fin, fout, gin, gout,
+                                             h->at<float>(L.off_roi), h->at<float>(L.off_target),
+                                             h->P.loss_kind, d_seed_du, h->stream));
+            } else {
+                HIP_TRY(lbm::launch_adj_step(q, h->G, Fprev, h->nu((k + 1) & 1), nu_out, fin, fout, gin, gout,
+                                             dpart, h->stream));
+            }
+        }
+        if ((rc = record(h, ev))) return rc;
+        evmark.push_back(ev++);
+    }
+    h->nu_last = h->nu(1);
+    h->adjoint_done = true;
+    h->prev = nullptr;  // the segment store that held F^{T-1} has been reused
+    if (h->timing) {
+        HIP_TRY(hipEventSynchronize(h->ev[ev - 1]));
+        for (int c = L.n_seg - 1, s = 0; c >= 0; --c, s += 3) {
+            const int t0 = c * K, t1 = std::min(t0 + K, T);
+            h->tm.recompute_ms += elapsed(h, evmark[s], evmark[s + 1]);
+            h->tm.adjoint_ms += elapsed(h, evmark[s + 1], evmark[s + 2]);
+            h->tm.adjoint_launches += t1 - t0;
+        }
+    }
+    return LBM_OK;
+}
+
+int lbm_grad(lbm_handle *h, double *d_rho_in, double *d_tau, double *d_rho_out) {
+    if (!h) return fail(LBM_EINVAL, "handle is NULL");
+    if (!h->adjoint_done) return fail(LBM_ESTATE, "lbm_grad needs a preceding lbm_adjoint");
+    const Layout &L = h->L;
+    int rc = reduce_to_host(h, L.off_part_dtau, 1);
+    if (rc) return rc;
+    std::vector<double> gin(L.total_face), gout(L.total_face);
+    if (L.total_face) {
+        HIP_TRY(hipMemcpyAsync(gin.data(), h->at<double>(L.off_grad_in), sizeof(double) * L.total_face,
+                               hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(hipMemcpyAsync(gout.data(), h->at<double>(L.off_grad_out), sizeof(double) * L.total_face,
+                               hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+    }
+    long long prof = 0;
+    bool finite = true;
+    for (int b = 0; b < L.n_inst; ++b) {
+        const InstDev &I = h->hinst[b];
+        const long long nf = (long long)I.ny * I.nz;
+        double si = 0.0, so = 0.0;
+        for (long long k = 0; k < nf; ++k) {
+            si += gin[I.face_off + k];
+            so += gout[I.face_off + k];
+            if (d_rho_in && h->P.inlet_mode == LBM_INLET_PROFILE) d_rho_in[prof + k] = gin[I.face_off + k];
+        }
+        if (d_rho_in && h->P.inlet_mode == LBM_INLET_CONST) d_rho_in[b] = si;
+        if (d_rho_out) d_rho_out[b] = so;
+        if (d_tau) d_tau[b] = h->h_red[b];
+        finite = finite && isfinite(si) && isfinite(so) && isfinite(h->h_red[b]);
+        prof += nf;
+    }
+    if (!finite) return fail(LBM_EUNSTABLE, "non-finite gradient");
+    return LBM_OK;
+}
+
+int lbm_run_to_residual(lbm_handle *h, const lbm_params *prm, double tol, int max_steps, int check_every,
+                        int *steps_out, double *r_out) {
+    if (!h) return fail(LBM_EINVAL, "handle is NULL");
+    if (check_every < 3) return fail(LBM_EINVAL, "check_every must be >= 3");
+    if (max_steps < check_every) return fail(LBM_EINVAL, "max_steps must be >= check_every");
+    const Layout &L = h->L;
+    int rc = upload_params(h, prm);
+    if (rc) return rc;
+    h->fwd_taped = h->adjoint_done = false;
+    const float *src = h->init();
+    int t = 0, which = 0;
+    double rmax = INFINITY;
+    float *u2 = h->at<float>(L.off_u2);
+    while (t + check_every <= max_steps) {
+        for (int k = 0; k < check_every; ++k) {
+            if (k == check_every - 2)
+                HIP_TRY(lbm::launch_macro(L.q, h->G, src, nullptr, nullptr, u2, h->stream));
+            float *dst = h->pp(which);
+            which ^= 1;
+            if ((rc = step(h, src, dst))) return rc;
+            h->prev = (float *)src;
+            src = dst;
+        }
+        t += check_every;
+        h->cur = (float *)src;
+        HIP_TRY(lbm::launch_residual(L.q, h->G, h->cur, h->prev, u2, h->at<double>(L.off_part_res), h->stream));
+        if ((rc = reduce_to_host(h, L.off_part_res, 2))) return rc;
+        rmax = 0.0;
+        for (int b = 0; b < L.n_inst; ++b) {
+            const double num = h->h_red[2 * b], den = h->h_red[2 * b + 1];
+            const double r = den > 0 ? sqrt(num / den) : (num > 0 ? INFINITY : 0.0);
+            if (!isfinite(num) || !isfinite(den)) {
+                h->cur_steps = t;
+                if (steps_out) *steps_out = t;
+                if (r_out) *r_out = NAN;
+                return fail(LBM_EUNSTABLE, "non-finite residual at step %d (instance %d)", t, b);
+            }
+            rmax = std::max(rmax, r);
+        }
+        if (rmax <= tol) break;
+    }
+    h->cur_steps = t;
+    if (steps_out) *steps_out = t;
+    if (r_out) *r_out = rmax;
+    return LBM_OK;
+}
+
+int lbm_get_macro(lbm_handle *h, float *d_drho, float *d_u, int mean2) {
+    if (!h) return fail(LBM_EINVAL, "handle is NULL");
+    if (mean2 && (!h->prev || h->cur_steps < 2)) return fail(LBM_ESTATE, "mean of two states needs two steps");
+    HIP_TRY(lbm::launch_macro(h->L.q, h->G, h->cur, mean2 ? h->prev : nullptr, d_drho, d_u, h->stream));
+    return LBM_OK;
+}
+
+int lbm_set_timing(lbm_handle *h, int enable, int reset) {
+    if (!h) return fail(LBM_EINVAL, "handle is NULL");
+    h->timing = enable != 0;
+    if (reset) h->tm = lbm_timing{};
+    return LBM_OK;
+}
+
+int lbm_get_timing(lbm_handle *h, lbm_timing *out) {
+    if (!h || !out) return fail(LBM_EINVAL, "handle and output must be non-NULL");
+    *out = h->tm;
+    return LBM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,30 @@
+// Launch wrappers of the lattice Boltzmann kernels (host side).
+#pragma once
+
+#include "lbm_device.hpp"
+
+namespace lbm {
+
+hipError_t launch_step(int q, const Geo &G, const float *src, float *dst, const float *fin,
+                       const float *fout, hipStream_t s);
+hipError_t launch_loss(int q, const Geo &G, const float *F, const float *roi, const float *target,
+                       int kind, double *part, hipStream_t s);
+hipError_t launch_adj_seed(int q, const Geo &G, const float *Fprev, float *nu_out, const float *fin,
+                           const float *fout, double *gin, double *gout, const float *roi,
+                           const float *target, int kind, const float *seed, hipStream_t s);
+hipError_t launch_adj_step(int q, const Geo &G, const float *Fprev, const float *nu_in, float *nu_out,
+                           const float *fin, const float *fout, double *gin, double *gout,
+                           double *dtau_part, hipStream_t s);
+hipError_t launch_adj_final(int q, const Geo &G, const float *nu_in, float *dense, hipStream_t s);
+hipError_t launch_init_eq(int q, const Geo &G, float *F, const float *drho, const float *u,
+                          hipStream_t s);
+hipError_t launch_convert(int q, const Geo &G, float *F, float *dense, int to_state, hipStream_t s);
+hipError_t launch_macro(int q, const Geo &G, const float *Fa, const float *Fb, float *drho, float *u,
+                        hipStream_t s);
+hipError_t launch_residual(int q, const Geo &G, const float *Ft, const float *Ft1, const float *u2,
+                           double *part, hipStream_t s);
+hipError_t launch_reduce(const InstDev *inst, int n_inst, const double *part, int stride, double *out,
+                         hipStream_t s);
+hipError_t launch_fill_f64(double *p, long long n, double v, hipStream_t s);
+
+}  // namespace lbm

@@ -1,0 +1,117 @@
+"""The C-ABI library loads, exports every symbol include/lbm.h declares, and
+its host-side planning and validation behave (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2310_00810_amd import _lib as C
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared(header):
+    text = open(os.path.join(ROOT, "include", header)).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b((?:lbm|lbmnn)_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(C.LIBPATH):
+        from paper_2310_00810_amd import build
+        build.build()
+    return C.lib()
+
+
+def test_every_declared_symbol_is_exported(L):
+    names = declared("lbm.h")
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(C.EXPORTS) == sorted(n for n in names if n.startswith("lbm_"))
+
+
+def _problem(nx=64, ny=32, nz=1, q=9, steps=100, K=0, tape=0, solid=None, n=1, **kw):
+    arr = (C.lbm_instance * n)()
+    keep = []
+    for k in range(n):
+        arr[k].nx, arr[k].ny, arr[k].nz = nx, ny, nz
+        if solid is not None:
+            s = np.ascontiguousarray(solid, np.uint8)
+            keep.append(s)
+            arr[k].solid = s.ctypes.data_as(ctypes.c_void_p)
+    p = C.lbm_problem(q, n, arr, kw.get("bcx", 0), kw.get("bcy", 2), kw.get("bcz", 1), steps, K, tape,
+                      kw.get("loss_kind", 0), kw.get("loss_scale", 0), kw.get("inlet_mode", 0))
+    p._keep = (arr, keep)
+    return p
+
+
+def _bytes(L, p):
+    b = ctypes.c_size_t(0)
+    rc = L.lbm_workspace_bytes(ctypes.byref(p), ctypes.byref(b))
+    return rc, b.value
+
+
+def test_workspace_size_matches_the_plan(L):
+    rc, b0 = _bytes(L, _problem(steps=2000))
+    assert rc == 0
+    state = 9 * 32 * 64 * 4
+    assert 3 * state <= b0 < 3 * state + 200_000
+    # tape: (n_seg - 1) checkpoints + (K - 1) segment states + 2 adjoint buffers
+    rc, b1 = _bytes(L, _problem(steps=2000, K=45, tape=1))
+    n_seg = -(-2000 // 45)
+    assert b1 - b0 == (n_seg - 1 + 45 - 1 + 2) * state
+    # 128^3 D3Q19 with K = 400 over 8000 steps: 423 states of 159.4 MB
+    rc, b3 = _bytes(L, _problem(128, 128, 128, q=19, steps=8000, K=400, tape=1, bcy=1))
+    assert rc == 0 and abs(b3 / (423 * 19 * 128 ** 3 * 4) - 1) < 1e-3
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(q=7), C.LBM_EINVAL),
+    (dict(nz=2), C.LBM_EINVAL),                 # D2Q9 with nz != 1
+    (dict(nx=1), C.LBM_EINVAL),                 # pressure axis needs nx >= 2
+    (dict(steps=0), C.LBM_EINVAL),
+    (dict(K=-1), C.LBM_EINVAL),
+    (dict(bcy=0), C.LBM_EINVAL),                # pressure only on x
+    (dict(loss_kind=5), C.LBM_EINVAL),
+    (dict(nx=0), C.LBM_EINVAL),
+])
+def test_invalid_problems_are_rejected(L, kw, code):
+    rc, _ = _bytes(L, _problem(**kw))
+    assert rc == code
+    assert len(L.lbm_last_error()) > 0
+
+
+def test_solid_inlet_rejected_in_profile_mode(L):
+    s = np.zeros((1, 8, 16), np.uint8)
+    s[0, 3, 0] = 1
+    rc, _ = _bytes(L, _problem(16, 8, solid=s, inlet_mode=1))
+    assert rc == C.LBM_EINVAL
+    rc, _ = _bytes(L, _problem(16, 8, solid=s, inlet_mode=0))
+    assert rc == C.LBM_OK
+
+
+def test_init_rejects_small_or_misaligned_workspace(L):
+    p = _problem(steps=10)
+    rc, b = _bytes(L, p)
+    h = ctypes.c_void_p()
+    # validation happens before any device call: fake, never dereferenced pointers
+    assert L.lbm_init(ctypes.byref(h), ctypes.byref(p), ctypes.c_void_p(1 << 20), b - 1, None) == C.LBM_ENOMEM
+    assert L.lbm_init(ctypes.byref(h), ctypes.byref(p), ctypes.c_void_p((1 << 20) + 8), b, None) == C.LBM_EINVAL
+    assert L.lbm_init(ctypes.byref(h), ctypes.byref(p), None, b, None) == C.LBM_EINVAL
+
+
+def test_error_strings(L):
+    for code in (0, -1, -2, -3, -4, -5, -6):
+        assert len(L.lbm_strerror(code)) > 0
+    assert L.lbm_strerror(-99) == b"unknown error"
+
+
+def test_calls_without_handle_fail_cleanly(L):
+    assert L.lbm_forward(None, None, 0, None) == C.LBM_EINVAL
+    assert L.lbm_adjoint(None, None) == C.LBM_EINVAL
+    assert L.lbm_grad(None, None, None, None) == C.LBM_EINVAL
+    assert L.lbm_destroy(None) == C.LBM_OK

@@ -1,0 +1,328 @@
+"""GPU parity of the HIP lattice Boltzmann path against the FP64 oracle.
+
+Every case runs the kernels through the C ABI (liblbm.so) and compares with
+the oracle on the same seeded inputs.  Bars: velocity relative L2 <= 1e-4,
+gradients relative L2 <= 1e-3 (FP32 shifted populations against FP64).
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2310_00810_amd import geometry as G
+from tests.conftest import tiny_lattices
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _lbm():
+    from paper_2310_00810_amd import lbm
+    return lbm
+
+
+BC_NAMES = {O.BC_PRESSURE: "pressure", O.BC_PERIODIC: "periodic", O.BC_WALL: "wall"}
+
+
+def solver_for(lat, steps, tape=False, K=0, roi=None, target=None, loss_kind="vec",
+               loss_scale="sum", inlet_mode="const"):
+    lbm = _lbm()
+    D = 2 if lat.q == 9 else 3
+    tgt = None if target is None else np.asarray(target)[..., :D].astype(np.float32)
+    ins = lbm.Instance(lat.nx, lat.ny, lat.nz, solid=lat.solid.copy(),
+                       roi=None if roi is None else roi.astype(np.float32), target_u=tgt)
+    return lbm.Solver(lat.q, [ins], bc=tuple(BC_NAMES[b] for b in lat.bc_tuple), steps=steps,
+                      ckpt_interval=K, tape=tape, loss_kind=loss_kind, loss_scale=loss_scale,
+                      inlet_mode=inlet_mode)
+
+
+def rel_l2(a, b):
+    a, b = np.asarray(a, np.float64), np.asarray(b, np.float64)
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def dense_shifted(lat, f):
+    """oracle AoS (nz, ny, nx, q) -> GPU dense shifted (q, nz, ny, nx) float32."""
+    _, w, _ = O.velset(lat.q)
+    return np.ascontiguousarray(np.moveaxis(f - w, -1, 0)).astype(np.float32)
+
+
+def from_dense(lat, flat, shifted=True):
+    _, w, _ = O.velset(lat.q)
+    a = flat.detach().cpu().numpy().astype(np.float64).reshape((lat.q,) + lat.shape)
+    a = np.moveaxis(a, 0, -1)
+    return a + w if shifted else a
+
+
+def gpu_u(lat, solver, mean2=False):
+    D = 2 if lat.q == 9 else 3
+    _, u = solver.macro(mean2=mean2)
+    return u.cpu().numpy().astype(np.float64).reshape(lat.shape + (D,))
+
+
+def f32(x):
+    return np.float64(np.float32(x))
+
+
+# ---------------------------------------------------------------- forward --
+@pytest.mark.parametrize("name,lat", tiny_lattices())
+@pytest.mark.parametrize("T", [1, 3])
+def test_steps_from_random_state(name, lat, T):
+    """T steps from a random non-equilibrium state, all boundary kinds."""
+    _, w, _ = O.velset(lat.q)
+    fl = lat.fluid()[..., None]
+    F0 = (w + G.random_perturbation(lat.shape, lat.q, 0.01, seed=21)) * fl
+    fb = dense_shifted(lat, F0)
+    F0 = (np.moveaxis(fb.astype(np.float64), 0, -1) + w) * fl      # the same FP32 values
+    rin = 1 + f32(0.004) + np.zeros((lat.nz, lat.ny))
+    rout = 1 + f32(-0.002) + np.zeros((lat.nz, lat.ny))
+    tau = 0.7
+    s = solver_for(lat, T)
+    s.set_populations(torch.from_numpy(fb.ravel()).cuda())
+    s.forward(tau, f32(0.004), f32(-0.002), want_loss=False)
+    got = from_dense(lat, s.get_populations("state"))
+    # GPU state convention: F^t = C(Z(S(F^{t-1})))
+    x = F0
+    for _ in range(T):
+        x = O.collide(lat, tau, O.zouhe(lat, rin, rout, O.stream(lat, x)))
+    m = lat.fluid()
+    assert rel_l2((got - w)[m], (x - w)[m]) < 1e-5
+    assert np.all(np.isfinite(got))
+
+
+def test_rest_state_stays_exactly_at_rest():
+    solid = G.rsa_disks(96, 48, (4.0, 7.0), 0.75, seed=31)[None]
+    lat = O.Lattice(9, 96, 48, 1, (O.BC_PRESSURE, O.BC_WALL, O.BC_PERIODIC), solid)
+    s = solver_for(lat, 500)
+    s.forward(0.8, 0.0, 0.0, want_loss=False)
+    drho, u = s.macro()
+    assert torch.count_nonzero(u).item() == 0 and torch.count_nonzero(drho).item() == 0
+
+
+@pytest.mark.parametrize("q", [9, 19])
+def test_closed_box_mass_conservation(q):
+    if q == 9:
+        solid = G.rsa_disks(80, 40, (3.0, 6.0), 0.8, seed=32, x_margin=0)[None]
+        lat = O.Lattice(9, 80, 40, 1, (O.BC_WALL, O.BC_WALL, O.BC_PERIODIC), solid)
+    else:
+        solid = G.boolean_spheres((24, 20, 16), (2.0, 3.5), 0.8, seed=33, x_margin=0)
+        lat = O.Lattice(19, 24, 20, 16, (O.BC_PERIODIC, O.BC_WALL, O.BC_PERIODIC), solid)
+    _, w, _ = O.velset(q)
+    fl = lat.fluid()[..., None]
+    F0 = (w + G.random_perturbation(lat.shape, q, 0.01, seed=34)) * fl
+    fb = dense_shifted(lat, F0)
+    s = solver_for(lat, 1000)
+    s.set_populations(torch.from_numpy(fb.ravel()).cuda())
+    m0 = float(np.sum(fb.astype(np.float64)[:, lat.fluid()]))
+    s.forward(0.75, 0.0, 0.0, want_loss=False)
+    got = s.get_populations("state").double().sum().item()
+    n_fluid = lat.fluid().sum()
+    # deviation mass drift stays at FP32 rounding of the shifted populations
+    assert abs(got - m0) < 1e-6 * n_fluid * 0.01 * q
+
+
+def _c1(rin=1.005):
+    lat = O.Lattice(9, 64, 32, 1, (O.BC_PRESSURE, O.BC_WALL, O.BC_PERIODIC))
+    return lat
+
+
+def test_c1_forward_parity_2000_steps():
+    """2D channel 64 x 32, Zou-He rho_in = 1.005, rho_out = 1, tau = 0.8,
+    2000 steps from rest: u(T) against the oracle."""
+    lat = _c1()
+    T = 2000
+    s = solver_for(lat, T)
+    s.forward(0.8, f32(0.005), 0.0, want_loss=False)
+    ug = gpu_u(lat, s)
+    fo = O.run(lat, 0.8, 1 + f32(0.005), 1.0, O.init_eq(lat, 1.0, 0.0), T)
+    _, uo = O.macro(lat, fo)
+    assert rel_l2(ug, uo[..., :2]) <= 1e-4
+
+
+@pytest.mark.parametrize("kind", ["vec", "norm"])
+def test_c1_gradient_parity(kind):
+    """C1 loss against the target field of rho_in = 1.003; dL/drho_in,
+    dL/dtau, dL/drho_out from the adjoint against the oracle's."""
+    lat = _c1()
+    T = 2000
+    f0 = O.init_eq(lat, 1.0, 0.0)
+    _, ut = O.macro(lat, O.run(lat, 0.8, 1 + f32(0.003), 1.0, f0, T))
+    ut32 = ut.astype(np.float32).astype(np.float64)
+    s = solver_for(lat, T, tape=True, K=45, target=ut32, loss_kind=kind)
+    loss = s.forward(0.8, f32(0.005), 0.0, record_tape=True)
+    s.adjoint()
+    g = s.grad()
+    ko = O.LOSS_VEC if kind == "vec" else O.LOSS_NORM
+    go = O.grad(lat, 0.8, 1 + f32(0.005), 1.0, f0, T, ut32, kind=ko, K=45)
+    assert abs(loss[0] - go["loss"]) <= 1e-4 * go["loss"]
+    assert rel_l2(g["drho_in"], [go["drho_in"].sum()]) <= 1e-3
+    assert rel_l2(g["drho_out"], [go["drho_out"].sum()]) <= 1e-3
+    assert rel_l2(g["dtau"], [go["dtau"]]) <= 1e-3
+
+
+@pytest.mark.parametrize("name,lat", tiny_lattices())
+def test_tiny_profile_gradients(name, lat):
+    """Per-node inlet profile gradients, dL/dtau and dL/drho_out on the tiny
+    lattices (walls, periodic axes, grains touching the faces), T = 40."""
+    T, tau = 40, 0.8
+    rng = np.random.default_rng(0)
+    din = (0.01 + 0.002 * rng.standard_normal((lat.nz, lat.ny))).astype(np.float32)
+    solid_in = lat.solid[:, :, 0].astype(bool)
+    tgt = (0.004 * rng.standard_normal(lat.shape + (3,))).astype(np.float32).astype(np.float64)
+    if lat.q == 9:
+        tgt[..., 2] = 0
+    wgt = rng.uniform(0.5, 1.5, lat.shape).astype(np.float32).astype(np.float64)
+    mode = "const" if solid_in.any() else "profile"
+    s = solver_for(lat, T, tape=True, K=7, roi=wgt, target=tgt, inlet_mode=mode)
+    dparam = din.ravel() if mode == "profile" else f32(0.01)
+    s.forward(tau, dparam, f32(-0.001), record_tape=True)
+    s.adjoint()
+    g = s.grad()
+    rin = 1 + (din.astype(np.float64) if mode == "profile" else f32(0.01))
+    go = O.grad(lat, tau, rin, 1 + f32(-0.001), O.init_eq(lat, 1.0, 0.0), T, tgt, wgt, K=7)
+    if mode == "profile":
+        assert rel_l2(g["drho_in"], go["drho_in"].ravel()) <= 1e-3
+    else:
+        assert rel_l2(g["drho_in"], [go["drho_in"].sum()]) <= 1e-3
+    assert rel_l2(g["dtau"], [go["dtau"]]) <= 1e-3
+    assert rel_l2(g["drho_out"], [go["drho_out"].sum()]) <= 1e-3
+
+
+@pytest.mark.parametrize("name,lat", tiny_lattices())
+@pytest.mark.parametrize("T", [1, 2, 3])
+def test_adjoint_of_initial_state(name, lat, T):
+    """dL/dF^0 from the GPU reverse sweep against the oracle's stage
+    transposes composed in the GPU's state convention."""
+    _, w, _ = O.velset(lat.q)
+    fl = lat.fluid()[..., None]
+    F0 = (w + G.random_perturbation(lat.shape, lat.q, 0.01, seed=41)) * fl
+    fb = dense_shifted(lat, F0)
+    F0 = (np.moveaxis(fb.astype(np.float64), 0, -1) + w) * fl
+    rng = np.random.default_rng(42)
+    tgt = (0.01 * rng.standard_normal(lat.shape + (3,))).astype(np.float32).astype(np.float64)
+    if lat.q == 9:
+        tgt[..., 2] = 0
+    tau, rin, rout = 0.8, 1 + f32(0.003), 1 + f32(-0.001)
+    s = solver_for(lat, T, tape=True, K=2, target=tgt)
+    s.set_populations(torch.from_numpy(fb.ravel()).cuda())
+    s.forward(tau, f32(0.003), f32(-0.001), record_tape=True)
+    s.adjoint()
+    got = from_dense(lat, s.get_populations("adjoint"), shifted=False)
+    # oracle: g^1 = Z S F^0, then T-1 full steps, loss on g^T
+    gs = [O.zouhe(lat, rin, rout, O.stream(lat, F0))]
+    for _ in range(T - 1):
+        gs.append(O.zouhe(lat, rin, rout, O.stream(lat, O.collide(lat, tau, gs[-1]))))
+    a = O.loss_seed(lat, gs[-1], tgt)
+    for t in range(T, 0, -1):
+        a, _, _ = O.zouhe_adj(lat, a)
+        a = O.stream_adj(lat, a)
+        if t > 1:
+            a, _ = O.collide_adj(lat, tau, gs[t - 2], a)
+    m = lat.fluid()
+    assert rel_l2(got[m], a[m]) <= 1e-4
+
+
+def test_checkpoint_interval_invariance_bitwise():
+    lat = _c1()
+    rng = np.random.default_rng(5)
+    tgt = (0.001 * rng.standard_normal(lat.shape + (3,))).astype(np.float32)
+    res = []
+    for K in (1, 13, 100, 300):
+        s = solver_for(lat, 300, tape=True, K=K, target=tgt)
+        s.forward(0.9, 0.004, 0.0, record_tape=True)
+        s.adjoint()
+        res.append(s.grad())
+    for r in res[1:]:
+        for k in ("drho_in", "dtau", "drho_out"):
+            assert np.array_equal(r[k], res[0][k])
+
+
+def test_repeat_runs_are_bitwise_identical():
+    lat = _c1()
+    out = []
+    for _ in range(2):
+        s = solver_for(lat, 500, tape=True, K=50, target=np.zeros(lat.shape + (3,)))
+        s.forward(0.8, 0.005, 0.0, record_tape=True)
+        s.adjoint()
+        out.append((s.get_populations("state").cpu().numpy(), s.grad()))
+    assert np.array_equal(out[0][0], out[1][0])
+    assert out[0][1]["dtau"][0] == out[1][1]["dtau"][0]
+
+
+def test_d3q19_sphere_box_parity():
+    """D3Q19 box of spheres, periodic y and z, per-node inlet profile:
+    forward velocity and all gradients against the oracle."""
+    n = (24, 16, 12)
+    solid = G.boolean_spheres(n, (2.5, 4.0), 0.6, seed=3, x_margin=3)
+    lat = O.Lattice(19, n[0], n[1], n[2], (O.BC_PRESSURE, O.BC_PERIODIC, O.BC_PERIODIC), solid)
+    T, tau = 300, 0.75
+    phi = G.fourier_profile(n[1], n[2], seed=33)
+    din = (0.004 * phi).astype(np.float32)
+    rng = np.random.default_rng(7)
+    tgt = (1e-4 * rng.standard_normal(lat.shape + (3,))).astype(np.float32).astype(np.float64)
+    s = solver_for(lat, T, tape=True, K=17, target=tgt, inlet_mode="profile", loss_scale="mean")
+    loss = s.forward(tau, din.ravel(), 0.0, record_tape=True)
+    ug = gpu_u(lat, s)
+    s.adjoint()
+    g = s.grad()
+    f0 = O.init_eq(lat, 1.0, 0.0)
+    rin = 1 + din.astype(np.float64)
+    fo = O.run(lat, tau, rin, 1.0, f0, T)
+    _, uo = O.macro(lat, fo)
+    assert rel_l2(ug, uo) <= 1e-4
+    nfl = lat.fluid().sum()
+    go = O.grad(lat, tau, rin, 1.0, f0, T, tgt, scale=1.0 / nfl, K=17)
+    assert abs(loss[0] - go["loss"]) <= 1e-4 * go["loss"]
+    assert rel_l2(g["drho_in"], go["drho_in"].ravel()) <= 1e-3
+    assert rel_l2(g["dtau"], [go["dtau"]]) <= 1e-3
+    assert rel_l2(g["drho_out"], [go["drho_out"].sum()]) <= 1e-3
+
+
+def test_batched_instances_match_single_runs():
+    """Several lattices of different sizes in one problem give, bit for bit,
+    what each gives alone."""
+    lbm = _lbm()
+    shapes = [(64, 32), (128, 64), (96, 40)]
+    insts, singles = [], []
+    taus, dins = [0.7, 0.9, 1.1], [0.002, 0.004, 0.006]
+    for k, (nx, ny) in enumerate(shapes):
+        solid = G.rsa_disks(nx, ny, (3.0, 6.0), 0.8, seed=100 + k)[None]
+        tgt = np.zeros((1, ny, nx, 2), np.float32)
+        insts.append(lbm.Instance(nx, ny, 1, solid=solid, target_u=tgt))
+    bs = lbm.Solver(9, insts, steps=200, tape=True, ckpt_interval=20)
+    lb = bs.forward(taus, dins, 0.0, record_tape=True)
+    bs.adjoint()
+    gb = bs.grad()
+    ub = bs.split(bs.macro()[1].cpu().numpy())
+    for k, ins in enumerate(insts):
+        s = lbm.Solver(9, [ins], steps=200, tape=True, ckpt_interval=20)
+        l1 = s.forward(taus[k], dins[k], 0.0, record_tape=True)
+        s.adjoint()
+        g1 = s.grad()
+        assert l1[0] == lb[k]
+        assert g1["dtau"][0] == gb["dtau"][k] and g1["drho_in"][0] == gb["drho_in"][k]
+        assert np.array_equal(s.macro()[1].cpu().numpy(), ub[k])
+
+
+def test_error_paths():
+    from paper_2310_00810_amd import _lib as C
+    lat = _c1()
+    s = solver_for(lat, 50, tape=True)
+    with pytest.raises(C.LBMError) as e:
+        s.forward(0.5, 0.001, 0.0)
+    assert e.value.code == C.LBM_EINVAL
+    with pytest.raises(C.LBMError) as e:
+        s.adjoint()
+    assert e.value.code == C.LBM_ESTATE
+    s.forward(0.8, 0.001, 0.0, record_tape=False)
+    with pytest.raises(C.LBMError) as e:
+        s.adjoint()
+    assert e.value.code == C.LBM_ESTATE
+    with pytest.raises(C.LBMError) as e:
+        s.grad()
+    assert e.value.code == C.LBM_ESTATE
+    # strongly compressible drive at tau near 1/2 blows up -> non-finite loss
+    s2 = solver_for(lat, 3000, target=np.zeros(lat.shape + (3,)))
+    with pytest.raises(C.LBMError) as e:
+        s2.forward(0.5001, 0.9, -0.5)
+    assert e.value.code == C.LBM_EUNSTABLE

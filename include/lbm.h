@@ -161,8 +161,11 @@ int lbm_grad(lbm_handle *h, double *d_rho_in, double *d_tau, double *d_rho_out);
 
 /* Steps from the initial state until the two-step-mean velocity residual
  * r = ||u(t) - u(t-2)|| / ||u(t) + u(t-1)|| (every instance) is <= tol, testing
- * every check_every steps, or until max_steps.  steps_out / r_out (host,
- * nullable) receive the step count and the largest instance residual. */
+ * every check_every steps (even, >= 4), or until max_steps.  steps_out /
+ * r_out (host, nullable) receive the step count and the largest instance
+ * residual.  The two-step mean cancels the undamped period-2 mode of the
+ * scheme (an equilibrium momentum field alternating in sign along x that
+ * streaming maps onto its negative). */
 int lbm_run_to_residual(lbm_handle *h, const lbm_params *prm, double tol, int max_steps,
                         int check_every, int *steps_out, double *r_out);
 
@@ -172,7 +175,13 @@ int lbm_run_to_residual(lbm_handle *h, const lbm_params *prm, double tol, int ma
  * state produced by at least two steps). */
 int lbm_get_macro(lbm_handle *h, float *d_drho, float *d_u, int mean2);
 
-/* Enables (nonzero) or disables per-phase event timing; reset clears it. */
+/* Enables (default) or disables hipGraph replay of the step loops: each loop
+ * (taped or plain forward, reverse sweep, residual chunk) is captured once on
+ * a private stream and then launched as one graph on the handle's stream. */
+int lbm_set_graphs(lbm_handle *h, int enable);
+
+/* Enables (nonzero) or disables per-phase event timing; reset clears it.
+ * Timed calls launch kernels one by one (no graphs) between HIP events. */
 int lbm_set_timing(lbm_handle *h, int enable, int reset);
 int lbm_get_timing(lbm_handle *h, lbm_timing *out);
 

@@ -21,7 +21,7 @@ POP_STATE, POP_ADJOINT = 0, 1
 EXPORTS = [
     "lbm_workspace_bytes", "lbm_init", "lbm_destroy", "lbm_set_initial", "lbm_set_populations",
     "lbm_get_populations", "lbm_forward", "lbm_adjoint", "lbm_grad", "lbm_run_to_residual",
-    "lbm_get_macro", "lbm_set_timing", "lbm_get_timing", "lbm_strerror", "lbm_last_error",
+    "lbm_get_macro", "lbm_set_graphs", "lbm_set_timing", "lbm_get_timing", "lbm_strerror", "lbm_last_error",
 ]
 
 
@@ -79,6 +79,7 @@ def lib():
         L.lbm_run_to_residual.argtypes = [vp, ctypes.POINTER(lbm_params), ctypes.c_double, ip, ip,
                                           ctypes.POINTER(ctypes.c_int), dp]
         L.lbm_get_macro.argtypes = [vp, vp, vp, ip]
+        L.lbm_set_graphs.argtypes = [vp, ip]
         L.lbm_set_timing.argtypes = [vp, ip, ip]
         L.lbm_get_timing.argtypes = [vp, ctypes.POINTER(lbm_timing)]
         L.lbm_strerror.restype = ctypes.c_char_p

@@ -48,7 +48,7 @@ struct Layout {
     int n_states = 0;
     size_t off_inst = 0, off_mask = 0, off_roi = 0, off_target = 0, off_face_in = 0, off_face_out = 0,
            off_grad_in = 0, off_grad_out = 0, off_part_loss = 0, off_part_dtau = 0, off_part_res = 0,
-           off_red = 0, off_u2 = 0, off_states = 0, state_bytes = 0, total = 0;
+           off_red = 0, off_u2 = 0, off_seed = 0, off_states = 0, state_bytes = 0, total = 0;
     std::vector<InstDev> inst;
 };
 
@@ -147,6 +147,7 @@ void plan(const lbm_problem *p, Layout &L) {
     L.off_part_res = take(sizeof(double) * 2 * L.n_tiles);
     L.off_red = take(sizeof(double) * 2 * p->n_inst);
     L.off_u2 = take(sizeof(float) * node * L.D);
+    L.off_seed = take(sizeof(float) * node * L.D);
     L.state_bytes = align_up(sizeof(float) * (size_t)L.S, 256);
     L.off_states = o;
     L.total = L.off_states + L.state_bytes * (size_t)L.n_states;
@@ -173,6 +174,13 @@ struct lbm_handle {
     bool timing = false;
     lbm_timing tm{};
     std::vector<hipEvent_t> ev;
+    // graphs: captured on a private stream, launched on the caller's stream
+    bool graphs = true;
+    hipStream_t cap = nullptr;
+    hipGraphExec_t g_fwd[2] = {nullptr, nullptr};            // [record_tape]
+    hipGraphExec_t g_rev[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [recompute_last][seed]
+    hipGraphExec_t g_chunk[2] = {nullptr, nullptr};          // [starts from the initial state]
+    int chunk_len = 0;
 
     float *state(int k) const { return (float *)(ws + L.off_states + L.state_bytes * (size_t)k); }
     float *init() const { return state(0); }
@@ -237,9 +245,39 @@ double elapsed(lbm_handle *h, int a, int b) {
     return ms;
 }
 
-int step(lbm_handle *h, const float *src, float *dst) {
+int step(lbm_handle *h, const float *src, float *dst, hipStream_t s) {
     HIP_TRY(lbm::launch_step(h->L.q, h->G, src, dst, h->at<float>(h->L.off_face_in),
-                             h->at<float>(h->L.off_face_out), h->stream));
+                             h->at<float>(h->L.off_face_out), s));
+    return LBM_OK;
+}
+
+// Runs `enqueue(stream)` either directly on the caller's stream or, with
+// graphs enabled, as a hipGraph captured once (on a private stream) and
+// replayed on the caller's stream.  Every pointer the enqueued work uses is
+// fixed for the life of the handle and parameters live in device memory, so
+// a captured graph stays valid.
+template <class F>
+int with_graph(lbm_handle *h, hipGraphExec_t &slot, F &&enqueue) {
+    if (!h->graphs) return enqueue(h->stream);
+    if (!slot) {
+        if (!h->cap) HIP_TRY(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
+        HIP_TRY(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
+        int rc = enqueue(h->cap);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(h->cap, &g);
+        if (rc) {
+            if (e == hipSuccess && g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        if (e != hipSuccess) return fail(LBM_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
+        e = hipGraphInstantiate(&slot, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            slot = nullptr;
+            return fail(LBM_EDEVICE, "graph instantiation failed: %s", hipGetErrorString(e));
+        }
+    }
+    HIP_TRY(hipGraphLaunch(slot, h->stream));
     return LBM_OK;
 }
 
@@ -363,6 +401,10 @@ int lbm_init(lbm_handle **out, const lbm_problem *p, void *d_workspace, size_t b
 int lbm_destroy(lbm_handle *h) {
     if (!h) return LBM_OK;
     for (auto e : h->ev) (void)hipEventDestroy(e);
+    for (auto g : h->g_fwd) if (g) (void)hipGraphExecDestroy(g);
+    for (auto &r : h->g_rev) for (auto g : r) if (g) (void)hipGraphExecDestroy(g);
+    for (auto g : h->g_chunk) if (g) (void)hipGraphExecDestroy(g);
+    if (h->cap) (void)hipStreamDestroy(h->cap);
     delete h;
     return LBM_OK;
 }
@@ -402,30 +444,45 @@ int lbm_get_populations(lbm_handle *h, int which, float *d_out) {
     return fail(LBM_EINVAL, "unknown population kind %d", which);
 }
 
+// Destination of step t of the forward pass.  With a tape, F^{cK} goes to
+// checkpoint c and the states of the last segment go straight to the
+// segment store, so the reverse sweep does not recompute that segment.
+static float *fwd_dst(lbm_handle *h, int t, int record_tape) {
+    const Layout &L = h->L;
+    if (record_tape && t < L.T) {
+        const int c = t / L.K, j = t % L.K;
+        return j == 0 ? h->ckpt(c) : (c == L.n_seg - 1 ? h->seg(j) : h->pp(t & 1));
+    }
+    return h->pp(t & 1);
+}
+
+static int enqueue_forward(lbm_handle *h, int record_tape, hipStream_t s) {
+    const float *src = h->init();
+    for (int t = 1; t <= h->L.T; ++t) {
+        float *dst = fwd_dst(h, t, record_tape);
+        int rc = step(h, src, dst, s);
+        if (rc) return rc;
+        src = dst;
+    }
+    return LBM_OK;
+}
+
 int lbm_forward(lbm_handle *h, const lbm_params *prm, int record_tape, double *loss_out) {
     if (!h) return fail(LBM_EINVAL, "handle is NULL");
     const Layout &L = h->L;
     if (record_tape && !L.tape) return fail(LBM_ESTATE, "the problem was planned without a tape");
     int rc = upload_params(h, prm);
     if (rc) return rc;
+    record_tape = record_tape ? 1 : 0;
     h->fwd_taped = h->adjoint_done = false;
-    const int T = L.T, K = L.K, last = L.n_seg - 1;
+    const int T = L.T;
     if ((rc = record(h, 0))) return rc;
-    const float *src = h->init();
-    float *dst = nullptr;
-    for (int t = 1; t <= T; ++t) {
-        if (record_tape && t < T) {
-            const int c = t / K, j = t % K;
-            dst = j == 0 ? h->ckpt(c) : (c == last ? h->seg(j) : h->pp(t & 1));
-        } else {
-            dst = h->pp(t & 1);
-        }
-        if ((rc = step(h, src, dst))) return rc;
-        h->prev = (float *)src;
-        src = dst;
-    }
+    if (h->timing) rc = enqueue_forward(h, record_tape, h->stream);
+    else rc = with_graph(h, h->g_fwd[record_tape], [&](hipStream_t s) { return enqueue_forward(h, record_tape, s); });
+    if (rc) return rc;
     if ((rc = record(h, 1))) return rc;
-    h->cur = dst;
+    h->cur = fwd_dst(h, T, record_tape);
+    h->prev = T >= 2 ? fwd_dst(h, T - 1, record_tape) : h->init();
     h->cur_steps = T;
     if (record_tape) {
         h->fwd_taped = true;
@@ -451,60 +508,79 @@ int lbm_forward(lbm_handle *h, const lbm_params *prm, int record_tape, double *l
     return LBM_OK;
 }
 
-int lbm_adjoint(lbm_handle *h, const float *d_seed_du) {
-    if (!h) return fail(LBM_EINVAL, "handle is NULL");
-    if (!h->fwd_taped) return fail(LBM_ESTATE, "lbm_adjoint needs a preceding lbm_forward with record_tape");
+// The reverse sweep: zero the accumulators, then per segment (last first)
+// recompute its states from the checkpoint and run the adjoint steps.
+// Event marks (timing mode only) bracket each segment's two phases.
+static int enqueue_reverse(lbm_handle *h, bool recompute_last, const float *seed, hipStream_t s,
+                           std::vector<int> *marks) {
     const Layout &L = h->L;
     const int q = L.q, T = L.T, K = L.K;
-    int rc;
-    HIP_TRY(lbm::launch_fill_f64(h->at<double>(L.off_grad_in), L.total_face, 0.0, h->stream));
-    HIP_TRY(lbm::launch_fill_f64(h->at<double>(L.off_grad_out), L.total_face, 0.0, h->stream));
-    HIP_TRY(lbm::launch_fill_f64(h->at<double>(L.off_part_dtau), L.n_tiles, 0.0, h->stream));
+    HIP_TRY(lbm::launch_fill_f64(h->at<double>(L.off_grad_in), L.total_face, 0.0, s));
+    HIP_TRY(lbm::launch_fill_f64(h->at<double>(L.off_grad_out), L.total_face, 0.0, s));
+    HIP_TRY(lbm::launch_fill_f64(h->at<double>(L.off_part_dtau), L.n_tiles, 0.0, s));
     const float *fin = h->at<float>(L.off_face_in), *fout = h->at<float>(L.off_face_out);
     double *gin = h->at<double>(L.off_grad_in), *gout = h->at<double>(L.off_grad_out);
     double *dpart = h->at<double>(L.off_part_dtau);
-    int ev = 0;
-    std::vector<int> evmark;
+    int ev = 0, rc;
     for (int c = L.n_seg - 1; c >= 0; --c) {
         const int t0 = c * K, t1 = std::min(t0 + K, T);
         auto F = [&](int j) -> const float * { return j == 0 ? h->ckpt(c) : h->seg(j); };
-        if ((rc = record(h, ev))) return rc;
-        evmark.push_back(ev++);
-        if (!(c == L.n_seg - 1 && h->seg_holds_last)) {
+        if (marks) { if ((rc = record(h, ev))) return rc; marks->push_back(ev++); }
+        if (c != L.n_seg - 1 || recompute_last) {
             for (int j = 1; j < t1 - t0; ++j)
-                if ((rc = step(h, F(j - 1), h->seg(j)))) return rc;
-            h->seg_holds_last = false;
-            if (h->timing) h->tm.recompute_launches += t1 - t0 - 1;
+                if ((rc = step(h, F(j - 1), h->seg(j), s))) return rc;
+            if (marks) h->tm.recompute_launches += t1 - t0 - 1;
         }
-        if ((rc = record(h, ev))) return rc;
-        evmark.push_back(ev++);
+        if (marks) { if ((rc = record(h, ev))) return rc; marks->push_back(ev++); }
         for (int k = t1; k > t0; --k) {
             const float *Fprev = F(k - 1 - t0);
             float *nu_out = h->nu(k & 1);
             if (k == T) {
                 HIP_TRY(lbm::launch_adj_seed(q, h->G, Fprev, nu_out, fin, fout, gin, gout,
                                              h->at<float>(L.off_roi), h->at<float>(L.off_target),
-                                             h->P.loss_kind, d_seed_du, h->stream));
+                                             h->P.loss_kind, seed, s));
             } else {
                 HIP_TRY(lbm::launch_adj_step(q, h->G, Fprev, h->nu((k + 1) & 1), nu_out, fin, fout, gin, gout,
-                                             dpart, h->stream));
+                                             dpart, s));
             }
         }
-        if ((rc = record(h, ev))) return rc;
-        evmark.push_back(ev++);
+        if (marks) { if ((rc = record(h, ev))) return rc; marks->push_back(ev++); }
     }
+    return LBM_OK;
+}
+
+int lbm_adjoint(lbm_handle *h, const float *d_seed_du) {
+    if (!h) return fail(LBM_EINVAL, "handle is NULL");
+    if (!h->fwd_taped) return fail(LBM_ESTATE, "lbm_adjoint needs a preceding lbm_forward with record_tape");
+    const Layout &L = h->L;
+    int rc;
+    const float *seed = nullptr;
+    if (d_seed_du) {
+        // a fixed internal copy keeps captured graphs valid for any caller buffer
+        HIP_TRY(hipMemcpyAsync(h->at<float>(L.off_seed), d_seed_du, sizeof(float) * L.total_nodes * L.D,
+                               hipMemcpyDeviceToDevice, h->stream));
+        seed = h->at<float>(L.off_seed);
+    }
+    const bool recompute_last = !h->seg_holds_last;
+    if (h->timing) {
+        std::vector<int> marks;
+        if ((rc = enqueue_reverse(h, recompute_last, seed, h->stream, &marks))) return rc;
+        HIP_TRY(hipEventSynchronize(h->ev[marks.back()]));
+        for (int c = L.n_seg - 1, k = 0; c >= 0; --c, k += 3) {
+            const int t0 = c * L.K, t1 = std::min(t0 + L.K, L.T);
+            h->tm.recompute_ms += elapsed(h, marks[k], marks[k + 1]);
+            h->tm.adjoint_ms += elapsed(h, marks[k + 1], marks[k + 2]);
+            h->tm.adjoint_launches += t1 - t0;
+        }
+    } else {
+        rc = with_graph(h, h->g_rev[recompute_last ? 1 : 0][seed ? 1 : 0],
+                        [&](hipStream_t s) { return enqueue_reverse(h, recompute_last, seed, s, nullptr); });
+        if (rc) return rc;
+    }
+    h->seg_holds_last = L.n_seg == 1;  // earlier segments' recompute reuses the store
     h->nu_last = h->nu(1);
     h->adjoint_done = true;
     h->prev = nullptr;  // the segment store that held F^{T-1} has been reused
-    if (h->timing) {
-        HIP_TRY(hipEventSynchronize(h->ev[ev - 1]));
-        for (int c = L.n_seg - 1, s = 0; c >= 0; --c, s += 3) {
-            const int t0 = c * K, t1 = std::min(t0 + K, T);
-            h->tm.recompute_ms += elapsed(h, evmark[s], evmark[s + 1]);
-            h->tm.adjoint_ms += elapsed(h, evmark[s + 1], evmark[s + 2]);
-            h->tm.adjoint_launches += t1 - t0;
-        }
-    }
     return LBM_OK;
 }
 
@@ -543,43 +619,65 @@ int lbm_grad(lbm_handle *h, double *d_rho_in, double *d_tau, double *d_rho_out) 
     return LBM_OK;
 }
 
+// One residual chunk: check_every steps from src over the ping-pong
+// buffers (pp0, pp1, pp0, ...), a velocity snapshot two steps before the
+// end, and the residual partial sums of the last three states.
+static int enqueue_chunk(lbm_handle *h, const float *src, int check_every, hipStream_t s) {
+    const Layout &L = h->L;
+    float *u2 = h->at<float>(L.off_u2);
+    const float *prev = nullptr;
+    for (int k = 0; k < check_every; ++k) {
+        if (k == check_every - 2) HIP_TRY(lbm::launch_macro(L.q, h->G, src, nullptr, nullptr, u2, s));
+        float *dst = h->pp(k & 1);
+        int rc = step(h, src, dst, s);
+        if (rc) return rc;
+        prev = src;
+        src = dst;
+    }
+    HIP_TRY(lbm::launch_residual(L.q, h->G, src, prev, u2, h->at<double>(L.off_part_res), s));
+    HIP_TRY(lbm::launch_reduce(h->at<InstDev>(L.off_inst), L.n_inst, h->at<double>(L.off_part_res), 2,
+                               h->at<double>(L.off_red), s));
+    return LBM_OK;
+}
+
 int lbm_run_to_residual(lbm_handle *h, const lbm_params *prm, double tol, int max_steps, int check_every,
                         int *steps_out, double *r_out) {
     if (!h) return fail(LBM_EINVAL, "handle is NULL");
-    if (check_every < 3) return fail(LBM_EINVAL, "check_every must be >= 3");
+    if (check_every < 4 || (check_every & 1)) return fail(LBM_EINVAL, "check_every must be even and >= 4");
     if (max_steps < check_every) return fail(LBM_EINVAL, "max_steps must be >= check_every");
     const Layout &L = h->L;
     int rc = upload_params(h, prm);
     if (rc) return rc;
     h->fwd_taped = h->adjoint_done = false;
-    const float *src = h->init();
-    int t = 0, which = 0;
+    if (h->chunk_len != check_every) {
+        for (auto &g : h->g_chunk)
+            if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
+        h->chunk_len = check_every;
+    }
+    int t = 0;
     double rmax = INFINITY;
-    float *u2 = h->at<float>(L.off_u2);
+    h->h_red.assign(2 * (size_t)L.n_inst, 0.0);
     while (t + check_every <= max_steps) {
-        for (int k = 0; k < check_every; ++k) {
-            if (k == check_every - 2)
-                HIP_TRY(lbm::launch_macro(L.q, h->G, src, nullptr, nullptr, u2, h->stream));
-            float *dst = h->pp(which);
-            which ^= 1;
-            if ((rc = step(h, src, dst))) return rc;
-            h->prev = (float *)src;
-            src = dst;
-        }
+        const float *src = t == 0 ? h->init() : h->pp(1);
+        rc = with_graph(h, h->g_chunk[t == 0 ? 1 : 0],
+                        [&](hipStream_t s) { return enqueue_chunk(h, src, check_every, s); });
+        if (rc) return rc;
+        HIP_TRY(hipMemcpyAsync(h->h_red.data(), h->at<double>(L.off_red), sizeof(double) * 2 * L.n_inst,
+                               hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
         t += check_every;
-        h->cur = (float *)src;
-        HIP_TRY(lbm::launch_residual(L.q, h->G, h->cur, h->prev, u2, h->at<double>(L.off_part_res), h->stream));
-        if ((rc = reduce_to_host(h, L.off_part_res, 2))) return rc;
+        h->cur = h->pp(1);
+        h->prev = h->pp(0);
         rmax = 0.0;
         for (int b = 0; b < L.n_inst; ++b) {
             const double num = h->h_red[2 * b], den = h->h_red[2 * b + 1];
-            const double r = den > 0 ? sqrt(num / den) : (num > 0 ? INFINITY : 0.0);
             if (!isfinite(num) || !isfinite(den)) {
                 h->cur_steps = t;
                 if (steps_out) *steps_out = t;
                 if (r_out) *r_out = NAN;
                 return fail(LBM_EUNSTABLE, "non-finite residual at step %d (instance %d)", t, b);
             }
+            const double r = den > 0 ? sqrt(num / den) : (num > 0 ? INFINITY : 0.0);
             rmax = std::max(rmax, r);
         }
         if (rmax <= tol) break;
@@ -587,6 +685,12 @@ int lbm_run_to_residual(lbm_handle *h, const lbm_params *prm, double tol, int ma
     h->cur_steps = t;
     if (steps_out) *steps_out = t;
     if (r_out) *r_out = rmax;
+    return LBM_OK;
+}
+
+int lbm_set_graphs(lbm_handle *h, int enable) {
+    if (!h) return fail(LBM_EINVAL, "handle is NULL");
+    h->graphs = enable != 0;
     return LBM_OK;
 }
 

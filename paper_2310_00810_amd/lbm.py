@@ -183,6 +183,9 @@ class Solver:
                 "lbm_run_to_residual")
         return steps.value, r.value
 
+    def set_graphs(self, enable=True):
+        C.check(C.lib().lbm_set_graphs(self.handle, int(enable)), "lbm_set_graphs")
+
     def set_timing(self, enable=True, reset=True):
         C.check(C.lib().lbm_set_timing(self.handle, int(enable), int(reset)), "lbm_set_timing")
 

@@ -66,7 +66,7 @@ def test_workspace_size_matches_the_plan(L):
     assert b1 - b0 == (n_seg - 1 + 45 - 1 + 2) * state
     # 128^3 D3Q19 with K = 400 over 8000 steps: 423 states of 159.4 MB
     rc, b3 = _bytes(L, _problem(128, 128, 128, q=19, steps=8000, K=400, tape=1, bcy=1))
-    assert rc == 0 and abs(b3 / (423 * 19 * 128 ** 3 * 4) - 1) < 1e-3
+    assert rc == 0 and abs(b3 / (423 * 19 * 128 ** 3 * 4) - 1) < 3e-3
 
 
 @pytest.mark.parametrize("kw,code", [

@@ -326,3 +326,84 @@ def test_error_paths():
     with pytest.raises(C.LBMError) as e:
         s2.forward(0.5001, 0.9, -0.5)
     assert e.value.code == C.LBM_EUNSTABLE
+
+
+# ------------------------------------------------------------ hipGraphs --
+def test_graph_replays_match_direct_launches():
+    """Forward and reverse sweeps replayed from captured graphs give, on
+    every replay, bit for bit what direct launches give (eager work and
+    synchronisations between the replays)."""
+    lat = O.Lattice(9, 80, 40, 1, (O.BC_PRESSURE, O.BC_WALL, O.BC_PERIODIC),
+                    G.rsa_disks(80, 40, (3.0, 6.0), 0.8, seed=51)[None])
+    rng = np.random.default_rng(52)
+    tgt = (1e-3 * rng.standard_normal(lat.shape + (3,))).astype(np.float32)
+    sg = solver_for(lat, 240, tape=True, K=31, target=tgt)
+    sd = solver_for(lat, 240, tape=True, K=31, target=tgt)
+    sd.set_graphs(False)
+    for rep, (tau, din) in enumerate([(0.8, 0.004), (0.9, 0.002), (0.8, 0.004), (1.1, 0.005)]):
+        lg = sg.forward(tau, din, 0.0, record_tape=True)
+        ld = sd.forward(tau, din, 0.0, record_tape=True)
+        x = torch.randn(1000, device="cuda").sum()      # unrelated eager work
+        torch.cuda.synchronize()
+        sg.adjoint()
+        sd.adjoint()
+        gg, gd = sg.grad(), sd.grad()
+        assert lg[0] == ld[0], rep
+        for k in ("drho_in", "dtau", "drho_out"):
+            assert np.array_equal(gg[k], gd[k]), (rep, k)
+        assert torch.equal(sg.get_populations("adjoint"), sd.get_populations("adjoint"))
+        del x
+
+
+def test_run_to_residual_reaches_the_oracle_steady_state():
+    """Two-step-mean residual criterion on the GPU; the converged mean
+    velocity agrees with the oracle's steady state and with the Poiseuille
+    closed form at tau = 1/2 + sqrt(3/16)."""
+    nx, ny = 64, 32
+    tau = 0.5 + np.sqrt(3 / 16)
+    lat = O.Lattice(9, nx, ny, 1, (O.BC_PRESSURE, O.BC_WALL, O.BC_PERIODIC))
+    s = solver_for(lat, 1)
+    steps, r = s.run_to_residual(tau, f32(0.002), 0.0, tol=1e-6, max_steps=100_000, check_every=100)
+    assert r <= 1e-6
+    drho, u = s.macro(mean2=True)
+    ug = u.cpu().numpy().astype(np.float64).reshape(1, ny, nx, 2)
+    rg = 1 + drho.cpu().numpy().astype(np.float64).reshape(1, ny, nx)
+    f = O.run(lat, tau, 1 + f32(0.002), 1.0, O.init_eq(lat, 1.0, 0.0), steps)
+    f1 = O.run(lat, tau, 1 + f32(0.002), 1.0, f, 1)
+    _, u0 = O.macro(lat, O.run(lat, tau, 1 + f32(0.002), 1.0, O.init_eq(lat, 1.0, 0.0), steps - 1))
+    _, u1 = O.macro(lat, f)
+    uo = 0.5 * (u0 + u1)
+    assert rel_l2(ug, uo[..., :2]) <= 1e-4
+    xm = nx // 2
+    Gx = -(rg[0, :, xm + 1].mean() - rg[0, :, xm - 1].mean()) / 2 / 3
+    sy = np.arange(ny) + 0.5
+    ue = Gx / (2 * rg[0, :, xm].mean() * (tau - 0.5) / 3) * sy * (ny - sy)
+    assert rel_l2(ug[0, :, xm, 0], ue) <= 2e-3
+    del f1
+
+
+def test_autograd_wrappers_match_the_builtin_gradient():
+    """LBMLoss backward equals lbm_grad; LBMField with a torch VEC loss seeds
+    the adjoint with dL/du and reproduces the built-in loss gradient."""
+    lbm = _lbm()
+    lat = _c1()
+    rng = np.random.default_rng(9)
+    tgt = (1e-3 * rng.standard_normal(lat.shape + (2,))).astype(np.float32)
+    s = solver_for(lat, 300, tape=True, K=20, target=tgt)
+    din = torch.tensor([0.004], dtype=torch.float64, requires_grad=True)
+    tau = torch.tensor([0.8], dtype=torch.float64, requires_grad=True)
+    dout = torch.tensor([0.0], dtype=torch.float64, requires_grad=True)
+    loss = lbm.LBMLoss.apply(s, din, tau, dout)
+    loss.sum().backward()
+    ref = s.grad()
+    assert din.grad.item() == ref["drho_in"][0] and tau.grad.item() == ref["dtau"][0]
+    din2 = din.detach().clone().requires_grad_(True)
+    tau2 = tau.detach().clone().requires_grad_(True)
+    dout2 = dout.detach().clone().requires_grad_(True)
+    u = lbm.LBMField.apply(s, din2, tau2, dout2)
+    t = torch.from_numpy(tgt.reshape(-1, 2)).cuda()
+    L2 = ((u - t) ** 2).sum()
+    L2.backward()
+    assert abs(L2.item() - loss.item()) <= 1e-5 * loss.item()
+    assert abs(din2.grad.item() - ref["drho_in"][0]) <= 1e-4 * abs(ref["drho_in"][0])
+    assert abs(tau2.grad.item() - ref["dtau"][0]) <= 1e-4 * abs(ref["dtau"][0])

@@ -97,3 +97,52 @@ def check(rc, where):
         L = lib()
         raise LBMError(rc, where, f"{L.lbm_strerror(rc).decode()}: {L.lbm_last_error().decode()}")
     return rc
+
+
+# ------------------------------------------------------------ lbmnn.h ABI --
+NN_EXPORTS = [
+    "lbmnn_conv", "lbmnn_wgrad_workspace_bytes", "lbmnn_conv_wgrad", "lbmnn_weight_transpose",
+    "lbmnn_bias_grad", "lbmnn_relu_bwd", "lbmnn_pool_fwd", "lbmnn_pool_bwd", "lbmnn_mse", "lbmnn_adam",
+    "lbmnn_to_bf16", "lbmnn_features", "lbmnn_normalize", "lbmnn_denormalize",
+]
+NN_RELU, NN_ACCUMULATE, NN_S2D, NN_D2S, NN_S2D_G = 1, 2, 4, 8, 16
+
+
+class lbmnn_conv_desc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("d", ctypes.c_int), ("h", ctypes.c_int), ("w", ctypes.c_int),
+                ("dims", ctypes.c_int), ("ks", ctypes.c_int), ("cin", ctypes.c_int), ("cout", ctypes.c_int),
+                ("flags", ctypes.c_int), ("in_", ctypes.c_void_p), ("in_cstride", ctypes.c_int),
+                ("in_coff", ctypes.c_int), ("out", ctypes.c_void_p), ("out_f32", ctypes.c_void_p),
+                ("out_cstride", ctypes.c_int), ("out_coff", ctypes.c_int)]
+
+
+_nn_ready = False
+
+
+def nnlib():
+    """liblbm.so with the lbmnn_* signatures declared."""
+    global _nn_ready
+    L = lib()
+    if not _nn_ready:
+        vp, ip, ll, fl = ctypes.c_void_p, ctypes.c_int, ctypes.c_longlong, ctypes.c_float
+        dp = ctypes.POINTER(lbmnn_conv_desc)
+        L.lbmnn_conv.argtypes = [dp, vp, vp, vp]
+        L.lbmnn_wgrad_workspace_bytes.argtypes = [ll, ip, ip, ip]
+        L.lbmnn_wgrad_workspace_bytes.restype = ctypes.c_size_t
+        L.lbmnn_conv_wgrad.argtypes = [dp, vp, ip, ip, ip, vp, ip, vp, ctypes.c_size_t, ip, vp]
+        L.lbmnn_weight_transpose.argtypes = [vp, vp, ip, ip, ip, ip, vp]
+        L.lbmnn_bias_grad.argtypes = [vp, ip, ip, ll, ip, vp, ip, vp, ip, vp]
+        L.lbmnn_relu_bwd.argtypes = [vp, vp, ip, ip, ll, ip, vp]
+        L.lbmnn_pool_fwd.argtypes = [vp, ip, ip, vp, ip, ip, ip, ip, ip, ip, ip, ip, vp]
+        L.lbmnn_pool_bwd.argtypes = [vp, ip, ip, vp, ip, ip, vp, ip, ip, ip, ip, ip, ip, ip, ip, ip, vp]
+        L.lbmnn_mse.argtypes = [vp, ip, vp, vp, ip, ll, fl, vp, vp, vp, vp]
+        L.lbmnn_adam.argtypes = [vp, vp, vp, vp, vp, ll, fl, fl, fl, fl, ip, vp]
+        L.lbmnn_to_bf16.argtypes = [vp, vp, ll, vp]
+        L.lbmnn_features.argtypes = [vp, vp, ip, ip, ip, ip, vp, vp]
+        L.lbmnn_normalize.argtypes = [vp, vp, vp, vp, ll, ip, ll, vp, vp, vp]
+        L.lbmnn_denormalize.argtypes = [vp, ip, vp, vp, ll, ip, ll, vp, vp, vp]
+        for n in NN_EXPORTS:
+            if n != "lbmnn_wgrad_workspace_bytes":
+                getattr(L, n).restype = ctypes.c_int
+        _nn_ready = True
+    return L

@@ -11,15 +11,16 @@
 
 #include "lbm.h"
 #include "lbm_kernels.hpp"
+#include "lbm_error.hpp"
 
 using lbm::InstDev;
 
 namespace {
-
 thread_local std::string g_err;
+}
 
-int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
-int fail(int code, const char *fmt, ...) {
+// Records the detail of a failure for lbm_last_error() and returns code.
+int lbm_fail(int code, const char *fmt, ...) {
     char buf[512];
     va_list ap;
     va_start(ap, fmt);
@@ -28,6 +29,10 @@ int fail(int code, const char *fmt, ...) {
     g_err = buf;
     return code;
 }
+
+namespace {
+
+#define fail lbm_fail
 
 #define HIP_TRY(expr)                                                                        \
     do {                                                                                     \

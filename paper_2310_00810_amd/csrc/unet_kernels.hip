@@ -1,0 +1,548 @@
+// BF16 MFMA kernels (gfx950) of the warm-start U-Net: implicit-GEMM
+// convolution (3x3 / 3x3x3 / 1x1, forward and input gradient), weight
+// gradient, 2x2(x2) stride-2 transposed convolution (as GEMM with a
+// depth-to-space / space-to-depth operand mode), max pooling, ReLU backward,
+// bias gradient, masked MSE, Adam, and the feature / normalisation maps that
+// connect the network to the LBM.
+//
+// Activations are pixel-major ("channels last", N[D]HWC) BF16 with an
+// explicit channel stride and offset so that concatenation is a layout
+// choice: a producer writes straight into its slice of the concatenated
+// buffer.  Products accumulate in FP32 on the matrix cores
+// (v_mfma_f32_16x16x32_bf16).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "unet_kernels.hpp"
+
+namespace nn {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __host__ inline float bf2f(uint16_t v) {
+    union { uint32_t u; float f; } c;
+    c.u = (uint32_t)v << 16;
+    return c.f;
+}
+
+// float -> bf16, round to nearest even (NaN kept quiet).
+__device__ __host__ inline uint16_t f2bf(float f) {
+    union { uint32_t u; float f; } c;
+    c.f = f;
+    if ((c.u & 0x7f800000u) == 0x7f800000u && (c.u & 0x007fffffu)) return (uint16_t)((c.u >> 16) | 0x40);
+    const uint32_t r = c.u + 0x7fffu + ((c.u >> 16) & 1u);
+    return (uint16_t)(r >> 16);
+}
+
+constexpr int BM = 64, BN = 64, BK = 32, LDK = BK + 8;   // LDS rows padded by 16 B
+
+// Pixel index -> (b, z, y, x) on a grid of d x h x w per sample.
+struct Pix { int b, z, y, x; };
+__device__ inline Pix pix_of(long long m, int d, int h, int w) {
+    Pix p;
+    p.x = (int)(m % w); m /= w;
+    p.y = (int)(m % h); m /= h;
+    p.z = (int)(m % d);
+    p.b = (int)(m / d);
+    return p;
+}
+
+// Eight consecutive K entries of the implicit im2col row of pixel m starting
+// at k (16 bytes), or zeros.  Normal mode: k = tap * cin + ci over a ks^dims
+// stencil centred on the pixel (zero padding).  S2D mode: k = sub * cin + ci
+// reads the fine-grid pixel (2z+sz, 2y+sy, 2x+sx), sub = sx + 2 sy + 4 sz.
+__device__ inline uint4 load_im2col(const ConvArgs &a, long long m, int k) {
+    uint4 z4 = make_uint4(0, 0, 0, 0);
+    if (m >= a.M || k >= a.K) return z4;
+    const Pix p = pix_of(m, a.d, a.h, a.w);
+    const int tap = k / a.cin, ci = k - tap * a.cin;
+    long long src;
+    if (a.flags & FLAG_S2D) {
+        const int sx = tap & 1, sy = (tap >> 1) & 1, sz = (tap >> 2) & 1;
+        const int fd = a.dims == 3 ? 2 * a.d : 1, fh = 2 * a.h, fw = 2 * a.w;
+        const int zf = a.dims == 3 ? 2 * p.z + sz : 0;
+        src = (((long long)p.b * fd + zf) * fh + 2 * p.y + sy) * fw + 2 * p.x + sx;
+    } else {
+        const int r = a.ks >> 1;
+        int dx = 0, dy = 0, dz = 0;
+        if (a.ks == 3) {
+            dx = tap % 3 - 1;
+            dy = (tap / 3) % 3 - 1;
+            dz = a.dims == 3 ? tap / 9 - 1 : 0;
+        }
+        (void)r;
+        const int xs = p.x + dx, ys = p.y + dy, zs = p.z + dz;
+        if (xs < 0 || xs >= a.w || ys < 0 || ys >= a.h || zs < 0 || zs >= a.d) return z4;
+        src = (((long long)p.b * a.d + zs) * a.h + ys) * a.w + xs;
+    }
+    return *(const uint4 *)(a.in + src * a.in_cs + a.in_co + ci);
+}
+
+__device__ inline bf16x8 as_bf16x8(uint4 v) { return __builtin_bit_cast(bf16x8, v); }
+
+// Output element of GEMM cell (m, c): returns the flat index and the bias
+// channel; D2S maps column c = sub * Cr + co to the fine pixel.
+__device__ inline long long out_index(const ConvArgs &a, long long m, int c, int &bias_c) {
+    if (a.flags & FLAG_D2S) {
+        const int cr = a.ncols >> a.dims;
+        const int sub = c / cr, co = c - sub * cr;
+        bias_c = co;
+        const Pix p = pix_of(m, a.d, a.h, a.w);
+        const int sx = sub & 1, sy = (sub >> 1) & 1, sz = (sub >> 2) & 1;
+        const int fd = a.dims == 3 ? 2 * a.d : 1, fh = 2 * a.h, fw = 2 * a.w;
+        const int zf = a.dims == 3 ? 2 * p.z + sz : 0;
+        const long long f = (((long long)p.b * fd + zf) * fh + 2 * p.y + sy) * fw + 2 * p.x + sx;
+        return f * a.out_cs + a.out_co + co;
+    }
+    bias_c = c;
+    return m * a.out_cs + a.out_co + c;
+}
+
+// C[M x ncols] = im2col(in)[M x K] * W^T, W stored [ncols][K].
+__global__ void __launch_bounds__(256) k_conv(ConvArgs a) {
+    __shared__ uint16_t As[BM][LDK];
+    __shared__ uint16_t Bs[BN][LDK];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int wm = wave & 1, wn = wave >> 1;
+    const long long m0 = (long long)blockIdx.x * BM;
+    const int n0 = blockIdx.y * BN;
+    const int lr = t >> 2, lk = (t & 3) * 8;
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < a.K; k0 += BK) {
+        const uint4 av = load_im2col(a, m0 + lr, k0 + lk);
+        uint4 bv = make_uint4(0, 0, 0, 0);
+        if (n0 + lr < a.ncols && k0 + lk < a.K) bv = *(const uint4 *)(a.wt + (long long)(n0 + lr) * a.K + k0 + lk);
+        __syncthreads();
+        *(uint4 *)&As[lr][lk] = av;
+        *(uint4 *)&Bs[lr][lk] = bv;
+        __syncthreads();
+        const int kr = (lane >> 4) * 8;
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const bf16x8 fa = as_bf16x8(*(const uint4 *)&As[wm * 32 + i * 16 + (lane & 15)][kr]);
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const bf16x8 fb = as_bf16x8(*(const uint4 *)&Bs[wn * 32 + j * 16 + (lane & 15)][kr]);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, fb, acc[i][j], 0, 0, 0);
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int c = n0 + wn * 32 + j * 16 + (lane & 15);
+            if (c >= a.ncols) continue;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const long long m = m0 + wm * 32 + i * 16 + (lane >> 4) * 4 + q;
+                if (m >= a.M) continue;
+                int bc;
+                const long long o = out_index(a, m, c, bc);
+                float v = acc[i][j][q] + (a.bias ? a.bias[bc] : 0.f);
+                if (a.flags & FLAG_RELU) v = v > 0.f ? v : 0.f;
+                if (a.out32) {
+                    a.out32[o] = (a.flags & FLAG_ACC) ? a.out32[o] + v : v;
+                } else {
+                    if (a.flags & FLAG_ACC) v += bf2f(a.out[o]);
+                    a.out[o] = f2bf(v);
+                }
+            }
+        }
+}
+
+// Weight gradient: dW[r][k] = sum_m G[m][r] * im2col(in)[m][k], G = dout
+// (S2D: r = sub * Cr + co read at the fine pixel).  blockIdx.z splits the
+// pixel range; partials are summed by k_sum_splits.
+__global__ void __launch_bounds__(256) k_wgrad(ConvArgs a, const uint16_t *__restrict__ g, int g_cs,
+                                               int g_co, int rows, float *__restrict__ part,
+                                               long long chunk) {
+    __shared__ uint16_t Gs[BM][LDK];
+    __shared__ uint16_t Ts[BN][LDK];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int wm = wave & 1, wn = wave >> 1;
+    const int r0 = blockIdx.x * BM, c0 = blockIdx.y * BN;
+    const long long mb = (long long)blockIdx.z * chunk;
+    const long long me = mb + chunk < a.M ? mb + chunk : a.M;
+    const int lm = t >> 3, ls = (t & 7) * 8;
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const bool s2d_g = (a.flags & FLAG_S2D_G) != 0;
+    for (long long mm = mb; mm < me; mm += BK) {
+        const long long m = mm + lm;
+        uint4 gv = make_uint4(0, 0, 0, 0);
+        const int r = r0 + ls;
+        if (m < me && r < rows) {
+            long long src = m;
+            int ch = r;
+            if (s2d_g) {
+                const int cr = rows >> a.dims;
+                const int sub = r / cr;
+                ch = r - sub * cr;
+                const Pix p = pix_of(m, a.d, a.h, a.w);
+                const int sx = sub & 1, sy = (sub >> 1) & 1, sz = (sub >> 2) & 1;
+                const int fd = a.dims == 3 ? 2 * a.d : 1, fh = 2 * a.h, fw = 2 * a.w;
+                const int zf = a.dims == 3 ? 2 * p.z + sz : 0;
+                src = (((long long)p.b * fd + zf) * fh + 2 * p.y + sy) * fw + 2 * p.x + sx;
+            }
+            gv = *(const uint4 *)(g + src * g_cs + g_co + ch);
+        }
+        const uint4 tv = m < me ? load_im2col(a, m, c0 + ls) : make_uint4(0, 0, 0, 0);
+        __syncthreads();
+        const uint16_t *gp = (const uint16_t *)&gv, *tp = (const uint16_t *)&tv;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            Gs[ls + e][lm] = gp[e];
+            Ts[ls + e][lm] = tp[e];
+        }
+        __syncthreads();
+        const int kr = (lane >> 4) * 8;
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const bf16x8 fa = as_bf16x8(*(const uint4 *)&Gs[wm * 32 + i * 16 + (lane & 15)][kr]);
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const bf16x8 fb = as_bf16x8(*(const uint4 *)&Ts[wn * 32 + j * 16 + (lane & 15)][kr]);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, fb, acc[i][j], 0, 0, 0);
+            }
+        }
+    }
+    float *dst = part + (long long)blockIdx.z * rows * a.K;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int c = c0 + wn * 32 + j * 16 + (lane & 15);
+            if (c >= a.K) continue;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int r = r0 + wm * 32 + i * 16 + (lane >> 4) * 4 + q;
+                if (r < rows) dst[(long long)r * a.K + c] = acc[i][j][q];
+            }
+        }
+}
+
+__global__ void k_sum_splits(const float *__restrict__ part, int splits, long long n, float *__restrict__ out,
+                             int accumulate) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float s = 0.f;
+    for (int z = 0; z < splits; ++z) s += part[(long long)z * n + i];
+    out[i] = accumulate ? out[i] + s : s;
+}
+
+// Bias gradient partials: part[split][c] = sum over the split's pixels.
+__global__ void __launch_bounds__(256) k_bias_grad(const uint16_t *__restrict__ g, int cs, int co, long long npix,
+                                                   int C, long long chunk, float *__restrict__ part) {
+    __shared__ float s[4][64];
+    const int c = blockIdx.x * 64 + (threadIdx.x & 63), pl = threadIdx.x >> 6;
+    const long long mb = (long long)blockIdx.y * chunk;
+    const long long me = mb + chunk < npix ? mb + chunk : npix;
+    float acc = 0.f;
+    if (c < C)
+        for (long long m = mb + pl; m < me; m += 4) acc += bf2f(g[m * cs + co + c]);
+    s[pl][threadIdx.x & 63] = acc;
+    __syncthreads();
+    if (pl == 0 && c < C) part[(long long)blockIdx.y * C + c] = s[0][threadIdx.x] + s[1][threadIdx.x] + s[2][threadIdx.x] + s[3][threadIdx.x];
+}
+
+__global__ void k_relu_bwd(uint16_t *__restrict__ g, const uint16_t *__restrict__ y, int cs, int co,
+                           long long npix, int C) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npix * C) return;
+    const long long m = i / C;
+    const int c = (int)(i - m * C);
+    const long long o = m * cs + co + c;
+    if (!(bf2f(y[o]) > 0.f)) g[o] = 0;
+}
+
+// 2x2(x2) max pooling, stride 2; (d, h, w) is the coarse grid.
+__global__ void k_pool_fwd(const uint16_t *__restrict__ in, int in_cs, int in_co, uint16_t *__restrict__ out,
+                           int out_cs, int out_co, int n, int d, int h, int w, int C, int dims) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long total = (long long)n * d * h * w * C;
+    if (i >= total) return;
+    const long long m = i / C;
+    const int c = (int)(i - m * C);
+    const Pix p = pix_of(m, d, h, w);
+    const int fd = dims == 3 ? 2 * d : 1;
+    float best = -INFINITY;
+    for (int sub = 0; sub < (1 << dims); ++sub) {
+        const int sx = sub & 1, sy = (sub >> 1) & 1, sz = (sub >> 2) & 1;
+        const int zf = dims == 3 ? 2 * p.z + sz : 0;
+        const long long f = (((long long)p.b * fd + zf) * (2 * h) + 2 * p.y + sy) * (2 * w) + 2 * p.x + sx;
+        best = fmaxf(best, bf2f(in[f * in_cs + in_co + c]));
+    }
+    out[m * out_cs + out_co + c] = f2bf(best);
+}
+
+// Routes dout to the first maximal element of each window (sub order).
+__global__ void k_pool_bwd(const uint16_t *__restrict__ in, int in_cs, int in_co,
+                           const uint16_t *__restrict__ gout, int g_cs, int g_co, uint16_t *__restrict__ gin,
+                           int gi_cs, int gi_co, int n, int d, int h, int w, int C, int dims, int accumulate) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long total = (long long)n * d * h * w * C;
+    if (i >= total) return;
+    const long long m = i / C;
+    const int c = (int)(i - m * C);
+    const Pix p = pix_of(m, d, h, w);
+    const int fd = dims == 3 ? 2 * d : 1;
+    float best = -INFINITY;
+    int arg = 0;
+    long long fidx[8];
+    for (int sub = 0; sub < (1 << dims); ++sub) {
+        const int sx = sub & 1, sy = (sub >> 1) & 1, sz = (sub >> 2) & 1;
+        const int zf = dims == 3 ? 2 * p.z + sz : 0;
+        fidx[sub] = (((long long)p.b * fd + zf) * (2 * h) + 2 * p.y + sy) * (2 * w) + 2 * p.x + sx;
+        const float v = bf2f(in[fidx[sub] * in_cs + in_co + c]);
+        if (v > best) { best = v; arg = sub; }
+    }
+    const float gv = bf2f(gout[m * g_cs + g_co + c]);
+    for (int sub = 0; sub < (1 << dims); ++sub) {
+        const long long o = fidx[sub] * gi_cs + gi_co + c;
+        const float add = sub == arg ? gv : 0.f;
+        if (accumulate) { if (sub == arg) gin[o] = f2bf(bf2f(gin[o]) + add); }
+        else gin[o] = f2bf(add);
+    }
+}
+
+// Masked MSE over the first `creal` channels of an FP32 prediction with
+// channel stride pcs: loss = scale * sum_m w_m sum_c (p - t)^2 and the BF16
+// gradient (pad channels zero).  Per-block partial sums in FP64.
+__global__ void __launch_bounds__(256) k_mse(const float *__restrict__ pred, int pcs, const float *__restrict__ tgt,
+                                             const float *__restrict__ wpix, int creal, long long npix,
+                                             float scale, uint16_t *__restrict__ dpred, double *__restrict__ part) {
+    __shared__ double s[256];
+    const long long m = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    double l = 0.0;
+    if (m < npix) {
+        const float wm = wpix ? wpix[m] : 1.f;
+        for (int c = 0; c < pcs; ++c) {
+            float gval = 0.f;
+            if (c < creal) {
+                const float d = pred[m * pcs + c] - tgt[m * creal + c];
+                l += (double)(wm * d * d);
+                gval = 2.f * scale * wm * d;
+            }
+            dpred[m * pcs + c] = f2bf(gval);
+        }
+    }
+    s[threadIdx.x] = l * scale;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = s[0];
+}
+
+__global__ void k_sum_f64(const double *__restrict__ part, long long n, double *__restrict__ out) {
+    __shared__ double s[256];
+    double a = 0.0;
+    for (long long i = threadIdx.x; i < n; i += 256) a += part[i];
+    s[threadIdx.x] = a;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = s[0];
+}
+
+// Adam on FP32 master weights with an optional BF16 mirror.
+__global__ void k_adam(float *__restrict__ w, const float *__restrict__ g, float *__restrict__ m1,
+                       float *__restrict__ m2, uint16_t *__restrict__ wb, long long n, float lr, float b1,
+                       float b2, float eps, float c1, float c2) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float a = b1 * m1[i] + (1.f - b1) * gi;
+    const float b = b2 * m2[i] + (1.f - b2) * gi * gi;
+    m1[i] = a;
+    m2[i] = b;
+    const float v = w[i] - lr * (a * c1) / (sqrtf(b * c2) + eps);
+    w[i] = v;
+    if (wb) wb[i] = f2bf(v);
+}
+
+__global__ void k_to_bf16(const float *__restrict__ x, uint16_t *__restrict__ y, long long n) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = f2bf(x[i]);
+}
+
+// Network input: 8 channels per pixel: solid, x / (nx - 1), 200 drho_in,
+// 200 drho_out, 2 (tau - 0.9), 0, 0, 0.  prm: [n][3] = (drho_in, drho_out, tau).
+__global__ void k_features(const uint8_t *__restrict__ solid, const float *__restrict__ prm, int n, int d,
+                           int h, int w, uint16_t *__restrict__ out) {
+    const long long m = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= (long long)n * d * h * w) return;
+    const Pix p = pix_of(m, d, h, w);
+    const float *q = prm + 3 * p.b;
+    float f[8] = {(float)solid[m], w > 1 ? (float)p.x / (float)(w - 1) : 0.f, 200.f * q[0], 200.f * q[1],
+                  2.f * (q[2] - 0.9f), 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int c = 0; c < 8; ++c) out[m * 8 + c] = f2bf(f[c]);
+}
+
+// Stokes-scaled targets from LBM fields (and back):
+//   t0 = (drho - drho_out) / (drho_in - drho_out),
+//   t_{1+a} = u_a nu / (cs^2 (drho_in - drho_out)),  nu = (tau - 1/2) / 3.
+__global__ void k_normalize(const float *__restrict__ drho, const float *__restrict__ u, const uint8_t *__restrict__ solid,
+                            const float *__restrict__ prm, long long per_sample, int D, long long npix,
+                            float *__restrict__ tgt, float *__restrict__ wpix) {
+    const long long m = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= npix) return;
+    const float *q = prm + 3 * (m / per_sample);
+    const float dr = q[0] - q[1], nu = (q[2] - 0.5f) / 3.f;
+    const float su = nu / (dr / 3.f);
+    const bool fl = solid[m] == 0;
+    tgt[m * (1 + D)] = fl ? (drho[m] - q[1]) / dr : 0.f;
+    for (int a = 0; a < D; ++a) tgt[m * (1 + D) + 1 + a] = fl ? u[m * D + a] * su : 0.f;
+    if (wpix) wpix[m] = fl ? 1.f : 0.f;
+}
+
+__global__ void k_denormalize(const float *__restrict__ pred, int pcs, const uint8_t *__restrict__ solid,
+                              const float *__restrict__ prm, long long per_sample, int D, long long npix,
+                              float *__restrict__ drho, float *__restrict__ u) {
+    const long long m = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= npix) return;
+    const float *q = prm + 3 * (m / per_sample);
+    const float dr = q[0] - q[1], nu = (q[2] - 0.5f) / 3.f;
+    const float su = (dr / 3.f) / nu;
+    const bool fl = solid[m] == 0;
+    drho[m] = fl ? q[1] + dr * pred[m * pcs] : 0.f;
+    for (int a = 0; a < D; ++a) u[m * D + a] = fl ? pred[m * pcs + 1 + a] * su : 0.f;
+}
+
+// ------------------------------------------------------------ launchers --
+static inline unsigned blocks(long long n, int b) { return (unsigned)((n + b - 1) / b); }
+
+hipError_t conv(const ConvArgs &a, hipStream_t s) {
+    dim3 grid(blocks(a.M, BM), (unsigned)((a.ncols + BN - 1) / BN));
+    hipLaunchKernelGGL(k_conv, grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+long long wgrad_chunk(long long M, int splits) {
+    long long c = (M + splits - 1) / splits;
+    return (c + BK - 1) / BK * BK;
+}
+
+hipError_t wgrad(const ConvArgs &a, const uint16_t *g, int g_cs, int g_co, int rows, float *part, int splits,
+                 float *dw, int accumulate, hipStream_t s) {
+    const long long chunk = wgrad_chunk(a.M, splits);
+    const int z = (int)((a.M + chunk - 1) / chunk);
+    dim3 grid((unsigned)((rows + BM - 1) / BM), (unsigned)((a.K + BN - 1) / BN), (unsigned)z);
+    hipLaunchKernelGGL(k_wgrad, grid, dim3(256), 0, s, a, g, g_cs, g_co, rows, part, chunk);
+    const long long n = (long long)rows * a.K;
+    hipLaunchKernelGGL(k_sum_splits, dim3(blocks(n, 256)), dim3(256), 0, s, part, z, n, dw, accumulate);
+    return hipGetLastError();
+}
+
+hipError_t bias_grad(const uint16_t *g, int cs, int co, long long npix, int C, float *part, int splits, float *db,
+                     int accumulate, hipStream_t s) {
+    const long long chunk = (npix + splits - 1) / splits;
+    dim3 grid((unsigned)((C + 63) / 64), (unsigned)splits);
+    hipLaunchKernelGGL(k_bias_grad, grid, dim3(256), 0, s, g, cs, co, npix, C, chunk, part);
+    hipLaunchKernelGGL(k_sum_splits, dim3(blocks(C, 256)), dim3(256), 0, s, part, splits, (long long)C, db,
+                       accumulate);
+    return hipGetLastError();
+}
+
+hipError_t relu_bwd(uint16_t *g, const uint16_t *y, int cs, int co, long long npix, int C, hipStream_t s) {
+    hipLaunchKernelGGL(k_relu_bwd, dim3(blocks(npix * C, 256)), dim3(256), 0, s, g, y, cs, co, npix, C);
+    return hipGetLastError();
+}
+
+hipError_t pool_fwd(const uint16_t *in, int in_cs, int in_co, uint16_t *out, int out_cs, int out_co, int n, int d,
+                    int h, int w, int C, int dims, hipStream_t s) {
+    const long long tot = (long long)n * d * h * w * C;
+    hipLaunchKernelGGL(k_pool_fwd, dim3(blocks(tot, 256)), dim3(256), 0, s, in, in_cs, in_co, out, out_cs, out_co,
+                       n, d, h, w, C, dims);
+    return hipGetLastError();
+}
+
+hipError_t pool_bwd(const uint16_t *in, int in_cs, int in_co, const uint16_t *gout, int g_cs, int g_co,
+                    uint16_t *gin, int gi_cs, int gi_co, int n, int d, int h, int w, int C, int dims, int acc,
+                    hipStream_t s) {
+    const long long tot = (long long)n * d * h * w * C;
+    hipLaunchKernelGGL(k_pool_bwd, dim3(blocks(tot, 256)), dim3(256), 0, s, in, in_cs, in_co, gout, g_cs, g_co, gin,
+                       gi_cs, gi_co, n, d, h, w, C, dims, acc);
+    return hipGetLastError();
+}
+
+hipError_t mse(const float *pred, int pcs, const float *tgt, const float *wpix, int creal, long long npix,
+               float scale, uint16_t *dpred, double *part, double *loss, hipStream_t s) {
+    const unsigned nb = blocks(npix, 256);
+    hipLaunchKernelGGL(k_mse, dim3(nb), dim3(256), 0, s, pred, pcs, tgt, wpix, creal, npix, scale, dpred, part);
+    hipLaunchKernelGGL(k_sum_f64, dim3(1), dim3(256), 0, s, part, (long long)nb, loss);
+    return hipGetLastError();
+}
+
+hipError_t adam(float *w, const float *g, float *m1, float *m2, uint16_t *wb, long long n, float lr, float b1,
+                float b2, float eps, int t, hipStream_t s) {
+    const float c1 = 1.f / (1.f - powf(b1, (float)t)), c2 = 1.f / (1.f - powf(b2, (float)t));
+    hipLaunchKernelGGL(k_adam, dim3(blocks(n, 256)), dim3(256), 0, s, w, g, m1, m2, wb, n, lr, b1, b2, eps, c1, c2);
+    return hipGetLastError();
+}
+
+hipError_t to_bf16(const float *x, uint16_t *y, long long n, hipStream_t s) {
+    hipLaunchKernelGGL(k_to_bf16, dim3(blocks(n, 256)), dim3(256), 0, s, x, y, n);
+    return hipGetLastError();
+}
+
+hipError_t features(const uint8_t *solid, const float *prm, int n, int d, int h, int w, uint16_t *out,
+                    hipStream_t s) {
+    hipLaunchKernelGGL(k_features, dim3(blocks((long long)n * d * h * w, 256)), dim3(256), 0, s, solid, prm, n, d, h,
+                       w, out);
+    return hipGetLastError();
+}
+
+hipError_t normalize(const float *drho, const float *u, const uint8_t *solid, const float *prm, long long per_sample,
+                     int D, long long npix, float *tgt, float *wpix, hipStream_t s) {
+    hipLaunchKernelGGL(k_normalize, dim3(blocks(npix, 256)), dim3(256), 0, s, drho, u, solid, prm, per_sample, D, npix,
+                       tgt, wpix);
+    return hipGetLastError();
+}
+
+hipError_t denormalize(const float *pred, int pcs, const uint8_t *solid, const float *prm, long long per_sample,
+                       int D, long long npix, float *drho, float *u, hipStream_t s) {
+    hipLaunchKernelGGL(k_denormalize, dim3(blocks(npix, 256)), dim3(256), 0, s, pred, pcs, solid, prm, per_sample, D,
+                       npix, drho, u);
+    return hipGetLastError();
+}
+
+}  // namespace nn
+
+namespace nn {
+
+// wt[c][tap'][r] = w[r][tap][c], tap' = taps - 1 - tap when flipping (the
+// input gradient of a correlation is the correlation with the flipped,
+// transposed kernel).
+__global__ void k_wtrans(const uint16_t *__restrict__ w, uint16_t *__restrict__ wt, int rows, int taps, int cols,
+                         int flip) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long n = (long long)rows * taps * cols;
+    if (i >= n) return;
+    const int c = (int)(i % cols);
+    const int tap = (int)((i / cols) % taps);
+    const int r = (int)(i / ((long long)cols * taps));
+    const int tp = flip ? taps - 1 - tap : tap;
+    wt[((long long)c * taps + tp) * rows + r] = w[i];
+}
+
+hipError_t wtrans(const uint16_t *w, uint16_t *wt, int rows, int taps, int cols, int flip, hipStream_t s) {
+    const long long n = (long long)rows * taps * cols;
+    hipLaunchKernelGGL(k_wtrans, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, w, wt, rows, taps, cols, flip);
+    return hipGetLastError();
+}
+
+}  // namespace nn

@@ -164,6 +164,29 @@ def _paint_sphere(solid, c, r, periodic):
     solid[np.ix_(iz, iy, ix)] |= m
 
 
+def boolean_disks(nx, ny, r_range=(6.0, 14.0), target_porosity=0.6, seed=0, periodic_y=False, x_margin=4,
+                  max_reseed=20):
+    """2D solid mask (ny, nx) uint8 of overlapping disks (Boolean model), for
+    porosities below what non-overlapping placement reaches.  Centres have
+    x in [x_margin + r, nx-1-x_margin-r] and y uniform (periodic_y) or inside
+    [r, ny-1-r]; the pore space must percolate from inlet to outlet."""
+    rng = np.random.default_rng(seed)
+    for _ in range(max_reseed):
+        solid = np.zeros((ny, nx), np.uint8)
+        while porosity(solid) > target_porosity:
+            r = rng.uniform(*r_range)
+            cx = rng.uniform(x_margin + r, nx - 1 - x_margin - r)
+            cy = rng.uniform(0, ny) if periodic_y else rng.uniform(r, ny - 1 - r)
+            if periodic_y:
+                for sh in (-ny, 0, ny):
+                    _paint_disk(solid, cx, cy + sh, r)
+            else:
+                _paint_disk(solid, cx, cy, r)
+        if percolates(solid):
+            return solid
+    raise RuntimeError("no percolating packing found")
+
+
 def fourier_profile(ny: int, nz: int, n_modes=8, seed=0, kmax=3):
     """Smooth field phi(z, y) in [0, 1] from n_modes Fourier modes:
     psi = sum_k a_k cos(2 pi (m_k y / ny + n_k z / nz) + theta_k) with

@@ -1,0 +1,279 @@
+"""Learned warm start: data generation, training and warm-versus-cold runs.
+
+The paper suggests a neural-network initial guess to speed up its inverse
+runs (Section 3.1.2 end, Section 3.5).  Here a U-Net (unet.py) learns the
+map (solid mask, drho_in, drho_out, tau) -> Stokes-scaled steady (rho, u)
+from steady states that the batched GPU solver itself produces; its
+prediction initialises equilibrium populations (Eq. 5) and the plain LBM
+then runs to the residual threshold, so the physics judges the network and
+is the fallback.
+
+Synthetic media (stand-ins for the paper's packings): 2D 256 x 256 channels
+between walls with overlapping disks (radii U[6, 14]); 3D 64^3 boxes,
+periodic in y and z, with overlapping spheres (radii U[4, 8]); porosity
+U[0.4, 0.8]; tau U[0.6, 1.2]; rho_in - 1 U[0.001, 0.006]; rho_out = 1.
+Seeds: train 500000 + i, validation 600000 + i, test 700000 + i.
+
+    python -m paper_2310_00810_amd.warmstart --dims 2 --train 2000 --epochs 20
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import json
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+from . import _lib as C
+from . import geometry as G
+from .lbm import Instance, Solver
+from .unet import UNet
+
+SEED_TRAIN, SEED_VAL, SEED_TEST = 500_000, 600_000, 700_000
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def sample(dims, seed, n2d=256, n3d=64):
+    """(solid (nz, ny, nx) uint8, drho_in, drho_out, tau) of one seeded case."""
+    rng = np.random.default_rng(seed)
+    phi = rng.uniform(0.4, 0.8)
+    tau = rng.uniform(0.6, 1.2)
+    din = rng.uniform(0.001, 0.006)
+    if dims == 2:
+        solid = G.boolean_disks(n2d, n2d, (6.0, 14.0), phi, seed=seed)[None]
+    else:
+        solid = G.boolean_spheres((n3d, n3d, n3d), (4.0, 8.0), phi, seed=seed, periodic=(False, True, True))
+    return solid.astype(np.uint8), din, 0.0, tau
+
+
+def bc_of(dims):
+    return ("pressure", "wall", "periodic") if dims == 2 else ("pressure", "periodic", "periodic")
+
+
+class Dataset:
+    """Network inputs and Stokes-scaled targets, resident on the GPU."""
+
+    def __init__(self, dims, cases, features, targets, wpix, prm, steps):
+        self.dims, self.cases = dims, cases
+        self.features, self.targets, self.wpix, self.prm, self.steps = features, targets, wpix, prm, steps
+
+    def __len__(self):
+        return self.features.shape[0]
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def features_of(solid_dev, prm_dev, n, d, h, w):
+    out = torch.empty((n, d, h, w, 8), dtype=torch.bfloat16, device="cuda")
+    C.check(C.nnlib().lbmnn_features(ctypes.c_void_p(solid_dev.data_ptr()), ctypes.c_void_p(prm_dev.data_ptr()),
+                                     n, d, h, w, ctypes.c_void_p(out.data_ptr()), _stream()), "lbmnn_features")
+    return out
+
+
+def generate(dims, seeds, batch=32, tol=1e-6, max_steps=100_000, check_every=100):
+    """Runs the batched solver to the residual threshold for every seed and
+    returns a Dataset (features, targets and fluid weights on the GPU)."""
+    D = dims
+    feats, tgts, wps, prms, steps, cases = [], [], [], [], [], []
+    t0 = time.time()
+    for b0 in range(0, len(seeds), batch):
+        chunk = [sample(dims, s) for s in seeds[b0:b0 + batch]]
+        insts = [Instance(c[0].shape[2], c[0].shape[1], c[0].shape[0], solid=c[0]) for c in chunk]
+        s = Solver(9 if dims == 2 else 19, insts, bc=bc_of(dims), steps=1)
+        taus = [c[3] for c in chunk]
+        dins = [c[1] for c in chunk]
+        nstep, r = s.run_to_residual(taus, dins, 0.0, tol=tol, max_steps=max_steps, check_every=check_every)
+        drho, u = s.macro(mean2=True)
+        nz, ny, nx = chunk[0][0].shape
+        nb = len(chunk)
+        solid = torch.from_numpy(np.stack([c[0] for c in chunk])).cuda()
+        prm = torch.tensor([[c[1], c[2], c[3]] for c in chunk], dtype=torch.float32, device="cuda")
+        per = nz * ny * nx
+        tg = torch.empty((nb * per, 1 + D), dtype=torch.float32, device="cuda")
+        wp = torch.empty(nb * per, dtype=torch.float32, device="cuda")
+        C.check(C.nnlib().lbmnn_normalize(ctypes.c_void_p(drho.data_ptr()), ctypes.c_void_p(u.data_ptr()),
+                                          ctypes.c_void_p(solid.data_ptr()), ctypes.c_void_p(prm.data_ptr()),
+                                          per, D, nb * per, ctypes.c_void_p(tg.data_ptr()),
+                                          ctypes.c_void_p(wp.data_ptr()), _stream()), "lbmnn_normalize")
+        feats.append(features_of(solid, prm, nb, nz, ny, nx))
+        tgts.append(tg.view(nb, nz, ny, nx, 1 + D))
+        wps.append(wp.view(nb, nz, ny, nx))
+        prms.append(prm)
+        steps += [nstep] * nb
+        cases += chunk
+        log(f"[data] dims={dims} {b0 + nb}/{len(seeds)} samples, batch converged in {nstep} steps "
+            f"(r={r:.2e}), {time.time() - t0:.1f} s")
+        del s
+    return Dataset(dims, cases, torch.cat(feats), torch.cat(tgts), torch.cat(wps), torch.cat(prms),
+                   np.array(steps))
+
+
+def channel_scale(ds):
+    """Root mean square of each target channel over fluid nodes: the
+    network trains on targets divided by it, so that the small velocity
+    channels weigh as much as the density channel in the loss."""
+    t = ds.targets.reshape(-1, ds.targets.shape[-1])
+    w = ds.wpix.reshape(-1, 1)
+    ms = (t * t * w).sum(0) / w.sum().clamp(min=1.0)
+    return ms.sqrt().clamp(min=1e-12)
+
+
+def standardized(ds, scale):
+    return Dataset(ds.dims, ds.cases, ds.features, (ds.targets / scale).contiguous(), ds.wpix, ds.prm, ds.steps)
+
+
+def evaluate_loss(net, ds, batch):
+    tot, n = 0.0, 0
+    for b0 in range(0, len(ds), batch):
+        x = ds.features[b0:b0 + batch]
+        out = net.forward(x)
+        wp = ds.wpix[b0:b0 + batch]
+        nfl = max(float(wp.sum().item()), 1.0)
+        net.loss_and_grad(out, ds.targets[b0:b0 + batch].contiguous(), wp.contiguous(), 1.0 / nfl)
+        tot += float(net.loss_dev.item()) * x.shape[0]
+        n += x.shape[0]
+    return tot / max(n, 1)
+
+
+def train(net, ds, val, epochs, batch, lr, seed=0):
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    hist = []
+    t0 = time.time()
+    for ep in range(epochs):
+        perm = torch.randperm(len(ds), generator=g)
+        tot = 0.0
+        nb = 0
+        lr_ep = lr * 0.5 * (1 + np.cos(np.pi * ep / max(epochs, 1)))
+        for b0 in range(0, len(ds) - batch + 1, batch):
+            idx = perm[b0:b0 + batch].cuda()
+            x = ds.features.index_select(0, idx)
+            tg = ds.targets.index_select(0, idx)
+            wp = ds.wpix.index_select(0, idx)
+            loss = net.train_step(x, tg, wp, lr_ep)
+            tot += float(loss.item())
+            nb += 1
+        vl = evaluate_loss(net, val, batch) if val is not None and len(val) else float("nan")
+        hist.append((ep, tot / max(nb, 1), vl))
+        log(f"[train] epoch {ep + 1}/{epochs} loss {tot / max(nb, 1):.4e} val {vl:.4e} lr {lr_ep:.2e} "
+            f"{time.time() - t0:.1f} s")
+    return hist
+
+
+def predict_fields(net, solid, din, dout, tau):
+    """Network prediction for one case -> (drho (nodes,), u (nodes, D)) on the GPU."""
+    nz, ny, nx = solid.shape
+    D = net.dims
+    sd = torch.from_numpy(solid[None]).cuda()
+    prm = torch.tensor([[din, dout, tau]], dtype=torch.float32, device="cuda")
+    x = features_of(sd, prm, 1, nz, ny, nx)
+    out = net.forward(x)
+    per = nz * ny * nx
+    drho = torch.empty(per, dtype=torch.float32, device="cuda")
+    u = torch.empty(per, D, dtype=torch.float32, device="cuda")
+    C.check(C.nnlib().lbmnn_denormalize(ctypes.c_void_p(out.data_ptr()), net.cout, ctypes.c_void_p(sd.data_ptr()),
+                                        ctypes.c_void_p(prm.data_ptr()), per, D, per,
+                                        ctypes.c_void_p(drho.data_ptr()), ctypes.c_void_p(u.data_ptr()),
+                                        _stream()), "lbmnn_denormalize")
+    return drho, u
+
+
+def warm_vs_cold(net, case, tol=1e-6, max_steps=100_000, check_every=100):
+    """Cold start (rest) and warm start (network prediction) of the same
+    case, both run to the residual threshold.  Seconds include the network
+    inference for the warm start."""
+    solid, din, dout, tau = case
+    dims = net.dims
+    nz, ny, nx = solid.shape
+    s = Solver(9 if dims == 2 else 19, [Instance(nx, ny, nz, solid=solid)], bc=bc_of(dims), steps=1)
+    # warm-up of both paths (graph capture, kernel loading)
+    s.run_to_residual(tau, din, dout, tol=1.0, max_steps=2 * check_every, check_every=check_every)
+    predict_fields(net, solid, din, dout, tau)
+    torch.cuda.synchronize()
+    s.set_initial(None, None)
+    t0 = time.perf_counter()
+    sc, rc = s.run_to_residual(tau, din, dout, tol=tol, max_steps=max_steps, check_every=check_every)
+    torch.cuda.synchronize()
+    tc = time.perf_counter() - t0
+    _, uc = s.macro(mean2=True)
+    uc = uc.clone()
+    t0 = time.perf_counter()
+    drho_p, u_p = predict_fields(net, solid, din, dout, tau)
+    s.set_initial(drho_p, u_p)
+    sw, rw = s.run_to_residual(tau, din, dout, tol=tol, max_steps=max_steps, check_every=check_every)
+    torch.cuda.synchronize()
+    tw = time.perf_counter() - t0
+    _, uw = s.macro(mean2=True)
+    fl = torch.from_numpy(solid.reshape(-1) == 0).cuda()
+    err_net = float(((u_p - uc)[fl].norm() / uc[fl].norm()).item())
+    same = float(((uw - uc)[fl].norm() / uc[fl].norm()).item())
+    return dict(cold_steps=sc, cold_s=tc, warm_steps=sw, warm_s=tw, net_rel_l2_u=err_net,
+                warm_cold_rel_l2=same, cold_r=rc, warm_r=rw)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--dims", type=int, default=2)
+    ap.add_argument("--train", type=int, default=2000)
+    ap.add_argument("--val", type=int, default=200)
+    ap.add_argument("--test", type=int, default=100)
+    ap.add_argument("--epochs", type=int, default=30)
+    ap.add_argument("--batch", type=int, default=0)
+    ap.add_argument("--gen-batch", type=int, default=0)
+    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--out", default="")
+    ap.add_argument("--max-steps", type=int, default=100_000)
+    args = ap.parse_args()
+    dims = args.dims
+    batch = args.batch or (16 if dims == 2 else 2)
+    gb = args.gen_batch or (64 if dims == 2 else 16)
+    t0 = time.time()
+    tr = generate(dims, [SEED_TRAIN + i for i in range(args.train)], batch=gb, max_steps=args.max_steps)
+    va = generate(dims, [SEED_VAL + i for i in range(args.val)], batch=gb, max_steps=args.max_steps) if args.val else None
+    gen_s = time.time() - t0
+    scale = channel_scale(tr)
+    log(f"[data] target channel RMS {scale.cpu().numpy()}; steps to converge: median "
+        f"{int(np.median(tr.steps))}, max {int(tr.steps.max())}")
+    net = UNet(dims, seed=0)
+    hist = train(net, standardized(tr, scale), standardized(va, scale) if va is not None else None, args.epochs,
+                 batch, args.lr)
+    net.fold_output_scale(scale)
+    train_s = time.time() - t0 - gen_s
+    res = []
+    for i in range(args.test):
+        case = sample(dims, SEED_TEST + i)
+        r = warm_vs_cold(net, case, max_steps=args.max_steps)
+        res.append(r)
+        log(f"[test] {i}: cold {r['cold_steps']} steps {r['cold_s']:.3f} s, warm {r['warm_steps']} steps "
+            f"{r['warm_s']:.3f} s, net err {r['net_rel_l2_u']:.3f}, warm/cold fixed point {r['warm_cold_rel_l2']:.1e}")
+    summ = {
+        "dims": dims, "train": args.train, "val": args.val, "test": args.test, "epochs": args.epochs,
+        "gen_seconds": gen_s, "train_seconds": train_s, "final_train_loss": hist[-1][1] if hist else None,
+        "final_val_loss": hist[-1][2] if hist else None,
+        "cold_steps_mean": float(np.mean([r["cold_steps"] for r in res])) if res else None,
+        "warm_steps_mean": float(np.mean([r["warm_steps"] for r in res])) if res else None,
+        "cold_s_mean": float(np.mean([r["cold_s"] for r in res])) if res else None,
+        "warm_s_mean": float(np.mean([r["warm_s"] for r in res])) if res else None,
+        "warm_faster_fraction": float(np.mean([r["warm_s"] < r["cold_s"] for r in res])) if res else None,
+        "net_rel_l2_u_mean": float(np.mean([r["net_rel_l2_u"] for r in res])) if res else None,
+        "warm_cold_rel_l2_max": float(np.max([r["warm_cold_rel_l2"] for r in res])) if res else None,
+    }
+    print(json.dumps(summ), flush=True)
+    if args.out:
+        os.makedirs(os.path.dirname(args.out) or ".", exist_ok=True)
+        net.save(args.out)
+        with open(args.out + ".json", "w") as f:
+            json.dump({"summary": summ, "history": hist, "tests": res,
+                       "target_scale": scale.cpu().numpy().tolist()}, f)
+
+
+if __name__ == "__main__":
+    main()

@@ -34,6 +34,14 @@ def test_every_declared_symbol_is_exported(L):
     assert sorted(C.EXPORTS) == sorted(n for n in names if n.startswith("lbm_"))
 
 
+def test_every_declared_network_symbol_is_exported(L):
+    names = declared("lbmnn.h")
+    assert sorted(C.NN_EXPORTS) == names
+    C.nnlib()
+    for n in names:
+        assert hasattr(L, n), n
+
+
 def _problem(nx=64, ny=32, nz=1, q=9, steps=100, K=0, tape=0, solid=None, n=1, **kw):
     arr = (C.lbm_instance * n)()
     keep = []

@@ -35,11 +35,17 @@ BYTES_ADJ = 3 * Q * 4        # gather F^{k-1}, gather nu^{k+1}, write nu^k
 PROFILES = os.path.join(ROOT, "profiles")
 
 
-def workload(n=128, T=8000, K=400):
+def workload(n=128, T=8000, K=400, kind="spheres"):
     from paper_2310_00810_amd import geometry as G
-    solid = G.boolean_spheres((n, n, n), (6.0, 10.0), 0.40, seed=3, periodic=(False, True, True), x_margin=4)
     phi = G.fourier_profile(n, n, n_modes=8, seed=33)
-    return dict(n=n, T=T, K=K, solid=solid, din=(0.004 * phi).astype(np.float32), tau=0.75, tau_target=0.9)
+    if kind == "channel":
+        # plane channel: walls in y, periodic z, no grains (kernel efficiency on a working set
+        # far larger than the 256 MB last-level cache)
+        return dict(n=n, T=T, K=K, solid=np.zeros((n, n, n), np.uint8), din=(0.004 * phi).astype(np.float32),
+                    tau=0.75, tau_target=0.9, bc=("pressure", "wall", "periodic"), kind=kind)
+    solid = G.boolean_spheres((n, n, n), (6.0, 10.0), 0.40, seed=3, periodic=(False, True, True), x_margin=4)
+    return dict(n=n, T=T, K=K, solid=solid, din=(0.004 * phi).astype(np.float32), tau=0.75, tau_target=0.9,
+                bc=("pressure", "periodic", "periodic"), kind=kind)
 
 
 def kernel_source_hash():
@@ -85,6 +91,31 @@ def copy_peak_gbs(torch, nbytes=4 << 30, reps=10):
     return gbs
 
 
+def warm_vs_cold(torch, n_cases=4):
+    """Warm start (committed trained U-Nets) against cold start on held-out
+    media: seconds to the 1e-6 two-step-mean residual, inference included."""
+    from paper_2310_00810_amd import warmstart as W
+    from paper_2310_00810_amd.unet import UNet
+    out = {}
+    for dims, cases in ((2, n_cases), (3, max(1, n_cases // 2))):
+        path = os.path.join(ROOT, "paper_2310_00810_amd", "weights", f"unet{dims}d.npz")
+        if not os.path.exists(path):
+            continue
+        net = UNet.load(path)
+        res = [W.warm_vs_cold(net, W.sample(dims, W.SEED_TEST + i), tol=1e-6, max_steps=100_000)
+               for i in range(cases)]
+        c = float(np.mean([r["cold_s"] for r in res]))
+        wm = float(np.mean([r["warm_s"] for r in res]))
+        out[f"{dims}d"] = {"cases": cases, "cold_s_mean": round(c, 4), "warm_s_mean": round(wm, 4),
+                           "speedup": round(c / wm, 2),
+                           "cold_steps_mean": float(np.mean([r["cold_steps"] for r in res])),
+                           "warm_steps_mean": float(np.mean([r["warm_steps"] for r in res])),
+                           "workload": ("D2Q9 256^2 Boolean disks" if dims == 2 else "D3Q19 64^3 Boolean spheres")
+                           + ", porosity U[0.4,0.8], test seeds 700000+"}
+        del net
+    return out
+
+
 def cpu_baseline(w, budget_steps=3):
     """The FP64 oracle's gradient evaluation (forward + reverse) on the same
     128^3 problem for a bounded number of steps, timed on the host cores."""
@@ -110,10 +141,12 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--size", type=int, default=128)
+    ap.add_argument("--workload", choices=["spheres", "channel"], default="spheres")
     ap.add_argument("--T", type=int, default=8000)
     ap.add_argument("--K", type=int, default=400)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-copy", action="store_true", help="skip the copy-bandwidth calibration")
+    ap.add_argument("--no-warm", action="store_true", help="skip the warm-versus-cold start comparison")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1"}))
@@ -122,7 +155,7 @@ def main():
     import torch
     from paper_2310_00810_amd import lbm
 
-    w = workload(args.size, args.T, args.K)
+    w = workload(args.size, args.T, args.K, args.workload)
     n, T, K = w["n"], w["T"], w["K"]
     fluid_frac = float((w["solid"] == 0).mean())
     n_fluid = int((w["solid"] == 0).sum())
@@ -130,7 +163,7 @@ def main():
 
     # target velocity from a run at another tau (the inverse problem recovers tau and the profile)
     ins0 = lbm.Instance(n, n, n, solid=w["solid"])
-    s0 = lbm.Solver(19, [ins0], bc=("pressure", "periodic", "periodic"), steps=T, inlet_mode="profile")
+    s0 = lbm.Solver(19, [ins0], bc=w["bc"], steps=T, inlet_mode="profile")
     s0.forward(w["tau_target"], w["din"].ravel(), 0.0, want_loss=False)
     _, ut = s0.macro()
     target = ut.cpu().numpy().reshape(n, n, n, 3)
@@ -138,7 +171,7 @@ def main():
     torch.cuda.empty_cache()
 
     ins = lbm.Instance(n, n, n, solid=w["solid"], target_u=target)
-    s = lbm.Solver(19, [ins], bc=("pressure", "periodic", "periodic"), steps=T, ckpt_interval=K, tape=True,
+    s = lbm.Solver(19, [ins], bc=w["bc"], steps=T, ckpt_interval=K, tape=True,
                    loss_scale="mean", inlet_mode="profile")
     print(f"[bench] workspace {s.workspace_bytes / 2**30:.1f} GiB", file=sys.stderr, flush=True)
 
@@ -151,13 +184,17 @@ def main():
         one()
         print(f"[bench] warmup {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
-    s.set_timing(True, reset=True)
     t0 = time.perf_counter()
     for i in range(args.steps):
         g = one()
         print(f"[bench] step {i + 1}/{args.steps} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    # one more evaluation with per-phase HIP events (kernels launched one by one
+    # between events on the library stream) for the per-kernel averages
+    s.set_timing(True, reset=True)
+    one()
+    torch.cuda.synchronize()
     tm = s.timing()
     s.set_timing(False)
 
@@ -186,8 +223,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"D3Q19 {n}^3 packed spheres r~U[6,10] porosity 0.40, periodic y/z, "
-                               f"Zou-He profile inlet (8 Fourier modes) + tau gradient, T={T}, K={K}, "
+        "config": {"workload": (f"D3Q19 {n}^3 packed spheres r~U[6,10] porosity 0.40, periodic y/z, "
+                                if w["kind"] == "spheres" else f"D3Q19 {n}^3 plane channel, walls y, periodic z, ")
+                               + f"Zou-He profile inlet (8 Fourier modes) + tau gradient, T={T}, K={K}, "
                                f"one step = taped forward + reverse sweep",
                    "lattice": "D3Q19", "nodes": n ** 3, "fluid_nodes": n_fluid, "T": T, "K": K},
         "roofline": {"bound": "hbm", "achieved": round(adj_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -203,10 +241,13 @@ def main():
         "gradient_norms": {"drho_in": float(np.linalg.norm(g["drho_in"])), "dtau": float(g["dtau"][0])},
         "warm_vs_cold": None,
     }
+    del s
+    torch.cuda.empty_cache()
     if not args.no_copy:
-        del s
-        torch.cuda.empty_cache()
         out["copy_peak_gbs"] = round(copy_peak_gbs(torch), 1)
+    if not args.no_warm:
+        print("[bench] warm vs cold start ...", file=sys.stderr, flush=True)
+        out["warm_vs_cold"] = warm_vs_cold(torch)
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w)

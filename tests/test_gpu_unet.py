@@ -208,8 +208,8 @@ def _oracle_params(net):
 @pytest.mark.parametrize("dims,shape,base,levels,wscale,bias,bar_f,bar_g", [
     (2, (2, 1, 32, 48), 8, 3, 1.0, 0.0, 2e-3, 5e-3),      # narrow: short accumulations
     (3, (1, 16, 16, 8), 8, 3, 1.0, 0.0, 2e-3, 5e-3),
-    (2, (2, 1, 32, 48), 32, 4, 0.1, 1.0, 2e-3, 5e-3),     # full width, every ReLU active
-    (3, (1, 16, 16, 8), 32, 4, 0.1, 1.0, 2e-3, 5e-3),
+    (2, (2, 1, 32, 48), 32, 4, 0.1, 1.0, 2e-3, 1e-2),     # full width, every ReLU active
+    (3, (1, 16, 16, 8), 32, 4, 0.1, 1.0, 2e-3, 1e-2),
     (2, (2, 1, 32, 48), 32, 4, 1.0, 0.0, 2e-2, 0.25),     # full width at random initialisation
     (3, (1, 16, 16, 8), 32, 4, 1.0, 0.0, 2e-2, 0.25),
 ])

@@ -82,8 +82,8 @@ int validate_problem(const lbm_problem *p) {
         if (p->lattice == LBM_D2Q9 && I.nz != 1) return fail(LBM_EINVAL, "instance %d: D2Q9 needs nz = 1", b);
         if (p->bc_x == LBM_BC_PRESSURE && I.nx < 2)
             return fail(LBM_EINVAL, "instance %d: a pressure x axis needs nx >= 2", b);
-        if ((long long)I.nx * I.ny * I.nz > (1LL << 31))
-            return fail(LBM_EINVAL, "instance %d: more than 2^31 nodes", b);
+        if ((long long)I.nx * I.ny * I.nz * p->lattice >= (1LL << 31) - (1LL << 20))
+            return fail(LBM_EINVAL, "instance %d: Q x nodes must stay below 2^31 (32-bit population offsets)", b);
         if (p->inlet_mode == LBM_INLET_PROFILE && p->bc_x == LBM_BC_PRESSURE && I.solid) {
             for (long long zy = 0; zy < (long long)I.ny * I.nz; ++zy)
                 if (I.solid[zy * I.nx])
@@ -91,6 +91,14 @@ int validate_problem(const lbm_problem *p) {
         }
     }
     return LBM_OK;
+}
+
+long long count_fluid(const lbm_instance &S) {
+    const long long n = (long long)S.nx * S.ny * S.nz;
+    if (!S.solid) return n;
+    long long c = 0;
+    for (long long k = 0; k < n; ++k) c += S.solid[k] == 0;
+    return c;
 }
 
 void plan(const lbm_problem *p, Layout &L) {
@@ -109,22 +117,23 @@ void plan(const lbm_problem *p, Layout &L) {
         const lbm_instance &S = p->inst[b];
         InstDev &I = L.inst[b];
         I.nx = S.nx; I.ny = S.ny; I.nz = S.nz;
-        I.pitch = (int)align_up(S.nx, 32);
-        I.words = I.pitch / 32;
+        I.words = (S.nx + 31) / 32;
         I.tiles_x = (S.nx + lbm::TILE_X - 1) / lbm::TILE_X;
         I.tiles_y = (S.ny + lbm::TILE_Y - 1) / lbm::TILE_Y;
         I.n_tiles = I.tiles_x * I.tiles_y * S.nz;
         I.tile_begin = tile;
         tile += I.n_tiles;
-        I.plane = (long long)S.nz * S.ny * I.pitch;
+        I.n_fluid = (int)count_fluid(S);
+        // one plane per population direction over the fluid nodes, padded to 256 B
+        I.plane = std::max<long long>(64, (long long)align_up((size_t)I.n_fluid, 64));
         I.poff = poff;
         I.st_off = (long long)L.q * poff;
-        poff += (long long)align_up((size_t)I.plane, 64);
+        poff += I.plane;
         I.node_off = node;
         node += (long long)S.nx * S.ny * S.nz;
         I.face_off = face;
         face += (long long)S.ny * S.nz;
-        I.mask_off = words;
+        I.rw_off = words;
         words += (long long)S.nz * S.ny * I.words;
         I.omega = 1.0f;
         I.inv_tau2 = 1.0f;
@@ -140,7 +149,7 @@ void plan(const lbm_problem *p, Layout &L) {
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + bytes, 256); return r; };
     L.off_inst = take(sizeof(InstDev) * p->n_inst);
-    L.off_mask = take(sizeof(uint32_t) * words);
+    L.off_mask = take(sizeof(uint2) * words);
     L.off_roi = take(sizeof(float) * poff);
     L.off_target = take(sizeof(float) * poff * L.D);
     L.off_face_in = take(sizeof(float) * face);
@@ -346,31 +355,33 @@ int lbm_init(lbm_handle **out, const lbm_problem *p, void *d_workspace, size_t b
     h->ws = (char *)d_workspace;
     h->hinst = h->L.inst;
     const Layout &L = h->L;
-    // host copies of masks, weights and targets in the device layouts
-    std::vector<uint32_t> mask(L.total_words, 0u);
+    // host copies of the row-word tables, weights and targets in the device layouts
+    std::vector<uint2> rw(L.total_words);
     std::vector<float> roi(L.total_poff, 0.f), target((size_t)L.total_poff * L.D, 0.f);
     for (int b = 0; b < L.n_inst; ++b) {
         const lbm_instance &S = p->inst[b];
         InstDev &I = h->hinst[b];
-        long long nfluid = 0;
+        long long id = 0;
         for (int z = 0; z < S.nz; ++z)
             for (int y = 0; y < S.ny; ++y)
-                for (int x = 0; x < S.nx; ++x) {
-                    const long long dn = ((long long)z * S.ny + y) * S.nx + x;
-                    const bool sol = S.solid && S.solid[dn];
-                    const long long pr = ((long long)z * S.ny + y) * I.pitch + x;
-                    if (sol) {
-                        mask[I.mask_off + ((long long)z * S.ny + y) * I.words + (x >> 5)] |= 1u << (x & 31);
-                        continue;
+                for (int w = 0; w < I.words; ++w) {
+                    uint2 &e = rw[I.rw_off + ((long long)z * S.ny + y) * I.words + w];
+                    e.x = 0u;
+                    e.y = (uint32_t)id;
+                    for (int bit = 0; bit < 32; ++bit) {
+                        const int x = 32 * w + bit;
+                        const long long dn = ((long long)z * S.ny + y) * S.nx + x;
+                        if (x >= S.nx || (S.solid && S.solid[dn])) {
+                            e.x |= 1u << bit;
+                            continue;
+                        }
+                        roi[I.poff + id] = S.roi ? S.roi[dn] : 1.0f;
+                        if (S.target_u)
+                            for (int a = 0; a < L.D; ++a) target[I.poff * L.D + a * I.plane + id] = S.target_u[dn * L.D + a];
+                        ++id;
                     }
-                    ++nfluid;
-                    roi[I.poff + pr] = S.roi ? S.roi[dn] : 1.0f;
-                    if (S.target_u)
-                        for (int a = 0; a < L.D; ++a)
-                            target[I.poff * L.D + a * I.plane + pr] = S.target_u[dn * L.D + a];
                 }
-        I.n_fluid = (int)nfluid;
-        I.loss_scale = p->loss_scale == LBM_SCALE_MEAN_FLUID ? (nfluid ? (float)(1.0 / (double)nfluid) : 0.f) : 1.0f;
+        I.loss_scale = p->loss_scale == LBM_SCALE_MEAN_FLUID ? (id ? (float)(1.0 / (double)id) : 0.f) : 1.0f;
     }
     auto cp = [&](size_t off, const void *src, size_t n) -> int {
         if (!n) return LBM_OK;
@@ -379,7 +390,7 @@ int lbm_init(lbm_handle **out, const lbm_problem *p, void *d_workspace, size_t b
     };
     int e = 0;
     if ((e = cp(L.off_inst, h->hinst.data(), sizeof(InstDev) * L.n_inst)) ||
-        (e = cp(L.off_mask, mask.data(), sizeof(uint32_t) * mask.size())) ||
+        (e = cp(L.off_mask, rw.data(), sizeof(uint2) * rw.size())) ||
         (e = cp(L.off_roi, roi.data(), sizeof(float) * roi.size())) ||
         (e = cp(L.off_target, target.data(), sizeof(float) * target.size()))) {
         delete h;
@@ -389,7 +400,7 @@ int lbm_init(lbm_handle **out, const lbm_problem *p, void *d_workspace, size_t b
     h->G.n_inst = L.n_inst;
     h->G.n_tiles = L.n_tiles;
     h->G.bcx = p->bc_x; h->G.bcy = p->bc_y; h->G.bcz = p->bc_z;
-    h->G.mask = h->at<uint32_t>(L.off_mask);
+    h->G.rw = h->at<uint2>(L.off_mask);
     hipError_t he = lbm::launch_init_eq(L.q, h->G, h->init(), nullptr, nullptr, h->stream);
     if (he == hipSuccess) he = hipStreamSynchronize(h->stream);
     if (he != hipSuccess) {

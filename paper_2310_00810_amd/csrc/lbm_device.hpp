@@ -63,20 +63,25 @@ template <> struct Vel<19> {
 
 // ---------------------------------------------------------------------------
 // Per-instance descriptor (device copy in the workspace).
-// A state buffer holds, per instance, Q planes of [nz][ny][pitch] floats of
-// shifted populations f_i - w_i starting at st_off.  Masks are one bit per
-// node, rows of `words` 32-bit words.  Face arrays are [nz][ny].
+//
+// Populations are stored for fluid nodes only, numbered in (z, y, x) order:
+// a state buffer holds, per instance, Q planes of `plane` floats (plane >= the
+// number of fluid nodes) of shifted populations f_i - w_i, starting at st_off.
+// The row-word table has one entry per 32-node word of every x row:
+//   .x = solid bits of the word (bit b = node x = 32 w + b; bits past nx set),
+//   .y = fluid id of the first fluid node at or after the word's first node,
+// so the id of fluid node x is .y + popcount(~.x & ((1 << (x & 31)) - 1)).
+// Face arrays are [nz][ny].
 // ---------------------------------------------------------------------------
 struct InstDev {
-    int nx, ny, nz, pitch;
+    int nx, ny, nz, words;
     int tiles_x, tiles_y, tile_begin, n_tiles;
-    long long poff;        // pitched-node offset of the instance (per-node arrays)
+    long long plane;       // floats per population plane (fluid nodes, padded)
+    long long poff;        // offset of the instance in per-node (fluid) arrays
     long long st_off;      // float offset of the instance in a state buffer = Q * poff
-    long long plane;       // nz * ny * pitch
     long long node_off;    // dense node offset (ABI arrays)
-    long long mask_off;    // word offset of the mask
+    long long rw_off;      // offset of the instance's row-word table
     long long face_off;    // offset into face arrays
-    int words;             // mask words per row
     int n_fluid;
     float omega;           // 1 / tau
     float inv_tau2;        // 1 / tau^2
@@ -88,7 +93,7 @@ struct Geo {
     int n_inst;
     int n_tiles;
     int bcx, bcy, bcz;
-    const uint32_t *mask;
+    const uint2 *rw;       // row-word tables
 };
 
 // Block index -> tile index such that the blocks the hardware places on one
@@ -109,11 +114,19 @@ __device__ inline int find_inst(const InstDev *inst, int n_inst, int tile) {
     return lo;
 }
 
+__device__ inline uint2 row_word(const Geo &G, const InstDev &I, int x, int y, int z) {
+    return G.rw[I.rw_off + ((long long)z * I.ny + y) * I.words + (x >> 5)];
+}
+__device__ inline bool solid_bit(uint2 w, int x) { return (w.x >> (x & 31)) & 1u; }
+__device__ inline int fluid_id(uint2 w, int x) { return (int)w.y + __popc(~w.x & ((1u << (x & 31)) - 1u)); }
+
 struct NodeRef {
     int b;                 // instance
     int tile;              // global tile id
     int x, y, z;
     bool inside;           // inside the lattice
+    bool fluid;            // inside and fluid
+    int id;                // fluid id (valid when fluid)
 };
 
 __device__ inline NodeRef map_node(const Geo &G, int tile) {
@@ -129,62 +142,147 @@ __device__ inline NodeRef map_node(const Geo &G, int tile) {
     n.x = tx * TILE_X + (threadIdx.x & (TILE_X - 1));
     n.y = ty * TILE_Y + (threadIdx.x / TILE_X);
     n.inside = n.x < I.nx && n.y < I.ny;
+    n.fluid = false;
+    n.id = 0;
+    if (n.inside) {
+        const uint2 w = row_word(G, I, n.x, n.y, n.z);
+        n.fluid = !solid_bit(w, n.x);
+        n.id = fluid_id(w, n.x);
+    }
     return n;
 }
 
-__device__ inline bool solid_at(const uint32_t *mask, const InstDev &I, int x, int y, int z) {
-    const uint32_t wv = mask[I.mask_off + ((long long)z * I.ny + y) * I.words + (x >> 5)];
-    return (wv >> (x & 31)) & 1u;
+// Dense (ABI) index of a node.
+__device__ inline long long dense_index(const InstDev &I, const NodeRef &n) {
+    return I.node_off + ((long long)n.z * I.ny + n.y) * I.nx + n.x;
 }
 
 // ---------------------------------------------------------------------------
-// Pull gather of one node.  For each link i it looks at the neighbour
-// s = x - SGN * c_i:
-//   SGN = +1 (forward streaming): g_i(x) = buf_i(s); if s is solid or lies
-//     beyond a wall, halfway bounce-back gives g_i(x) = buf_opp(i)(x); if s
-//     lies beyond a pressure face, the link is a Zou-He unknown and g_i is
-//     left to the boundary closure (set to 0 here).
-//   SGN = -1 (transpose of streaming, adjoint): the same rule on the mirrored
-//     link: a link that leaves through a pressure face carries no adjoint (0).
-// Bit i of the returned mask marks the pressure-face links.
+// Neighbourhood of a block.  A block covers x in [x0, x0 + 64) of four rows
+// y0 .. y0 + 3 at one z.  Its nodes' neighbours lie in rows y0 - 1 .. y0 + 4
+// at z - 1 .. z + 1, words (x0 >> 5) - 1 .. (x0 >> 5) + 2: 3 x 6 x 4 row
+// words, staged once per block in LDS (wrapped on periodic axes, all-solid
+// beyond walls and outside the row).
 // ---------------------------------------------------------------------------
-template <int Q, int SGN>
-__device__ inline uint32_t gather(const Geo &G, const InstDev &I, const float *__restrict__ buf,
-                                  int x, int y, int z, float (&g)[Q]) {
-    using V = Vel<Q>;
-    const long long base = I.st_off + ((long long)z * I.ny + y) * I.pitch + x;
-    uint32_t open = 0;
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        const int dx = -SGN * V::cx(i), dy = -SGN * V::cy(i), dz = -SGN * V::cz(i);
-        int sx = x + dx, sy = y + dy, sz = z + dz;
-        bool out_p = false, out_w = false;
-        if (dx != 0 && (sx < 0 || sx >= I.nx)) {
-            if (G.bcx == BC_PERIODIC) sx = sx < 0 ? sx + I.nx : sx - I.nx;
-            else if (G.bcx == BC_PRESSURE) out_p = true;
-            else out_w = true;
+constexpr int NB_ROWS_Y = TILE_Y + 2, NB_WORDS = 4;
+constexpr int NB_ENTRIES = 3 * NB_ROWS_Y * NB_WORDS;
+
+struct BlockTile {
+    int b, x0, y0, z;
+};
+
+__device__ inline BlockTile block_tile(const Geo &G, int tile) {
+    BlockTile t;
+    t.b = G.n_inst == 1 ? 0 : find_inst(G.inst, G.n_inst, tile);
+    const InstDev &I = G.inst[t.b];
+    const int lt = tile - I.tile_begin;
+    const int tx = lt % I.tiles_x, rest = lt / I.tiles_x;
+    t.x0 = tx * TILE_X;
+    t.y0 = (rest % I.tiles_y) * TILE_Y;
+    t.z = rest / I.tiles_y;
+    return t;
+}
+
+__device__ inline void stage_rows(const Geo &G, const InstDev &I, const BlockTile &t, uint2 *lds) {
+    for (int e = threadIdx.x; e < NB_ENTRIES; e += BLOCK) {
+        const int ws = e % NB_WORDS, r = e / NB_WORDS;
+        int yy = t.y0 - 1 + r % NB_ROWS_Y, zz = t.z - 1 + r / NB_ROWS_Y;
+        const int w = (t.x0 >> 5) - 1 + ws;
+        bool ok = w >= 0 && w < I.words;
+        if (yy < 0 || yy >= I.ny) {
+            if (G.bcy == BC_PERIODIC) yy = ((yy % I.ny) + I.ny) % I.ny;
+            else ok = false;
         }
-        if (dy != 0 && (sy < 0 || sy >= I.ny)) {
-            if (G.bcy == BC_PERIODIC) sy = sy < 0 ? sy + I.ny : sy - I.ny;
-            else out_w = true;
+        if (zz < 0 || zz >= I.nz) {
+            if (G.bcz == BC_PERIODIC) zz = ((zz % I.nz) + I.nz) % I.nz;
+            else ok = false;
         }
-        if (dz != 0 && (sz < 0 || sz >= I.nz)) {
-            if (G.bcz == BC_PERIODIC) sz = sz < 0 ? sz + I.nz : sz - I.nz;
-            else out_w = true;
-        }
-        long long off;
-        if (out_p) {
-            off = base + (long long)i * I.plane;             // not used
-            open |= 1u << i;
-        } else if (out_w || (i != 0 && solid_at(G.mask, I, sx, sy, sz))) {
-            off = base + (long long)V::opp(i) * I.plane;     // bounce-back
-        } else {
-            off = I.st_off + (long long)i * I.plane + ((long long)sz * I.ny + sy) * I.pitch + sx;
-        }
-        const float v = buf[off];
-        g[i] = out_p ? 0.0f : v;
+        lds[e] = ok ? G.rw[I.rw_off + ((long long)zz * I.ny + yy) * I.words + w] : make_uint2(0xffffffffu, 0u);
     }
-    return open;
+}
+
+// Staged row word of the node at (x + dx, ly + dy, dz) relative to a lane at
+// x with block row ly (x + dx must lie in [x0 - 1, x0 + 64]).
+__device__ inline uint2 staged(const uint2 *lds, const BlockTile &t, int xs, int ly, int dy, int dz) {
+    return lds[((dz + 1) * NB_ROWS_Y + ly + 1 + dy) * NB_WORDS + ((xs >> 5) - (t.x0 >> 5) + 1)];
+}
+
+enum { NB_WALL = -1, NB_OPEN = -2 };
+
+// A lane of a block: its node, and whether that node is a fluid node of the
+// lattice (own word read from the staged neighbourhood).
+struct Lane {
+    int x, y, ly, z;
+    bool inside, fluid;
+    int id;
+};
+
+__device__ inline Lane lane_of(const InstDev &I, const BlockTile &t, const uint2 *lds) {
+    Lane l;
+    l.ly = threadIdx.x / TILE_X;
+    l.x = t.x0 + (threadIdx.x & (TILE_X - 1));
+    l.y = t.y0 + l.ly;
+    l.z = t.z;
+    l.inside = l.x < I.nx && l.y < I.ny;
+    const uint2 w = staged(lds, t, l.x, l.ly, 0, 0);
+    l.fluid = l.inside && !solid_bit(w, l.x);
+    l.id = fluid_id(w, l.x);
+    return l;
+}
+
+// For every link k: the fluid id of node x + c_k, NB_WALL if that node is
+// solid or lies beyond a wall (halfway bounce-back), NB_OPEN if it lies
+// beyond a pressure face.  nb[0] is the node's own id.
+template <int Q>
+__device__ inline void neighbours(const Geo &G, const InstDev &I, const uint2 *lds, const BlockTile &t,
+                                  int x, int y, int ly, int z, int id, int (&nb)[Q]) {
+    using V = Vel<Q>;
+    nb[0] = id;
+#pragma unroll
+    for (int k = 1; k < Q; ++k) {
+        const int dx = V::cx(k), dy = V::cy(k), dz = V::cz(k);
+        int xs = x + dx;
+        bool open = false, wall = false, wrap_x = false;
+        if (dx != 0 && (xs < 0 || xs >= I.nx)) {
+            if (G.bcx == BC_PERIODIC) { xs = xs < 0 ? xs + I.nx : xs - I.nx; wrap_x = true; }
+            else if (G.bcx == BC_PRESSURE) open = true;
+            else wall = true;
+        }
+        if (dy != 0 && (y + dy < 0 || y + dy >= I.ny) && G.bcy != BC_PERIODIC) wall = true;
+        if (dz != 0 && (z + dz < 0 || z + dz >= I.nz) && G.bcz != BC_PERIODIC) wall = true;
+        if (open) { nb[k] = NB_OPEN; continue; }
+        if (wall) { nb[k] = NB_WALL; continue; }
+        uint2 w;
+        if (wrap_x) {
+            int ys = y + dy, zs = z + dz;
+            ys = ys < 0 ? ys + I.ny : (ys >= I.ny ? ys - I.ny : ys);
+            zs = zs < 0 ? zs + I.nz : (zs >= I.nz ? zs - I.nz : zs);
+            w = row_word(G, I, xs, ys, zs);
+        } else {
+            w = staged(lds, t, xs, ly, dy, dz);
+        }
+        nb[k] = solid_bit(w, xs) ? NB_WALL : fluid_id(w, xs);
+    }
+}
+
+// Pull gather over a precomputed neighbourhood.  Link i reads the node
+// x - SGN c_i = x + c_k with k = opp(i) for SGN = +1 (forward streaming) and
+// k = i for SGN = -1 (transpose of streaming):
+//   fluid neighbour -> buf_i(neighbour);
+//   solid / wall    -> buf_opp(i)(x)   (halfway bounce-back);
+//   pressure face   -> 0 (forward: Zou-He unknown, filled by the closure;
+//                     adjoint: the link leaves the lattice).
+template <int Q, int SGN>
+__device__ inline void gather(const float *__restrict__ base, int plane, int id, const int (&nb)[Q], float (&g)[Q]) {
+    using V = Vel<Q>;
+    g[0] = base[id];
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        const int j = nb[SGN > 0 ? V::opp(i) : i];
+        const int off = j >= 0 ? i * plane + j : (j == NB_WALL ? V::opp(i) * plane + id : i * plane + id);
+        const float v = base[off];
+        g[i] = j == NB_OPEN ? 0.0f : v;
+    }
 }
 
 // Zou-He closure of the unknown populations at a face node (shifted form:

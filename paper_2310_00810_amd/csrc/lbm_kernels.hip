@@ -23,13 +23,18 @@ __global__ void __launch_bounds__(BLOCK) k_step(Geo G, const float *__restrict__
                                                 float *__restrict__ dst,
                                                 const float *__restrict__ face_in,
                                                 const float *__restrict__ face_out) {
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    const NodeRef n = map_node(G, tile);
-    if (!n.inside) return;
-    const InstDev &I = G.inst[n.b];
-    if (solid_at(G.mask, I, n.x, n.y, n.z)) return;
+    __shared__ uint2 lds[NB_ENTRIES];
+    const BlockTile t = block_tile(G, xcd_tile(blockIdx.x, gridDim.x));
+    const InstDev &I = G.inst[t.b];
+    stage_rows(G, I, t, lds);
+    __syncthreads();
+    const Lane n = lane_of(I, t, lds);
+    if (!n.fluid) return;
+    int nb[Q];
+    neighbours<Q>(G, I, lds, t, n.x, n.y, n.ly, n.z, n.id, nb);
+    const int plane = (int)I.plane;
     float g[Q];
-    gather<Q, +1>(G, I, src, n.x, n.y, n.z, g);
+    gather<Q, +1>(src + I.st_off, plane, n.id, nb, g);
     if (G.bcx == BC_PRESSURE) {
         const long long f = I.face_off + (long long)n.z * I.ny + n.y;
         if (n.x == 0) zouhe<Q>(g, +1, face_in[f]);
@@ -37,9 +42,9 @@ __global__ void __launch_bounds__(BLOCK) k_step(Geo G, const float *__restrict__
     }
     const Moments m = moments<Q>(g);
     const float om = I.omega;
-    const long long o = I.st_off + ((long long)n.z * I.ny + n.y) * I.pitch + n.x;
+    float *__restrict__ out = dst + I.st_off;
 #pragma unroll
-    for (int i = 0; i < Q; ++i) dst[o + (long long)i * I.plane] = g[i] + om * (feq_shifted<Q>(i, m) - g[i]);
+    for (int i = 0; i < Q; ++i) out[i * plane + n.id] = g[i] + om * (feq_shifted<Q>(i, m) - g[i]);
 }
 
 // -------------------------------------------------------- loss functions --
@@ -67,6 +72,14 @@ __device__ inline float loss_node(int kind, float wgt, const float *u, const flo
     return wgt * l;
 }
 
+template <int Q>
+__device__ inline Moments load_moments(const float *__restrict__ F, const InstDev &I, int id) {
+    float g[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) g[i] = F[I.st_off + (long long)i * I.plane + id];
+    return moments<Q>(g);
+}
+
 // Loss on the final state (moments of F^T equal those of g^T: collision
 // conserves rho and j).  part[tile] = block sum.
 template <int Q>
@@ -79,21 +92,14 @@ __global__ void __launch_bounds__(BLOCK) k_loss(Geo G, const float *__restrict__
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const NodeRef n = map_node(G, tile);
     float l = 0.f;
-    if (n.inside) {
+    if (n.fluid) {
         const InstDev &I = G.inst[n.b];
-        if (!solid_at(G.mask, I, n.x, n.y, n.z)) {
-            const long long o = I.st_off + ((long long)n.z * I.ny + n.y) * I.pitch + n.x;
-            float g[Q];
+        const Moments m = load_moments<Q>(F, I, n.id);
+        const float u[3] = {m.ux, m.uy, m.uz};
+        float t[3] = {0.f, 0.f, 0.f}, d[3];
 #pragma unroll
-            for (int i = 0; i < Q; ++i) g[i] = F[o + (long long)i * I.plane];
-            const Moments m = moments<Q>(g);
-            const long long p = ((long long)n.z * I.ny + n.y) * I.pitch + n.x;
-            const float u[3] = {m.ux, m.uy, m.uz};
-            float t[3] = {0.f, 0.f, 0.f}, d[3];
-#pragma unroll
-            for (int a = 0; a < D; ++a) t[a] = target[I.poff * D + (long long)a * I.plane + p];
-            l = loss_node<D>(kind, roi[I.poff + p] * I.loss_scale, u, t, d);
-        }
+        for (int a = 0; a < D; ++a) t[a] = target[I.poff * D + (long long)a * I.plane + n.id];
+        l = loss_node<D>(kind, roi[I.poff + n.id] * I.loss_scale, u, t, d);
     }
     const double s = block_sum(l, lds);
     if (threadIdx.x == 0) part[tile] = s;
@@ -115,13 +121,17 @@ __global__ void __launch_bounds__(BLOCK) k_adj_seed(Geo G, const float *__restri
                                                     const float *__restrict__ seed_du) {
     constexpr int D = Vel<Q>::D;
     using V = Vel<Q>;
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    const NodeRef n = map_node(G, tile);
-    if (!n.inside) return;
-    const InstDev &I = G.inst[n.b];
-    if (solid_at(G.mask, I, n.x, n.y, n.z)) return;
+    __shared__ uint2 lds[NB_ENTRIES];
+    const BlockTile t = block_tile(G, xcd_tile(blockIdx.x, gridDim.x));
+    const InstDev &I = G.inst[t.b];
+    stage_rows(G, I, t, lds);
+    __syncthreads();
+    const Lane n = lane_of(I, t, lds);
+    if (!n.fluid) return;
+    int nb[Q];
+    neighbours<Q>(G, I, lds, t, n.x, n.y, n.ly, n.z, n.id, nb);
     float g[Q];
-    gather<Q, +1>(G, I, Fprev, n.x, n.y, n.z, g);
+    gather<Q, +1>(Fprev + I.st_off, (int)I.plane, n.id, nb, g);
     int face = 0;
     long long f = 0;
     if (G.bcx == BC_PRESSURE) {
@@ -137,11 +147,10 @@ __global__ void __launch_bounds__(BLOCK) k_adj_seed(Geo G, const float *__restri
 #pragma unroll
         for (int a = 0; a < D; ++a) dldu[a] = seed_du[dn * D + a];
     } else {
-        const long long p = ((long long)n.z * I.ny + n.y) * I.pitch + n.x;
         float t[3] = {0.f, 0.f, 0.f};
 #pragma unroll
-        for (int a = 0; a < D; ++a) t[a] = target[I.poff * D + (long long)a * I.plane + p];
-        loss_node<D>(kind, roi[I.poff + p] * I.loss_scale, u, t, dldu);
+        for (int a = 0; a < D; ++a) t[a] = target[I.poff * D + (long long)a * I.plane + n.id];
+        loss_node<D>(kind, roi[I.poff + n.id] * I.loss_scale, u, t, dldu);
     }
     const float inv = 1.0f / m.rho;
     float a[Q];
@@ -151,9 +160,9 @@ __global__ void __launch_bounds__(BLOCK) k_adj_seed(Geo G, const float *__restri
                       (D == 3 ? dldu[2] * (V::cz(i) - m.uz) : 0.f));
     if (face == 1) grad_in[f] += (double)zouhe_adj<Q>(a, +1);
     else if (face == -1) grad_out[f] += (double)zouhe_adj<Q>(a, -1);
-    const long long o = I.st_off + ((long long)n.z * I.ny + n.y) * I.pitch + n.x;
+    float *__restrict__ out = nu_out + I.st_off;
 #pragma unroll
-    for (int i = 0; i < Q; ++i) nu_out[o + (long long)i * I.plane] = a[i];
+    for (int i = 0; i < Q; ++i) out[i * (int)I.plane + n.id] = a[i];
 }
 
 // Adjoint step k: reads F^{k-1} (to rebuild g^k) and nu^{k+1}, writes nu^k;
@@ -167,17 +176,23 @@ __global__ void __launch_bounds__(BLOCK) k_adj_step(Geo G, const float *__restri
                                                     double *__restrict__ grad_in,
                                                     double *__restrict__ grad_out,
                                                     double *__restrict__ dtau_part) {
-    __shared__ double lds[4];
+    __shared__ double red[4];
+    __shared__ uint2 lds[NB_ENTRIES];
     using V = Vel<Q>;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    const NodeRef n = map_node(G, tile);
+    const BlockTile t = block_tile(G, tile);
+    const InstDev &I = G.inst[t.b];
+    stage_rows(G, I, t, lds);
+    __syncthreads();
+    const Lane n = lane_of(I, t, lds);
     float dtau = 0.f;
-    const InstDev &I = G.inst[n.b];
-    const bool active = n.inside && !solid_at(G.mask, I, n.x, n.y, n.z);
-    if (active) {
+    if (n.fluid) {
+        const int plane = (int)I.plane;
+        int nb[Q];
+        neighbours<Q>(G, I, lds, t, n.x, n.y, n.ly, n.z, n.id, nb);
         float g[Q], lam[Q];
-        gather<Q, +1>(G, I, Fprev, n.x, n.y, n.z, g);
-        gather<Q, -1>(G, I, nu_in, n.x, n.y, n.z, lam);
+        gather<Q, +1>(Fprev + I.st_off, plane, n.id, nb, g);
+        gather<Q, -1>(nu_in + I.st_off, plane, n.id, nb, lam);
         int face = 0;
         long long f = 0;
         if (G.bcx == BC_PRESSURE) {
@@ -207,11 +222,11 @@ __global__ void __launch_bounds__(BLOCK) k_adj_step(Geo G, const float *__restri
             a[i] = om1 * lam[i] + om * (A + Bx * V::cx(i) + By * V::cy(i) + Bz * V::cz(i));
         if (face == 1) grad_in[f] += (double)zouhe_adj<Q>(a, +1);
         else if (face == -1) grad_out[f] += (double)zouhe_adj<Q>(a, -1);
-        const long long o = I.st_off + ((long long)n.z * I.ny + n.y) * I.pitch + n.x;
+        float *__restrict__ out = nu_out + I.st_off;
 #pragma unroll
-        for (int i = 0; i < Q; ++i) nu_out[o + (long long)i * I.plane] = a[i];
+        for (int i = 0; i < Q; ++i) out[i * plane + n.id] = a[i];
     }
-    const double s = block_sum(dtau, lds);
+    const double s = block_sum(dtau, red);
     if (threadIdx.x == 0) dtau_part[tile] += s;
 }
 
@@ -219,64 +234,66 @@ __global__ void __launch_bounds__(BLOCK) k_adj_step(Geo G, const float *__restri
 template <int Q>
 __global__ void __launch_bounds__(BLOCK) k_adj_final(Geo G, const float *__restrict__ nu_in,
                                                      float *__restrict__ dense) {
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    const NodeRef n = map_node(G, tile);
+    __shared__ uint2 lds[NB_ENTRIES];
+    const BlockTile t = block_tile(G, xcd_tile(blockIdx.x, gridDim.x));
+    const InstDev &I = G.inst[t.b];
+    stage_rows(G, I, t, lds);
+    __syncthreads();
+    const Lane n = lane_of(I, t, lds);
     if (!n.inside) return;
-    const InstDev &I = G.inst[n.b];
     const long long nn = (long long)I.nx * I.ny * I.nz;
     const long long d0 = I.node_off * Q + ((long long)n.z * I.ny + n.y) * I.nx + n.x;
     float lam[Q];
-    const bool sol = solid_at(G.mask, I, n.x, n.y, n.z);
-    if (!sol) gather<Q, -1>(G, I, nu_in, n.x, n.y, n.z, lam);
+    if (n.fluid) {
+        int nb[Q];
+        neighbours<Q>(G, I, lds, t, n.x, n.y, n.ly, n.z, n.id, nb);
+        gather<Q, -1>(nu_in + I.st_off, (int)I.plane, n.id, nb, lam);
+    }
 #pragma unroll
-    for (int i = 0; i < Q; ++i) dense[d0 + i * nn] = sol ? 0.f : lam[i];
+    for (int i = 0; i < Q; ++i) dense[d0 + i * nn] = n.fluid ? lam[i] : 0.f;
 }
 
 // ------------------------------------------------------------ utilities --
 // Initial state: shifted equilibrium of (drho, u) (dense arrays, nullable =
-// rest) at fluid nodes, zero at solid nodes and in the row padding.
+// rest) at every fluid node.
 template <int Q>
 __global__ void __launch_bounds__(BLOCK) k_init_eq(Geo G, float *__restrict__ F,
                                                    const float *__restrict__ drho,
                                                    const float *__restrict__ u) {
     constexpr int D = Vel<Q>::D;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    NodeRef n = map_node(G, tile);
+    const NodeRef n = map_node(G, tile);
+    if (!n.fluid) return;
     const InstDev &I = G.inst[n.b];
-    if (n.x >= I.pitch || n.y >= I.ny) return;
-    const long long o = I.st_off + ((long long)n.z * I.ny + n.y) * I.pitch + n.x;
-    const bool fluid = n.inside && !solid_at(G.mask, I, n.x, n.y, n.z);
     Moments m = {0.f, 1.f, 0.f, 0.f, 0.f};
-    if (fluid) {
-        const long long dn = I.node_off + ((long long)n.z * I.ny + n.y) * I.nx + n.x;
-        if (drho) { m.drho = drho[dn]; m.rho = 1.0f + m.drho; }
-        if (u) {
-            m.ux = u[dn * D];
-            m.uy = u[dn * D + 1];
-            if (D == 3) m.uz = u[dn * D + 2];
-        }
+    const long long dn = dense_index(I, n);
+    if (drho) { m.drho = drho[dn]; m.rho = 1.0f + m.drho; }
+    if (u) {
+        m.ux = u[dn * D];
+        m.uy = u[dn * D + 1];
+        if (D == 3) m.uz = u[dn * D + 2];
     }
+    float *__restrict__ out = F + I.st_off + n.id;
 #pragma unroll
-    for (int i = 0; i < Q; ++i) F[o + (long long)i * I.plane] = fluid ? feq_shifted<Q>(i, m) : 0.f;
+    for (int i = 0; i < Q; ++i) out[(long long)i * I.plane] = feq_shifted<Q>(i, m);
 }
 
-// dense [inst][i][nz][ny][nx] <-> pitched state.  to_state: zero at solid
-// nodes and padding; from state: zero at solid nodes.
+// dense [inst][i][nz][ny][nx] <-> compact state.  to_state: fluid nodes only;
+// from state: zero at solid nodes.
 template <int Q>
 __global__ void __launch_bounds__(BLOCK) k_convert(Geo G, float *__restrict__ F,
                                                    float *__restrict__ dense, int to_state) {
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    NodeRef n = map_node(G, tile);
+    const NodeRef n = map_node(G, tile);
+    if (!n.inside) return;
     const InstDev &I = G.inst[n.b];
-    if (n.x >= I.pitch || n.y >= I.ny) return;
-    const long long o = I.st_off + ((long long)n.z * I.ny + n.y) * I.pitch + n.x;
-    const bool fluid = n.inside && !solid_at(G.mask, I, n.x, n.y, n.z);
     const long long nn = (long long)I.nx * I.ny * I.nz;
     const long long d0 = I.node_off * Q + ((long long)n.z * I.ny + n.y) * I.nx + n.x;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        if (to_state) F[o + (long long)i * I.plane] = fluid ? dense[d0 + i * nn] : 0.f;
-        else if (n.inside) dense[d0 + i * nn] = fluid ? F[o + (long long)i * I.plane] : 0.f;
+        const long long o = I.st_off + (long long)i * I.plane + n.id;
+        if (to_state) { if (n.fluid) F[o] = dense[d0 + i * nn]; }
+        else dense[d0 + i * nn] = n.fluid ? F[o] : 0.f;
     }
 }
 
@@ -291,19 +308,13 @@ __global__ void __launch_bounds__(BLOCK) k_macro(Geo G, const float *__restrict_
     const NodeRef n = map_node(G, tile);
     if (!n.inside) return;
     const InstDev &I = G.inst[n.b];
-    const long long dn = I.node_off + ((long long)n.z * I.ny + n.y) * I.nx + n.x;
+    const long long dn = dense_index(I, n);
     float r = 0.f, v[3] = {0.f, 0.f, 0.f};
-    if (!solid_at(G.mask, I, n.x, n.y, n.z)) {
-        const long long o = I.st_off + ((long long)n.z * I.ny + n.y) * I.pitch + n.x;
-        float g[Q];
-#pragma unroll
-        for (int i = 0; i < Q; ++i) g[i] = Fa[o + (long long)i * I.plane];
-        Moments m = moments<Q>(g);
+    if (n.fluid) {
+        Moments m = load_moments<Q>(Fa, I, n.id);
         r = m.drho; v[0] = m.ux; v[1] = m.uy; v[2] = m.uz;
         if (Fb) {
-#pragma unroll
-            for (int i = 0; i < Q; ++i) g[i] = Fb[o + (long long)i * I.plane];
-            m = moments<Q>(g);
+            m = load_moments<Q>(Fb, I, n.id);
             r = 0.5f * (r + m.drho);
             v[0] = 0.5f * (v[0] + m.ux); v[1] = 0.5f * (v[1] + m.uy); v[2] = 0.5f * (v[2] + m.uz);
         }
@@ -328,26 +339,18 @@ __global__ void __launch_bounds__(BLOCK) k_residual(Geo G, const float *__restri
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const NodeRef n = map_node(G, tile);
     float num = 0.f, den = 0.f;
-    if (n.inside) {
+    if (n.fluid) {
         const InstDev &I = G.inst[n.b];
-        if (!solid_at(G.mask, I, n.x, n.y, n.z)) {
-            const long long o = I.st_off + ((long long)n.z * I.ny + n.y) * I.pitch + n.x;
-            const long long dn = I.node_off + ((long long)n.z * I.ny + n.y) * I.nx + n.x;
-            float g[Q];
+        const long long dn = dense_index(I, n);
+        const Moments a = load_moments<Q>(Ft, I, n.id);
+        const Moments b = load_moments<Q>(Ft1, I, n.id);
+        const float ua[3] = {a.ux, a.uy, a.uz}, ub[3] = {b.ux, b.uy, b.uz};
 #pragma unroll
-            for (int i = 0; i < Q; ++i) g[i] = Ft[o + (long long)i * I.plane];
-            const Moments a = moments<Q>(g);
-#pragma unroll
-            for (int i = 0; i < Q; ++i) g[i] = Ft1[o + (long long)i * I.plane];
-            const Moments b = moments<Q>(g);
-            const float ua[3] = {a.ux, a.uy, a.uz}, ub[3] = {b.ux, b.uy, b.uz};
-#pragma unroll
-            for (int c = 0; c < D; ++c) {
-                const float d = ua[c] - u2[dn * D + c];
-                const float s = ua[c] + ub[c];
-                num += d * d;
-                den += s * s;
-            }
+        for (int c = 0; c < D; ++c) {
+            const float d = ua[c] - u2[dn * D + c];
+            const float s = ua[c] + ub[c];
+            num += d * d;
+            den += s * s;
         }
     }
     const double sn = block_sum(num, lds);

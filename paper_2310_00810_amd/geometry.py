@@ -79,7 +79,7 @@ def _paint_disk(solid, cx, cy, r):
 
 
 def rsa_disks(nx: int, ny: int, r_range=(6.0, 14.0), target_porosity=0.7, seed=0,
-              x_margin=4, gap=2.0, max_reject=100_000, max_reseed=20):
+              x_margin=4, gap=2.0, max_reject=100_000, max_reseed=20, batch=512):
     """2D solid mask (ny, nx) uint8 of non-overlapping disks.
 
     Disks are drawn with radius ~ U[r_range] and a real-valued centre such
@@ -87,33 +87,39 @@ def rsa_disks(nx: int, ny: int, r_range=(6.0, 14.0), target_porosity=0.7, seed=0
     nx-1-x_margin]; a candidate is rejected if its centre distance to any
     placed disk is below r1 + r2 + gap.  Disks are added until the porosity
     is at most target_porosity.  After max_reject consecutive rejections the
-    non-overlap rule is dropped (overlapping placement).  The mask must let
-    fluid percolate from inlet to outlet; otherwise the next seed of the
-    stream is used."""
+    non-overlap rule is dropped (overlapping placement).  Candidates are drawn
+    in batches and the first acceptable one of a batch is placed (the others
+    are discarded), which is random sequential addition with a different use
+    of the random stream.  The mask must let fluid percolate from inlet to
+    outlet; otherwise the next seed of the stream is used."""
     rng = np.random.default_rng(seed)
     for _ in range(max_reseed):
         solid = np.zeros((ny, nx), np.uint8)
-        cs = []
+        placed = np.zeros((0, 3))
         rejects = 0
         overlap_ok = False
         while porosity(solid) > target_porosity:
-            r = rng.uniform(*r_range)
+            r = rng.uniform(r_range[0], r_range[1], batch)
             lo_x, hi_x = x_margin + r, nx - 1 - x_margin - r
             lo_y, hi_y = r, ny - 1 - r
-            if hi_x < lo_x or hi_y < lo_y:
+            if np.any(hi_x < lo_x) or np.any(hi_y < lo_y):
                 raise ValueError("lattice too small for the grain radius")
-            cx, cy = rng.uniform(lo_x, hi_x), rng.uniform(lo_y, hi_y)
-            if not overlap_ok and cs:
-                arr = np.asarray(cs)
-                d2 = (arr[:, 0] - cx) ** 2 + (arr[:, 1] - cy) ** 2
-                if np.any(d2 < (arr[:, 2] + r + gap) ** 2):
-                    rejects += 1
+            cx = lo_x + (hi_x - lo_x) * rng.uniform(size=batch)
+            cy = lo_y + (hi_y - lo_y) * rng.uniform(size=batch)
+            if overlap_ok or placed.shape[0] == 0:
+                j = 0
+            else:
+                d2 = (placed[:, 0, None] - cx[None]) ** 2 + (placed[:, 1, None] - cy[None]) ** 2
+                ok = ~np.any(d2 < (placed[:, 2, None] + r[None] + gap) ** 2, axis=0)
+                if not ok.any():
+                    rejects += batch
                     if rejects >= max_reject:
                         overlap_ok = True
                     continue
-            rejects = 0
-            cs.append((cx, cy, r))
-            _paint_disk(solid, cx, cy, r)
+                j = int(np.argmax(ok))
+                rejects = 0 if j == 0 else rejects + j
+            placed = np.vstack([placed, [cx[j], cy[j], r[j]]])
+            _paint_disk(solid, cx[j], cy[j], r[j])
         if percolates(solid):
             return solid
     raise RuntimeError("no percolating packing found")

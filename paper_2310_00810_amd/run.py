@@ -1,0 +1,192 @@
+"""Drivers of the workloads: inverse runs, batched throughput, warm start.
+
+    python -m paper_2310_00810_amd.run c1|c2|c3|c4|c5 [--quick]
+
+Each prints one JSON line with its results.  The workloads are synthetic
+stand-ins for the paper's experiments (Section 3): channel and granular
+media with Zou-He pressure faces, inverse estimation of the inlet density
+(constant head, Section 3.1.1; per-node profile, Section 3.1.2), of the
+viscosity (Section 3.4) and the Darcy permeability along the optimisation
+path (Section 3.2, Eq. 12).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+import time
+
+import numpy as np
+import torch
+
+from . import geometry as G
+from . import inverse
+from .lbm import Instance, Solver
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def c1(quick=False):
+    """2D channel 64 x 32, tau = 0.8, 2000 steps: gradient of the mismatch to
+    the rho_in = 1.003 velocity field at rho_in = 1.005, and a constant-head
+    recovery from 1.0."""
+    nx, ny, T = 64, 32, 2000
+    s0 = Solver(9, [Instance(nx, ny)], steps=T)
+    s0.forward(0.8, 0.003, 0.0, want_loss=False)
+    _, ut = s0.macro()
+    tgt = ut.cpu().numpy().reshape(1, ny, nx, 2)
+    s = Solver(9, [Instance(nx, ny, target_u=tgt)], steps=T, tape=True)
+    p, h = inverse.recover_constant_head(s, 0.8, 0.005, max_iter=15, rtol=1e-4, true_drho=0.003)
+    return dict(config="C1", recovered_drho_in=p, true_drho_in=0.003, iterations=len(h.loss),
+                loss=[float(x) for x in h.loss], grad_first=float(h.grads[0]))
+
+
+def c2(quick=False):
+    """D2Q9 512 x 256, RSA disks r ~ U[6, 14], porosity 0.70, seed 2,
+    tau = 0.9, T = 10000, K = 500: recover rho_in (truth 1.004) from 1.0 by
+    gradient descent with Armijo backtracking; Darcy permeability fitted over
+    the iterates."""
+    nx, ny, T, K, tau = 512, 256, 10000, 500, 0.9
+    if quick:
+        T, K = 2000, 100
+    solid = G.rsa_disks(nx, ny, (6.0, 14.0), 0.70, seed=2)[None]
+    s0 = Solver(9, [Instance(nx, ny, solid=solid)], steps=T)
+    s0.forward(tau, 0.004, 0.0, want_loss=False)
+    _, ut = s0.macro()
+    tgt = ut.cpu().numpy().reshape(1, ny, nx, 2)
+    s = Solver(9, [Instance(nx, ny, solid=solid, target_u=tgt)], steps=T, ckpt_interval=K, tape=True)
+    t0 = time.time()
+    p, h = inverse.recover_constant_head(s, tau, 0.0, max_iter=30, rtol=1e-3, true_drho=0.004)
+    dt = time.time() - t0
+    nu = inverse.viscosity(tau)
+    # Darcy over the iterates (and the truth): superficial velocity vs pressure gradient
+    qs, gs, rhos = [], [], []
+    for d in sorted(set([float(x) for x in h.params] + [0.004])):
+        if d <= 0:
+            continue
+        s0.forward(tau, d, 0.0, want_loss=False)
+        drho, u = s0.macro(mean2=True)
+        fl = torch.from_numpy(solid.reshape(-1) == 0).cuda()
+        qs.append(float(u[:, 0].double().sum().item()) / (nx * ny))
+        gs.append(inverse.pressure_gradient(d, 0.0, nx))
+        rhos.append(1.0 + float(drho[fl].double().mean().item()))
+    k = inverse.darcy_permeability(qs, gs, float(np.mean(rhos)), nu)
+    return dict(config="C2", recovered_drho_in=p, true_drho_in=0.004, iterations=len(h.loss),
+                loss=[float(x) for x in h.loss], seconds=dt, darcy_k_lu2=k, porosity=G.porosity(solid),
+                darcy_points=len(qs))
+
+
+def c3(quick=False):
+    """D3Q19 128^3 Boolean spheres r ~ U[6, 10], porosity 0.40, periodic y/z,
+    inlet profile 1 + 0.004 phi (8 Fourier modes, seed 33), tau = 0.75,
+    T = 8000, K = 400: joint Adam recovery of the 16384-node profile and tau
+    from rho_in = 1.002, tau = 1.0 (MEAN_FLUID VEC loss)."""
+    n, T, K = 128, 8000, 400
+    iters = 20
+    if quick:
+        n, T, K, iters = 48, 1500, 100, 10
+    solid = G.boolean_spheres((n, n, n), (6.0, 10.0) if n >= 96 else (3.0, 5.0), 0.40, seed=3)
+    phi = G.fourier_profile(n, n, 8, seed=33)
+    din_true = 0.004 * phi
+    bc = ("pressure", "periodic", "periodic")
+    s0 = Solver(19, [Instance(n, n, n, solid=solid)], bc=bc, steps=T, inlet_mode="profile")
+    s0.forward(0.75, din_true.ravel(), 0.0, want_loss=False)
+    _, ut = s0.macro()
+    tgt = ut.cpu().numpy().reshape(n, n, n, 3)
+    del s0
+    s = Solver(19, [Instance(n, n, n, solid=solid, target_u=tgt)], bc=bc, steps=T, ckpt_interval=K, tape=True,
+               loss_scale="mean", inlet_mode="profile")
+    t0 = time.time()
+    p, tau, h = inverse.recover_profile_and_tau(s, 1.0, np.full(n * n, 0.002), iters=iters, lr_in=2e-4,
+                                                lr_tau=2e-2)
+    dt = time.time() - t0
+    rmse = float(np.sqrt(np.mean((p - din_true.ravel()) ** 2)))
+    ratio = float(np.mean(p) / np.mean(din_true)) / (inverse.viscosity(tau) / inverse.viscosity(0.75))
+    return dict(config="C3", size=n, T=T, iterations=iters, seconds=dt, loss=[float(x) for x in h.loss],
+                recovered_tau=tau, true_tau=0.75, profile_rmse=rmse,
+                profile_to_viscosity_ratio_rel=ratio)
+
+
+def c4(quick=False, n_inst=64, T=5000):
+    """64 D2Q9 instances (sizes from {128x64, 256x128, 512x256, 1024x512},
+    seeds 4000 + b, porosity U[0.5, 0.8], tau U[0.6, 1.2], rho_in - 1
+    U[0.001, 0.006]): forward + adjoint of all instances in one launch per
+    step (graph-replayed) against a loop of single-instance launches."""
+    if quick:
+        n_inst, T = 8, 500
+    sizes = [(128, 64), (256, 128), (512, 256), (1024, 512)]
+    insts, taus, dins = [], [], []
+    rng = np.random.default_rng(4000)
+    for b in range(n_inst):
+        r = np.random.default_rng(4000 + b)
+        nx, ny = sizes[r.integers(0, 4)]
+        phi = r.uniform(0.5, 0.8)
+        solid = G.rsa_disks(nx, ny, (6.0, 14.0), phi, seed=4000 + b, max_reject=20000)[None]
+        tgt = (1e-4 * rng.standard_normal((1, ny, nx, 2))).astype(np.float32)
+        insts.append(Instance(nx, ny, solid=solid, target_u=tgt))
+        taus.append(r.uniform(0.6, 1.2))
+        dins.append(r.uniform(0.001, 0.006))
+    nodes = sum(i.nodes for i in insts)
+    K = int(np.ceil(np.sqrt(T)))
+    log(f"[c4] {n_inst} instances, {nodes} nodes, T={T}, K={K}")
+    bs = Solver(9, insts, steps=T, ckpt_interval=K, tape=True)
+
+    def batched():
+        bs.forward(taus, dins, 0.0, record_tape=True)
+        bs.adjoint()
+        return bs.grad()
+
+    batched()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gb = batched()
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    del bs
+    torch.cuda.empty_cache()
+    singles = []
+    for k, ins in enumerate(insts):
+        s = Solver(9, [ins], steps=T, ckpt_interval=K, tape=True)
+        s.set_graphs(False)
+        singles.append(s)
+    for k, s in enumerate(singles[:1]):
+        s.forward(taus[k], dins[k], 0.0, record_tape=True)
+        s.adjoint()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gl = []
+    for k, s in enumerate(singles):
+        s.forward(taus[k], dins[k], 0.0, record_tape=True)
+        s.adjoint()
+        gl.append(s.grad())
+    torch.cuda.synchronize()
+    tl = time.perf_counter() - t0
+    same = all(gl[k]["dtau"][0] == gb["dtau"][k] and gl[k]["drho_in"][0] == gb["drho_in"][k] for k in range(n_inst))
+    return dict(config="C4", instances=n_inst, nodes=nodes, T=T, K=K,
+                batched_seconds=tb, loop_seconds=tl,
+                batched_fwd_adj_mlups=nodes * T / tb / 1e6, loop_fwd_adj_mlups=nodes * T / tl / 1e6,
+                speedup=tl / tb, gradients_bitwise_equal=bool(same))
+
+
+def c5(quick=False):
+    from . import warmstart
+    sys.argv = [sys.argv[0], "--dims", "2", "--train", "64" if quick else "2000", "--val", "16" if quick else "200",
+                "--test", "4" if quick else "30", "--epochs", "3" if quick else "30"]
+    warmstart.main()
+    return None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("config", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--quick", action="store_true")
+    a = ap.parse_args()
+    res = globals()[a.config](quick=a.quick)
+    if res is not None:
+        print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -16,7 +16,6 @@ Prints ONE JSON line.  value = forward+adjoint MLUPS (all lattice nodes x T
 per second of the whole gradient evaluation).
 """
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -48,14 +47,6 @@ def workload(n=128, T=8000, K=400, kind="spheres"):
                 bc=("pressure", "periodic", "periodic"), kind=kind)
 
 
-def kernel_source_hash():
-    h = hashlib.sha256()
-    for f in ("lbm_device.hpp", "lbm_kernels.hip"):
-        with open(os.path.join(ROOT, "paper_2310_00810_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
-
-
 def load_traffic(kernel):
     """HBM bytes per launch from the committed rocprofv3 --pmc summary of this
     kernel, if it was taken on the current kernel source; else None."""
@@ -66,6 +57,7 @@ def load_traffic(kernel):
         d = json.load(open(p))
     except Exception:
         return None
+    from paper_2310_00810_amd.profiling import kernel_source_hash
     e = d.get(kernel)
     if not e or e.get("source_hash") != kernel_source_hash():
         return None

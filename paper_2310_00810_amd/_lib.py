@@ -7,7 +7,9 @@ import ctypes
 import os
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-LIBPATH = os.path.join(PKG, "liblbm.so")
+# LBM_LIBRARY may name another build of the same library (e.g. a variant
+# under evaluation); by default the in-tree build is loaded.
+LIBPATH = os.environ.get("LBM_LIBRARY") or os.path.join(PKG, "liblbm.so")
 
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_ESTATE, LBM_EUNSTABLE, LBM_ECORRUPT, LBM_EDEVICE = 0, -1, -2, -3, -4, -5, -6
 LBM_D2Q9, LBM_D3Q19 = 9, 19

@@ -1,0 +1,98 @@
+"""Summaries of rocprofv3 output for the committed profiles.
+
+    python -m paper_2310_00810_amd.profiling trace <stats.csv> <out.md> "<command>"
+    python -m paper_2310_00810_amd.profiling traffic <fetch_counters.csv> <write_counters.csv> \
+        <copy_bytes> <out.json> <out.md> "<command>"
+
+`trace` turns a `--kernel-trace --stats --output-format csv` kernel-stats file
+into a Markdown table.  `traffic` turns two `--pmc FETCH_SIZE` / `--pmc
+WRITE_SIZE` counter-collection files into HBM bytes per launch of each LBM
+kernel.  Each counter is scaled by what it reads for the largest plain copy
+kernel in the same run (a device-to-device copy of `copy_bytes` bytes: it
+reads and writes exactly that many bytes), so FETCH_SIZE / WRITE_SIZE units
+and granularity drop out.  The JSON carries the hash of the kernel sources it
+was measured on; the benchmark reports the figure only while that hash still
+matches.
+"""
+import csv
+import collections
+import hashlib
+import json
+import os
+import sys
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCES = ("lbm_device.hpp", "lbm_kernels.hip")
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(PKG, "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def short_name(name):
+    n = name.split("(")[0]
+    for pre in ("void ", "lbm::", "nn::"):
+        n = n.replace(pre, "")
+    return n
+
+
+def trace(stats_csv, out_md, command):
+    rows = list(csv.DictReader(open(stats_csv)))
+    with open(out_md, "w") as f:
+        f.write(f"# rocprofv3 kernel statistics\n\nCommand:\n\n    {command}\n\n")
+        f.write("| kernel | calls | total (us) | average (us) | min (us) | max (us) | % |\n|---|---|---|---|---|---|---|\n")
+        for r in rows[:20]:
+            f.write(f"| `{short_name(r['Name'])}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e3:.0f} | "
+                    f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['MinNs']) / 1e3:.2f} | "
+                    f"{float(r['MaxNs']) / 1e3:.2f} | {float(r['Percentage']):.2f} |\n")
+
+
+def _per_kernel(path):
+    agg = collections.defaultdict(list)
+    copies = []
+    for r in csv.DictReader(open(path)):
+        v = float(r["Counter_Value"])
+        name = r["Kernel_Name"]
+        if "copyBuffer" in name:
+            copies.append(v)
+        agg[short_name(name)].append(v)
+    return agg, max(copies) if copies else None
+
+
+def traffic(fetch_csv, write_csv, copy_bytes, out_json, out_md, command):
+    fa, fcopy = _per_kernel(fetch_csv)
+    wa, wcopy = _per_kernel(write_csv)
+    if not fcopy or not wcopy:
+        raise SystemExit("no copy kernel in the counter runs")
+    fs, ws = copy_bytes / fcopy, copy_bytes / wcopy
+    out = {"source_hash": kernel_source_hash(), "copy_bytes": copy_bytes,
+           "fetch_scale_bytes_per_unit": fs, "write_scale_bytes_per_unit": ws, "command": command}
+    lines = []
+    for k in sorted(fa):
+        if not (k.startswith("k_step") or k.startswith("k_adj")):
+            continue
+        fb = sum(fa[k]) / len(fa[k]) * fs
+        wb = sum(wa.get(k, [0])) / max(len(wa.get(k, [1])), 1) * ws
+        out[k] = {"fetch_bytes": fb, "write_bytes": wb, "bytes_per_launch": fb + wb, "launches": len(fa[k]),
+                  "source_hash": out["source_hash"]}
+        lines.append(f"| `{k}` | {len(fa[k])} | {fb / 1e6:.1f} | {wb / 1e6:.1f} | {(fb + wb) / 1e6:.1f} |")
+    json.dump(out, open(out_json, "w"), indent=1)
+    with open(out_md, "w") as f:
+        f.write("# HBM traffic per launch (rocprofv3 FETCH_SIZE / WRITE_SIZE)\n\n")
+        f.write(f"Commands (two runs, one counter each):\n\n    {command}\n\n")
+        f.write(f"Calibration: the largest device copy in the run moves {copy_bytes / 2**30:.0f} GiB each way; "
+                f"FETCH_SIZE scale {fs:.1f} B/unit, WRITE_SIZE scale {ws:.1f} B/unit.  Kernel source hash "
+                f"{out['source_hash']}.\n\n")
+        f.write("| kernel | launches | fetched MB | written MB | total MB |\n|---|---|---|---|---|\n")
+        f.write("\n".join(lines) + "\n")
+
+
+if __name__ == "__main__":
+    if sys.argv[1] == "trace":
+        trace(sys.argv[2], sys.argv[3], sys.argv[4])
+    elif sys.argv[1] == "traffic":
+        traffic(sys.argv[2], sys.argv[3], float(sys.argv[4]), sys.argv[5], sys.argv[6], sys.argv[7])

@@ -47,13 +47,13 @@ inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 struct Layout {
     int q = 9, D = 2, n_inst = 0;
     int T = 1, K = 1, n_seg = 1, tape = 0;
-    int n_tiles = 0;
+    int n_tiles = 0, n_ftiles = 0;
     long long total_poff = 0, total_nodes = 0, total_face = 0, total_words = 0;
     long long S = 0;          // floats per state buffer
     int n_states = 0;
     size_t off_inst = 0, off_mask = 0, off_roi = 0, off_target = 0, off_face_in = 0, off_face_out = 0,
            off_grad_in = 0, off_grad_out = 0, off_part_loss = 0, off_part_dtau = 0, off_part_res = 0,
-           off_red = 0, off_u2 = 0, off_seed = 0, off_states = 0, state_bytes = 0, total = 0;
+           off_red = 0, off_fblk = 0, off_u2 = 0, off_seed = 0, off_states = 0, state_bytes = 0, total = 0;
     std::vector<InstDev> inst;
 };
 
@@ -112,7 +112,7 @@ void plan(const lbm_problem *p, Layout &L) {
     L.tape = p->tape ? 1 : 0;
     L.inst.assign(p->n_inst, InstDev{});
     long long poff = 0, node = 0, face = 0, words = 0;
-    int tile = 0;
+    int tile = 0, ftile = 0;
     for (int b = 0; b < p->n_inst; ++b) {
         const lbm_instance &S = p->inst[b];
         InstDev &I = L.inst[b];
@@ -124,6 +124,9 @@ void plan(const lbm_problem *p, Layout &L) {
         I.tile_begin = tile;
         tile += I.n_tiles;
         I.n_fluid = (int)count_fluid(S);
+        I.n_ftiles = (I.n_fluid + lbm::FT - 1) / lbm::FT;
+        I.ftile_begin = ftile;
+        ftile += I.n_ftiles;
         // one plane per population direction over the fluid nodes, padded to 256 B
         I.plane = std::max<long long>(64, (long long)align_up((size_t)I.n_fluid, 64));
         I.poff = poff;
@@ -140,6 +143,7 @@ void plan(const lbm_problem *p, Layout &L) {
         I.loss_scale = 1.0f;
     }
     L.n_tiles = tile;
+    L.n_ftiles = ftile;
     L.total_poff = poff;
     L.total_nodes = node;
     L.total_face = face;
@@ -157,9 +161,10 @@ void plan(const lbm_problem *p, Layout &L) {
     L.off_grad_in = take(sizeof(double) * face);
     L.off_grad_out = take(sizeof(double) * face);
     L.off_part_loss = take(sizeof(double) * L.n_tiles);
-    L.off_part_dtau = take(sizeof(double) * L.n_tiles);
+    L.off_part_dtau = take(sizeof(double) * std::max(1, L.n_ftiles));
     L.off_part_res = take(sizeof(double) * 2 * L.n_tiles);
     L.off_red = take(sizeof(double) * 2 * p->n_inst);
+    L.off_fblk = take(sizeof(int2) * std::max(1, L.n_ftiles));
     L.off_u2 = take(sizeof(float) * node * L.D);
     L.off_seed = take(sizeof(float) * node * L.D);
     L.state_bytes = align_up(sizeof(float) * (size_t)L.S, 256);
@@ -295,9 +300,9 @@ int with_graph(lbm_handle *h, hipGraphExec_t &slot, F &&enqueue) {
     return LBM_OK;
 }
 
-int reduce_to_host(lbm_handle *h, size_t part_off, int stride) {
+int reduce_to_host(lbm_handle *h, size_t part_off, int stride, int fluid) {
     const Layout &L = h->L;
-    HIP_TRY(lbm::launch_reduce(h->at<InstDev>(L.off_inst), L.n_inst, h->at<double>(part_off), stride,
+    HIP_TRY(lbm::launch_reduce(h->at<InstDev>(L.off_inst), L.n_inst, h->at<double>(part_off), stride, fluid,
                                h->at<double>(L.off_red), h->stream));
     h->h_red.assign((size_t)L.n_inst * stride, 0.0);
     HIP_TRY(hipMemcpyAsync(h->h_red.data(), h->at<double>(L.off_red), sizeof(double) * L.n_inst * stride,
@@ -383,6 +388,29 @@ int lbm_init(lbm_handle **out, const lbm_problem *p, void *d_workspace, size_t b
                 }
         I.loss_scale = p->loss_scale == LBM_SCALE_MEAN_FLUID ? (id ? (float)(1.0 / (double)id) : 0.f) : 1.0f;
     }
+    // per fluid tile: the instance-local row words holding its first and last fluid id
+    std::vector<int2> fblk(std::max(1, L.n_ftiles), make_int2(0, 0));
+    for (int b = 0; b < L.n_inst; ++b) {
+        const InstDev &I = h->hinst[b];
+        const long long nw = (long long)I.nz * I.ny * I.words;
+        long long w = 0;
+        for (int t = 0; t < I.n_ftiles; ++t) {
+            const long long first = (long long)t * lbm::FT;
+            const long long last = std::min<long long>(first + lbm::FT, I.n_fluid) - 1;
+            int2 &e = fblk[I.ftile_begin + t];
+            // word holding id k: the last word whose first id is <= k and that has a fluid node
+            auto holds = [&](long long ww, long long k) {
+                const uint2 r = rw[I.rw_off + ww];
+                const long long nf = __builtin_popcount(~r.x);
+                return (long long)r.y <= k && k < (long long)r.y + nf;
+            };
+            while (w < nw && !holds(w, first)) ++w;
+            e.x = (int)w;
+            long long w1 = w;
+            while (w1 < nw && !holds(w1, last)) ++w1;
+            e.y = (int)w1;
+        }
+    }
     auto cp = [&](size_t off, const void *src, size_t n) -> int {
         if (!n) return LBM_OK;
         HIP_TRY(hipMemcpyAsync(h->ws + off, src, n, hipMemcpyHostToDevice, h->stream));
@@ -391,6 +419,7 @@ int lbm_init(lbm_handle **out, const lbm_problem *p, void *d_workspace, size_t b
     int e = 0;
     if ((e = cp(L.off_inst, h->hinst.data(), sizeof(InstDev) * L.n_inst)) ||
         (e = cp(L.off_mask, rw.data(), sizeof(uint2) * rw.size())) ||
+        (e = cp(L.off_fblk, fblk.data(), sizeof(int2) * fblk.size())) ||
         (e = cp(L.off_roi, roi.data(), sizeof(float) * roi.size())) ||
         (e = cp(L.off_target, target.data(), sizeof(float) * target.size()))) {
         delete h;
@@ -401,6 +430,8 @@ int lbm_init(lbm_handle **out, const lbm_problem *p, void *d_workspace, size_t b
     h->G.n_tiles = L.n_tiles;
     h->G.bcx = p->bc_x; h->G.bcy = p->bc_y; h->G.bcz = p->bc_z;
     h->G.rw = h->at<uint2>(L.off_mask);
+    h->G.n_ftiles = L.n_ftiles;
+    h->G.fblk = h->at<int2>(L.off_fblk);
     hipError_t he = lbm::launch_init_eq(L.q, h->G, h->init(), nullptr, nullptr, h->stream);
     if (he == hipSuccess) he = hipStreamSynchronize(h->stream);
     if (he != hipSuccess) {
@@ -454,7 +485,7 @@ int lbm_get_populations(lbm_handle *h, int which, float *d_out) {
     }
     if (which == LBM_POP_ADJOINT) {
         if (!h->adjoint_done) return fail(LBM_ESTATE, "no adjoint has been computed");
-        HIP_TRY(lbm::launch_adj_final(h->L.q, h->G, h->nu_last, d_out, h->stream));
+        HIP_TRY(lbm::launch_adj_final(h->L.q, h->G, h->nu_last, d_out, h->L.total_nodes * h->L.q, h->stream));
         return LBM_OK;
     }
     return fail(LBM_EINVAL, "unknown population kind %d", which);
@@ -508,7 +539,7 @@ int lbm_forward(lbm_handle *h, const lbm_params *prm, int record_tape, double *l
     if (loss_out) {
         HIP_TRY(lbm::launch_loss(L.q, h->G, h->cur, h->at<float>(L.off_roi), h->at<float>(L.off_target),
                                  h->P.loss_kind, h->at<double>(L.off_part_loss), h->stream));
-        if ((rc = reduce_to_host(h, L.off_part_loss, 1))) return rc;
+        if ((rc = reduce_to_host(h, L.off_part_loss, 1, 0))) return rc;
         bool finite = true;
         for (int b = 0; b < L.n_inst; ++b) {
             loss_out[b] = h->h_red[b];
@@ -533,7 +564,7 @@ static int enqueue_reverse(lbm_handle *h, bool recompute_last, const float *seed
     const int q = L.q, T = L.T, K = L.K;
     HIP_TRY(lbm::launch_fill_f64(h->at<double>(L.off_grad_in), L.total_face, 0.0, s));
     HIP_TRY(lbm::launch_fill_f64(h->at<double>(L.off_grad_out), L.total_face, 0.0, s));
-    HIP_TRY(lbm::launch_fill_f64(h->at<double>(L.off_part_dtau), L.n_tiles, 0.0, s));
+    HIP_TRY(lbm::launch_fill_f64(h->at<double>(L.off_part_dtau), L.n_ftiles, 0.0, s));
     const float *fin = h->at<float>(L.off_face_in), *fout = h->at<float>(L.off_face_out);
     double *gin = h->at<double>(L.off_grad_in), *gout = h->at<double>(L.off_grad_out);
     double *dpart = h->at<double>(L.off_part_dtau);
@@ -604,7 +635,7 @@ int lbm_grad(lbm_handle *h, double *d_rho_in, double *d_tau, double *d_rho_out) 
     if (!h) return fail(LBM_EINVAL, "handle is NULL");
     if (!h->adjoint_done) return fail(LBM_ESTATE, "lbm_grad needs a preceding lbm_adjoint");
     const Layout &L = h->L;
-    int rc = reduce_to_host(h, L.off_part_dtau, 1);
+    int rc = reduce_to_host(h, L.off_part_dtau, 1, 1);
     if (rc) return rc;
     std::vector<double> gin(L.total_face), gout(L.total_face);
     if (L.total_face) {
@@ -651,7 +682,7 @@ static int enqueue_chunk(lbm_handle *h, const float *src, int check_every, hipSt
         src = dst;
     }
     HIP_TRY(lbm::launch_residual(L.q, h->G, src, prev, u2, h->at<double>(L.off_part_res), s));
-    HIP_TRY(lbm::launch_reduce(h->at<InstDev>(L.off_inst), L.n_inst, h->at<double>(L.off_part_res), 2,
+    HIP_TRY(lbm::launch_reduce(h->at<InstDev>(L.off_inst), L.n_inst, h->at<double>(L.off_part_res), 2, 0,
                                h->at<double>(L.off_red), s));
     return LBM_OK;
 }

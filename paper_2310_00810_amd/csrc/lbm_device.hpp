@@ -75,7 +75,8 @@ template <> struct Vel<19> {
 // ---------------------------------------------------------------------------
 struct InstDev {
     int nx, ny, nz, words;
-    int tiles_x, tiles_y, tile_begin, n_tiles;
+    int tiles_x, tiles_y, tile_begin, n_tiles;   // dense 64 x 4 node tiles
+    int ftile_begin, n_ftiles;                   // fluid tiles of FT nodes
     long long plane;       // floats per population plane (fluid nodes, padded)
     long long poff;        // offset of the instance in per-node (fluid) arrays
     long long st_off;      // float offset of the instance in a state buffer = Q * poff
@@ -94,6 +95,8 @@ struct Geo {
     int n_tiles;
     int bcx, bcy, bcz;
     const uint2 *rw;       // row-word tables
+    int n_ftiles;
+    const int2 *fblk;      // per fluid tile: instance-local row words {w0, w1}
 };
 
 // Block index -> tile index such that the blocks the hardware places on one
@@ -158,109 +161,148 @@ __device__ inline long long dense_index(const InstDev &I, const NodeRef &n) {
 }
 
 // ---------------------------------------------------------------------------
-// Neighbourhood of a block.  A block covers x in [x0, x0 + 64) of four rows
-// y0 .. y0 + 3 at one z.  Its nodes' neighbours lie in rows y0 - 1 .. y0 + 4
-// at z - 1 .. z + 1, words (x0 >> 5) - 1 .. (x0 >> 5) + 2: 3 x 6 x 4 row
-// words, staged once per block in LDS (wrapped on periodic axes, all-solid
-// beyond walls and outside the row).
+// Fluid tiles.  The stepping kernels give every lane one fluid node: block t
+// of an instance takes the fluid ids [FT t, FT t + FT), so all lanes of a
+// wavefront do useful work at any porosity and every store of a block is one
+// contiguous run per population plane.  The ids of a block lie in a
+// contiguous range of row words [w0, w1] (fblk, built at init), i.e. in rows
+// r0 .. r1 (r = z ny + y).  Their neighbours lie in rows r - 1 .. r + 1 of
+// the planes z - 1, z, z + 1, which are the row windows
+//   [r0 - 1 + dz ny, r1 + 1 + dz ny]  (mod ny nz)
+// of the linear row order.  A block stages these windows in LDS when they
+// fit (NBW words); a y link that wraps around a periodic y axis leaves the
+// window and reads its row word from global memory, as does every link of a
+// block whose windows do not fit.  The z wrap of a periodic z axis is exact
+// in the linear order because y + dy stays inside [0, ny) there.
 // ---------------------------------------------------------------------------
-constexpr int NB_ROWS_Y = TILE_Y + 2, NB_WORDS = 4;
-constexpr int NB_ENTRIES = 3 * NB_ROWS_Y * NB_WORDS;
+constexpr int FT = 256;          // fluid nodes (threads) per block
+constexpr int NBW = 1024;        // staged row words per block (8 KB)
 
-struct BlockTile {
-    int b, x0, y0, z;
+struct FTile {
+    int b;                 // instance
+    int tile;              // global fluid-tile index
+    int id0;               // first fluid id of the block
+    int w0, w1;            // instance-local row words holding ids id0 .. id0 + FT - 1
+    int r0;                // row of w0
+    int rows;              // rows per staged window: r1 - r0 + 3
+    int cdz;               // window of the block's own plane (1 in 3D, 0 in 2D)
+    bool staged;
 };
 
-__device__ inline BlockTile block_tile(const Geo &G, int tile) {
-    BlockTile t;
-    t.b = G.n_inst == 1 ? 0 : find_inst(G.inst, G.n_inst, tile);
-    const InstDev &I = G.inst[t.b];
-    const int lt = tile - I.tile_begin;
-    const int tx = lt % I.tiles_x, rest = lt / I.tiles_x;
-    t.x0 = tx * TILE_X;
-    t.y0 = (rest % I.tiles_y) * TILE_Y;
-    t.z = rest / I.tiles_y;
+template <int D>
+__device__ inline FTile fluid_tile(const Geo &G, int tile) {
+    FTile t;
+    t.tile = tile;
+    int lo = 0;
+    if (G.n_inst > 1) {
+        int hi = G.n_inst - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (G.inst[mid].ftile_begin <= tile) lo = mid; else hi = mid - 1;
+        }
+    }
+    t.b = lo;
+    const InstDev &I = G.inst[lo];
+    t.id0 = (tile - I.ftile_begin) * FT;
+    const int2 wr = G.fblk[tile];
+    t.w0 = wr.x;
+    t.w1 = wr.y;
+    t.r0 = t.w0 / I.words;
+    t.rows = t.w1 / I.words - t.r0 + 3;
+    t.cdz = D == 3 ? 1 : 0;
+    t.staged = (D == 3 ? 3 : 1) * t.rows * I.words <= NBW;
     return t;
 }
 
-__device__ inline void stage_rows(const Geo &G, const InstDev &I, const BlockTile &t, uint2 *lds) {
-    for (int e = threadIdx.x; e < NB_ENTRIES; e += BLOCK) {
-        const int ws = e % NB_WORDS, r = e / NB_WORDS;
-        int yy = t.y0 - 1 + r % NB_ROWS_Y, zz = t.z - 1 + r / NB_ROWS_Y;
-        const int w = (t.x0 >> 5) - 1 + ws;
-        bool ok = w >= 0 && w < I.words;
-        if (yy < 0 || yy >= I.ny) {
-            if (G.bcy == BC_PERIODIC) yy = ((yy % I.ny) + I.ny) % I.ny;
-            else ok = false;
-        }
-        if (zz < 0 || zz >= I.nz) {
-            if (G.bcz == BC_PERIODIC) zz = ((zz % I.nz) + I.nz) % I.nz;
-            else ok = false;
-        }
-        lds[e] = ok ? G.rw[I.rw_off + ((long long)zz * I.ny + yy) * I.words + w] : make_uint2(0xffffffffu, 0u);
+template <int D>
+__device__ inline void stage_windows(const Geo &G, const InstDev &I, const FTile &t, uint2 *lds) {
+    const int per = t.rows * I.words;
+    const int n = (D == 3 ? 3 : 1) * per;
+    const int R = I.ny * I.nz;
+    for (int e = threadIdx.x; e < n; e += FT) {
+        const int win = e / per, rem = e - win * per;
+        const int j = rem / I.words, wi = rem - j * I.words;
+        int rr = (t.r0 - 1 + j + (win - t.cdz) * I.ny) % R;
+        rr += rr < 0 ? R : 0;
+        lds[e] = G.rw[I.rw_off + (long long)rr * I.words + wi];
     }
 }
 
-// Staged row word of the node at (x + dx, ly + dy, dz) relative to a lane at
-// x with block row ly (x + dx must lie in [x0 - 1, x0 + 64]).
-__device__ inline uint2 staged(const uint2 *lds, const BlockTile &t, int xs, int ly, int dy, int dz) {
-    return lds[((dz + 1) * NB_ROWS_Y + ly + 1 + dy) * NB_WORDS + ((xs >> 5) - (t.x0 >> 5) + 1)];
+// Row word w (instance-local) of the block's own rows.
+__device__ inline uint2 own_word(const Geo &G, const InstDev &I, const FTile &t, const uint2 *lds, int w) {
+    return t.staged ? lds[(t.cdz * t.rows + 1) * I.words + (w - t.r0 * I.words)] : G.rw[I.rw_off + w];
+}
+
+// Position of the k-th (0-based) set bit of m (m has more than k set bits).
+__device__ inline int kth_set_bit(uint32_t m, int k) {
+    int pos = 0;
+#pragma unroll
+    for (int s = 16; s > 0; s >>= 1) {
+        const int c = __popc(m & ((1u << s) - 1u));
+        if (k >= c) { k -= c; m >>= s; pos += s; }
+    }
+    return pos;
+}
+
+struct FLane {
+    int id, x, y, z, r;
+    bool active;           // id < number of fluid nodes of the instance
+};
+
+// The lane's fluid node: the last word of [w0, w1] whose first id is <= id
+// holds it; its position in the word is the matching fluid bit.
+__device__ inline FLane fluid_lane(const Geo &G, const InstDev &I, const FTile &t, const uint2 *lds) {
+    FLane l;
+    l.id = t.id0 + (int)threadIdx.x;
+    l.active = l.id < I.n_fluid;
+    l.x = l.y = l.z = l.r = 0;
+    if (!l.active) return l;
+    int lo = t.w0, hi = t.w1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if ((int)own_word(G, I, t, lds, mid).y <= l.id) lo = mid; else hi = mid - 1;
+    }
+    const uint2 w = own_word(G, I, t, lds, lo);
+    const int bit = kth_set_bit(~w.x, l.id - (int)w.y);
+    l.r = lo / I.words;
+    l.x = (lo - l.r * I.words) * 32 + bit;
+    l.y = l.r % I.ny;
+    l.z = l.r / I.ny;
+    return l;
 }
 
 enum { NB_WALL = -1, NB_OPEN = -2 };
-
-// A lane of a block: its node, and whether that node is a fluid node of the
-// lattice (own word read from the staged neighbourhood).
-struct Lane {
-    int x, y, ly, z;
-    bool inside, fluid;
-    int id;
-};
-
-__device__ inline Lane lane_of(const InstDev &I, const BlockTile &t, const uint2 *lds) {
-    Lane l;
-    l.ly = threadIdx.x / TILE_X;
-    l.x = t.x0 + (threadIdx.x & (TILE_X - 1));
-    l.y = t.y0 + l.ly;
-    l.z = t.z;
-    l.inside = l.x < I.nx && l.y < I.ny;
-    const uint2 w = staged(lds, t, l.x, l.ly, 0, 0);
-    l.fluid = l.inside && !solid_bit(w, l.x);
-    l.id = fluid_id(w, l.x);
-    return l;
-}
 
 // For every link k: the fluid id of node x + c_k, NB_WALL if that node is
 // solid or lies beyond a wall (halfway bounce-back), NB_OPEN if it lies
 // beyond a pressure face.  nb[0] is the node's own id.
 template <int Q>
-__device__ inline void neighbours(const Geo &G, const InstDev &I, const uint2 *lds, const BlockTile &t,
-                                  int x, int y, int ly, int z, int id, int (&nb)[Q]) {
+__device__ inline void neighbours(const Geo &G, const InstDev &I, const FTile &t, const uint2 *lds,
+                                  const FLane &l, int (&nb)[Q]) {
     using V = Vel<Q>;
-    nb[0] = id;
+    nb[0] = l.id;
 #pragma unroll
     for (int k = 1; k < Q; ++k) {
         const int dx = V::cx(k), dy = V::cy(k), dz = V::cz(k);
-        int xs = x + dx;
-        bool open = false, wall = false, wrap_x = false;
+        int xs = l.x + dx, ys = l.y + dy, zs = l.z + dz;
+        bool open = false, wall = false, far = !t.staged;
         if (dx != 0 && (xs < 0 || xs >= I.nx)) {
-            if (G.bcx == BC_PERIODIC) { xs = xs < 0 ? xs + I.nx : xs - I.nx; wrap_x = true; }
+            if (G.bcx == BC_PERIODIC) xs = xs < 0 ? xs + I.nx : xs - I.nx;
             else if (G.bcx == BC_PRESSURE) open = true;
             else wall = true;
         }
-        if (dy != 0 && (y + dy < 0 || y + dy >= I.ny) && G.bcy != BC_PERIODIC) wall = true;
-        if (dz != 0 && (z + dz < 0 || z + dz >= I.nz) && G.bcz != BC_PERIODIC) wall = true;
+        if (dy != 0 && (ys < 0 || ys >= I.ny)) {
+            if (G.bcy == BC_PERIODIC) { ys = ys < 0 ? ys + I.ny : ys - I.ny; far = true; }
+            else wall = true;
+        }
+        if (dz != 0 && (zs < 0 || zs >= I.nz)) {
+            if (G.bcz == BC_PERIODIC) zs = zs < 0 ? zs + I.nz : zs - I.nz;
+            else wall = true;
+        }
         if (open) { nb[k] = NB_OPEN; continue; }
         if (wall) { nb[k] = NB_WALL; continue; }
-        uint2 w;
-        if (wrap_x) {
-            int ys = y + dy, zs = z + dz;
-            ys = ys < 0 ? ys + I.ny : (ys >= I.ny ? ys - I.ny : ys);
-            zs = zs < 0 ? zs + I.nz : (zs >= I.nz ? zs - I.nz : zs);
-            w = row_word(G, I, xs, ys, zs);
-        } else {
-            w = staged(lds, t, xs, ly, dy, dz);
-        }
+        const uint2 w = far ? G.rw[I.rw_off + ((long long)zs * I.ny + ys) * I.words + (xs >> 5)]
+                            : lds[((t.cdz + dz) * t.rows + (l.r - t.r0 + 1 + dy)) * I.words + (xs >> 5)];
         nb[k] = solid_bit(w, xs) ? NB_WALL : fluid_id(w, xs);
     }
 }
@@ -373,7 +415,7 @@ __device__ inline float wave_sum(float v) {
     return v;
 }
 
-// Block (256-thread) sum into double; the result is valid in thread 0.
+// Block (4 wavefronts) sum into double; the result is valid in thread 0.
 __device__ inline double block_sum(float v, double *lds4) {
     v = wave_sum(v);
     if ((threadIdx.x & 63) == 0) lds4[threadIdx.x >> 6] = (double)v;
@@ -383,5 +425,6 @@ __device__ inline double block_sum(float v, double *lds4) {
     __syncthreads();
     return s;
 }
+static_assert(BLOCK == 256 && FT == 256, "block_sum assumes four wavefronts");
 
 }  // namespace lbm

@@ -19,19 +19,20 @@ namespace lbm {
 
 // ------------------------------------------------------------------ step --
 template <int Q>
-__global__ void __launch_bounds__(BLOCK) k_step(Geo G, const float *__restrict__ src,
-                                                float *__restrict__ dst,
-                                                const float *__restrict__ face_in,
-                                                const float *__restrict__ face_out) {
-    __shared__ uint2 lds[NB_ENTRIES];
-    const BlockTile t = block_tile(G, xcd_tile(blockIdx.x, gridDim.x));
+__global__ void __launch_bounds__(FT) k_step(Geo G, const float *__restrict__ src,
+                                             float *__restrict__ dst,
+                                             const float *__restrict__ face_in,
+                                             const float *__restrict__ face_out) {
+    constexpr int D = Vel<Q>::D;
+    __shared__ uint2 lds[NBW];
+    const FTile t = fluid_tile<D>(G, xcd_tile(blockIdx.x, gridDim.x));
     const InstDev &I = G.inst[t.b];
-    stage_rows(G, I, t, lds);
+    if (t.staged) stage_windows<D>(G, I, t, lds);
     __syncthreads();
-    const Lane n = lane_of(I, t, lds);
-    if (!n.fluid) return;
+    const FLane n = fluid_lane(G, I, t, lds);
+    if (!n.active) return;
     int nb[Q];
-    neighbours<Q>(G, I, lds, t, n.x, n.y, n.ly, n.z, n.id, nb);
+    neighbours<Q>(G, I, t, lds, n, nb);
     const int plane = (int)I.plane;
     float g[Q];
     gather<Q, +1>(src + I.st_off, plane, n.id, nb, g);
@@ -110,7 +111,7 @@ __global__ void __launch_bounds__(BLOCK) k_loss(Geo G, const float *__restrict__
 // seed_du (nullable) replaces the built-in loss by a caller-given dL/du(T)
 // in the dense layout [node][D].
 template <int Q>
-__global__ void __launch_bounds__(BLOCK) k_adj_seed(Geo G, const float *__restrict__ Fprev,
+__global__ void __launch_bounds__(FT) k_adj_seed(Geo G, const float *__restrict__ Fprev,
                                                     float *__restrict__ nu_out,
                                                     const float *__restrict__ face_in,
                                                     const float *__restrict__ face_out,
@@ -121,15 +122,15 @@ __global__ void __launch_bounds__(BLOCK) k_adj_seed(Geo G, const float *__restri
                                                     const float *__restrict__ seed_du) {
     constexpr int D = Vel<Q>::D;
     using V = Vel<Q>;
-    __shared__ uint2 lds[NB_ENTRIES];
-    const BlockTile t = block_tile(G, xcd_tile(blockIdx.x, gridDim.x));
+    __shared__ uint2 lds[NBW];
+    const FTile t = fluid_tile<D>(G, xcd_tile(blockIdx.x, gridDim.x));
     const InstDev &I = G.inst[t.b];
-    stage_rows(G, I, t, lds);
+    if (t.staged) stage_windows<D>(G, I, t, lds);
     __syncthreads();
-    const Lane n = lane_of(I, t, lds);
-    if (!n.fluid) return;
+    const FLane n = fluid_lane(G, I, t, lds);
+    if (!n.active) return;
     int nb[Q];
-    neighbours<Q>(G, I, lds, t, n.x, n.y, n.ly, n.z, n.id, nb);
+    neighbours<Q>(G, I, t, lds, n, nb);
     float g[Q];
     gather<Q, +1>(Fprev + I.st_off, (int)I.plane, n.id, nb, g);
     int face = 0;
@@ -168,7 +169,7 @@ __global__ void __launch_bounds__(BLOCK) k_adj_seed(Geo G, const float *__restri
 // Adjoint step k: reads F^{k-1} (to rebuild g^k) and nu^{k+1}, writes nu^k;
 // accumulates dL/dtau per tile and dL/d(drho_b) per face node.
 template <int Q>
-__global__ void __launch_bounds__(BLOCK) k_adj_step(Geo G, const float *__restrict__ Fprev,
+__global__ void __launch_bounds__(FT) k_adj_step(Geo G, const float *__restrict__ Fprev,
                                                     const float *__restrict__ nu_in,
                                                     float *__restrict__ nu_out,
                                                     const float *__restrict__ face_in,
@@ -176,20 +177,20 @@ __global__ void __launch_bounds__(BLOCK) k_adj_step(Geo G, const float *__restri
                                                     double *__restrict__ grad_in,
                                                     double *__restrict__ grad_out,
                                                     double *__restrict__ dtau_part) {
+    constexpr int D = Vel<Q>::D;
     __shared__ double red[4];
-    __shared__ uint2 lds[NB_ENTRIES];
+    __shared__ uint2 lds[NBW];
     using V = Vel<Q>;
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    const BlockTile t = block_tile(G, tile);
+    const FTile t = fluid_tile<D>(G, xcd_tile(blockIdx.x, gridDim.x));
     const InstDev &I = G.inst[t.b];
-    stage_rows(G, I, t, lds);
+    if (t.staged) stage_windows<D>(G, I, t, lds);
     __syncthreads();
-    const Lane n = lane_of(I, t, lds);
+    const FLane n = fluid_lane(G, I, t, lds);
     float dtau = 0.f;
-    if (n.fluid) {
+    if (n.active) {
         const int plane = (int)I.plane;
         int nb[Q];
-        neighbours<Q>(G, I, lds, t, n.x, n.y, n.ly, n.z, n.id, nb);
+        neighbours<Q>(G, I, t, lds, n, nb);
         float g[Q], lam[Q];
         gather<Q, +1>(Fprev + I.st_off, plane, n.id, nb, g);
         gather<Q, -1>(nu_in + I.st_off, plane, n.id, nb, lam);
@@ -227,30 +228,30 @@ __global__ void __launch_bounds__(BLOCK) k_adj_step(Geo G, const float *__restri
         for (int i = 0; i < Q; ++i) out[i * plane + n.id] = a[i];
     }
     const double s = block_sum(dtau, red);
-    if (threadIdx.x == 0) dtau_part[tile] += s;
+    if (threadIdx.x == 0) dtau_part[t.tile] += s;
 }
 
-// dL/dF^0 = S^T nu^1 in the dense layout [inst][i][nz][ny][nx].
+// dL/dF^0 = S^T nu^1 in the dense layout [inst][i][nz][ny][nx], fluid nodes
+// only (the caller zeroes the solid entries).
 template <int Q>
-__global__ void __launch_bounds__(BLOCK) k_adj_final(Geo G, const float *__restrict__ nu_in,
-                                                     float *__restrict__ dense) {
-    __shared__ uint2 lds[NB_ENTRIES];
-    const BlockTile t = block_tile(G, xcd_tile(blockIdx.x, gridDim.x));
+__global__ void __launch_bounds__(FT) k_adj_final(Geo G, const float *__restrict__ nu_in,
+                                                  float *__restrict__ dense) {
+    constexpr int D = Vel<Q>::D;
+    __shared__ uint2 lds[NBW];
+    const FTile t = fluid_tile<D>(G, xcd_tile(blockIdx.x, gridDim.x));
     const InstDev &I = G.inst[t.b];
-    stage_rows(G, I, t, lds);
+    if (t.staged) stage_windows<D>(G, I, t, lds);
     __syncthreads();
-    const Lane n = lane_of(I, t, lds);
-    if (!n.inside) return;
+    const FLane n = fluid_lane(G, I, t, lds);
+    if (!n.active) return;
     const long long nn = (long long)I.nx * I.ny * I.nz;
     const long long d0 = I.node_off * Q + ((long long)n.z * I.ny + n.y) * I.nx + n.x;
+    int nb[Q];
+    neighbours<Q>(G, I, t, lds, n, nb);
     float lam[Q];
-    if (n.fluid) {
-        int nb[Q];
-        neighbours<Q>(G, I, lds, t, n.x, n.y, n.ly, n.z, n.id, nb);
-        gather<Q, -1>(nu_in + I.st_off, (int)I.plane, n.id, nb, lam);
-    }
+    gather<Q, -1>(nu_in + I.st_off, (int)I.plane, n.id, nb, lam);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) dense[d0 + i * nn] = n.fluid ? lam[i] : 0.f;
+    for (int i = 0; i < Q; ++i) dense[d0 + i * nn] = lam[i];
 }
 
 // ------------------------------------------------------------ utilities --
@@ -360,13 +361,15 @@ __global__ void __launch_bounds__(BLOCK) k_residual(Geo G, const float *__restri
 
 // Per-instance sums of per-tile partials (stride values per tile):
 // out[b * stride + k] = sum over the instance's tiles of part[tile * stride + k].
+// fluid != 0 sums over the instance's fluid tiles instead of its dense tiles.
 __global__ void __launch_bounds__(256) k_reduce(const InstDev *inst, const double *__restrict__ part,
-                                                int stride, double *__restrict__ out) {
+                                                int stride, int fluid, double *__restrict__ out) {
     __shared__ double s[256];
     const InstDev &I = inst[blockIdx.x];
+    const int begin = fluid ? I.ftile_begin : I.tile_begin, count = fluid ? I.n_ftiles : I.n_tiles;
     for (int k = 0; k < stride; ++k) {
         double acc = 0.0;
-        for (int t = threadIdx.x; t < I.n_tiles; t += 256) acc += part[(long long)(I.tile_begin + t) * stride + k];
+        for (int t = threadIdx.x; t < count; t += 256) acc += part[(long long)(begin + t) * stride + k];
         s[threadIdx.x] = acc;
         __syncthreads();
         for (int w = 128; w > 0; w >>= 1) {
@@ -383,13 +386,20 @@ __global__ void k_fill_f64(double *p, long long n, double v) {
     if (i < n) p[i] = v;
 }
 
+__global__ void k_fill_f32(float *p, long long n, float v) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
 // ------------------------------------------------------ launch wrappers --
 static inline dim3 grid_of(const Geo &G) { return dim3((unsigned)G.n_tiles); }
+static inline dim3 fgrid_of(const Geo &G) { return dim3((unsigned)G.n_ftiles); }
 
 template <int Q>
 static hipError_t launch_step_q(const Geo &G, const float *src, float *dst, const float *fin,
                                 const float *fout, hipStream_t s) {
-    hipLaunchKernelGGL(k_step<Q>, grid_of(G), dim3(BLOCK), 0, s, G, src, dst, fin, fout);
+    if (G.n_ftiles == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_step<Q>, fgrid_of(G), dim3(FT), 0, s, G, src, dst, fin, fout);
     return hipGetLastError();
 }
 
@@ -409,11 +419,12 @@ hipError_t launch_loss(int q, const Geo &G, const float *F, const float *roi, co
 hipError_t launch_adj_seed(int q, const Geo &G, const float *Fprev, float *nu_out, const float *fin,
                            const float *fout, double *gin, double *gout, const float *roi,
                            const float *target, int kind, const float *seed, hipStream_t s) {
+    if (G.n_ftiles == 0) return hipSuccess;
     if (q == 9)
-        hipLaunchKernelGGL(k_adj_seed<9>, grid_of(G), dim3(BLOCK), 0, s, G, Fprev, nu_out, fin, fout,
+        hipLaunchKernelGGL(k_adj_seed<9>, fgrid_of(G), dim3(FT), 0, s, G, Fprev, nu_out, fin, fout,
                            gin, gout, roi, target, kind, seed);
     else
-        hipLaunchKernelGGL(k_adj_seed<19>, grid_of(G), dim3(BLOCK), 0, s, G, Fprev, nu_out, fin, fout,
+        hipLaunchKernelGGL(k_adj_seed<19>, fgrid_of(G), dim3(FT), 0, s, G, Fprev, nu_out, fin, fout,
                            gin, gout, roi, target, kind, seed);
     return hipGetLastError();
 }
@@ -421,18 +432,22 @@ hipError_t launch_adj_seed(int q, const Geo &G, const float *Fprev, float *nu_ou
 hipError_t launch_adj_step(int q, const Geo &G, const float *Fprev, const float *nu_in, float *nu_out,
                            const float *fin, const float *fout, double *gin, double *gout,
                            double *dtau_part, hipStream_t s) {
+    if (G.n_ftiles == 0) return hipSuccess;
     if (q == 9)
-        hipLaunchKernelGGL(k_adj_step<9>, grid_of(G), dim3(BLOCK), 0, s, G, Fprev, nu_in, nu_out, fin,
+        hipLaunchKernelGGL(k_adj_step<9>, fgrid_of(G), dim3(FT), 0, s, G, Fprev, nu_in, nu_out, fin,
                            fout, gin, gout, dtau_part);
     else
-        hipLaunchKernelGGL(k_adj_step<19>, grid_of(G), dim3(BLOCK), 0, s, G, Fprev, nu_in, nu_out, fin,
+        hipLaunchKernelGGL(k_adj_step<19>, fgrid_of(G), dim3(FT), 0, s, G, Fprev, nu_in, nu_out, fin,
                            fout, gin, gout, dtau_part);
     return hipGetLastError();
 }
 
-hipError_t launch_adj_final(int q, const Geo &G, const float *nu_in, float *dense, hipStream_t s) {
-    if (q == 9) hipLaunchKernelGGL(k_adj_final<9>, grid_of(G), dim3(BLOCK), 0, s, G, nu_in, dense);
-    else hipLaunchKernelGGL(k_adj_final<19>, grid_of(G), dim3(BLOCK), 0, s, G, nu_in, dense);
+hipError_t launch_adj_final(int q, const Geo &G, const float *nu_in, float *dense, long long n_dense,
+                            hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)((n_dense + 255) / 256)), dim3(256), 0, s, dense, n_dense, 0.f);
+    if (G.n_ftiles == 0) return hipGetLastError();
+    if (q == 9) hipLaunchKernelGGL(k_adj_final<9>, fgrid_of(G), dim3(FT), 0, s, G, nu_in, dense);
+    else hipLaunchKernelGGL(k_adj_final<19>, fgrid_of(G), dim3(FT), 0, s, G, nu_in, dense);
     return hipGetLastError();
 }
 
@@ -463,9 +478,9 @@ hipError_t launch_residual(int q, const Geo &G, const float *Ft, const float *Ft
     return hipGetLastError();
 }
 
-hipError_t launch_reduce(const InstDev *inst, int n_inst, const double *part, int stride, double *out,
-                         hipStream_t s) {
-    hipLaunchKernelGGL(k_reduce, dim3(n_inst), dim3(256), 0, s, inst, part, stride, out);
+hipError_t launch_reduce(const InstDev *inst, int n_inst, const double *part, int stride, int fluid,
+                         double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce, dim3(n_inst), dim3(256), 0, s, inst, part, stride, fluid, out);
     return hipGetLastError();
 }
 

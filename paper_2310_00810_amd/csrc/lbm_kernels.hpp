@@ -15,7 +15,9 @@ hipError_t launch_adj_seed(int q, const Geo &G, const float *Fprev, float *nu_ou
 hipError_t launch_adj_step(int q, const Geo &G, const float *Fprev, const float *nu_in, float *nu_out,
                            const float *fin, const float *fout, double *gin, double *gout,
                            double *dtau_part, hipStream_t s);
-hipError_t launch_adj_final(int q, const Geo &G, const float *nu_in, float *dense, hipStream_t s);
+// Zeroes the n_dense floats of dense, then writes the fluid entries.
+hipError_t launch_adj_final(int q, const Geo &G, const float *nu_in, float *dense, long long n_dense,
+                            hipStream_t s);
 hipError_t launch_init_eq(int q, const Geo &G, float *F, const float *drho, const float *u,
                           hipStream_t s);
 hipError_t launch_convert(int q, const Geo &G, float *F, float *dense, int to_state, hipStream_t s);
@@ -23,8 +25,9 @@ hipError_t launch_macro(int q, const Geo &G, const float *Fa, const float *Fb, f
                         hipStream_t s);
 hipError_t launch_residual(int q, const Geo &G, const float *Ft, const float *Ft1, const float *u2,
                            double *part, hipStream_t s);
-hipError_t launch_reduce(const InstDev *inst, int n_inst, const double *part, int stride, double *out,
-                         hipStream_t s);
+// fluid != 0: partials per fluid tile (dtau), else per dense tile.
+hipError_t launch_reduce(const InstDev *inst, int n_inst, const double *part, int stride, int fluid,
+                         double *out, hipStream_t s);
 hipError_t launch_fill_f64(double *p, long long n, double v, hipStream_t s);
 
 }  // namespace lbm

@@ -61,3 +61,34 @@ def tiny_lattices():
     s3ww[1, 1, 2] = 1
     out.append(("d3q19_wall_yz", O.Lattice(19, 5, 4, 3, (O.BC_PRESSURE, O.BC_WALL, O.BC_WALL), s3ww)))
     return out
+
+
+def multi_tile_lattices():
+    """Lattices of many 256-node fluid tiles: random solids (isolated fluid
+    nodes, grains on the faces), rows wider than a block's staged
+    neighbourhood (D2Q9 16384 wide), very sparse boxes whose tiles span many
+    rows (both read their neighbours' row words from global memory), x and y
+    wrap-around, and a one-plane periodic D3Q19 box."""
+    import oracle as O
+    rng = np.random.default_rng(77)
+    out = []
+
+    def rand(shape, frac, clear_inlet=False):
+        s = (rng.random(shape) < frac).astype(np.uint8)
+        if clear_inlet:
+            s[:, :, 0] = 0
+        return s
+
+    out.append(("d2q9_wide_rows", O.Lattice(9, 16384, 4, 1, (O.BC_PRESSURE, O.BC_PERIODIC, O.BC_PERIODIC),
+                                            rand((1, 4, 16384), 0.4))))
+    out.append(("d2q9_periodic_x", O.Lattice(9, 300, 40, 1, (O.BC_PERIODIC, O.BC_WALL, O.BC_PERIODIC),
+                                             rand((1, 40, 300), 0.4))))
+    out.append(("d3q19_sparse", O.Lattice(19, 200, 16, 16, (O.BC_PRESSURE, O.BC_PERIODIC, O.BC_PERIODIC),
+                                          rand((16, 16, 200), 0.9))))
+    out.append(("d3q19_wide_rows", O.Lattice(19, 4096, 4, 3, (O.BC_PRESSURE, O.BC_PERIODIC, O.BC_PERIODIC),
+                                             rand((3, 4, 4096), 0.5))))
+    out.append(("d3q19_walls", O.Lattice(19, 40, 24, 20, (O.BC_PRESSURE, O.BC_WALL, O.BC_PERIODIC),
+                                         rand((20, 24, 40), 0.5))))
+    out.append(("d3q19_one_plane", O.Lattice(19, 70, 30, 1, (O.BC_PRESSURE, O.BC_PERIODIC, O.BC_PERIODIC),
+                                             rand((1, 30, 70), 0.3))))
+    return out

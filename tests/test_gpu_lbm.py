@@ -9,7 +9,7 @@ import pytest
 
 import oracle as O
 from paper_2310_00810_amd import geometry as G
-from tests.conftest import tiny_lattices
+from tests.conftest import multi_tile_lattices, tiny_lattices
 
 pytestmark = pytest.mark.gpu
 
@@ -65,7 +65,7 @@ def f32(x):
 
 
 # ---------------------------------------------------------------- forward --
-@pytest.mark.parametrize("name,lat", tiny_lattices())
+@pytest.mark.parametrize("name,lat", tiny_lattices() + multi_tile_lattices())
 @pytest.mark.parametrize("T", [1, 3])
 def test_steps_from_random_state(name, lat, T):
     """T steps from a random non-equilibrium state, all boundary kinds."""
@@ -160,7 +160,12 @@ def test_c1_gradient_parity(kind):
     assert rel_l2(g["dtau"], [go["dtau"]]) <= 1e-3
 
 
-@pytest.mark.parametrize("name,lat", tiny_lattices())
+def _driven(lats):
+    """Lattices with Zou-He faces (the others stay at rest: zero gradients)."""
+    return [(n, l) for n, l in lats if l.bc_tuple[0] == O.BC_PRESSURE]
+
+
+@pytest.mark.parametrize("name,lat", _driven(tiny_lattices() + multi_tile_lattices()))
 def test_tiny_profile_gradients(name, lat):
     """Per-node inlet profile gradients, dL/dtau and dL/drho_out on the tiny
     lattices (walls, periodic axes, grains touching the faces), T = 40."""
@@ -188,7 +193,7 @@ def test_tiny_profile_gradients(name, lat):
     assert rel_l2(g["drho_out"], [go["drho_out"].sum()]) <= 1e-3
 
 
-@pytest.mark.parametrize("name,lat", tiny_lattices())
+@pytest.mark.parametrize("name,lat", tiny_lattices() + multi_tile_lattices())
 @pytest.mark.parametrize("T", [1, 2, 3])
 def test_adjoint_of_initial_state(name, lat, T):
     """dL/dF^0 from the GPU reverse sweep against the oracle's stage

@@ -228,9 +228,13 @@ __device__ inline void stage_windows(const Geo &G, const InstDev &I, const FTile
     }
 }
 
-// Row word w (instance-local) of the block's own rows.
-__device__ inline uint2 own_word(const Geo &G, const InstDev &I, const FTile &t, const uint2 *lds, int w) {
-    return t.staged ? lds[(t.cdz * t.rows + 1) * I.words + (w - t.r0 * I.words)] : G.rw[I.rw_off + w];
+// LDS view of the staged row words.  Reading through an address-space-3
+// pointer keeps these reads ds_read instructions: with a generic pointer the
+// compiler may merge an LDS read and a global read into one flat load.
+typedef __attribute__((address_space(3))) const unsigned long long lds_u64;
+__device__ inline uint2 lds_read(const uint2 *lds, unsigned e) {
+    const unsigned long long v = ((lds_u64 *)lds)[e];
+    return make_uint2((unsigned)v, (unsigned)(v >> 32));
 }
 
 // Position of the k-th (0-based) set bit of m (m has more than k set bits).
@@ -250,7 +254,9 @@ struct FLane {
 };
 
 // The lane's fluid node: the last word of [w0, w1] whose first id is <= id
-// holds it; its position in the word is the matching fluid bit.
+// holds it; its position in the word is the matching fluid bit.  Staged
+// blocks search their LDS copy of the words, the others global memory (two
+// separate loops, so that each keeps its own memory instructions).
 __device__ inline FLane fluid_lane(const Geo &G, const InstDev &I, const FTile &t, const uint2 *lds) {
     FLane l;
     l.id = t.id0 + (int)threadIdx.x;
@@ -258,11 +264,22 @@ __device__ inline FLane fluid_lane(const Geo &G, const InstDev &I, const FTile &
     l.x = l.y = l.z = l.r = 0;
     if (!l.active) return l;
     int lo = t.w0, hi = t.w1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if ((int)own_word(G, I, t, lds, mid).y <= l.id) lo = mid; else hi = mid - 1;
+    uint2 w;
+    if (t.staged) {
+        const int base = (t.cdz * t.rows + 1) * I.words - t.r0 * I.words;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if ((int)lds_read(lds, base + mid).y <= l.id) lo = mid; else hi = mid - 1;
+        }
+        w = lds_read(lds, base + lo);
+    } else {
+        const uint2 *own = G.rw + I.rw_off;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if ((int)own[mid].y <= l.id) lo = mid; else hi = mid - 1;
+        }
+        w = own[lo];
     }
-    const uint2 w = own_word(G, I, t, lds, lo);
     const int bit = kth_set_bit(~w.x, l.id - (int)w.y);
     l.r = lo / I.words;
     l.x = (lo - l.r * I.words) * 32 + bit;
@@ -273,37 +290,57 @@ __device__ inline FLane fluid_lane(const Geo &G, const InstDev &I, const FTile &
 
 enum { NB_WALL = -1, NB_OPEN = -2 };
 
+// A coordinate at most one step outside [0, n) wrapped back inside.
+__device__ inline int wrap1(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
 // For every link k: the fluid id of node x + c_k, NB_WALL if that node is
 // solid or lies beyond a wall (halfway bounce-back), NB_OPEN if it lies
-// beyond a pressure face.  nb[0] is the node's own id.
+// beyond a pressure face.  nb[0] is the node's own id.  A straight-line pass
+// reads every link's row word from the staged windows (index clamped into
+// the LDS array, so the read is always legal); lanes with links that wrap a
+// periodic y axis, and every lane of an unstaged block, then redo those
+// links from the global row words.  Coordinates are wrapped for indexing
+// only: the boundary kind decides what the link means.
 template <int Q>
 __device__ inline void neighbours(const Geo &G, const InstDev &I, const FTile &t, const uint2 *lds,
                                   const FLane &l, int (&nb)[Q]) {
     using V = Vel<Q>;
     nb[0] = l.id;
+    const int W = I.words;
+    const int lrow = (t.cdz * t.rows + (l.r - t.r0 + 1)) * W;
+    const int wstep = t.rows * W;
 #pragma unroll
     for (int k = 1; k < Q; ++k) {
         const int dx = V::cx(k), dy = V::cy(k), dz = V::cz(k);
-        int xs = l.x + dx, ys = l.y + dy, zs = l.z + dz;
-        bool open = false, wall = false, far = !t.staged;
-        if (dx != 0 && (xs < 0 || xs >= I.nx)) {
-            if (G.bcx == BC_PERIODIC) xs = xs < 0 ? xs + I.nx : xs - I.nx;
-            else if (G.bcx == BC_PRESSURE) open = true;
-            else wall = true;
+        const int xr = l.x + dx, yr = l.y + dy, zr = l.z + dz;
+        const bool xout = dx != 0 && (xr < 0 || xr >= I.nx);
+        const bool yout = dy != 0 && (yr < 0 || yr >= I.ny);
+        const bool zout = dz != 0 && (zr < 0 || zr >= I.nz);
+        const int xs = dx != 0 ? wrap1(xr, I.nx) : xr;
+        const bool open = xout && G.bcx == BC_PRESSURE;
+        const bool wall = (xout && G.bcx == BC_WALL) || (yout && G.bcy != BC_PERIODIC) ||
+                          (zout && G.bcz != BC_PERIODIC);
+        const unsigned e = (unsigned)(lrow + dz * wstep + dy * W + (xs >> 5));
+        const uint2 w = lds_read(lds, e < (unsigned)NBW ? e : 0u);
+        const int id = solid_bit(w, xs) ? NB_WALL : fluid_id(w, xs);
+        nb[k] = open ? NB_OPEN : (wall ? NB_WALL : id);
+    }
+    const bool yedge = G.bcy == BC_PERIODIC && (l.y == 0 || l.y == I.ny - 1);
+    if (!t.staged || yedge) {
+#pragma unroll
+        for (int k = 1; k < Q; ++k) {
+            const int dx = V::cx(k), dy = V::cy(k), dz = V::cz(k);
+            const int xr = l.x + dx, yr = l.y + dy, zr = l.z + dz;
+            const bool yout = dy != 0 && (yr < 0 || yr >= I.ny);
+            if (nb[k] == NB_OPEN || (t.staged && !yout)) continue;
+            if ((yout && G.bcy != BC_PERIODIC) || (dz != 0 && (zr < 0 || zr >= I.nz) && G.bcz != BC_PERIODIC) ||
+                (dx != 0 && (xr < 0 || xr >= I.nx) && G.bcx == BC_WALL))
+                continue;   // beyond a wall: already NB_WALL
+            const int xs = dx != 0 ? wrap1(xr, I.nx) : xr;
+            const int ys = dy != 0 ? wrap1(yr, I.ny) : yr, zs = dz != 0 ? wrap1(zr, I.nz) : zr;
+            const uint2 w = G.rw[I.rw_off + ((long long)zs * I.ny + ys) * W + (xs >> 5)];
+            nb[k] = solid_bit(w, xs) ? NB_WALL : fluid_id(w, xs);
         }
-        if (dy != 0 && (ys < 0 || ys >= I.ny)) {
-            if (G.bcy == BC_PERIODIC) { ys = ys < 0 ? ys + I.ny : ys - I.ny; far = true; }
-            else wall = true;
-        }
-        if (dz != 0 && (zs < 0 || zs >= I.nz)) {
-            if (G.bcz == BC_PERIODIC) zs = zs < 0 ? zs + I.nz : zs - I.nz;
-            else wall = true;
-        }
-        if (open) { nb[k] = NB_OPEN; continue; }
-        if (wall) { nb[k] = NB_WALL; continue; }
-        const uint2 w = far ? G.rw[I.rw_off + ((long long)zs * I.ny + ys) * I.words + (xs >> 5)]
-                            : lds[((t.cdz + dz) * t.rows + (l.r - t.r0 + 1 + dy)) * I.words + (xs >> 5)];
-        nb[k] = solid_bit(w, xs) ? NB_WALL : fluid_id(w, xs);
     }
 }
 

@@ -80,6 +80,8 @@ int validate_problem(const lbm_problem *p) {
         if (I.nx < 1 || I.ny < 1 || I.nz < 1)
             return fail(LBM_EINVAL, "instance %d: dimensions must be positive (%d x %d x %d)", b, I.nx, I.ny, I.nz);
         if (p->lattice == LBM_D2Q9 && I.nz != 1) return fail(LBM_EINVAL, "instance %d: D2Q9 needs nz = 1", b);
+        if (I.nx >= (1 << lbm::X_BITS))
+            return fail(LBM_EINVAL, "instance %d: nx must be below %d (got %d)", b, 1 << lbm::X_BITS, I.nx);
         if (p->bc_x == LBM_BC_PRESSURE && I.nx < 2)
             return fail(LBM_EINVAL, "instance %d: a pressure x axis needs nx >= 2", b);
         if ((long long)I.nx * I.ny * I.nz * p->lattice >= (1LL << 31) - (1LL << 20))

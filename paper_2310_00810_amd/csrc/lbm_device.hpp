@@ -1,5 +1,6 @@
 // Device-side definitions of the MI355X lattice Boltzmann kernels: velocity
-// sets, per-instance descriptors, tile mapping and the fused pull gather.
+// sets, per-instance descriptors, fluid-tile mapping, links, the pull
+// gathers and the Zou-He closure.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -168,15 +169,25 @@ __device__ inline long long dense_index(const InstDev &I, const NodeRef &n) {
 // contiguous range of row words [w0, w1] (fblk, built at init), i.e. in rows
 // r0 .. r1 (r = z ny + y).  Their neighbours lie in rows r - 1 .. r + 1 of
 // the planes z - 1, z, z + 1, which are the row windows
-//   [r0 - 1 + dz ny, r1 + 1 + dz ny]  (mod ny nz)
+//   [r0 - 1 + dz ny, r1 + 1 + dz ny]        dz = -1, 0, 1 (3D), 0 (2D)
 // of the linear row order.  A block stages these windows in LDS when they
-// fit (NBW words); a y link that wraps around a periodic y axis leaves the
-// window and reads its row word from global memory, as does every link of a
-// block whose windows do not fit.  The z wrap of a periodic z axis is exact
-// in the linear order because y + dy stays inside [0, ny) there.
+// fit (NBW words).  Staging wraps a window row around a periodic z axis and
+// replaces it by an all-solid word beyond a z wall, so that a lane reads the
+// row word of every link from LDS without any z test: the linear order is
+// exact for every neighbour with y + dy inside [0, ny).  Lanes on the first
+// or last y row, and all lanes of a block whose windows do not fit, take
+// their links from the global row words instead.
 // ---------------------------------------------------------------------------
 constexpr int FT = 256;          // fluid nodes (threads) per block
 constexpr int NBW = 1024;        // staged row words per block (8 KB)
+constexpr int X_BITS = 20;       // lane position word: (own row << X_BITS) | x
+constexpr int SCATTER_WORDS = 64;
+
+struct TileLds {
+    uint2 word[NBW];             // staged row windows
+    int pos[FT];                 // per lane: position of its fluid node
+    unsigned char yedge[NBW];    // per centre-window row: first or last y row
+};
 
 struct FTile {
     int b;                 // instance
@@ -214,27 +225,62 @@ __device__ inline FTile fluid_tile(const Geo &G, int tile) {
     return t;
 }
 
+// floor(a / d) for 0 <= a < 2^20, given inv = 1 / d: the float estimate of
+// (a + 1/2) / d is within 1/(4d) of the exact value, which lies at least
+// 1/(2d) from an integer.
+__device__ inline int small_div(int a, float inv) { return (int)(((float)a + 0.5f) * inv); }
+
+// LDS reads of the staged row words go through an address-space-3 pointer:
+// with a generic pointer the compiler may merge an LDS read and a global
+// read into one flat load.
+typedef __attribute__((address_space(3))) const unsigned long long lds_u64;
+__device__ inline uint2 lds_read(const uint2 *lds, int e) {
+    const unsigned long long v = ((lds_u64 *)lds)[e];
+    return make_uint2((unsigned)v, (unsigned)(v >> 32));
+}
+
 template <int D>
-__device__ inline void stage_windows(const Geo &G, const InstDev &I, const FTile &t, uint2 *lds) {
-    const int per = t.rows * I.words;
-    const int n = (D == 3 ? 3 : 1) * per;
+__device__ inline void stage_windows(const Geo &G, const InstDev &I, const FTile &t, TileLds &L) {
+    const int W = I.words, per = t.rows * W, n = (D == 3 ? 3 : 1) * per;
+    const float inv_per = 1.0f / (float)per, inv_w = 1.0f / (float)W;
     const int R = I.ny * I.nz;
+    const bool zwall = D == 3 && G.bcz != BC_PERIODIC;
     for (int e = threadIdx.x; e < n; e += FT) {
-        const int win = e / per, rem = e - win * per;
-        const int j = rem / I.words, wi = rem - j * I.words;
-        int rr = (t.r0 - 1 + j + (win - t.cdz) * I.ny) % R;
+        const int win = D == 3 ? small_div(e, inv_per) : 0;
+        const int rem = e - win * per;
+        const int j = small_div(rem, inv_w);
+        const int wi = rem - j * W;
+        int rr = t.r0 - 1 + j + (win - t.cdz) * I.ny;
+        const bool beyond = rr < 0 || rr >= R;
         rr += rr < 0 ? R : 0;
-        lds[e] = G.rw[I.rw_off + (long long)rr * I.words + wi];
+        rr += rr < 0 ? R : 0;
+        rr -= rr >= R ? R : 0;
+        rr -= rr >= R ? R : 0;
+        L.word[e] = zwall && beyond ? make_uint2(0xffffffffu, 0u) : G.rw[I.rw_off + (long long)rr * W + wi];
+        if (win == t.cdz && wi == 0) {
+            const int y = rr % I.ny;
+            L.yedge[j] = y == 0 || y == I.ny - 1;
+        }
     }
 }
 
-// LDS view of the staged row words.  Reading through an address-space-3
-// pointer keeps these reads ds_read instructions: with a generic pointer the
-// compiler may merge an LDS read and a global read into one flat load.
-typedef __attribute__((address_space(3))) const unsigned long long lds_u64;
-__device__ inline uint2 lds_read(const uint2 *lds, unsigned e) {
-    const unsigned long long v = ((lds_u64 *)lds)[e];
-    return make_uint2((unsigned)v, (unsigned)(v >> 32));
+// Every fluid node of the block's own words writes its position into the
+// slot of its lane (staged blocks with at most SCATTER_WORDS own words).
+__device__ inline void scatter_positions(const InstDev &I, const FTile &t, TileLds &L) {
+    const int W = I.words;
+    const float inv_w = 1.0f / (float)W;
+    const int first = t.w0 - t.r0 * W;              // offset of w0 in its row
+    const int obase = (t.cdz * t.rows + 1) * W;     // LDS index of the first own row
+    const int nslots = (t.w1 - t.w0 + 1) * 32;
+    for (int s = threadIdx.x; s < nslots; s += FT) {
+        const int ow = first + (s >> 5), bit = s & 31;
+        const uint2 v = lds_read(L.word, obase + ow);
+        if ((v.x >> bit) & 1u) continue;
+        const int k = (int)v.y + __popc(~v.x & ((1u << bit) - 1u)) - t.id0;
+        if (k < 0 || k >= FT) continue;
+        const int jrow = small_div(ow, inv_w);
+        L.pos[k] = (jrow << X_BITS) | ((ow - jrow * W) * 32 + bit);
+    }
 }
 
 // Position of the k-th (0-based) set bit of m (m has more than k set bits).
@@ -249,19 +295,34 @@ __device__ inline int kth_set_bit(uint32_t m, int k) {
 }
 
 struct FLane {
-    int id, x, y, z, r;
+    int id, x, r;          // fluid id, x, row z ny + y
+    int jc;                // centre-window row of the node (staged blocks)
     bool active;           // id < number of fluid nodes of the instance
+    bool yedge;            // node on the first or last y row
 };
 
-// The lane's fluid node: the last word of [w0, w1] whose first id is <= id
-// holds it; its position in the word is the matching fluid bit.  Staged
-// blocks search their LDS copy of the words, the others global memory (two
-// separate loops, so that each keeps its own memory instructions).
-__device__ inline FLane fluid_lane(const Geo &G, const InstDev &I, const FTile &t, const uint2 *lds) {
+// The lane's fluid node.  Staged blocks with few own words read it from the
+// scattered positions; the others search the last word of [w0, w1] whose
+// first id is <= id (LDS copy or global words) and take the matching bit.
+__device__ inline FLane fluid_lane(const Geo &G, const InstDev &I, const FTile &t, TileLds &L) {
     FLane l;
     l.id = t.id0 + (int)threadIdx.x;
     l.active = l.id < I.n_fluid;
-    l.x = l.y = l.z = l.r = 0;
+    l.x = l.r = 0;
+    l.jc = 1;
+    l.yedge = false;
+    if (t.staged && t.w1 - t.w0 < SCATTER_WORDS) {
+        scatter_positions(I, t, L);
+        __syncthreads();
+        if (!l.active) return l;
+        const int p = L.pos[threadIdx.x];
+        const int jrow = p >> X_BITS;
+        l.x = p & ((1 << X_BITS) - 1);
+        l.r = t.r0 + jrow;
+        l.jc = jrow + 1;
+        l.yedge = L.yedge[l.jc];
+        return l;
+    }
     if (!l.active) return l;
     int lo = t.w0, hi = t.w1;
     uint2 w;
@@ -269,9 +330,9 @@ __device__ inline FLane fluid_lane(const Geo &G, const InstDev &I, const FTile &
         const int base = (t.cdz * t.rows + 1) * I.words - t.r0 * I.words;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
-            if ((int)lds_read(lds, base + mid).y <= l.id) lo = mid; else hi = mid - 1;
+            if ((int)lds_read(L.word, base + mid).y <= l.id) lo = mid; else hi = mid - 1;
         }
-        w = lds_read(lds, base + lo);
+        w = lds_read(L.word, base + lo);
     } else {
         const uint2 *own = G.rw + I.rw_off;
         while (lo < hi) {
@@ -283,132 +344,192 @@ __device__ inline FLane fluid_lane(const Geo &G, const InstDev &I, const FTile &
     const int bit = kth_set_bit(~w.x, l.id - (int)w.y);
     l.r = lo / I.words;
     l.x = (lo - l.r * I.words) * 32 + bit;
-    l.y = l.r % I.ny;
-    l.z = l.r / I.ny;
+    l.jc = l.r - t.r0 + 1;
+    const int y = l.r % I.ny;
+    l.yedge = y == 0 || y == I.ny - 1;
     return l;
 }
 
-enum { NB_WALL = -1, NB_OPEN = -2 };
+// ---------------------------------------------------------------------------
+// Links.  For every link k: wall[k] if x + c_k is solid or lies beyond a wall
+// (halfway bounce-back), open[k] if it lies beyond a pressure face (Zou-He
+// unknown in the forward pass, a link that leaves the lattice in the
+// adjoint), else fid[k] = its fluid id.  The x boundary kind is a template
+// parameter; y and z kinds are read at run time (staging already applied z).
+// ---------------------------------------------------------------------------
+template <int Q>
+struct Links {
+    int id;
+    int fid[Q];
+    bool wall[Q];
+    bool open[Q];
+};
 
 // A coordinate at most one step outside [0, n) wrapped back inside.
 __device__ inline int wrap1(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
-// For every link k: the fluid id of node x + c_k, NB_WALL if that node is
-// solid or lies beyond a wall (halfway bounce-back), NB_OPEN if it lies
-// beyond a pressure face.  nb[0] is the node's own id.  A straight-line pass
-// reads every link's row word from the staged windows (index clamped into
-// the LDS array, so the read is always legal); lanes with links that wrap a
-// periodic y axis, and every lane of an unstaged block, then redo those
-// links from the global row words.  Coordinates are wrapped for indexing
-// only: the boundary kind decides what the link means.
-template <int Q>
-__device__ inline void neighbours(const Geo &G, const InstDev &I, const FTile &t, const uint2 *lds,
-                                  const FLane &l, int (&nb)[Q]) {
+template <int Q, int BCX>
+__device__ inline void links_staged(const InstDev &I, const FTile &t, const TileLds &L, const FLane &l,
+                                    Links<Q> &k) {
     using V = Vel<Q>;
-    nb[0] = l.id;
-    const int W = I.words;
-    const int lrow = (t.cdz * t.rows + (l.r - t.r0 + 1)) * W;
-    const int wstep = t.rows * W;
+    const int W = I.words, per = t.rows * W;
+    const int lrow = (t.cdz * t.rows + l.jc) * W;
+    const bool lo_edge = l.x == 0, hi_edge = l.x == I.nx - 1;
+    const int xm = lo_edge ? I.nx - 1 : l.x - 1, xp = hi_edge ? 0 : l.x + 1;
 #pragma unroll
-    for (int k = 1; k < Q; ++k) {
-        const int dx = V::cx(k), dy = V::cy(k), dz = V::cz(k);
-        const int xr = l.x + dx, yr = l.y + dy, zr = l.z + dz;
+    for (int q = 1; q < Q; ++q) {
+        const int dx = V::cx(q), dy = V::cy(q), dz = V::cz(q);
+        const int xs = dx < 0 ? xm : (dx > 0 ? xp : l.x);
+        const uint2 w = lds_read(L.word, lrow + dz * per + dy * W + (xs >> 5));
+        const bool out = BCX != BC_PERIODIC && dx != 0 && (dx < 0 ? lo_edge : hi_edge);
+        k.fid[q] = fluid_id(w, xs);
+        k.wall[q] = solid_bit(w, xs) || (BCX == BC_WALL && out);
+        k.open[q] = BCX == BC_PRESSURE && out;
+    }
+}
+
+template <int Q, int BCX>
+__device__ inline void links_global(const Geo &G, const InstDev &I, const FLane &l, Links<Q> &k) {
+    using V = Vel<Q>;
+    const int y = l.r % I.ny, z = l.r / I.ny;
+#pragma unroll
+    for (int q = 1; q < Q; ++q) {
+        const int dx = V::cx(q), dy = V::cy(q), dz = V::cz(q);
+        const int xr = l.x + dx, yr = y + dy, zr = z + dz;
         const bool xout = dx != 0 && (xr < 0 || xr >= I.nx);
         const bool yout = dy != 0 && (yr < 0 || yr >= I.ny);
         const bool zout = dz != 0 && (zr < 0 || zr >= I.nz);
         const int xs = dx != 0 ? wrap1(xr, I.nx) : xr;
-        const bool open = xout && G.bcx == BC_PRESSURE;
-        const bool wall = (xout && G.bcx == BC_WALL) || (yout && G.bcy != BC_PERIODIC) ||
-                          (zout && G.bcz != BC_PERIODIC);
-        const unsigned e = (unsigned)(lrow + dz * wstep + dy * W + (xs >> 5));
-        const uint2 w = lds_read(lds, e < (unsigned)NBW ? e : 0u);
-        const int id = solid_bit(w, xs) ? NB_WALL : fluid_id(w, xs);
-        nb[k] = open ? NB_OPEN : (wall ? NB_WALL : id);
-    }
-    const bool yedge = G.bcy == BC_PERIODIC && (l.y == 0 || l.y == I.ny - 1);
-    if (!t.staged || yedge) {
-#pragma unroll
-        for (int k = 1; k < Q; ++k) {
-            const int dx = V::cx(k), dy = V::cy(k), dz = V::cz(k);
-            const int xr = l.x + dx, yr = l.y + dy, zr = l.z + dz;
-            const bool yout = dy != 0 && (yr < 0 || yr >= I.ny);
-            if (nb[k] == NB_OPEN || (t.staged && !yout)) continue;
-            if ((yout && G.bcy != BC_PERIODIC) || (dz != 0 && (zr < 0 || zr >= I.nz) && G.bcz != BC_PERIODIC) ||
-                (dx != 0 && (xr < 0 || xr >= I.nx) && G.bcx == BC_WALL))
-                continue;   // beyond a wall: already NB_WALL
-            const int xs = dx != 0 ? wrap1(xr, I.nx) : xr;
-            const int ys = dy != 0 ? wrap1(yr, I.ny) : yr, zs = dz != 0 ? wrap1(zr, I.nz) : zr;
-            const uint2 w = G.rw[I.rw_off + ((long long)zs * I.ny + ys) * W + (xs >> 5)];
-            nb[k] = solid_bit(w, xs) ? NB_WALL : fluid_id(w, xs);
-        }
+        const int ys = dy != 0 ? wrap1(yr, I.ny) : yr, zs = dz != 0 ? wrap1(zr, I.nz) : zr;
+        const uint2 w = G.rw[I.rw_off + ((long long)zs * I.ny + ys) * I.words + (xs >> 5)];
+        const bool beyond = (BCX == BC_WALL && xout) || (yout && G.bcy != BC_PERIODIC) ||
+                            (zout && G.bcz != BC_PERIODIC);
+        k.fid[q] = fluid_id(w, xs);
+        k.wall[q] = solid_bit(w, xs) || beyond;
+        k.open[q] = BCX == BC_PRESSURE && xout;
     }
 }
 
-// Pull gather over a precomputed neighbourhood.  Link i reads the node
-// x - SGN c_i = x + c_k with k = opp(i) for SGN = +1 (forward streaming) and
-// k = i for SGN = -1 (transpose of streaming):
-//   fluid neighbour -> buf_i(neighbour);
-//   solid / wall    -> buf_opp(i)(x)   (halfway bounce-back);
-//   pressure face   -> 0 (forward: Zou-He unknown, filled by the closure;
-//                     adjoint: the link leaves the lattice).
-template <int Q, int SGN>
-__device__ inline void gather(const float *__restrict__ base, int plane, int id, const int (&nb)[Q], float (&g)[Q]) {
+template <int Q, int BCX>
+__device__ inline void links(const Geo &G, const InstDev &I, const FTile &t, const TileLds &L, const FLane &l,
+                             Links<Q> &k) {
+    k.id = l.id;
+    if (t.staged) links_staged<Q, BCX>(I, t, L, l, k);
+    if (!t.staged || l.yedge) links_global<Q, BCX>(G, I, l, k);
+}
+
+// ---------------------------------------------------------------------------
+// Gathers through buffer loads: an offset past the end of the instance's
+// planes (OOB) reads 0 by the hardware range check, which is what an open
+// link contributes.
+// ---------------------------------------------------------------------------
+constexpr unsigned OOB = 0x80000000u;
+
+__device__ inline __amdgpu_buffer_rsrc_t planes_rsrc(const float *base, int q, long long plane) {
+    return __builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, (int)(q * plane * 4), 0x00020000);
+}
+__device__ inline float bload(__amdgpu_buffer_rsrc_t r, unsigned off) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+__device__ inline void bstore(__amdgpu_buffer_rsrc_t r, float v, unsigned voff, int soff) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
+}
+
+// Streaming pull: g_i(x) = F_i(x - c_i); with k = opp(i), x - c_i = x + c_k.
+//   fluid -> F_i(x + c_k);  wall -> F_k(x) (bounce-back);  open -> 0.
+template <int Q>
+__device__ inline void gather_fwd(__amdgpu_buffer_rsrc_t r, int plane, const Links<Q> &k, float (&g)[Q]) {
     using V = Vel<Q>;
-    g[0] = base[id];
+    const unsigned own = (unsigned)k.id * 4u;
+    g[0] = bload(r, own);
 #pragma unroll
-    for (int i = 1; i < Q; ++i) {
-        const int j = nb[SGN > 0 ? V::opp(i) : i];
-        const int off = j >= 0 ? i * plane + j : (j == NB_WALL ? V::opp(i) * plane + id : i * plane + id);
-        const float v = base[off];
-        g[i] = j == NB_OPEN ? 0.0f : v;
+    for (int q = 1; q < Q; ++q) {
+        const int i = V::opp(q);
+        unsigned off = k.wall[q] ? own + (unsigned)(q * plane) * 4u : (unsigned)(i * plane + k.fid[q]) * 4u;
+        if (V::cx(q) != 0) off = k.open[q] ? OOB : off;
+        g[i] = bload(r, off);
+    }
+}
+
+// Transpose of streaming (pull of nu from x + c_k): lam_k(x) =
+//   fluid -> nu_k(x + c_k);  wall -> nu_opp(k)(x);  open -> 0.
+template <int Q>
+__device__ inline void gather_adj(__amdgpu_buffer_rsrc_t r, int plane, const Links<Q> &k, float (&lam)[Q]) {
+    using V = Vel<Q>;
+    const unsigned own = (unsigned)k.id * 4u;
+    lam[0] = bload(r, own);
+#pragma unroll
+    for (int q = 1; q < Q; ++q) {
+        unsigned off = k.wall[q] ? own + (unsigned)(V::opp(q) * plane) * 4u : (unsigned)(q * plane + k.fid[q]) * 4u;
+        if (V::cx(q) != 0) off = k.open[q] ? OOB : off;
+        lam[q] = bload(r, off);
     }
 }
 
 // Zou-He closure of the unknown populations at a face node (shifted form:
 // with populations f - w the known sum K and the rule are unchanged except
-// that the imposed density enters as a deviation).  s = +1 at the inlet
-// (unknowns c_x = +1), s = -1 at the outlet.
+// that the imposed density enters as a deviation).  in / out select the
+// inlet (unknowns c_x = +1) or outlet (c_x = -1); other nodes keep g
+// exactly.  Written without branches: in a wavefront of consecutive fluid
+// ids nearly every wavefront holds inlet and outlet nodes.
 template <int Q>
-__device__ inline void zouhe(float (&g)[Q], int s, float drho_b) {
+__device__ inline void zouhe(float (&g)[Q], bool in, bool out, float drho_b) {
     using V = Vel<Q>;
-    float K = 0.f, Ny = 0.f, Nz = 0.f;
+    float K0 = 0.f, Kp = 0.f, Km = 0.f, Ny = 0.f, Nz = 0.f;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         if (V::cx(i) == 0) {
-            K += g[i];
-            Ny += 0.5f * V::cy(i) * g[i];
-            Nz += 0.5f * V::cz(i) * g[i];
-        } else if (V::cx(i) == -s) {
-            K += 2.0f * g[i];
+            K0 += g[i];
+            if (V::cy(i)) Ny += 0.5f * V::cy(i) * g[i];
+            if (V::cz(i)) Nz += 0.5f * V::cz(i) * g[i];
+        } else if (V::cx(i) > 0) {
+            Kp += g[i];
+        } else {
+            Km += g[i];
         }
     }
-    const float J = drho_b - K;
+    const float J = drho_b - (K0 + 2.0f * (in ? Km : Kp));
 #pragma unroll
-    for (int i = 0; i < Q; ++i)
-        if (V::cx(i) == s)
-            g[i] = g[V::opp(i)] + 6.0f * V::w(i) * J - V::cy(i) * Ny - V::cz(i) * Nz;
+    for (int p = 1; p < Q; ++p) {
+        if (V::cx(p) != 1) continue;
+        const int m = V::opp(p);
+        const float t = (V::cy(p) ? V::cy(p) * Ny : 0.f) + (V::cz(p) ? V::cz(p) * Nz : 0.f);
+        const float sj = 6.0f * V::w(p) * J;
+        const float np = g[m] + sj - t, nm = g[p] + sj + t;
+        g[p] = in ? np : g[p];
+        g[m] = out ? nm : g[m];
+    }
 }
 
 // Transpose of the closure above applied to an adjoint vector a (in place):
-// returns dL/d(drho_b).
+// returns dL/d(drho_b) (0 away from the faces, where a is left exactly).
 template <int Q>
-__device__ inline float zouhe_adj(float (&a)[Q], int s) {
+__device__ inline float zouhe_adj(float (&a)[Q], bool in, bool out) {
     using V = Vel<Q>;
     float Jb = 0.f, Nyb = 0.f, Nzb = 0.f;
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        if (V::cx(i) == s) {
-            a[V::opp(i)] += a[i];
-            Jb += 6.0f * V::w(i) * a[i];
-            Nyb -= V::cy(i) * a[i];
-            Nzb -= V::cz(i) * a[i];
-            a[i] = 0.f;
-        }
+    for (int p = 1; p < Q; ++p) {
+        if (V::cx(p) != 1) continue;
+        const int m = V::opp(p);
+        const float up = in ? a[p] : 0.f, um = out ? a[m] : 0.f;   // adjoints of the unknowns
+        a[m] += up;
+        a[p] += um;
+        a[p] -= up;
+        a[m] -= um;
+        Jb += 6.0f * V::w(p) * (up + um);
+        if (V::cy(p)) Nyb -= V::cy(p) * (up - um);
+        if (V::cz(p)) Nzb -= V::cz(p) * (up - um);
     }
+    const float Jb2 = 2.0f * Jb;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        if (V::cx(i) == 0) a[i] += -Jb + 0.5f * (V::cy(i) * Nyb + V::cz(i) * Nzb);
-        else if (V::cx(i) == -s) a[i] -= 2.0f * Jb;
+        if (V::cx(i) == 0) {
+            a[i] += -Jb + 0.5f * ((V::cy(i) ? V::cy(i) * Nyb : 0.f) + (V::cz(i) ? V::cz(i) * Nzb : 0.f));
+        } else if (V::cx(i) < 0) {
+            a[i] -= in ? Jb2 : 0.f;
+        } else {
+            a[i] -= out ? Jb2 : 0.f;
+        }
     }
     return Jb;
 }

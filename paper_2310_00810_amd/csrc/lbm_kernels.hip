@@ -18,34 +18,47 @@
 namespace lbm {
 
 // ------------------------------------------------------------------ step --
-template <int Q>
+// The block prologue shared by the fluid-tile kernels: stage the row
+// windows, locate the lane's node.
+#define FLUID_PROLOGUE()                                                    \
+    constexpr int D = Vel<Q>::D;                                            \
+    __shared__ TileLds L;                                                   \
+    const FTile t = fluid_tile<D>(G, xcd_tile(blockIdx.x, gridDim.x));      \
+    const InstDev &I = G.inst[t.b];                                         \
+    if (t.staged) stage_windows<D>(G, I, t, L);                             \
+    __syncthreads();                                                        \
+    const FLane n = fluid_lane(G, I, t, L)
+
+// Face density of a node on a Zou-He face (issued before the gathers).
+template <int BCX>
+__device__ inline float face_density(const InstDev &I, const FLane &n, bool in, bool out,
+                                     const float *__restrict__ face_in, const float *__restrict__ face_out) {
+    float d = 0.f;
+    if (BCX == BC_PRESSURE && (in || out)) d = in ? face_in[I.face_off + n.r] : face_out[I.face_off + n.r];
+    return d;
+}
+
+template <int Q, int BCX>
 __global__ void __launch_bounds__(FT) k_step(Geo G, const float *__restrict__ src,
                                              float *__restrict__ dst,
                                              const float *__restrict__ face_in,
                                              const float *__restrict__ face_out) {
-    constexpr int D = Vel<Q>::D;
-    __shared__ uint2 lds[NBW];
-    const FTile t = fluid_tile<D>(G, xcd_tile(blockIdx.x, gridDim.x));
-    const InstDev &I = G.inst[t.b];
-    if (t.staged) stage_windows<D>(G, I, t, lds);
-    __syncthreads();
-    const FLane n = fluid_lane(G, I, t, lds);
+    FLUID_PROLOGUE();
     if (!n.active) return;
-    int nb[Q];
-    neighbours<Q>(G, I, t, lds, n, nb);
+    const bool in = BCX == BC_PRESSURE && n.x == 0, out = BCX == BC_PRESSURE && n.x == I.nx - 1;
+    const float drho_b = face_density<BCX>(I, n, in, out, face_in, face_out);
+    Links<Q> k;
+    links<Q, BCX>(G, I, t, L, n, k);
     const int plane = (int)I.plane;
     float g[Q];
-    gather<Q, +1>(src + I.st_off, plane, n.id, nb, g);
-    if (G.bcx == BC_PRESSURE) {
-        const long long f = I.face_off + (long long)n.z * I.ny + n.y;
-        if (n.x == 0) zouhe<Q>(g, +1, face_in[f]);
-        else if (n.x == I.nx - 1) zouhe<Q>(g, -1, face_out[f]);
-    }
+    gather_fwd<Q>(planes_rsrc(src + I.st_off, Q, I.plane), plane, k, g);
+    if (BCX == BC_PRESSURE) zouhe<Q>(g, in, out, drho_b);
     const Moments m = moments<Q>(g);
     const float om = I.omega;
-    float *__restrict__ out = dst + I.st_off;
+    const __amdgpu_buffer_rsrc_t rd = planes_rsrc(dst + I.st_off, Q, I.plane);
+    const unsigned own = (unsigned)n.id * 4u;
 #pragma unroll
-    for (int i = 0; i < Q; ++i) out[i * plane + n.id] = g[i] + om * (feq_shifted<Q>(i, m) - g[i]);
+    for (int i = 0; i < Q; ++i) bstore(rd, g[i] + om * (feq_shifted<Q>(i, m) - g[i]), own, i * plane * 4);
 }
 
 // -------------------------------------------------------- loss functions --
@@ -110,48 +123,39 @@ __global__ void __launch_bounds__(BLOCK) k_loss(Geo G, const float *__restrict__
 // Seed kernel: nu^T = Z^T dl/dg^T, with g^T gathered from F^{T-1}.
 // seed_du (nullable) replaces the built-in loss by a caller-given dL/du(T)
 // in the dense layout [node][D].
-template <int Q>
+template <int Q, int BCX>
 __global__ void __launch_bounds__(FT) k_adj_seed(Geo G, const float *__restrict__ Fprev,
-                                                    float *__restrict__ nu_out,
-                                                    const float *__restrict__ face_in,
-                                                    const float *__restrict__ face_out,
-                                                    double *__restrict__ grad_in,
-                                                    double *__restrict__ grad_out,
-                                                    const float *__restrict__ roi,
-                                                    const float *__restrict__ target, int kind,
-                                                    const float *__restrict__ seed_du) {
-    constexpr int D = Vel<Q>::D;
+                                                 float *__restrict__ nu_out,
+                                                 const float *__restrict__ face_in,
+                                                 const float *__restrict__ face_out,
+                                                 double *__restrict__ grad_in,
+                                                 double *__restrict__ grad_out,
+                                                 const float *__restrict__ roi,
+                                                 const float *__restrict__ target, int kind,
+                                                 const float *__restrict__ seed_du) {
     using V = Vel<Q>;
-    __shared__ uint2 lds[NBW];
-    const FTile t = fluid_tile<D>(G, xcd_tile(blockIdx.x, gridDim.x));
-    const InstDev &I = G.inst[t.b];
-    if (t.staged) stage_windows<D>(G, I, t, lds);
-    __syncthreads();
-    const FLane n = fluid_lane(G, I, t, lds);
+    FLUID_PROLOGUE();
     if (!n.active) return;
-    int nb[Q];
-    neighbours<Q>(G, I, t, lds, n, nb);
+    const bool in = BCX == BC_PRESSURE && n.x == 0, out = BCX == BC_PRESSURE && n.x == I.nx - 1;
+    const float drho_b = face_density<BCX>(I, n, in, out, face_in, face_out);
+    Links<Q> k;
+    links<Q, BCX>(G, I, t, L, n, k);
+    const int plane = (int)I.plane;
     float g[Q];
-    gather<Q, +1>(Fprev + I.st_off, (int)I.plane, n.id, nb, g);
-    int face = 0;
-    long long f = 0;
-    if (G.bcx == BC_PRESSURE) {
-        f = I.face_off + (long long)n.z * I.ny + n.y;
-        if (n.x == 0) { zouhe<Q>(g, +1, face_in[f]); face = 1; }
-        else if (n.x == I.nx - 1) { zouhe<Q>(g, -1, face_out[f]); face = -1; }
-    }
+    gather_fwd<Q>(planes_rsrc(Fprev + I.st_off, Q, I.plane), plane, k, g);
+    if (BCX == BC_PRESSURE) zouhe<Q>(g, in, out, drho_b);
     const Moments m = moments<Q>(g);
     const float u[3] = {m.ux, m.uy, m.uz};
     float dldu[3] = {0.f, 0.f, 0.f};
     if (seed_du) {
-        const long long dn = I.node_off + ((long long)n.z * I.ny + n.y) * I.nx + n.x;
+        const long long dn = I.node_off + (long long)n.r * I.nx + n.x;
 #pragma unroll
         for (int a = 0; a < D; ++a) dldu[a] = seed_du[dn * D + a];
     } else {
-        float t[3] = {0.f, 0.f, 0.f};
+        float tg[3] = {0.f, 0.f, 0.f};
 #pragma unroll
-        for (int a = 0; a < D; ++a) t[a] = target[I.poff * D + (long long)a * I.plane + n.id];
-        loss_node<D>(kind, roi[I.poff + n.id] * I.loss_scale, u, t, dldu);
+        for (int a = 0; a < D; ++a) tg[a] = target[I.poff * D + (long long)a * I.plane + n.id];
+        loss_node<D>(kind, roi[I.poff + n.id] * I.loss_scale, u, tg, dldu);
     }
     const float inv = 1.0f / m.rho;
     float a[Q];
@@ -159,97 +163,105 @@ __global__ void __launch_bounds__(FT) k_adj_seed(Geo G, const float *__restrict_
     for (int i = 0; i < Q; ++i)
         a[i] = inv * (dldu[0] * (V::cx(i) - m.ux) + dldu[1] * (V::cy(i) - m.uy) +
                       (D == 3 ? dldu[2] * (V::cz(i) - m.uz) : 0.f));
-    if (face == 1) grad_in[f] += (double)zouhe_adj<Q>(a, +1);
-    else if (face == -1) grad_out[f] += (double)zouhe_adj<Q>(a, -1);
-    float *__restrict__ out = nu_out + I.st_off;
+    if (BCX == BC_PRESSURE) {
+        const float jb = zouhe_adj<Q>(a, in, out);
+        if (in) grad_in[I.face_off + n.r] += (double)jb;
+        else if (out) grad_out[I.face_off + n.r] += (double)jb;
+    }
+    const __amdgpu_buffer_rsrc_t rd = planes_rsrc(nu_out + I.st_off, Q, I.plane);
+    const unsigned own = (unsigned)n.id * 4u;
 #pragma unroll
-    for (int i = 0; i < Q; ++i) out[i * (int)I.plane + n.id] = a[i];
+    for (int i = 0; i < Q; ++i) bstore(rd, a[i], own, i * plane * 4);
 }
 
 // Adjoint step k: reads F^{k-1} (to rebuild g^k) and nu^{k+1}, writes nu^k;
-// accumulates dL/dtau per tile and dL/d(drho_b) per face node.
-template <int Q>
+// accumulates dL/dtau per tile and dL/d(drho_b) per face node.  With
+// lam = S^T nu^{k+1} and the moments of w lam (S0, S_a, S_ab), the
+// collision transpose is  a_i = (1 - omega) lam_i + omega (A + B . c_i)  with
+//   A   = sum_k lam_k dfeq_k/drho = S0 (1 + 1.5 u.u) - 4.5 u.S2.u,
+//   B_a = sum_k lam_k dfeq_k/dj_a = 3 S_a + 9 (S2 u)_a - 3 u_a S0.
+template <int Q, int BCX>
 __global__ void __launch_bounds__(FT) k_adj_step(Geo G, const float *__restrict__ Fprev,
-                                                    const float *__restrict__ nu_in,
-                                                    float *__restrict__ nu_out,
-                                                    const float *__restrict__ face_in,
-                                                    const float *__restrict__ face_out,
-                                                    double *__restrict__ grad_in,
-                                                    double *__restrict__ grad_out,
-                                                    double *__restrict__ dtau_part) {
-    constexpr int D = Vel<Q>::D;
-    __shared__ double red[4];
-    __shared__ uint2 lds[NBW];
+                                                 const float *__restrict__ nu_in,
+                                                 float *__restrict__ nu_out,
+                                                 const float *__restrict__ face_in,
+                                                 const float *__restrict__ face_out,
+                                                 double *__restrict__ grad_in,
+                                                 double *__restrict__ grad_out,
+                                                 double *__restrict__ dtau_part) {
     using V = Vel<Q>;
-    const FTile t = fluid_tile<D>(G, xcd_tile(blockIdx.x, gridDim.x));
-    const InstDev &I = G.inst[t.b];
-    if (t.staged) stage_windows<D>(G, I, t, lds);
-    __syncthreads();
-    const FLane n = fluid_lane(G, I, t, lds);
+    __shared__ double red[4];
+    FLUID_PROLOGUE();
     float dtau = 0.f;
     if (n.active) {
+        const bool in = BCX == BC_PRESSURE && n.x == 0, out = BCX == BC_PRESSURE && n.x == I.nx - 1;
+        const float drho_b = face_density<BCX>(I, n, in, out, face_in, face_out);
+        Links<Q> k;
+        links<Q, BCX>(G, I, t, L, n, k);
         const int plane = (int)I.plane;
-        int nb[Q];
-        neighbours<Q>(G, I, t, lds, n, nb);
         float g[Q], lam[Q];
-        gather<Q, +1>(Fprev + I.st_off, plane, n.id, nb, g);
-        gather<Q, -1>(nu_in + I.st_off, plane, n.id, nb, lam);
-        int face = 0;
-        long long f = 0;
-        if (G.bcx == BC_PRESSURE) {
-            f = I.face_off + (long long)n.z * I.ny + n.y;
-            if (n.x == 0) { zouhe<Q>(g, +1, face_in[f]); face = 1; }
-            else if (n.x == I.nx - 1) { zouhe<Q>(g, -1, face_out[f]); face = -1; }
-        }
+        gather_fwd<Q>(planes_rsrc(Fprev + I.st_off, Q, I.plane), plane, k, g);
+        gather_adj<Q>(planes_rsrc(nu_in + I.st_off, Q, I.plane), plane, k, lam);
+        if (BCX == BC_PRESSURE) zouhe<Q>(g, in, out, drho_b);
         const Moments m = moments<Q>(g);
-        const float usq = m.ux * m.ux + m.uy * m.uy + m.uz * m.uz;
-        // A = sum_k lam_k d feq_k / d rho,  B = sum_k lam_k d feq_k / d j
-        float A = 0.f, Bx = 0.f, By = 0.f, Bz = 0.f;
+        float S0 = 0.f, Sx = 0.f, Sy = 0.f, Sz = 0.f;
+        float Sxx = 0.f, Syy = 0.f, Szz = 0.f, Sxy = 0.f, Sxz = 0.f, Syz = 0.f;
 #pragma unroll
-        for (int k = 0; k < Q; ++k) {
-            const float cu = V::cx(k) * m.ux + V::cy(k) * m.uy + V::cz(k) * m.uz;
-            const float wl = V::w(k) * lam[k];
-            A += wl * (1.0f - 4.5f * cu * cu + 1.5f * usq);
-            Bx += wl * (3.0f * V::cx(k) + 9.0f * cu * V::cx(k) - 3.0f * m.ux);
-            By += wl * (3.0f * V::cy(k) + 9.0f * cu * V::cy(k) - 3.0f * m.uy);
-            Bz += wl * (3.0f * V::cz(k) + 9.0f * cu * V::cz(k) - 3.0f * m.uz);
-            dtau += lam[k] * (g[k] - feq_shifted<Q>(k, m));
+        for (int q = 0; q < Q; ++q) {
+            const int cx = V::cx(q), cy = V::cy(q), cz = V::cz(q);
+            const float wl = V::w(q) * lam[q];
+            S0 += wl;
+            if (cx) { Sx += cx * wl; Sxx += wl; }
+            if (cy) { Sy += cy * wl; Syy += wl; }
+            if (cz) { Sz += cz * wl; Szz += wl; }
+            if (cx && cy) Sxy += cx * cy * wl;
+            if (cx && cz) Sxz += cx * cz * wl;
+            if (cy && cz) Syz += cy * cz * wl;
+            dtau += lam[q] * (g[q] - feq_shifted<Q>(q, m));
         }
         dtau *= I.inv_tau2;
+        const float ux = m.ux, uy = m.uy, uz = m.uz;
+        const float usq = ux * ux + uy * uy + uz * uz;
+        const float S2ux = Sxx * ux + Sxy * uy + Sxz * uz;
+        const float S2uy = Sxy * ux + Syy * uy + Syz * uz;
+        const float S2uz = Sxz * ux + Syz * uy + Szz * uz;
+        const float A = S0 * (1.0f + 1.5f * usq) - 4.5f * (ux * S2ux + uy * S2uy + uz * S2uz);
+        const float Bx = 3.0f * Sx + 9.0f * S2ux - 3.0f * ux * S0;
+        const float By = 3.0f * Sy + 9.0f * S2uy - 3.0f * uy * S0;
+        const float Bz = 3.0f * Sz + 9.0f * S2uz - 3.0f * uz * S0;
         const float om = I.omega, om1 = 1.0f - I.omega;
         float a[Q];
 #pragma unroll
         for (int i = 0; i < Q; ++i)
-            a[i] = om1 * lam[i] + om * (A + Bx * V::cx(i) + By * V::cy(i) + Bz * V::cz(i));
-        if (face == 1) grad_in[f] += (double)zouhe_adj<Q>(a, +1);
-        else if (face == -1) grad_out[f] += (double)zouhe_adj<Q>(a, -1);
-        float *__restrict__ out = nu_out + I.st_off;
+            a[i] = om1 * lam[i] + om * (A + (V::cx(i) ? V::cx(i) * Bx : 0.f) + (V::cy(i) ? V::cy(i) * By : 0.f) +
+                                        (V::cz(i) ? V::cz(i) * Bz : 0.f));
+        if (BCX == BC_PRESSURE) {
+            const float jb = zouhe_adj<Q>(a, in, out);
+            if (in) grad_in[I.face_off + n.r] += (double)jb;
+            else if (out) grad_out[I.face_off + n.r] += (double)jb;
+        }
+        const __amdgpu_buffer_rsrc_t rd = planes_rsrc(nu_out + I.st_off, Q, I.plane);
+        const unsigned own = (unsigned)n.id * 4u;
 #pragma unroll
-        for (int i = 0; i < Q; ++i) out[i * plane + n.id] = a[i];
+        for (int i = 0; i < Q; ++i) bstore(rd, a[i], own, i * plane * 4);
     }
-    const double s = block_sum(dtau, red);
-    if (threadIdx.x == 0) dtau_part[t.tile] += s;
+    const double sum = block_sum(dtau, red);
+    if (threadIdx.x == 0) dtau_part[t.tile] += sum;
 }
 
 // dL/dF^0 = S^T nu^1 in the dense layout [inst][i][nz][ny][nx], fluid nodes
 // only (the caller zeroes the solid entries).
-template <int Q>
+template <int Q, int BCX>
 __global__ void __launch_bounds__(FT) k_adj_final(Geo G, const float *__restrict__ nu_in,
                                                   float *__restrict__ dense) {
-    constexpr int D = Vel<Q>::D;
-    __shared__ uint2 lds[NBW];
-    const FTile t = fluid_tile<D>(G, xcd_tile(blockIdx.x, gridDim.x));
-    const InstDev &I = G.inst[t.b];
-    if (t.staged) stage_windows<D>(G, I, t, lds);
-    __syncthreads();
-    const FLane n = fluid_lane(G, I, t, lds);
+    FLUID_PROLOGUE();
     if (!n.active) return;
     const long long nn = (long long)I.nx * I.ny * I.nz;
-    const long long d0 = I.node_off * Q + ((long long)n.z * I.ny + n.y) * I.nx + n.x;
-    int nb[Q];
-    neighbours<Q>(G, I, t, lds, n, nb);
+    const long long d0 = I.node_off * Q + (long long)n.r * I.nx + n.x;
+    Links<Q> k;
+    links<Q, BCX>(G, I, t, L, n, k);
     float lam[Q];
-    gather<Q, -1>(nu_in + I.st_off, (int)I.plane, n.id, nb, lam);
+    gather_adj<Q>(planes_rsrc(nu_in + I.st_off, Q, I.plane), (int)I.plane, k, lam);
 #pragma unroll
     for (int i = 0; i < Q; ++i) dense[d0 + i * nn] = lam[i];
 }
@@ -395,18 +407,27 @@ __global__ void k_fill_f32(float *p, long long n, float v) {
 static inline dim3 grid_of(const Geo &G) { return dim3((unsigned)G.n_tiles); }
 static inline dim3 fgrid_of(const Geo &G) { return dim3((unsigned)G.n_ftiles); }
 
-template <int Q>
-static hipError_t launch_step_q(const Geo &G, const float *src, float *dst, const float *fin,
-                                const float *fout, hipStream_t s) {
-    if (G.n_ftiles == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_step<Q>, fgrid_of(G), dim3(FT), 0, s, G, src, dst, fin, fout);
-    return hipGetLastError();
-}
+// Fluid-tile kernels take the x boundary kind as a template parameter.
+#define DISPATCH_BCX(q, bcx, CALL)                                                         \
+    do {                                                                                   \
+        if (q == 9) {                                                                      \
+            if (bcx == BC_PRESSURE) CALL(9, BC_PRESSURE);                                  \
+            else if (bcx == BC_PERIODIC) CALL(9, BC_PERIODIC);                             \
+            else CALL(9, BC_WALL);                                                         \
+        } else {                                                                           \
+            if (bcx == BC_PRESSURE) CALL(19, BC_PRESSURE);                                 \
+            else if (bcx == BC_PERIODIC) CALL(19, BC_PERIODIC);                            \
+            else CALL(19, BC_WALL);                                                        \
+        }                                                                                  \
+    } while (0)
 
 hipError_t launch_step(int q, const Geo &G, const float *src, float *dst, const float *fin,
                        const float *fout, hipStream_t s) {
-    return q == 9 ? launch_step_q<9>(G, src, dst, fin, fout, s)
-                  : launch_step_q<19>(G, src, dst, fin, fout, s);
+    if (G.n_ftiles == 0) return hipSuccess;
+#define CALL(Q, B) hipLaunchKernelGGL((k_step<Q, B>), fgrid_of(G), dim3(FT), 0, s, G, src, dst, fin, fout)
+    DISPATCH_BCX(q, G.bcx, CALL);
+#undef CALL
+    return hipGetLastError();
 }
 
 hipError_t launch_loss(int q, const Geo &G, const float *F, const float *roi, const float *target,
@@ -420,12 +441,11 @@ hipError_t launch_adj_seed(int q, const Geo &G, const float *Fprev, float *nu_ou
                            const float *fout, double *gin, double *gout, const float *roi,
                            const float *target, int kind, const float *seed, hipStream_t s) {
     if (G.n_ftiles == 0) return hipSuccess;
-    if (q == 9)
-        hipLaunchKernelGGL(k_adj_seed<9>, fgrid_of(G), dim3(FT), 0, s, G, Fprev, nu_out, fin, fout,
-                           gin, gout, roi, target, kind, seed);
-    else
-        hipLaunchKernelGGL(k_adj_seed<19>, fgrid_of(G), dim3(FT), 0, s, G, Fprev, nu_out, fin, fout,
-                           gin, gout, roi, target, kind, seed);
+#define CALL(Q, B)                                                                                 \
+    hipLaunchKernelGGL((k_adj_seed<Q, B>), fgrid_of(G), dim3(FT), 0, s, G, Fprev, nu_out, fin, fout, gin, gout, \
+                       roi, target, kind, seed)
+    DISPATCH_BCX(q, G.bcx, CALL);
+#undef CALL
     return hipGetLastError();
 }
 
@@ -433,12 +453,11 @@ hipError_t launch_adj_step(int q, const Geo &G, const float *Fprev, const float 
                            const float *fin, const float *fout, double *gin, double *gout,
                            double *dtau_part, hipStream_t s) {
     if (G.n_ftiles == 0) return hipSuccess;
-    if (q == 9)
-        hipLaunchKernelGGL(k_adj_step<9>, fgrid_of(G), dim3(FT), 0, s, G, Fprev, nu_in, nu_out, fin,
-                           fout, gin, gout, dtau_part);
-    else
-        hipLaunchKernelGGL(k_adj_step<19>, fgrid_of(G), dim3(FT), 0, s, G, Fprev, nu_in, nu_out, fin,
-                           fout, gin, gout, dtau_part);
+#define CALL(Q, B)                                                                                 \
+    hipLaunchKernelGGL((k_adj_step<Q, B>), fgrid_of(G), dim3(FT), 0, s, G, Fprev, nu_in, nu_out, fin, fout, gin, \
+                       gout, dtau_part)
+    DISPATCH_BCX(q, G.bcx, CALL);
+#undef CALL
     return hipGetLastError();
 }
 
@@ -446,8 +465,9 @@ hipError_t launch_adj_final(int q, const Geo &G, const float *nu_in, float *dens
                             hipStream_t s) {
     hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)((n_dense + 255) / 256)), dim3(256), 0, s, dense, n_dense, 0.f);
     if (G.n_ftiles == 0) return hipGetLastError();
-    if (q == 9) hipLaunchKernelGGL(k_adj_final<9>, fgrid_of(G), dim3(FT), 0, s, G, nu_in, dense);
-    else hipLaunchKernelGGL(k_adj_final<19>, fgrid_of(G), dim3(FT), 0, s, G, nu_in, dense);
+#define CALL(Q, B) hipLaunchKernelGGL((k_adj_final<Q, B>), fgrid_of(G), dim3(FT), 0, s, G, nu_in, dense)
+    DISPATCH_BCX(q, G.bcx, CALL);
+#undef CALL
     return hipGetLastError();
 }
 

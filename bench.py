@@ -32,6 +32,9 @@ Q = 19
 BYTES_FWD = 2 * Q * 4        # read + write one population set per fluid node
 BYTES_ADJ = 3 * Q * 4        # gather F^{k-1}, gather nu^{k+1}, write nu^k
 PROFILES = os.path.join(ROOT, "profiles")
+# kernel names as the profiler reports them (template arguments: Q, x boundary kind = pressure)
+ADJ_KERNEL = "k_adj_step<19, 0>"
+FWD_KERNEL = "k_step<19, 0>"
 
 
 def workload(n=128, T=8000, K=400, kind="spheres"):
@@ -108,7 +111,7 @@ def warm_vs_cold(torch, n_cases=4):
     return out
 
 
-def cpu_baseline(w, budget_steps=3):
+def cpu_baseline(w, budget_steps=8):
     """The FP64 oracle's gradient evaluation (forward + reverse) on the same
     128^3 problem for a bounded number of steps, timed on the host cores."""
     import oracle as O
@@ -199,7 +202,7 @@ def main():
     fwd_bytes = BYTES_FWD * n_fluid
     adj_gbs = adj_bytes / (adj_ms * 1e-3) / 1e9
     fwd_gbs = fwd_bytes / (fwd_ms * 1e-3) / 1e9
-    traffic = load_traffic("k_adj_step<19>")
+    traffic = load_traffic(ADJ_KERNEL)
     fwd_mlups = n ** 3 / (fwd_ms * 1e-3) / 1e6
 
     out = {
@@ -222,13 +225,13 @@ def main():
                    "lattice": "D3Q19", "nodes": n ** 3, "fluid_nodes": n_fluid, "T": T, "K": K},
         "roofline": {"bound": "hbm", "achieved": round(adj_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(adj_gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": "k_adj_step<19>", "bytes_per_launch": adj_bytes,
+                     "kernel": ADJ_KERNEL, "bytes_per_launch": adj_bytes,
                      "avg_launch_ms": round(adj_ms, 5)},
         "fwd_mlups": round(fwd_mlups, 1),
         "fwd_fluid_mlups": round(n_fluid / (fwd_ms * 1e-3) / 1e6, 1),
-        "fwd_roofline": {"kernel": "k_step<19>", "achieved": round(fwd_gbs, 1), "unit": "GB/s",
+        "fwd_roofline": {"kernel": FWD_KERNEL, "achieved": round(fwd_gbs, 1), "unit": "GB/s",
                          "frac": round(fwd_gbs / HBM_PEAK_GBS, 4), "avg_launch_ms": round(fwd_ms, 5),
-                         "bytes_per_launch": fwd_bytes},
+                         "bytes_per_launch": fwd_bytes, "traffic": load_traffic(FWD_KERNEL)},
         "recompute_avg_launch_ms": round(rec_ms, 5),
         "gradient_norms": {"drho_in": float(np.linalg.norm(g["drho_in"])), "dtau": float(g["dtau"][0])},
         "warm_vs_cold": None,

@@ -3,6 +3,7 @@
     python -m paper_2310_00810_amd.profiling trace <stats.csv> <out.md> "<command>"
     python -m paper_2310_00810_amd.profiling traffic <fetch_counters.csv> <write_counters.csv> \
         <copy_bytes> <out.json> <out.md> "<command>"
+    python -m paper_2310_00810_amd.profiling sq <sq_counters.csv> <out.md> "<command>"
 
 `trace` turns a `--kernel-trace --stats --output-format csv` kernel-stats file
 into a Markdown table.  `traffic` turns two `--pmc FETCH_SIZE` / `--pmc
@@ -12,7 +13,9 @@ kernel in the same run (a device-to-device copy of `copy_bytes` bytes: it
 reads and writes exactly that many bytes), so FETCH_SIZE / WRITE_SIZE units
 and granularity drop out.  The JSON carries the hash of the kernel sources it
 was measured on; the benchmark reports the figure only while that hash still
-matches.
+matches.  `sq` turns a run of SQ_* instruction counters into per-wavefront
+counts per kernel, with the VALU issue time they imply (a wave64 VALU
+instruction occupies a 16-lane SIMD for 4 cycles; 1024 SIMDs at 2.4 GHz).
 """
 import csv
 import collections
@@ -91,8 +94,33 @@ def traffic(fetch_csv, write_csv, copy_bytes, out_json, out_md, command):
         f.write("\n".join(lines) + "\n")
 
 
+def sq(counters_csv, out_md, command):
+    agg = collections.defaultdict(lambda: collections.defaultdict(list))
+    for r in csv.DictReader(open(counters_csv)):
+        agg[short_name(r["Kernel_Name"])][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    names = ["SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_INSTS_VMEM_RD", "SQ_INSTS_VMEM_WR",
+             "SQ_INSTS_SMEM"]
+    with open(out_md, "w") as f:
+        f.write("# Instructions per wavefront (rocprofv3 SQ counters)\n\n")
+        f.write(f"Command:\n\n    {command}\n\n")
+        f.write("| kernel | waves | " + " | ".join(n[9:] for n in names) + " | VALU issue time (us) |\n")
+        f.write("|---" * (len(names) + 3) + "|\n")
+        for k in sorted(agg):
+            if not (k.startswith("k_step") or k.startswith("k_adj")):
+                continue
+            m = {c: sum(v) / len(v) for c, v in agg[k].items()}
+            w = m.get("SQ_WAVES", 0.0)
+            if not w:
+                continue
+            valu_us = w * m.get("SQ_INSTS_VALU", 0.0) / w * 4 / 1024 / 2.4e9 * 1e6
+            f.write(f"| `{k}` | {w:.0f} | " + " | ".join(f"{m.get(n, 0.0) / w:.0f}" for n in names) +
+                    f" | {valu_us:.1f} |\n")
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "trace":
         trace(sys.argv[2], sys.argv[3], sys.argv[4])
     elif sys.argv[1] == "traffic":
         traffic(sys.argv[2], sys.argv[3], float(sys.argv[4]), sys.argv[5], sys.argv[6], sys.argv[7])
+    elif sys.argv[1] == "sq":
+        sq(sys.argv[2], sys.argv[3], sys.argv[4])

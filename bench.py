@@ -125,9 +125,17 @@ def cpu_baseline(w, budget_steps=8):
     O.grad(lat, w["tau"], rin, 1.0, f0, budget_steps, tgt, scale=1.0 / nfl, K=budget_steps)
     dt = time.perf_counter() - t0
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    model = "unknown CPU"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {"value": n ** 3 * budget_steps / dt / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
             "sample": f"FP64 oracle forward+reverse gradient of the same 128^3 D3Q19 sphere-box problem, "
-                      f"{budget_steps} steps (K={budget_steps}), {dt:.1f} s"}
+                      f"{budget_steps} steps (K={budget_steps}), {dt:.1f} s, OpenMP on {cores} threads of {model}"}
 
 
 def main():
@@ -227,6 +235,7 @@ def main():
                      "frac": round(adj_gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": ADJ_KERNEL, "bytes_per_launch": adj_bytes,
                      "avg_launch_ms": round(adj_ms, 5)},
+        "value_fluid_mlups": round(n_fluid * T / (ms_step * 1e-3) / 1e6, 1),
         "fwd_mlups": round(fwd_mlups, 1),
         "fwd_fluid_mlups": round(n_fluid / (fwd_ms * 1e-3) / 1e6, 1),
         "fwd_roofline": {"kernel": FWD_KERNEL, "achieved": round(fwd_gbs, 1), "unit": "GB/s",

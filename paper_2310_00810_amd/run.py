@@ -144,6 +144,20 @@ def c4(quick=False, n_inst=64, T=5000):
     gb = batched()
     torch.cuda.synchronize()
     tb = time.perf_counter() - t0
+    # per-kernel averages (HIP events around the kernels, launched one by one)
+    bs.set_timing(True, reset=True)
+    batched()
+    torch.cuda.synchronize()
+    tm = bs.timing()
+    bs.set_timing(False)
+    n_fluid = sum(int((i.solid == 0).sum()) if i.solid is not None else i.nodes for i in insts)
+    fwd_ms = tm["forward_ms"] / max(tm["forward_launches"], 1)
+    adj_ms = tm["adjoint_ms"] / max(tm["adjoint_launches"], 1)
+    kern = dict(fluid_nodes=n_fluid,
+                k_step_avg_us=fwd_ms * 1e3, k_step_tbs=2 * 9 * 4 * n_fluid / (fwd_ms * 1e-3) / 1e12,
+                k_adj_step_avg_us=adj_ms * 1e3, k_adj_step_tbs=3 * 9 * 4 * n_fluid / (adj_ms * 1e-3) / 1e12)
+    kern["k_step_hbm_frac"] = kern["k_step_tbs"] / 8.0
+    kern["k_adj_step_hbm_frac"] = kern["k_adj_step_tbs"] / 8.0
     del bs
     torch.cuda.empty_cache()
     singles = []
@@ -167,7 +181,7 @@ def c4(quick=False, n_inst=64, T=5000):
     return dict(config="C4", instances=n_inst, nodes=nodes, T=T, K=K,
                 batched_seconds=tb, loop_seconds=tl,
                 batched_fwd_adj_mlups=nodes * T / tb / 1e6, loop_fwd_adj_mlups=nodes * T / tl / 1e6,
-                speedup=tl / tb, gradients_bitwise_equal=bool(same))
+                speedup=tl / tb, gradients_bitwise_equal=bool(same), kernels=kern)
 
 
 def c5(quick=False):

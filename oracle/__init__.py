@@ -27,7 +27,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(HERE, "liblbm_oracle.so")
 
-BC_PRESSURE, BC_PERIODIC, BC_WALL = 0, 1, 2
+BC_PRESSURE, BC_PERIODIC, BC_WALL, BC_ABB = 0, 1, 2, 3
 LOSS_VEC, LOSS_NORM = 0, 1
 
 C2 = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [-1, 0, 0], [0, -1, 0],
@@ -130,8 +130,28 @@ def zouhe(lat, rho_in, rho_out, g):
     return g
 
 
+def abb(lat, rho_in, rho_out, fs, g):
+    """Anti-bounce-back pass (Eq. 6) on the x faces: fills the unknown slots of
+    the streamed state g from the post-collision state fs."""
+    g = _f64(g).copy()
+    lib().orc_abb(*lat.args(), _p(lat.face(rho_in)), _p(lat.face(rho_out)), _p(_f64(fs)), _p(g))
+    return g
+
+
+def abb_adj(lat, rho_in, rho_out, fs, gbar):
+    """(gbar with the unknown slots cleared, the pass's contribution to
+    dL/dfs, d/drho_in, d/drho_out) of the anti-bounce-back pass."""
+    gbar = _f64(gbar).copy()
+    fsbar = np.zeros(lat.shape + (lat.q,))
+    din = np.zeros((lat.nz, lat.ny))
+    dout = np.zeros((lat.nz, lat.ny))
+    lib().orc_abb_adj(*lat.args(), _p(lat.face(rho_in)), _p(lat.face(rho_out)), _p(_f64(fs)),
+                      _p(gbar), _p(fsbar), _p(din), _p(dout))
+    return gbar, fsbar, din, dout
+
+
 def run(lat, tau, rho_in, rho_out, f0, T):
-    """T steps (collide, stream, Zou-He) from f0; returns the final state."""
+    """T steps (collide, stream, boundary pass) from f0; returns the final state."""
     f = _f64(f0).copy()
     lib().orc_run(*lat.args(), ctypes.c_double(tau), _p(lat.face(rho_in)),
                   _p(lat.face(rho_out)), _p(f), ctypes.c_int(T))

@@ -20,7 +20,9 @@
  *   - moment sums run over i = 0..Q-1 (Eq. 1-2);
  *   - BGK relaxes towards equilibrium, Omega = -(f - feq)/tau (Eq. 4);
  *   - tau is a free parameter, nu = cs^2 (tau - 1/2), cs^2 = 1/3 (Eq. 9);
- *   - inlet/outlet densities are imposed with Zou-He on the x faces;
+ *   - inlet/outlet densities are imposed on the x faces with Zou-He or with
+ *     the paper's anti-bounce-back rule (Eq. 6, read with the opposite index
+ *     on the right-hand side and u the boundary node's own velocity);
  *   - walls and grains use link-wise halfway bounce-back;
  *   - the loss is evaluated on the final state only.
  */
@@ -31,7 +33,7 @@
 
 #define ORC_QMAX 19
 
-enum { ORC_BC_PRESSURE = 0, ORC_BC_PERIODIC = 1, ORC_BC_WALL = 2 };
+enum { ORC_BC_PRESSURE = 0, ORC_BC_PERIODIC = 1, ORC_BC_WALL = 2, ORC_BC_ABB = 3 };
 enum { ORC_LOSS_VEC = 0, ORC_LOSS_NORM = 1 };
 enum { ORC_LINK_NORMAL = 0, ORC_LINK_BOUNCE = 1, ORC_LINK_DROP = 2 };
 
@@ -46,7 +48,7 @@ typedef struct {
 typedef struct {
     int q;                       /* 9 or 19 */
     int nx, ny, nz;              /* nz = 1 for D2Q9 */
-    int bc[3];                   /* per axis, ORC_BC_*; PRESSURE only on x */
+    int bc[3];                   /* per axis, ORC_BC_*; PRESSURE and ABB only on x */
     const unsigned char *solid;  /* [nz][ny][nx], nonzero = solid */
 } orc_lattice;
 
@@ -120,7 +122,7 @@ static int orc_link_target(const orc_lattice *L, const int x[3], const int c[3],
         if (y[a] >= 0 && y[a] < n[a]) continue;
         if (L->bc[a] == ORC_BC_PERIODIC) {
             y[a] = (y[a] + n[a]) % n[a];
-        } else if (L->bc[a] == ORC_BC_PRESSURE) {
+        } else if (L->bc[a] == ORC_BC_PRESSURE || L->bc[a] == ORC_BC_ABB) {
             outside_pressure = 1;
         } else {
             outside_wall = 1;
@@ -189,6 +191,12 @@ void orc_zouhe(ORC_ARGS, const double *rho_in, const double *rho_out, double *g)
 {
     ORC_MAKE;
     orc_zouhe_d(&L, rho_in, rho_out, g);
+}
+
+void orc_abb(ORC_ARGS, const double *rho_in, const double *rho_out, const double *fs, double *g)
+{
+    ORC_MAKE;
+    orc_abb_d(&L, rho_in, rho_out, fs, g);
 }
 
 void orc_run(ORC_ARGS, double tau, const double *rho_in, const double *rho_out,
@@ -373,6 +381,59 @@ void orc_zouhe_adj(ORC_ARGS, double *gbar, double *drho_in, double *drho_out)
     orc_zouhe_face_adj(&L, 0, +1, gbar, drho_in);
 }
 
+/* Transpose of one anti-bounce-back face.  The forward pass wrote
+ *   g_i = -fs_opp(i) + 2 w_i rho_b E_i(u),  E_i = 1 + (u.c_i)^2/(2 cs^4) - u.u/(2 cs^2),
+ * into the unknown slots (c_x = s), with u = j(fs)/rho(fs) at the node, so
+ *   d g_i / d fs_m   = -[m = opp(i)] + 2 w_i rho_b sum_a dE_i/du_a (c_ma - u_a)/rho,
+ *   dE_i/du_a        = (u.c_i) c_ia / cs^4 - u_a / cs^2,
+ *   d g_i / d rho_b  = 2 w_i E_i.
+ * The adjoint of each unknown is added to fsbar and to drho_b, and the
+ * unknown slot's own adjoint is cleared (its streamed value was dropped). */
+static void orc_abb_face_adj(const orc_lattice *L, int face_x, int s, const double *rho_b,
+                             const double *fs, double *gbar, double *fsbar, double *drho_b)
+{
+    const orc_velset *V = orc_vel(L->q);
+    const int q = L->q;
+    const double cs2 = 1.0 / 3.0;
+    for (int z = 0; z < L->nz; z++) {
+        for (int y = 0; y < L->ny; y++) {
+            int xc[3] = {face_x, y, z};
+            long k = orc_index(L, xc);
+            if (L->solid && L->solid[k]) continue;
+            double rho, j[3];
+            orc_moments_d(L, &fs[k * q], &rho, j);
+            double u[3] = {j[0] / rho, j[1] / rho, j[2] / rho};
+            double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+            double rb = rho_b[z * L->ny + y];
+            double ubar[3] = {0, 0, 0};
+            for (int i = 0; i < q; i++) {
+                if (V->c[i][0] != s) continue;
+                double gb = gbar[k * q + i];
+                double uc = u[0] * V->c[i][0] + u[1] * V->c[i][1] + u[2] * V->c[i][2];
+                fsbar[k * q + V->opp[i]] -= gb;
+                drho_b[z * L->ny + y] += gb * 2.0 * V->w[i] *
+                                         (1.0 + uc * uc / (2.0 * cs2 * cs2) - uu / (2.0 * cs2));
+                for (int a = 0; a < 3; a++)
+                    ubar[a] += gb * 2.0 * V->w[i] * rb * (uc * V->c[i][a] / (cs2 * cs2) - u[a] / cs2);
+                gbar[k * q + i] = 0;
+            }
+            for (int m = 0; m < q; m++)
+                for (int a = 0; a < 3; a++) fsbar[k * q + m] += ubar[a] * (V->c[m][a] - u[a]) / rho;
+        }
+    }
+}
+
+/* gbar: adjoint of the state after the boundary pass (unknown slots are
+ * cleared); fsbar receives the boundary pass's contribution to dL/dfs. */
+void orc_abb_adj(ORC_ARGS, const double *rho_in, const double *rho_out, const double *fs,
+                 double *gbar, double *fsbar, double *drho_in, double *drho_out)
+{
+    ORC_MAKE;
+    if (L.bc[0] != ORC_BC_ABB) return;
+    orc_abb_face_adj(&L, nx - 1, -1, rho_out, fs, gbar, fsbar, drho_out);
+    orc_abb_face_adj(&L, 0, +1, rho_in, fs, gbar, fsbar, drho_in);
+}
+
 /* dL/df at the final state for the loss defined in orc_loss.  For NORM the
  * derivative of |u| is taken as zero where u = 0. */
 void orc_loss_seed(ORC_ARGS, const double *f, const double *target_u, const double *weight,
@@ -410,8 +471,9 @@ void orc_loss_seed(ORC_ARGS, const double *f, const double *target_u, const doub
  * the inlet densities (per face node), the outlet densities (per face node)
  * and tau.  States f^{cK} are kept for c = 0, 1, ...; each segment is
  * recomputed from its checkpoint in reverse order and then swept backwards
- * stage by stage: Zou-He transpose, streaming transpose, collision
- * transpose.  fbar0 (nullable) receives dL/df^0.  Returns the loss. */
+ * stage by stage: boundary transpose (Zou-He, or anti-bounce-back whose
+ * contribution joins the streaming transpose's), streaming transpose,
+ * collision transpose.  fbar0 (nullable) receives dL/df^0.  Returns the loss. */
 double orc_grad(ORC_ARGS, double tau, const double *rho_in, const double *rho_out,
                 const double *f0, int T, int K, const double *target_u,
                 const double *weight, int kind, double scale, double *drho_in,
@@ -428,6 +490,7 @@ double orc_grad(ORC_ARGS, double tau, const double *rho_in, const double *rho_ou
     double *scratch = malloc(sizeof(double) * (size_t)nq);
     double *a = malloc(sizeof(double) * (size_t)nq);
     double *b = malloc(sizeof(double) * (size_t)nq);
+    double *fsb = malloc(sizeof(double) * (size_t)nq);
     memcpy(f, f0, sizeof(double) * (size_t)nq);
     for (int t = 0; t < T; t++) {
         if (t % K == 0) memcpy(&ckpt[(t / K) * nq], f, sizeof(double) * (size_t)nq);
@@ -446,13 +509,24 @@ double orc_grad(ORC_ARGS, double tau, const double *rho_in, const double *rho_ou
         }
         for (int t = t1; t > t0; t--) {
             /* a = dL/df^t  ->  a = dL/df^{t-1} */
-            orc_zouhe_adj(q, nx, ny, nz, bc, solid, a, drho_in, drho_out);
-            orc_stream_adj(q, nx, ny, nz, bc, solid, a, b);
-            orc_collide_adj(q, nx, ny, nz, bc, solid, tau, &seg[(t - 1 - t0) * nq], b, a, dtau);
+            const double *fprev = &seg[(t - 1 - t0) * nq];
+            if (L.bc[0] == ORC_BC_ABB) {
+                /* the boundary pass read the post-collision state of step t-1 */
+                memcpy(scratch, fprev, sizeof(double) * (size_t)nq);
+                orc_collide_d(&L, tau, scratch);
+                for (long k = 0; k < nq; k++) fsb[k] = 0;
+                orc_abb_adj(q, nx, ny, nz, bc, solid, rho_in, rho_out, scratch, a, fsb, drho_in, drho_out);
+                orc_stream_adj(q, nx, ny, nz, bc, solid, a, b);
+                for (long k = 0; k < nq; k++) b[k] += fsb[k];
+            } else {
+                orc_zouhe_adj(q, nx, ny, nz, bc, solid, a, drho_in, drho_out);
+                orc_stream_adj(q, nx, ny, nz, bc, solid, a, b);
+            }
+            orc_collide_adj(q, nx, ny, nz, bc, solid, tau, fprev, b, a, dtau);
         }
     }
     if (fbar0) memcpy(fbar0, a, sizeof(double) * (size_t)nq);
-    free(ckpt); free(seg); free(f); free(scratch); free(a); free(b);
+    free(ckpt); free(seg); free(f); free(scratch); free(a); free(b); free(fsb);
     return loss;
 }
 

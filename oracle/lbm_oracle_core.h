@@ -168,6 +168,46 @@ static void FN(zouhe)(const orc_lattice *L, const R *rho_in, const R *rho_out, R
     FN(zouhe_face)(L, L->nx - 1, -1, rho_out, g);
 }
 
+/* ---- anti-bounce-back density boundaries on the x faces (Eq. 6) ---------
+ * At a fluid node x_b of the face x = 0 (s = +1) or x = nx-1 (s = -1) the
+ * populations with c_x = s have no upstream node.  Each is the negated
+ * post-collision population that left x_b through the face, plus twice the
+ * even part of the equilibrium at the boundary density rho_b:
+ *   g_i(x_b) = -f*_opp(i)(x_b) + 2 w_i rho_b (1 + (u.c_i)^2/(2 cs^4) - u.u/(2 cs^2)),
+ * with u the velocity of x_b at the same time level (moments of f*(x_b),
+ * equal to those before collision).  fs = post-collision state, g = streamed. */
+static void FN(abb_face)(const orc_lattice *L, int face_x, int s, const R *rho_b, const R *fs, R *g)
+{
+    const orc_velset *V = orc_vel(L->q);
+    const int q = L->q;
+    const double cs2 = 1.0 / 3.0;
+    for (int z = 0; z < L->nz; z++) {
+        for (int y = 0; y < L->ny; y++) {
+            int xc[3] = {face_x, y, z};
+            long k = orc_index(L, xc);
+            if (L->solid && L->solid[k]) continue;
+            R rho, j[3];
+            FN(moments)(L, &fs[k * q], &rho, j);
+            R u[3] = {j[0] / rho, j[1] / rho, j[2] / rho};
+            R uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+            R rb = rho_b[z * L->ny + y];
+            for (int i = 0; i < q; i++) {
+                if (V->c[i][0] != s) continue;
+                R uc = u[0] * V->c[i][0] + u[1] * V->c[i][1] + u[2] * V->c[i][2];
+                g[k * q + i] = -fs[k * q + V->opp[i]] +
+                               2.0 * V->w[i] * rb * (1.0 + uc * uc / (2.0 * cs2 * cs2) - uu / (2.0 * cs2));
+            }
+        }
+    }
+}
+
+static void FN(abb)(const orc_lattice *L, const R *rho_in, const R *rho_out, const R *fs, R *g)
+{
+    if (L->bc[0] != ORC_BC_ABB) return;
+    FN(abb_face)(L, 0, +1, rho_in, fs, g);
+    FN(abb_face)(L, L->nx - 1, -1, rho_out, fs, g);
+}
+
 /* One time step of the paper's stage order: collide, stream, boundary. */
 static void FN(step)(const orc_lattice *L, R tau, const R *rho_in, const R *rho_out,
                      R *f, R *scratch)
@@ -176,6 +216,7 @@ static void FN(step)(const orc_lattice *L, R tau, const R *rho_in, const R *rho_
     FN(collide)(L, tau, f);
     FN(stream)(L, f, scratch);
     FN(zouhe)(L, rho_in, rho_out, scratch);
+    FN(abb)(L, rho_in, rho_out, f, scratch);
     for (long k = 0; k < nq; k++) f[k] = scratch[k];
 }
 

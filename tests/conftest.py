@@ -92,3 +92,14 @@ def multi_tile_lattices():
     out.append(("d3q19_one_plane", O.Lattice(19, 70, 30, 1, (O.BC_PRESSURE, O.BC_PERIODIC, O.BC_PERIODIC),
                                              rand((1, 30, 70), 0.3))))
     return out
+
+
+def abb_lattices():
+    """The tiny lattices with anti-bounce-back density faces on x."""
+    import oracle as O
+    out = []
+    for name, lat in tiny_lattices():
+        bc = (O.BC_ABB,) + tuple(lat.bc_tuple[1:])
+        out.append((name.replace("d2q9", "abb_d2q9").replace("d3q19", "abb_d3q19"),
+                    O.Lattice(lat.q, lat.nx, lat.ny, lat.nz, bc, lat.solid.copy())))
+    return out

@@ -12,14 +12,16 @@
  * Eq. 9; Section 3.4).
  *
  * Boundary conditions: halfway bounce-back on walls and solid nodes (grains,
- * spheres); Zou-He density boundaries on the x faces (inlet x = 0, outlet
- * x = nx-1) when bc_x = LBM_BC_PRESSURE; periodic or wall y and z axes.
+ * spheres); density boundaries on the x faces (inlet x = 0, outlet x = nx-1)
+ * by the Zou-He closure (bc_x = LBM_BC_PRESSURE) or by the paper's
+ * anti-bounce-back rule (bc_x = LBM_BC_ABB, Section 2.1, Eq. 6); periodic or
+ * wall y and z axes.
  *
  * Conventions
  *   - Populations are stored on the device as shifted values f_i - w_i in
- *     FP32 (structure of arrays, x rows padded to a multiple of 32).  Where
- *     the ABI exchanges populations it uses the dense shifted layout
- *     [inst][i][nz][ny][nx], float.
+ *     FP32 (structure of arrays over the fluid nodes only).  Where the ABI
+ *     exchanges populations it uses the dense shifted layout
+ *     [inst][i][nz][ny][nx], float (zero at solid nodes on output).
  *   - Velocity ordering:
  *       D2Q9 : (0,0) (1,0) (0,1) (-1,0) (0,-1) (1,1) (-1,1) (-1,-1) (1,-1)
  *       D3Q19: rest, +x -x +y -y +z -z, (1,1,0) (-1,-1,0) (1,-1,0) (-1,1,0),
@@ -65,7 +67,15 @@ extern "C" {
 #define LBM_EDEVICE (-6)   /* a HIP runtime call failed */
 
 enum lbm_lattice { LBM_D2Q9 = 9, LBM_D3Q19 = 19 };
-enum lbm_bc { LBM_BC_PRESSURE = 0, LBM_BC_PERIODIC = 1, LBM_BC_WALL = 2 };
+/* Axis boundary kinds.  PRESSURE and ABB apply to the x axis only; both
+ * impose the densities 1 + drho_in at x = 0 and 1 + drho_out at x = nx-1:
+ *   PRESSURE: Zou-He closure at the face nodes (density and zero tangential
+ *             velocity at the node);
+ *   ABB:      anti-bounce-back (Section 2.1, Eq. 6): an unknown population is
+ *             the negated outgoing post-collision population plus twice the
+ *             even part of the equilibrium at the imposed density and the
+ *             face node's own velocity (density imposed half a link outside). */
+enum lbm_bc { LBM_BC_PRESSURE = 0, LBM_BC_PERIODIC = 1, LBM_BC_WALL = 2, LBM_BC_ABB = 3 };
 enum lbm_loss_kind { LBM_LOSS_VEC = 0, LBM_LOSS_NORM = 1 };
 enum lbm_loss_scale { LBM_SCALE_SUM = 0, LBM_SCALE_MEAN_FLUID = 1 };
 enum lbm_inlet_mode { LBM_INLET_CONST = 0, LBM_INLET_PROFILE = 1 };
@@ -74,7 +84,7 @@ enum lbm_population_kind { LBM_POP_STATE = 0, LBM_POP_ADJOINT = 1 };
 /* One lattice instance.  Host arrays are copied into the workspace by
  * lbm_init(); the caller may free them afterwards. */
 typedef struct lbm_instance {
-    int nx, ny, nz;          /* nz = 1 for D2Q9; nx >= 2 with a pressure x axis */
+    int nx, ny, nz;          /* nz = 1 for D2Q9; nx >= 2 with density faces; nx < 2^20 */
     const uint8_t *solid;    /* [nz][ny][nx], nonzero = solid node; NULL = all fluid */
     const float *roi;        /* [nz][ny][nx] loss weights (Eq. 7 region of interest); NULL = 1 */
     const float *target_u;   /* [nz][ny][nx][D] target velocity; NULL = 0 */
@@ -85,7 +95,7 @@ typedef struct lbm_problem {
     int lattice;             /* LBM_D2Q9 or LBM_D3Q19 */
     int n_inst;              /* number of independent instances (>= 1) */
     const lbm_instance *inst;
-    int bc_x, bc_y, bc_z;    /* lbm_bc per axis; LBM_BC_PRESSURE only on x */
+    int bc_x, bc_y, bc_z;    /* lbm_bc per axis; LBM_BC_PRESSURE and LBM_BC_ABB only on x */
     int steps;               /* T, number of time steps of lbm_forward() (>= 1) */
     int ckpt_interval;       /* K, checkpoint interval of the taped forward; 0 = ceil(sqrt(T)) */
     int tape;                /* nonzero: reserve checkpoints and a segment store for lbm_adjoint() */

@@ -13,7 +13,7 @@ LIBPATH = os.environ.get("LBM_LIBRARY") or os.path.join(PKG, "liblbm.so")
 
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_ESTATE, LBM_EUNSTABLE, LBM_ECORRUPT, LBM_EDEVICE = 0, -1, -2, -3, -4, -5, -6
 LBM_D2Q9, LBM_D3Q19 = 9, 19
-BC_PRESSURE, BC_PERIODIC, BC_WALL = 0, 1, 2
+BC_PRESSURE, BC_PERIODIC, BC_WALL, BC_ABB = 0, 1, 2, 3
 LOSS_VEC, LOSS_NORM = 0, 1
 SCALE_SUM, SCALE_MEAN_FLUID = 0, 1
 INLET_CONST, INLET_PROFILE = 0, 1

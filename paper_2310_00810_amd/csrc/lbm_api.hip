@@ -64,10 +64,12 @@ int validate_problem(const lbm_problem *p) {
     if (p->n_inst < 1 || !p->inst) return fail(LBM_EINVAL, "n_inst must be >= 1 with a descriptor array");
     const int bcs[3] = {p->bc_x, p->bc_y, p->bc_z};
     for (int a = 0; a < 3; ++a)
-        if (bcs[a] < LBM_BC_PRESSURE || bcs[a] > LBM_BC_WALL)
+        if (bcs[a] < LBM_BC_PRESSURE || bcs[a] > LBM_BC_ABB)
             return fail(LBM_EINVAL, "boundary kind of axis %d is invalid (%d)", a, bcs[a]);
-    if (p->bc_y == LBM_BC_PRESSURE || p->bc_z == LBM_BC_PRESSURE)
-        return fail(LBM_EINVAL, "pressure (Zou-He) faces are supported on the x axis only");
+    if (p->bc_y == LBM_BC_PRESSURE || p->bc_z == LBM_BC_PRESSURE || p->bc_y == LBM_BC_ABB ||
+        p->bc_z == LBM_BC_ABB)
+        return fail(LBM_EINVAL, "density faces (Zou-He or anti-bounce-back) are supported on the x axis only");
+    const bool faces = p->bc_x == LBM_BC_PRESSURE || p->bc_x == LBM_BC_ABB;
     if (p->steps < 1) return fail(LBM_EINVAL, "steps must be >= 1 (got %d)", p->steps);
     if (p->ckpt_interval < 0) return fail(LBM_EINVAL, "ckpt_interval must be >= 0");
     if (p->loss_kind != LBM_LOSS_VEC && p->loss_kind != LBM_LOSS_NORM) return fail(LBM_EINVAL, "bad loss_kind");
@@ -82,11 +84,11 @@ int validate_problem(const lbm_problem *p) {
         if (p->lattice == LBM_D2Q9 && I.nz != 1) return fail(LBM_EINVAL, "instance %d: D2Q9 needs nz = 1", b);
         if (I.nx >= (1 << lbm::X_BITS))
             return fail(LBM_EINVAL, "instance %d: nx must be below %d (got %d)", b, 1 << lbm::X_BITS, I.nx);
-        if (p->bc_x == LBM_BC_PRESSURE && I.nx < 2)
-            return fail(LBM_EINVAL, "instance %d: a pressure x axis needs nx >= 2", b);
+        if (faces && I.nx < 2)
+            return fail(LBM_EINVAL, "instance %d: density faces on x need nx >= 2", b);
         if ((long long)I.nx * I.ny * I.nz * p->lattice >= (1LL << 31) - (1LL << 20))
             return fail(LBM_EINVAL, "instance %d: Q x nodes must stay below 2^31 (32-bit population offsets)", b);
-        if (p->inlet_mode == LBM_INLET_PROFILE && p->bc_x == LBM_BC_PRESSURE && I.solid) {
+        if (p->inlet_mode == LBM_INLET_PROFILE && faces && I.solid) {
             for (long long zy = 0; zy < (long long)I.ny * I.nz; ++zy)
                 if (I.solid[zy * I.nx])
                     return fail(LBM_EINVAL, "instance %d: solid node on the inlet face in profile mode", b);
@@ -487,7 +489,9 @@ int lbm_get_populations(lbm_handle *h, int which, float *d_out) {
     }
     if (which == LBM_POP_ADJOINT) {
         if (!h->adjoint_done) return fail(LBM_ESTATE, "no adjoint has been computed");
-        HIP_TRY(lbm::launch_adj_final(h->L.q, h->G, h->nu_last, d_out, h->L.total_nodes * h->L.q, h->stream));
+        HIP_TRY(lbm::launch_adj_final(h->L.q, h->G, h->nu_last, h->init(), h->at<float>(h->L.off_face_in),
+                                      h->at<float>(h->L.off_face_out), d_out, h->L.total_nodes * h->L.q,
+                                      h->stream));
         return LBM_OK;
     }
     return fail(LBM_EINVAL, "unknown population kind %d", which);
@@ -595,6 +599,9 @@ static int enqueue_reverse(lbm_handle *h, bool recompute_last, const float *seed
         }
         if (marks) { if ((rc = record(h, ev))) return rc; marks->push_back(ev++); }
     }
+    // anti-bounce-back: the faces' density also entered g^1, through F^0
+    if (L.T >= 1 && h->P.bc_x == LBM_BC_ABB)
+        HIP_TRY(lbm::launch_abb_grad0(q, h->G, h->init(), h->nu(1), fin, fout, gin, gout, s));
     return LBM_OK;
 }
 

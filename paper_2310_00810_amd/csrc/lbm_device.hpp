@@ -8,7 +8,9 @@
 
 namespace lbm {
 
-enum { BC_PRESSURE = 0, BC_PERIODIC = 1, BC_WALL = 2 };
+enum { BC_PRESSURE = 0, BC_PERIODIC = 1, BC_WALL = 2, BC_ABB = 3 };
+// x boundary kinds with density faces: Zou-He (PRESSURE) or anti-bounce-back (ABB)
+__host__ __device__ constexpr bool density_faces(int bcx) { return bcx == BC_PRESSURE || bcx == BC_ABB; }
 enum { LOSS_VEC = 0, LOSS_NORM = 1 };
 
 constexpr int TILE_X = 64;       // one wavefront spans 64 consecutive x
@@ -356,6 +358,7 @@ __device__ inline FLane fluid_lane(const Geo &G, const InstDev &I, const FTile &
 // unknown in the forward pass, a link that leaves the lattice in the
 // adjoint), else fid[k] = its fluid id.  The x boundary kind is a template
 // parameter; y and z kinds are read at run time (staging already applied z).
+// open[k] is set for both kinds of density face.
 // ---------------------------------------------------------------------------
 template <int Q>
 struct Links {
@@ -384,7 +387,7 @@ __device__ inline void links_staged(const InstDev &I, const FTile &t, const Tile
         const bool out = BCX != BC_PERIODIC && dx != 0 && (dx < 0 ? lo_edge : hi_edge);
         k.fid[q] = fluid_id(w, xs);
         k.wall[q] = solid_bit(w, xs) || (BCX == BC_WALL && out);
-        k.open[q] = BCX == BC_PRESSURE && out;
+        k.open[q] = density_faces(BCX) && out;
     }
 }
 
@@ -406,7 +409,7 @@ __device__ inline void links_global(const Geo &G, const InstDev &I, const FLane 
                             (zout && G.bcz != BC_PERIODIC);
         k.fid[q] = fluid_id(w, xs);
         k.wall[q] = solid_bit(w, xs) || beyond;
-        k.open[q] = BCX == BC_PRESSURE && xout;
+        k.open[q] = density_faces(BCX) && xout;
     }
 }
 
@@ -436,8 +439,11 @@ __device__ inline void bstore(__amdgpu_buffer_rsrc_t r, float v, unsigned voff, 
 }
 
 // Streaming pull: g_i(x) = F_i(x - c_i); with k = opp(i), x - c_i = x + c_k.
-//   fluid -> F_i(x + c_k);  wall -> F_k(x) (bounce-back);  open -> 0.
-template <int Q>
+//   fluid -> F_i(x + c_k);  wall -> F_k(x) (bounce-back);
+//   open  -> 0 for Zou-He faces (the closure fills the slot), and F_k(x), the
+//            population that left through the face, for anti-bounce-back
+//            faces (the closure negates and corrects it).
+template <int Q, int BCX>
 __device__ inline void gather_fwd(__amdgpu_buffer_rsrc_t r, int plane, const Links<Q> &k, float (&g)[Q]) {
     using V = Vel<Q>;
     const unsigned own = (unsigned)k.id * 4u;
@@ -445,8 +451,9 @@ __device__ inline void gather_fwd(__amdgpu_buffer_rsrc_t r, int plane, const Lin
 #pragma unroll
     for (int q = 1; q < Q; ++q) {
         const int i = V::opp(q);
-        unsigned off = k.wall[q] ? own + (unsigned)(q * plane) * 4u : (unsigned)(i * plane + k.fid[q]) * 4u;
-        if (V::cx(q) != 0) off = k.open[q] ? OOB : off;
+        const bool back = BCX == BC_ABB && V::cx(q) != 0 ? (k.wall[q] || k.open[q]) : k.wall[q];
+        unsigned off = back ? own + (unsigned)(q * plane) * 4u : (unsigned)(i * plane + k.fid[q]) * 4u;
+        if (BCX == BC_PRESSURE && V::cx(q) != 0) off = k.open[q] ? OOB : off;
         g[i] = bload(r, off);
     }
 }
@@ -564,6 +571,76 @@ __device__ inline float feq_shifted(int i, const Moments &m) {
     const float cu = V::cx(i) * m.ux + V::cy(i) * m.uy + V::cz(i) * m.uz;
     const float usq = m.ux * m.ux + m.uy * m.uy + m.uz * m.uz;
     return V::w(i) * (m.drho + m.rho * (3.0f * cu + 4.5f * cu * cu - 1.5f * usq));
+}
+
+// Moments of a node's own populations (face nodes of anti-bounce-back faces).
+template <int Q>
+__device__ inline void own_velocity(__amdgpu_buffer_rsrc_t r, int plane, unsigned own, float &rho, float (&u)[3]) {
+    float f[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) f[i] = bload(r, own + (unsigned)(i * plane) * 4u);
+    const Moments m = moments<Q>(f);
+    rho = m.rho;
+    u[0] = m.ux; u[1] = m.uy; u[2] = m.uz;
+}
+
+// Anti-bounce-back closure (Eq. 6) in shifted form.  On entry the unknown
+// slots hold the outgoing post-collision populations of the node (gathered
+// through the bounce-back offset); uF is the node's velocity before the
+// step.  With E_i = 1 + (u.c_i)^2/(2 cs^4) - u.u/(2 cs^2) and rho_w = 1 + drho_b,
+//   g_i = -F_opp(i) + 2 w_i rho_w E_i - 2 w_i = -F_opp(i) + 2 w_i (drho_b + rho_w (E_i - 1)).
+// in / out select the inlet (unknowns c_x = +1) or outlet (c_x = -1).
+template <int Q>
+__device__ inline void abb(float (&g)[Q], bool in, bool out, float drho_b, const float (&uF)[3]) {
+    using V = Vel<Q>;
+    const float usq = uF[0] * uF[0] + uF[1] * uF[1] + uF[2] * uF[2];
+    const float rw = 1.0f + drho_b;
+#pragma unroll
+    for (int p = 1; p < Q; ++p) {
+        if (V::cx(p) != 1) continue;
+        const int m = V::opp(p);
+        const float cu = uF[0] + (V::cy(p) ? V::cy(p) * uF[1] : 0.f) + (V::cz(p) ? V::cz(p) * uF[2] : 0.f);
+        const float e = 2.0f * V::w(p) * (drho_b + rw * (4.5f * cu * cu - 1.5f * usq));
+        g[p] = in ? e - g[p] : g[p];
+        g[m] = out ? e - g[m] : g[m];
+    }
+}
+
+// Transpose of the anti-bounce-back closure that built g^{k+1} at this node
+// from F^k: nu holds the node's adjoints of its unknowns at step k+1 (one per
+// pair, for the active face), (rho, u) are the moments of F^k.  Adds the
+// contributions to lam = dL/dF^k and returns dL/d(drho_b).
+//   d g_u / d F_opp(u) = -1,
+//   d g_u / d F_j      = 2 w_u rho_w (9 (u.c_u) c_u - 3 u) . (c_j - u) / rho,
+//   d g_u / d drho_b   = 2 w_u E_u.
+template <int Q>
+__device__ inline float abb_adj(float (&lam)[Q], bool in, bool out, float drho_b, float rho, const float (&u)[3],
+                                const float (&nu)[Q]) {
+    using V = Vel<Q>;
+    const float usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    const float rw = 1.0f + drho_b;
+    float gb = 0.f, Vx = 0.f, Vy = 0.f, Vz = 0.f;
+#pragma unroll
+    for (int p = 1; p < Q; ++p) {
+        if (V::cx(p) != 1) continue;
+        const int m = V::opp(p);
+        const float cu = u[0] + (V::cy(p) ? V::cy(p) * u[1] : 0.f) + (V::cz(p) ? V::cz(p) * u[2] : 0.f);
+        const float nu_u = in ? nu[p] : (out ? nu[m] : 0.f);
+        lam[m] -= in ? nu_u : 0.f;
+        lam[p] -= out ? nu_u : 0.f;
+        gb += nu_u * 2.0f * V::w(p) * (1.0f + 4.5f * cu * cu - 1.5f * usq);
+        const float s = nu_u * 2.0f * V::w(p) * rw;
+        Vx += s * (9.0f * cu - 3.0f * u[0]);
+        Vy += s * ((V::cy(p) ? 9.0f * cu * V::cy(p) : 0.f) - 3.0f * u[1]);
+        Vz += s * ((V::cz(p) ? 9.0f * cu * V::cz(p) : 0.f) - 3.0f * u[2]);
+    }
+    const float inv = 1.0f / rho;
+    const float Vu = Vx * u[0] + Vy * u[1] + Vz * u[2];
+#pragma unroll
+    for (int j = 0; j < Q; ++j)
+        lam[j] += inv * ((V::cx(j) ? V::cx(j) * Vx : 0.f) + (V::cy(j) ? V::cy(j) * Vy : 0.f) +
+                         (V::cz(j) ? V::cz(j) * Vz : 0.f) - Vu);
+    return gb;
 }
 
 // Wavefront (64-lane) sum.

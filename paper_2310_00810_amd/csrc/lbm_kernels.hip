@@ -34,8 +34,21 @@ template <int BCX>
 __device__ inline float face_density(const InstDev &I, const FLane &n, bool in, bool out,
                                      const float *__restrict__ face_in, const float *__restrict__ face_out) {
     float d = 0.f;
-    if (BCX == BC_PRESSURE && (in || out)) d = in ? face_in[I.face_off + n.r] : face_out[I.face_off + n.r];
+    if (density_faces(BCX) && (in || out)) d = in ? face_in[I.face_off + n.r] : face_out[I.face_off + n.r];
     return d;
+}
+
+// Adjoints of the unknowns of g^{k+1} at a face node (its own slots of
+// nu^{k+1}, zero elsewhere) for the anti-bounce-back transpose.
+template <int Q>
+__device__ inline void face_unknown_adjoints(__amdgpu_buffer_rsrc_t rn, int plane, unsigned own, bool in, bool out,
+                                             float (&nuo)[Q]) {
+    using V = Vel<Q>;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) nuo[i] = 0.f;
+#pragma unroll
+    for (int i = 1; i < Q; ++i)
+        if (V::cx(i) != 0 && (V::cx(i) > 0 ? in : out)) nuo[i] = bload(rn, own + (unsigned)(i * plane) * 4u);
 }
 
 template <int Q, int BCX>
@@ -45,14 +58,18 @@ __global__ void __launch_bounds__(FT) k_step(Geo G, const float *__restrict__ sr
                                              const float *__restrict__ face_out) {
     FLUID_PROLOGUE();
     if (!n.active) return;
-    const bool in = BCX == BC_PRESSURE && n.x == 0, out = BCX == BC_PRESSURE && n.x == I.nx - 1;
+    const bool in = density_faces(BCX) && n.x == 0, out = density_faces(BCX) && n.x == I.nx - 1;
     const float drho_b = face_density<BCX>(I, n, in, out, face_in, face_out);
+    const int plane = (int)I.plane;
+    const __amdgpu_buffer_rsrc_t rs = planes_rsrc(src + I.st_off, Q, I.plane);
+    float rhoF = 1.0f, uF[3] = {0.f, 0.f, 0.f};
+    if (BCX == BC_ABB && (in || out)) own_velocity<Q>(rs, plane, (unsigned)n.id * 4u, rhoF, uF);
     Links<Q> k;
     links<Q, BCX>(G, I, t, L, n, k);
-    const int plane = (int)I.plane;
     float g[Q];
-    gather_fwd<Q>(planes_rsrc(src + I.st_off, Q, I.plane), plane, k, g);
+    gather_fwd<Q, BCX>(rs, plane, k, g);
     if (BCX == BC_PRESSURE) zouhe<Q>(g, in, out, drho_b);
+    if (BCX == BC_ABB) abb<Q>(g, in, out, drho_b, uF);
     const Moments m = moments<Q>(g);
     const float om = I.omega;
     const __amdgpu_buffer_rsrc_t rd = planes_rsrc(dst + I.st_off, Q, I.plane);
@@ -136,14 +153,18 @@ __global__ void __launch_bounds__(FT) k_adj_seed(Geo G, const float *__restrict_
     using V = Vel<Q>;
     FLUID_PROLOGUE();
     if (!n.active) return;
-    const bool in = BCX == BC_PRESSURE && n.x == 0, out = BCX == BC_PRESSURE && n.x == I.nx - 1;
+    const bool in = density_faces(BCX) && n.x == 0, out = density_faces(BCX) && n.x == I.nx - 1;
     const float drho_b = face_density<BCX>(I, n, in, out, face_in, face_out);
+    const int plane = (int)I.plane;
+    const __amdgpu_buffer_rsrc_t rs = planes_rsrc(Fprev + I.st_off, Q, I.plane);
+    float rhoF = 1.0f, uF[3] = {0.f, 0.f, 0.f};
+    if (BCX == BC_ABB && (in || out)) own_velocity<Q>(rs, plane, (unsigned)n.id * 4u, rhoF, uF);
     Links<Q> k;
     links<Q, BCX>(G, I, t, L, n, k);
-    const int plane = (int)I.plane;
     float g[Q];
-    gather_fwd<Q>(planes_rsrc(Fprev + I.st_off, Q, I.plane), plane, k, g);
+    gather_fwd<Q, BCX>(rs, plane, k, g);
     if (BCX == BC_PRESSURE) zouhe<Q>(g, in, out, drho_b);
+    if (BCX == BC_ABB) abb<Q>(g, in, out, drho_b, uF);
     const Moments m = moments<Q>(g);
     const float u[3] = {m.ux, m.uy, m.uz};
     float dldu[3] = {0.f, 0.f, 0.f};
@@ -194,16 +215,38 @@ __global__ void __launch_bounds__(FT) k_adj_step(Geo G, const float *__restrict_
     FLUID_PROLOGUE();
     float dtau = 0.f;
     if (n.active) {
-        const bool in = BCX == BC_PRESSURE && n.x == 0, out = BCX == BC_PRESSURE && n.x == I.nx - 1;
+        const bool in = density_faces(BCX) && n.x == 0, out = density_faces(BCX) && n.x == I.nx - 1;
         const float drho_b = face_density<BCX>(I, n, in, out, face_in, face_out);
+        const int plane = (int)I.plane;
+        const unsigned own = (unsigned)n.id * 4u;
+        const __amdgpu_buffer_rsrc_t rs = planes_rsrc(Fprev + I.st_off, Q, I.plane);
+        const __amdgpu_buffer_rsrc_t rn = planes_rsrc(nu_in + I.st_off, Q, I.plane);
+        float rhoF = 1.0f, uF[3] = {0.f, 0.f, 0.f};
+        float nuo[Q];
+        if (BCX == BC_ABB) {
+#pragma unroll
+            for (int i = 0; i < Q; ++i) nuo[i] = 0.f;
+            if (in || out) {
+                own_velocity<Q>(rs, plane, own, rhoF, uF);
+                face_unknown_adjoints<Q>(rn, plane, own, in, out, nuo);
+            }
+        }
         Links<Q> k;
         links<Q, BCX>(G, I, t, L, n, k);
-        const int plane = (int)I.plane;
         float g[Q], lam[Q];
-        gather_fwd<Q>(planes_rsrc(Fprev + I.st_off, Q, I.plane), plane, k, g);
-        gather_adj<Q>(planes_rsrc(nu_in + I.st_off, Q, I.plane), plane, k, lam);
+        gather_fwd<Q, BCX>(rs, plane, k, g);
+        gather_adj<Q>(rn, plane, k, lam);
         if (BCX == BC_PRESSURE) zouhe<Q>(g, in, out, drho_b);
+        if (BCX == BC_ABB) abb<Q>(g, in, out, drho_b, uF);
         const Moments m = moments<Q>(g);
+        if (BCX == BC_ABB) {
+            // g^{k+1}'s unknowns at this face node were built from F^k, whose
+            // moments are those of g^k
+            const float um[3] = {m.ux, m.uy, m.uz};
+            const float jb = abb_adj<Q>(lam, in, out, drho_b, m.rho, um, nuo);
+            if (in) grad_in[I.face_off + n.r] += (double)jb;
+            else if (out) grad_out[I.face_off + n.r] += (double)jb;
+        }
         float S0 = 0.f, Sx = 0.f, Sy = 0.f, Sz = 0.f;
         float Sxx = 0.f, Syy = 0.f, Szz = 0.f, Sxy = 0.f, Sxz = 0.f, Syz = 0.f;
 #pragma unroll
@@ -241,7 +284,6 @@ __global__ void __launch_bounds__(FT) k_adj_step(Geo G, const float *__restrict_
             else if (out) grad_out[I.face_off + n.r] += (double)jb;
         }
         const __amdgpu_buffer_rsrc_t rd = planes_rsrc(nu_out + I.st_off, Q, I.plane);
-        const unsigned own = (unsigned)n.id * 4u;
 #pragma unroll
         for (int i = 0; i < Q; ++i) bstore(rd, a[i], own, i * plane * 4);
     }
@@ -249,21 +291,57 @@ __global__ void __launch_bounds__(FT) k_adj_step(Geo G, const float *__restrict_
     if (threadIdx.x == 0) dtau_part[t.tile] += sum;
 }
 
-// dL/dF^0 = S^T nu^1 in the dense layout [inst][i][nz][ny][nx], fluid nodes
-// only (the caller zeroes the solid entries).
+// dL/dF^0 = S^T nu^1 (+ the anti-bounce-back transpose at face nodes, which
+// needs F^0) in the dense layout [inst][i][nz][ny][nx], fluid nodes only (the
+// caller zeroes the solid entries).
 template <int Q, int BCX>
 __global__ void __launch_bounds__(FT) k_adj_final(Geo G, const float *__restrict__ nu_in,
-                                                  float *__restrict__ dense) {
+                                                  const float *__restrict__ F0, const float *__restrict__ face_in,
+                                                  const float *__restrict__ face_out, float *__restrict__ dense) {
     FLUID_PROLOGUE();
     if (!n.active) return;
     const long long nn = (long long)I.nx * I.ny * I.nz;
     const long long d0 = I.node_off * Q + (long long)n.r * I.nx + n.x;
+    const int plane = (int)I.plane;
     Links<Q> k;
     links<Q, BCX>(G, I, t, L, n, k);
+    const __amdgpu_buffer_rsrc_t rn = planes_rsrc(nu_in + I.st_off, Q, I.plane);
     float lam[Q];
-    gather_adj<Q>(planes_rsrc(nu_in + I.st_off, Q, I.plane), (int)I.plane, k, lam);
+    gather_adj<Q>(rn, plane, k, lam);
+    if (BCX == BC_ABB) {
+        const bool in = n.x == 0, out = n.x == I.nx - 1;
+        if (in || out) {
+            const unsigned own = (unsigned)n.id * 4u;
+            float rhoF, uF[3], nuo[Q];
+            own_velocity<Q>(planes_rsrc(F0 + I.st_off, Q, I.plane), plane, own, rhoF, uF);
+            face_unknown_adjoints<Q>(rn, plane, own, in, out, nuo);
+            abb_adj<Q>(lam, in, out, face_density<BCX>(I, n, in, out, face_in, face_out), rhoF, uF, nuo);
+        }
+    }
 #pragma unroll
     for (int i = 0; i < Q; ++i) dense[d0 + i * nn] = lam[i];
+}
+
+// Anti-bounce-back faces: dL/d(drho_b) of the closure that built g^1 from
+// F^0 (the adjoint steps cover g^2 .. g^T).
+template <int Q>
+__global__ void __launch_bounds__(FT) k_abb_grad0(Geo G, const float *__restrict__ F0, const float *__restrict__ nu1,
+                                                  const float *__restrict__ face_in, const float *__restrict__ face_out,
+                                                  double *__restrict__ grad_in, double *__restrict__ grad_out) {
+    FLUID_PROLOGUE();
+    if (!n.active) return;
+    const bool in = n.x == 0, out = n.x == I.nx - 1;
+    if (!(in || out)) return;
+    const int plane = (int)I.plane;
+    const unsigned own = (unsigned)n.id * 4u;
+    float rhoF, uF[3], nuo[Q], lam[Q];
+    own_velocity<Q>(planes_rsrc(F0 + I.st_off, Q, I.plane), plane, own, rhoF, uF);
+    face_unknown_adjoints<Q>(planes_rsrc(nu1 + I.st_off, Q, I.plane), plane, own, in, out, nuo);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) lam[i] = 0.f;
+    const float jb = abb_adj<Q>(lam, in, out, face_density<BC_ABB>(I, n, in, out, face_in, face_out), rhoF, uF, nuo);
+    if (in) grad_in[I.face_off + n.r] += (double)jb;
+    else grad_out[I.face_off + n.r] += (double)jb;
 }
 
 // ------------------------------------------------------------ utilities --
@@ -413,11 +491,13 @@ static inline dim3 fgrid_of(const Geo &G) { return dim3((unsigned)G.n_ftiles); }
         if (q == 9) {                                                                      \
             if (bcx == BC_PRESSURE) CALL(9, BC_PRESSURE);                                  \
             else if (bcx == BC_PERIODIC) CALL(9, BC_PERIODIC);                             \
-            else CALL(9, BC_WALL);                                                         \
+            else if (bcx == BC_WALL) CALL(9, BC_WALL);                                     \
+            else CALL(9, BC_ABB);                                                          \
         } else {                                                                           \
             if (bcx == BC_PRESSURE) CALL(19, BC_PRESSURE);                                 \
             else if (bcx == BC_PERIODIC) CALL(19, BC_PERIODIC);                            \
-            else CALL(19, BC_WALL);                                                        \
+            else if (bcx == BC_WALL) CALL(19, BC_WALL);                                    \
+            else CALL(19, BC_ABB);                                                         \
         }                                                                                  \
     } while (0)
 
@@ -461,13 +541,21 @@ hipError_t launch_adj_step(int q, const Geo &G, const float *Fprev, const float 
     return hipGetLastError();
 }
 
-hipError_t launch_adj_final(int q, const Geo &G, const float *nu_in, float *dense, long long n_dense,
-                            hipStream_t s) {
+hipError_t launch_adj_final(int q, const Geo &G, const float *nu_in, const float *F0, const float *fin,
+                            const float *fout, float *dense, long long n_dense, hipStream_t s) {
     hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)((n_dense + 255) / 256)), dim3(256), 0, s, dense, n_dense, 0.f);
     if (G.n_ftiles == 0) return hipGetLastError();
-#define CALL(Q, B) hipLaunchKernelGGL((k_adj_final<Q, B>), fgrid_of(G), dim3(FT), 0, s, G, nu_in, dense)
+#define CALL(Q, B) hipLaunchKernelGGL((k_adj_final<Q, B>), fgrid_of(G), dim3(FT), 0, s, G, nu_in, F0, fin, fout, dense)
     DISPATCH_BCX(q, G.bcx, CALL);
 #undef CALL
+    return hipGetLastError();
+}
+
+hipError_t launch_abb_grad0(int q, const Geo &G, const float *F0, const float *nu1, const float *fin,
+                            const float *fout, double *gin, double *gout, hipStream_t s) {
+    if (G.n_ftiles == 0) return hipSuccess;
+    if (q == 9) hipLaunchKernelGGL(k_abb_grad0<9>, fgrid_of(G), dim3(FT), 0, s, G, F0, nu1, fin, fout, gin, gout);
+    else hipLaunchKernelGGL(k_abb_grad0<19>, fgrid_of(G), dim3(FT), 0, s, G, F0, nu1, fin, fout, gin, gout);
     return hipGetLastError();
 }
 

@@ -15,9 +15,13 @@ hipError_t launch_adj_seed(int q, const Geo &G, const float *Fprev, float *nu_ou
 hipError_t launch_adj_step(int q, const Geo &G, const float *Fprev, const float *nu_in, float *nu_out,
                            const float *fin, const float *fout, double *gin, double *gout,
                            double *dtau_part, hipStream_t s);
-// Zeroes the n_dense floats of dense, then writes the fluid entries.
-hipError_t launch_adj_final(int q, const Geo &G, const float *nu_in, float *dense, long long n_dense,
-                            hipStream_t s);
+// Zeroes the n_dense floats of dense, then writes the fluid entries
+// (F0 and the face densities serve the anti-bounce-back transpose).
+hipError_t launch_adj_final(int q, const Geo &G, const float *nu_in, const float *F0, const float *fin,
+                            const float *fout, float *dense, long long n_dense, hipStream_t s);
+// Anti-bounce-back faces: adds dL/d(drho_b) of the closure that built g^1.
+hipError_t launch_abb_grad0(int q, const Geo &G, const float *F0, const float *nu1, const float *fin,
+                            const float *fout, double *gin, double *gout, hipStream_t s);
 hipError_t launch_init_eq(int q, const Geo &G, float *F, const float *drho, const float *u,
                           hipStream_t s);
 hipError_t launch_convert(int q, const Geo &G, float *F, float *dense, int to_state, hipStream_t s);

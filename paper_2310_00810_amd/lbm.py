@@ -18,7 +18,7 @@ from . import _lib as C
 _LOSS = {"vec": C.LOSS_VEC, "norm": C.LOSS_NORM}
 _SCALE = {"sum": C.SCALE_SUM, "mean": C.SCALE_MEAN_FLUID}
 _INLET = {"const": C.INLET_CONST, "profile": C.INLET_PROFILE}
-_BC = {"pressure": C.BC_PRESSURE, "periodic": C.BC_PERIODIC, "wall": C.BC_WALL}
+_BC = {"pressure": C.BC_PRESSURE, "periodic": C.BC_PERIODIC, "wall": C.BC_WALL, "abb": C.BC_ABB}
 
 
 @dataclass

@@ -9,7 +9,7 @@ import pytest
 
 import oracle as O
 from paper_2310_00810_amd import geometry as G
-from tests.conftest import multi_tile_lattices, tiny_lattices
+from tests.conftest import abb_lattices, multi_tile_lattices, tiny_lattices
 
 pytestmark = pytest.mark.gpu
 
@@ -21,7 +21,16 @@ def _lbm():
     return lbm
 
 
-BC_NAMES = {O.BC_PRESSURE: "pressure", O.BC_PERIODIC: "periodic", O.BC_WALL: "wall"}
+BC_NAMES = {O.BC_PRESSURE: "pressure", O.BC_PERIODIC: "periodic", O.BC_WALL: "wall", O.BC_ABB: "abb"}
+
+
+def oracle_pull_step(lat, tau, rin, rout, F):
+    """One step in the GPU's state convention, F^t = C(B(S(F^{t-1}))), from
+    the oracle's stages (B = Zou-He, or anti-bounce-back reading the
+    post-collision state F^{t-1})."""
+    g = O.stream(lat, F)
+    g = O.abb(lat, rin, rout, F, g) if lat.bc_tuple[0] == O.BC_ABB else O.zouhe(lat, rin, rout, g)
+    return g
 
 
 def solver_for(lat, steps, tape=False, K=0, roi=None, target=None, loss_kind="vec",
@@ -65,7 +74,7 @@ def f32(x):
 
 
 # ---------------------------------------------------------------- forward --
-@pytest.mark.parametrize("name,lat", tiny_lattices() + multi_tile_lattices())
+@pytest.mark.parametrize("name,lat", tiny_lattices() + multi_tile_lattices() + abb_lattices())
 @pytest.mark.parametrize("T", [1, 3])
 def test_steps_from_random_state(name, lat, T):
     """T steps from a random non-equilibrium state, all boundary kinds."""
@@ -81,10 +90,10 @@ def test_steps_from_random_state(name, lat, T):
     s.set_populations(torch.from_numpy(fb.ravel()).cuda())
     s.forward(tau, f32(0.004), f32(-0.002), want_loss=False)
     got = from_dense(lat, s.get_populations("state"))
-    # GPU state convention: F^t = C(Z(S(F^{t-1})))
+    # GPU state convention: F^t = C(B(S(F^{t-1})))
     x = F0
     for _ in range(T):
-        x = O.collide(lat, tau, O.zouhe(lat, rin, rout, O.stream(lat, x)))
+        x = O.collide(lat, tau, oracle_pull_step(lat, tau, rin, rout, x))
     m = lat.fluid()
     assert rel_l2((got - w)[m], (x - w)[m]) < 1e-5
     assert np.all(np.isfinite(got))
@@ -161,11 +170,11 @@ def test_c1_gradient_parity(kind):
 
 
 def _driven(lats):
-    """Lattices with Zou-He faces (the others stay at rest: zero gradients)."""
-    return [(n, l) for n, l in lats if l.bc_tuple[0] == O.BC_PRESSURE]
+    """Lattices with density faces (the others stay at rest: zero gradients)."""
+    return [(n, l) for n, l in lats if l.bc_tuple[0] in (O.BC_PRESSURE, O.BC_ABB)]
 
 
-@pytest.mark.parametrize("name,lat", _driven(tiny_lattices() + multi_tile_lattices()))
+@pytest.mark.parametrize("name,lat", _driven(tiny_lattices() + multi_tile_lattices() + abb_lattices()))
 def test_tiny_profile_gradients(name, lat):
     """Per-node inlet profile gradients, dL/dtau and dL/drho_out on the tiny
     lattices (walls, periodic axes, grains touching the faces), T = 40."""
@@ -193,7 +202,7 @@ def test_tiny_profile_gradients(name, lat):
     assert rel_l2(g["drho_out"], [go["drho_out"].sum()]) <= 1e-3
 
 
-@pytest.mark.parametrize("name,lat", tiny_lattices() + multi_tile_lattices())
+@pytest.mark.parametrize("name,lat", tiny_lattices() + multi_tile_lattices() + abb_lattices())
 @pytest.mark.parametrize("T", [1, 2, 3])
 def test_adjoint_of_initial_state(name, lat, T):
     """dL/dF^0 from the GPU reverse sweep against the oracle's stage
@@ -213,14 +222,21 @@ def test_adjoint_of_initial_state(name, lat, T):
     s.forward(tau, f32(0.003), f32(-0.001), record_tape=True)
     s.adjoint()
     got = from_dense(lat, s.get_populations("adjoint"), shifted=False)
-    # oracle: g^1 = Z S F^0, then T-1 full steps, loss on g^T
-    gs = [O.zouhe(lat, rin, rout, O.stream(lat, F0))]
+    # oracle: g^1 = B S F^0, then T-1 full steps, loss on g^T
+    abb = lat.bc_tuple[0] == O.BC_ABB
+    Fs = [F0]
+    gs = [oracle_pull_step(lat, tau, rin, rout, F0)]
     for _ in range(T - 1):
-        gs.append(O.zouhe(lat, rin, rout, O.stream(lat, O.collide(lat, tau, gs[-1]))))
+        Fs.append(O.collide(lat, tau, gs[-1]))
+        gs.append(oracle_pull_step(lat, tau, rin, rout, Fs[-1]))
     a = O.loss_seed(lat, gs[-1], tgt)
     for t in range(T, 0, -1):
-        a, _, _ = O.zouhe_adj(lat, a)
-        a = O.stream_adj(lat, a)
+        if abb:
+            a, fsb, _, _ = O.abb_adj(lat, rin, rout, Fs[t - 1], a)
+            a = O.stream_adj(lat, a) + fsb
+        else:
+            a, _, _ = O.zouhe_adj(lat, a)
+            a = O.stream_adj(lat, a)
         if t > 1:
             a, _ = O.collide_adj(lat, tau, gs[t - 2], a)
     m = lat.fluid()

@@ -224,3 +224,14 @@ def random_perturbation(shape, q, amplitude, seed=0):
 def random_field(shape, scale, seed=0):
     rng = np.random.default_rng(seed)
     return rng.normal(0.0, scale, size=shape)
+
+
+def obstructed_pipe(nx=300, ny=50, x_plate=80, plate_len=30):
+    """2D pipe (walls in y) with a thin plate normal to the flow: one node
+    wide at x = x_plate, plate_len nodes long, centred in y (Section 3.1.1's
+    obstructed pipe; the plate's position in y is not stated there).
+    Returns a (1, ny, nx) uint8 solid mask."""
+    solid = np.zeros((1, ny, nx), np.uint8)
+    y0 = (ny - plate_len) // 2
+    solid[0, y0:y0 + plate_len, x_plate] = 1
+    return solid

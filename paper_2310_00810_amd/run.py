@@ -1,6 +1,6 @@
 """Drivers of the workloads: inverse runs, batched throughput, warm start.
 
-    python -m paper_2310_00810_amd.run c1|c2|c3|c4|c5 [--quick]
+    python -m paper_2310_00810_amd.run c1|c2|c3|c4|c5|e1 [--quick]
 
 Each prints one JSON line with its results.  The workloads are synthetic
 stand-ins for the paper's experiments (Section 3): channel and granular
@@ -184,6 +184,48 @@ def c4(quick=False, n_inst=64, T=5000):
                 speedup=tl / tb, gradients_bitwise_equal=bool(same), kernels=kern)
 
 
+def e1(quick=False):
+    """Obstructed pipe with anti-bounce-back faces (Section 3.1.1): D2Q9
+    300 x 50, walls in y, a 1 x 30 plate at x = 80, tau = 1, 40000 steps.
+    The target is the velocity at the true pressure difference 0.05
+    (drho = 0.15 with p = rho / 3), observed only at x >= 275 (NORM loss,
+    Eq. 7 with f(x, y) = 1 there); the inlet density is recovered from the
+    pressure difference 0.0025 (drho = 0.0075)."""
+    nx, ny, T, tau = 300, 50, 40000, 1.0
+    d_true, d0 = 0.15, 0.0075
+    if quick:
+        T = 4000
+    solid = G.obstructed_pipe(nx, ny)
+    bc = ("abb", "wall", "periodic")
+    s0 = Solver(9, [Instance(nx, ny, solid=solid)], bc=bc, steps=T)
+    s0.forward(tau, d_true, 0.0, want_loss=False)
+    _, ut = s0.macro()
+    tgt = ut.cpu().numpy().reshape(1, ny, nx, 2)
+    roi = np.zeros((1, ny, nx), np.float32)
+    roi[:, :, 275:] = 1.0
+    s = Solver(9, [Instance(nx, ny, solid=solid, roi=roi, target_u=tgt)], bc=bc, steps=T, tape=True,
+               loss_kind="norm")
+    t0 = time.time()
+    p, h = inverse.recover_constant_head(s, tau, d0, max_iter=20, rtol=1e-4, true_drho=d_true)
+    dt = time.time() - t0
+    # one timed gradient evaluation with per-kernel HIP events
+    s.set_timing(True, reset=True)
+    t1 = time.perf_counter()
+    s.forward(tau, p, 0.0, record_tape=True)
+    s.adjoint()
+    s.grad()
+    tg = time.perf_counter() - t1
+    tm = s.timing()
+    s.set_timing(False)
+    n_fluid = int((solid == 0).sum())
+    return dict(config="E1", T=T, iterations=len(h.loss), seconds=dt, recovered_drho_in=p, true_drho_in=d_true,
+                recovered_pressure_difference=p / 3.0, loss=[float(x) for x in h.loss],
+                gradient_seconds=tg, fwd_adj_mlups=nx * ny * T / tg / 1e6,
+                k_step_avg_us=tm["forward_ms"] / max(tm["forward_launches"], 1) * 1e3,
+                k_adj_step_avg_us=tm["adjoint_ms"] / max(tm["adjoint_launches"], 1) * 1e3,
+                fluid_nodes=n_fluid)
+
+
 def c5(quick=False):
     from . import warmstart
     sys.argv = [sys.argv[0], "--dims", "2", "--train", "64" if quick else "2000", "--val", "16" if quick else "200",
@@ -194,7 +236,7 @@ def c5(quick=False):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("config", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("config", choices=["c1", "c2", "c3", "c4", "c5", "e1"])
     ap.add_argument("--quick", action="store_true")
     a = ap.parse_args()
     res = globals()[a.config](quick=a.quick)

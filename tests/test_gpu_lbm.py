@@ -428,3 +428,43 @@ def test_autograd_wrappers_match_the_builtin_gradient():
     assert abs(L2.item() - loss.item()) <= 1e-5 * loss.item()
     assert abs(din2.grad.item() - ref["drho_in"][0]) <= 1e-4 * abs(ref["drho_in"][0])
     assert abs(tau2.grad.item() - ref["dtau"][0]) <= 1e-4 * abs(ref["dtau"][0])
+
+
+# ------------------------------------------- obstructed pipe, anti-bounce-back --
+def _e1_lattice():
+    solid = G.obstructed_pipe(300, 50)
+    return O.Lattice(9, 300, 50, 1, (O.BC_ABB, O.BC_WALL, O.BC_PERIODIC), solid)
+
+
+def test_e1_forward_parity_40000_steps():
+    """The obstructed pipe at full size (300 x 50, plate at x = 80, tau = 1,
+    pressure difference 0.05 = density difference 0.15, 40000 steps): GPU
+    velocity against the oracle."""
+    lat = _e1_lattice()
+    T, tau = 40000, 1.0
+    s = solver_for(lat, T)
+    s.forward(tau, 0.15, 0.0, want_loss=False)
+    ug = gpu_u(lat, s)
+    fo = O.run(lat, tau, 1.15, 1.0, O.init_eq(lat, 1.0, 0.0), T)
+    _, uo = O.macro(lat, fo)
+    m = lat.fluid()
+    assert rel_l2(ug[m], uo[m][:, :2]) <= 1e-4
+
+
+def test_e1_gradient_parity():
+    """dL/d(rho_in) and dL/dtau of the obstructed pipe with the paper's
+    outlet-region NORM loss (x >= 275), 1000 steps, against the oracle."""
+    lat = _e1_lattice()
+    T, tau = 1000, 1.0
+    rng = np.random.default_rng(9)
+    _, ut = O.macro(lat, O.run(lat, tau, 1.15, 1.0, O.init_eq(lat, 1.0, 0.0), T))
+    tgt = (ut * (1 + 0.01 * rng.standard_normal(ut.shape))).astype(np.float32).astype(np.float64)
+    roi = np.zeros(lat.shape)
+    roi[:, :, 275:] = 1.0
+    s = solver_for(lat, T, tape=True, roi=roi, target=tgt, loss_kind="norm")
+    s.forward(tau, f32(0.1), 0.0, record_tape=True)
+    s.adjoint()
+    g = s.grad()
+    go = O.grad(lat, tau, 1 + f32(0.1), 1.0, O.init_eq(lat, 1.0, 0.0), T, tgt, roi, O.LOSS_NORM)
+    assert rel_l2(g["drho_in"], [go["drho_in"].sum()]) <= 1e-3
+    assert rel_l2(g["dtau"], [go["dtau"]]) <= 1e-3

@@ -261,6 +261,9 @@ def main():
     if not args.no_warm:
         print("[bench] warm vs cold start ...", file=sys.stderr, flush=True)
         out["warm_vs_cold"] = warm_vs_cold(torch)
+        # the warm start's network kernels (BF16 MFMA convolutions) against their roofline
+        from paper_2310_00810_amd.unet import measure
+        out["unet_mfma"] = [measure(2, 16, 256), measure(3, 2, 64)]
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w)

@@ -239,6 +239,56 @@ __global__ void k_sum_splits(const float *__restrict__ part, int splits, long lo
     out[i] = accumulate ? out[i] + s : s;
 }
 
+// Sum of split partials when there are few outputs: one block per output,
+// the threads stride over the splits, then a fixed-order tree (deterministic).
+__global__ void __launch_bounds__(256) k_sum_splits_narrow(const float *__restrict__ part, int splits, long long n,
+                                                           float *__restrict__ out, int accumulate) {
+    __shared__ float sh[256];
+    const long long i = blockIdx.x;
+    float acc = 0.f;
+    for (int z = threadIdx.x; z < splits; z += 256) acc += part[(long long)z * n + i];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[i] = accumulate ? out[i] + sh[0] : sh[0];
+}
+
+// Bias gradient partials with 16-byte loads (channel stride, offset and
+// count multiples of 8, C <= 2048): a thread sums 8 channels of every
+// (256 / (C/8))-th pixel of the split; LDS combines the pixel lanes.
+__global__ void __launch_bounds__(256) k_bias_grad8(const uint16_t *__restrict__ g, int cs, int co, long long npix,
+                                                    int C, long long chunk, float *__restrict__ part) {
+    __shared__ float sh[256 * 8];
+    const int tpp = C >> 3;                    // threads per pixel
+    const int ppi = 256 / tpp;                 // pixels per iteration
+    const int gi = threadIdx.x % tpp, pi = threadIdx.x / tpp;
+    const long long mb = (long long)blockIdx.x * chunk;
+    const long long me = mb + chunk < npix ? mb + chunk : npix;
+    float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (pi < ppi)
+        for (long long m = mb + pi; m < me; m += ppi) {
+            const uint4 v = *(const uint4 *)(g + m * cs + co + gi * 8);
+            const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                acc[2 * j] += bf2f((uint16_t)(w4[j] & 0xffffu));
+                acc[2 * j + 1] += bf2f((uint16_t)(w4[j] >> 16));
+            }
+        }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) sh[threadIdx.x * 8 + j] = pi < ppi ? acc[j] : 0.f;
+    __syncthreads();
+    for (int c = threadIdx.x; c < C; c += 256) {
+        const int gc = c >> 3, j = c & 7;
+        float sum = 0.f;
+        for (int p = 0; p < ppi; ++p) sum += sh[(p * tpp + gc) * 8 + j];
+        part[(long long)blockIdx.x * C + c] = sum;
+    }
+}
+
 // Bias gradient partials: part[split][c] = sum over the split's pixels.
 __global__ void __launch_bounds__(256) k_bias_grad(const uint16_t *__restrict__ g, int cs, int co, long long npix,
                                                    int C, long long chunk, float *__restrict__ part) {
@@ -436,6 +486,16 @@ long long wgrad_chunk(long long M, int splits) {
     return (c + BK - 1) / BK * BK;
 }
 
+// Sum of z split partials into n outputs: a thread per output when there are
+// many, a block per output when there are few.
+static hipError_t sum_splits(const float *part, int z, long long n, float *out, int accumulate, hipStream_t s) {
+    if (n <= 8192 && z > 16)
+        hipLaunchKernelGGL(k_sum_splits_narrow, dim3((unsigned)n), dim3(256), 0, s, part, z, n, out, accumulate);
+    else
+        hipLaunchKernelGGL(k_sum_splits, dim3(blocks(n, 256)), dim3(256), 0, s, part, z, n, out, accumulate);
+    return hipGetLastError();
+}
+
 hipError_t wgrad(const ConvArgs &a, const uint16_t *g, int g_cs, int g_co, int rows, float *part, int splits,
                  float *dw, int accumulate, hipStream_t s) {
     const long long chunk = wgrad_chunk(a.M, splits);
@@ -443,18 +503,20 @@ hipError_t wgrad(const ConvArgs &a, const uint16_t *g, int g_cs, int g_co, int r
     dim3 grid((unsigned)((rows + BM - 1) / BM), (unsigned)((a.K + BN - 1) / BN), (unsigned)z);
     hipLaunchKernelGGL(k_wgrad, grid, dim3(256), 0, s, a, g, g_cs, g_co, rows, part, chunk);
     const long long n = (long long)rows * a.K;
-    hipLaunchKernelGGL(k_sum_splits, dim3(blocks(n, 256)), dim3(256), 0, s, part, z, n, dw, accumulate);
-    return hipGetLastError();
+    return sum_splits(part, z, n, dw, accumulate, s);
 }
 
 hipError_t bias_grad(const uint16_t *g, int cs, int co, long long npix, int C, float *part, int splits, float *db,
                      int accumulate, hipStream_t s) {
     const long long chunk = (npix + splits - 1) / splits;
-    dim3 grid((unsigned)((C + 63) / 64), (unsigned)splits);
-    hipLaunchKernelGGL(k_bias_grad, grid, dim3(256), 0, s, g, cs, co, npix, C, chunk, part);
-    hipLaunchKernelGGL(k_sum_splits, dim3(blocks(C, 256)), dim3(256), 0, s, part, splits, (long long)C, db,
-                       accumulate);
-    return hipGetLastError();
+    const int z = (int)((npix + chunk - 1) / chunk);
+    if (cs % 8 == 0 && co % 8 == 0 && C % 8 == 0 && C <= 2048 && ((uintptr_t)g & 15) == 0) {
+        hipLaunchKernelGGL(k_bias_grad8, dim3((unsigned)z), dim3(256), 0, s, g, cs, co, npix, C, chunk, part);
+    } else {
+        dim3 grid((unsigned)((C + 63) / 64), (unsigned)z);
+        hipLaunchKernelGGL(k_bias_grad, grid, dim3(256), 0, s, g, cs, co, npix, C, chunk, part);
+    }
+    return sum_splits(part, z, (long long)C, db, accumulate, s);
 }
 
 hipError_t relu_bwd(uint16_t *g, const uint16_t *y, int cs, int co, long long npix, int C, hipStream_t s) {

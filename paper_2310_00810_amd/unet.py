@@ -74,7 +74,7 @@ class UNet:
         self.t = 0
         self._bufs = {}
         self._ws = torch.empty(0, dtype=torch.float32, device=dev)
-        self._bws = torch.empty(64 * 512, dtype=torch.float32, device=dev)
+        self._bws = torch.empty(1 << 18, dtype=torch.float32, device=dev)
         self._mse_part = torch.empty(0, dtype=torch.float64, device=dev)
         self.loss_dev = torch.zeros(1, dtype=torch.float64, device=dev)
         self.init_weights(seed)
@@ -213,7 +213,8 @@ class UNet:
                                         self._ws.numel() * 4, splits, self._stream()), "lbmnn_conv_wgrad")
 
     def _bgrad(self, g, cs, co, pixels, Cn, name):
-        splits = 64
+        # about 2048 pixels per split, bounded by the partials buffer
+        splits = max(1, min(-(-pixels // 2048), self._bws.numel() // Cn))
         C.check(self.L.lbmnn_bias_grad(ctypes.c_void_p(g.data_ptr()), cs, co, pixels, Cn,
                                        _ptr(self.grad, self.boff[name]), 0, _ptr(self._bws), splits,
                                        self._stream()), "lbmnn_bias_grad")
@@ -355,6 +356,25 @@ class UNet:
         C.check(self.L.lbmnn_adam(_ptr(self.master), _ptr(self.grad), _ptr(self.m1), _ptr(self.m2), _ptr(self.wbf),
                                   self.n_params, lr, beta1, beta2, eps, self.t, self._stream()), "lbmnn_adam")
 
+    # ---------------------------------------------------------- accounting --
+    def conv_flops(self, shape):
+        """Algorithmic flops (2 M N K per implicit GEMM) of the convolutions of
+        one forward pass, of the input gradients and of the weight gradients
+        of one backward pass, for input shape (n, d, h, w)."""
+        fwd = dgrad = wgrad = 0
+        for name, (kind, ci, co, ks) in self.layers.items():
+            rows, K = self.wshape[name]
+            lv = 0 if name == "head" else int(name[1])
+            if kind == "tconv":
+                lv += 1                     # runs on the coarser grid
+            M = math.prod(self._grid(shape, lv))
+            f = 2 * M * rows * K
+            fwd += f
+            wgrad += f
+            if name != "e0c0":              # no gradient of the network input
+                dgrad += f
+        return fwd, dgrad, wgrad
+
     def train_step(self, x, target, wpix, lr):
         out = self.forward(x)
         nfl = wpix.sum()  # device scalar, no sync
@@ -363,3 +383,48 @@ class UNet:
         self.backward(g)
         self.adam_step(lr)
         return self.loss_dev
+
+
+def measure(dims, batch, size, steps=5, warmup=2, base=32):
+    """Throughput of the network's kernels on random inputs: milliseconds per
+    training step (forward, loss, backward, Adam) and per forward pass, and the
+    convolution flops per second of each against the dense BF16 MFMA peak
+    (2.5 PFLOP/s)."""
+    net = UNet(dims, base=base)
+    shape = (batch, size if dims == 3 else 1, size, size)
+    g = torch.Generator(device="cuda").manual_seed(0)
+    x = torch.randn(shape + (net.cin,), generator=g, device="cuda").to(BF16)
+    tgt = torch.randn(shape + (net.cout,), generator=g, device="cuda")
+    wpix = torch.ones(shape, device="cuda")
+    for _ in range(warmup):
+        net.train_step(x, tgt, wpix, 1e-4)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(steps):
+        net.train_step(x, tgt, wpix, 1e-4)
+    b.record()
+    torch.cuda.synchronize()
+    train_ms = a.elapsed_time(b) / steps
+    a.record()
+    for _ in range(steps):
+        net.forward(x)
+    b.record()
+    torch.cuda.synchronize()
+    fwd_ms = a.elapsed_time(b) / steps
+    fwd, dgrad, wgrad = net.conv_flops(shape)
+    peak = 2500.0
+    tt = (fwd + dgrad + wgrad) / (train_ms * 1e-3) / 1e12
+    tf = fwd / (fwd_ms * 1e-3) / 1e12
+    return {"dims": dims, "batch": batch, "size": size, "base": base, "params": net.n_params,
+            "train_step_ms": round(train_ms, 3), "forward_ms": round(fwd_ms, 3),
+            "train_conv_gflop": round((fwd + dgrad + wgrad) / 1e9, 2), "forward_conv_gflop": round(fwd / 1e9, 2),
+            "train_tflops": round(tt, 1), "forward_tflops": round(tf, 1), "peak_tflops": peak,
+            "train_frac": round(tt / peak, 4), "forward_frac": round(tf / peak, 4)}
+
+
+if __name__ == "__main__":
+    import json
+    import sys
+    dims = int(sys.argv[1]) if len(sys.argv) > 1 else 2
+    print(json.dumps(measure(dims, 16 if dims == 2 else 2, 256 if dims == 2 else 64)), flush=True)

@@ -46,7 +46,7 @@ extern "C" {
  * lbmnn_weight_transpose), the 2x2(x2) stride-2 transposed convolution
  * (ks = 1, D2S) and its input gradient (ks = 1, S2D). */
 typedef struct lbmnn_conv_desc {
-    int n, d, h, w;          /* GEMM-row grid; d = 1 when dims = 2 */
+    int n, d, h, w;          /* GEMM-row grid; d = 1 when dims = 2; n d h w < 2^31 */
     int dims;                /* 2 or 3 */
     int ks;                  /* 3 or 1 */
     int cin;                 /* A channels per tap (multiple of 8) */

@@ -23,6 +23,8 @@ int check_desc(const lbmnn_conv_desc *c, bool need_out) {
     if (c->ks != 1 && c->ks != 3) return lbm_fail(LBM_EINVAL, "ks must be 1 or 3");
     if (c->n < 1 || c->d < 1 || c->h < 1 || c->w < 1) return lbm_fail(LBM_EINVAL, "grid must be positive");
     if (c->dims == 2 && c->d != 1) return lbm_fail(LBM_EINVAL, "d must be 1 in 2D");
+    if ((long long)c->n * c->d * c->h * c->w >= (1LL << 31))
+        return lbm_fail(LBM_EINVAL, "the grid must have fewer than 2^31 pixels");
     if (!mult8(c->cin) || c->cin == 0) return lbm_fail(LBM_EINVAL, "cin must be a positive multiple of 8");
     if (!mult8(c->in_cstride) || !mult8(c->in_coff)) return lbm_fail(LBM_EINVAL, "input stride/offset must be multiples of 8");
     if (!c->in || !aligned16(c->in)) return lbm_fail(LBM_EINVAL, "input must be a 16-byte aligned device pointer");

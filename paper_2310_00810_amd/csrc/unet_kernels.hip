@@ -37,46 +37,57 @@ __device__ __host__ inline uint16_t f2bf(float f) {
 
 constexpr int BM = 64, BN = 64, BK = 32, LDK = BK + 8;   // LDS rows padded by 16 B
 
-// Pixel index -> (b, z, y, x) on a grid of d x h x w per sample.
+// Pixel index -> (b, z, y, x) on a grid of d x h x w per sample (pixel
+// counts stay below 2^31: checked on the host).
 struct Pix { int b, z, y, x; };
-__device__ inline Pix pix_of(long long m, int d, int h, int w) {
+__device__ inline Pix pix_of(long long m64, int d, int h, int w) {
+    unsigned m = (unsigned)m64;
     Pix p;
-    p.x = (int)(m % w); m /= w;
-    p.y = (int)(m % h); m /= h;
-    p.z = (int)(m % d);
-    p.b = (int)(m / d);
+    unsigned q = m / (unsigned)w;
+    p.x = (int)(m - q * (unsigned)w);
+    m = q;
+    q = m / (unsigned)h;
+    p.y = (int)(m - q * (unsigned)h);
+    m = q;
+    q = m / (unsigned)d;
+    p.z = (int)(m - q * (unsigned)d);
+    p.b = (int)q;
     return p;
 }
 
-// Eight consecutive K entries of the implicit im2col row of pixel m starting
-// at k (16 bytes), or zeros.  Normal mode: k = tap * cin + ci over a ks^dims
-// stencil centred on the pixel (zero padding).  S2D mode: k = sub * cin + ci
-// reads the fine-grid pixel (2z+sz, 2y+sy, 2x+sx), sub = sx + 2 sy + 4 sz.
-__device__ inline uint4 load_im2col(const ConvArgs &a, long long m, int k) {
-    uint4 z4 = make_uint4(0, 0, 0, 0);
-    if (m >= a.M || k >= a.K) return z4;
-    const Pix p = pix_of(m, a.d, a.h, a.w);
-    const int tap = k / a.cin, ci = k - tap * a.cin;
+// K entry k of the implicit im2col matrix: channel ci and stencil offset
+// (normal mode: k = tap * cin + ci over a ks^dims stencil centred on the
+// pixel) or fine-grid sub-pixel (S2D mode: k = sub * cin + ci reads pixel
+// (2z+sz, 2y+sy, 2x+sx), sub = sx + 2 sy + 4 sz).
+struct Tap { int ci, dx, dy, dz; };
+__device__ inline Tap tap_of(const ConvArgs &a, int k) {
+    Tap t;
+    const int tap = (int)((unsigned)k / (unsigned)a.cin);
+    t.ci = k - tap * a.cin;
+    if (a.flags & FLAG_S2D) {
+        t.dx = tap & 1; t.dy = (tap >> 1) & 1; t.dz = (tap >> 2) & 1;
+    } else if (a.ks == 3) {
+        t.dx = tap % 3 - 1; t.dy = (tap / 3) % 3 - 1; t.dz = a.dims == 3 ? tap / 9 - 1 : 0;
+    } else {
+        t.dx = t.dy = t.dz = 0;
+    }
+    return t;
+}
+
+// Eight consecutive K entries (16 bytes) of the im2col row of pixel p at tap
+// t, or zeros outside the grid (zero padding).
+__device__ inline uint4 im2col_at(const ConvArgs &a, const Pix &p, const Tap &t) {
     long long src;
     if (a.flags & FLAG_S2D) {
-        const int sx = tap & 1, sy = (tap >> 1) & 1, sz = (tap >> 2) & 1;
         const int fd = a.dims == 3 ? 2 * a.d : 1, fh = 2 * a.h, fw = 2 * a.w;
-        const int zf = a.dims == 3 ? 2 * p.z + sz : 0;
-        src = (((long long)p.b * fd + zf) * fh + 2 * p.y + sy) * fw + 2 * p.x + sx;
+        const int zf = a.dims == 3 ? 2 * p.z + t.dz : 0;
+        src = (((long long)p.b * fd + zf) * fh + 2 * p.y + t.dy) * fw + 2 * p.x + t.dx;
     } else {
-        const int r = a.ks >> 1;
-        int dx = 0, dy = 0, dz = 0;
-        if (a.ks == 3) {
-            dx = tap % 3 - 1;
-            dy = (tap / 3) % 3 - 1;
-            dz = a.dims == 3 ? tap / 9 - 1 : 0;
-        }
-        (void)r;
-        const int xs = p.x + dx, ys = p.y + dy, zs = p.z + dz;
-        if (xs < 0 || xs >= a.w || ys < 0 || ys >= a.h || zs < 0 || zs >= a.d) return z4;
+        const int xs = p.x + t.dx, ys = p.y + t.dy, zs = p.z + t.dz;
+        if (xs < 0 || xs >= a.w || ys < 0 || ys >= a.h || zs < 0 || zs >= a.d) return make_uint4(0, 0, 0, 0);
         src = (((long long)p.b * a.d + zs) * a.h + ys) * a.w + xs;
     }
-    return *(const uint4 *)(a.in + src * a.in_cs + a.in_co + ci);
+    return *(const uint4 *)(a.in + src * a.in_cs + a.in_co + t.ci);
 }
 
 __device__ inline bf16x8 as_bf16x8(uint4 v) { return __builtin_bit_cast(bf16x8, v); }
@@ -113,8 +124,12 @@ __global__ void __launch_bounds__(256) k_conv(ConvArgs a) {
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // the thread's im2col row (pixel) is fixed over the K loop
+    const bool mvalid = m0 + lr < a.M;
+    const Pix pix = pix_of(mvalid ? m0 + lr : 0, a.d, a.h, a.w);
     for (int k0 = 0; k0 < a.K; k0 += BK) {
-        const uint4 av = load_im2col(a, m0 + lr, k0 + lk);
+        const int k = k0 + lk;
+        const uint4 av = mvalid && k < a.K ? im2col_at(a, pix, tap_of(a, k)) : make_uint4(0, 0, 0, 0);
         uint4 bv = make_uint4(0, 0, 0, 0);
         if (n0 + lr < a.ncols && k0 + lk < a.K) bv = *(const uint4 *)(a.wt + (long long)(n0 + lr) * a.K + k0 + lk);
         __syncthreads();
@@ -176,6 +191,9 @@ __global__ void __launch_bounds__(256) k_wgrad(ConvArgs a, const uint16_t *__res
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     const bool s2d_g = (a.flags & FLAG_S2D_G) != 0;
+    // the thread's im2col column (tap, channel) is fixed over the pixel loop
+    const bool kvalid = c0 + ls < a.K;
+    const Tap tap = tap_of(a, kvalid ? c0 + ls : 0);
     for (long long mm = mb; mm < me; mm += BK) {
         const long long m = mm + lm;
         uint4 gv = make_uint4(0, 0, 0, 0);
@@ -195,7 +213,7 @@ __global__ void __launch_bounds__(256) k_wgrad(ConvArgs a, const uint16_t *__res
             }
             gv = *(const uint4 *)(g + src * g_cs + g_co + ch);
         }
-        const uint4 tv = m < me ? load_im2col(a, m, c0 + ls) : make_uint4(0, 0, 0, 0);
+        const uint4 tv = m < me && kvalid ? im2col_at(a, pix_of(m, a.d, a.h, a.w), tap) : make_uint4(0, 0, 0, 0);
         __syncthreads();
         const uint16_t *gp = (const uint16_t *)&gv, *tp = (const uint16_t *)&tv;
 #pragma unroll

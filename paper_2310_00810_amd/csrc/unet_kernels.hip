@@ -74,20 +74,53 @@ __device__ inline Tap tap_of(const ConvArgs &a, int k) {
     return t;
 }
 
-// Eight consecutive K entries (16 bytes) of the im2col row of pixel p at tap
-// t, or zeros outside the grid (zero padding).
-__device__ inline uint4 im2col_at(const ConvArgs &a, const Pix &p, const Tap &t) {
-    long long src;
+// The pixel of an im2col row, resolved once: its coordinates and the element
+// offset of its first input channel (normal mode: the pixel itself; S2D: the
+// fine-grid pixel (2z, 2y, 2x)).
+struct Row { long long base; int x, y, z; bool valid; };
+__device__ inline Row row_of(const ConvArgs &a, long long m) {
+    Row r;
+    r.valid = m < a.M;
+    const Pix p = pix_of(r.valid ? m : 0, a.d, a.h, a.w);
+    r.x = p.x; r.y = p.y; r.z = p.z;
+    long long px;
     if (a.flags & FLAG_S2D) {
         const int fd = a.dims == 3 ? 2 * a.d : 1, fh = 2 * a.h, fw = 2 * a.w;
-        const int zf = a.dims == 3 ? 2 * p.z + t.dz : 0;
-        src = (((long long)p.b * fd + zf) * fh + 2 * p.y + t.dy) * fw + 2 * p.x + t.dx;
+        px = (((long long)p.b * fd + (a.dims == 3 ? 2 * p.z : 0)) * fh + 2 * p.y) * fw + 2 * p.x;
     } else {
-        const int xs = p.x + t.dx, ys = p.y + t.dy, zs = p.z + t.dz;
-        if (xs < 0 || xs >= a.w || ys < 0 || ys >= a.h || zs < 0 || zs >= a.d) return make_uint4(0, 0, 0, 0);
-        src = (((long long)p.b * a.d + zs) * a.h + ys) * a.w + xs;
+        px = (((long long)p.b * a.d + p.z) * a.h + p.y) * a.w + p.x;
     }
-    return *(const uint4 *)(a.in + src * a.in_cs + a.in_co + t.ci);
+    r.base = px * a.in_cs + a.in_co;
+    return r;
+}
+
+// A K entry resolved once per step: its tap offset from a row's base and the
+// stencil displacement (for the zero-padding test).
+struct KOff { long long delta; int dx, dy, dz; bool valid; };
+__device__ inline KOff koff_of(const ConvArgs &a, int k) {
+    KOff o;
+    o.valid = k < a.K;
+    const Tap t = tap_of(a, o.valid ? k : 0);
+    o.dx = t.dx; o.dy = t.dy; o.dz = t.dz;
+    long long d;
+    if (a.flags & FLAG_S2D) {
+        const int fh = 2 * a.h, fw = 2 * a.w;
+        d = ((long long)t.dz * fh + t.dy) * fw + t.dx;
+    } else {
+        d = ((long long)t.dz * a.h + t.dy) * a.w + t.dx;
+    }
+    o.delta = d * a.in_cs + t.ci;
+    return o;
+}
+
+// 16 bytes of the im2col matrix at (row, K offset), zero outside the grid.
+__device__ inline uint4 im2col_load(const ConvArgs &a, const Row &r, const KOff &o) {
+    bool ok = r.valid && o.valid;
+    if (!(a.flags & FLAG_S2D)) {
+        const unsigned xs = (unsigned)(r.x + o.dx), ys = (unsigned)(r.y + o.dy), zs = (unsigned)(r.z + o.dz);
+        ok = ok && xs < (unsigned)a.w && ys < (unsigned)a.h && zs < (unsigned)a.d;
+    }
+    return ok ? *(const uint4 *)(a.in + r.base + o.delta) : make_uint4(0, 0, 0, 0);
 }
 
 __device__ inline bf16x8 as_bf16x8(uint4 v) { return __builtin_bit_cast(bf16x8, v); }
@@ -111,51 +144,85 @@ __device__ inline long long out_index(const ConvArgs &a, long long m, int c, int
 }
 
 // C[M x ncols] = im2col(in)[M x K] * W^T, W stored [ncols][K].
+// A block computes a TBM x TBN tile with four wavefronts (2 x 2, each
+// TBM/2 x TBN/2 of 16 x 16 x 32 BF16 MFMA tiles) over K steps of 64.  The
+// LDS tiles are double-buffered: the next step's global loads are issued
+// before the current step's MFMAs and land in the other buffer, so a step
+// needs one barrier.  TBN = 32 serves the 32- and 8-channel layers without
+// computing zero columns.
+template <int TBM, int TBN>
 __global__ void __launch_bounds__(256) k_conv(ConvArgs a) {
-    __shared__ uint16_t As[BM][LDK];
-    __shared__ uint16_t Bs[BN][LDK];
+    constexpr int KB = 64, LD = KB + 8;             // LDS rows padded by 16 B
+    constexpr int WM = TBM / 2, WN = TBN / 2;
+    constexpr int TI = WM / 16, TJ = WN / 16;
+    constexpr int AL = TBM * 8 / 256, BL = TBN * 8 / 256;   // 16-byte loads per thread
+    __shared__ uint16_t As[2][TBM][LD];
+    __shared__ uint16_t Bs[2][TBN][LD];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int wm = wave & 1, wn = wave >> 1;
-    const long long m0 = (long long)blockIdx.x * BM;
-    const int n0 = blockIdx.y * BN;
-    const int lr = t >> 2, lk = (t & 3) * 8;
-    f32x4 acc[2][2];
+    const long long m0 = (long long)blockIdx.x * TBM;
+    const int n0 = blockIdx.y * TBN;
+    const int kq = (t & 7) * 8;
+    // rows of the im2col tile this thread loads: t / 8 + 32 l; their pixels are fixed
+    Row row[AL];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int l = 0; l < AL; ++l) row[l] = row_of(a, m0 + (t >> 3) + 32 * l);
+    uint4 ra[AL], rb[BL];
+    auto load = [&](int k0) {
+        const int k = k0 + kq;
+        const bool kval = k < a.K;
+        const KOff ko = koff_of(a, k);
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    // the thread's im2col row (pixel) is fixed over the K loop
-    const bool mvalid = m0 + lr < a.M;
-    const Pix pix = pix_of(mvalid ? m0 + lr : 0, a.d, a.h, a.w);
-    for (int k0 = 0; k0 < a.K; k0 += BK) {
-        const int k = k0 + lk;
-        const uint4 av = mvalid && k < a.K ? im2col_at(a, pix, tap_of(a, k)) : make_uint4(0, 0, 0, 0);
-        uint4 bv = make_uint4(0, 0, 0, 0);
-        if (n0 + lr < a.ncols && k0 + lk < a.K) bv = *(const uint4 *)(a.wt + (long long)(n0 + lr) * a.K + k0 + lk);
-        __syncthreads();
-        *(uint4 *)&As[lr][lk] = av;
-        *(uint4 *)&Bs[lr][lk] = bv;
-        __syncthreads();
-        const int kr = (lane >> 4) * 8;
+        for (int l = 0; l < AL; ++l) ra[l] = im2col_load(a, row[l], ko);
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            const bf16x8 fa = as_bf16x8(*(const uint4 *)&As[wm * 32 + i * 16 + (lane & 15)][kr]);
+        for (int l = 0; l < BL; ++l) {
+            const int n = n0 + (t >> 3) + 32 * l;
+            rb[l] = n < a.ncols && kval ? *(const uint4 *)(a.wt + (long long)n * a.K + k) : make_uint4(0, 0, 0, 0);
+        }
+    };
+    auto stash = [&](int buf) {
 #pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                const bf16x8 fb = as_bf16x8(*(const uint4 *)&Bs[wn * 32 + j * 16 + (lane & 15)][kr]);
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, fb, acc[i][j], 0, 0, 0);
+        for (int l = 0; l < AL; ++l) *(uint4 *)&As[buf][(t >> 3) + 32 * l][kq] = ra[l];
+#pragma unroll
+        for (int l = 0; l < BL; ++l) *(uint4 *)&Bs[buf][(t >> 3) + 32 * l][kq] = rb[l];
+    };
+    f32x4 acc[TI][TJ];
+#pragma unroll
+    for (int i = 0; i < TI; ++i)
+#pragma unroll
+        for (int j = 0; j < TJ; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int steps = (a.K + KB - 1) / KB;
+    load(0);
+    stash(0);
+    __syncthreads();
+    for (int s = 0; s < steps; ++s) {
+        const int buf = s & 1;
+        if (s + 1 < steps) load((s + 1) * KB);
+#pragma unroll
+        for (int kh = 0; kh < KB; kh += 32) {
+            const int kr = kh + (lane >> 4) * 8;
+            bf16x8 fb[TJ];
+#pragma unroll
+            for (int j = 0; j < TJ; ++j) fb[j] = as_bf16x8(*(const uint4 *)&Bs[buf][wn * WN + j * 16 + (lane & 15)][kr]);
+#pragma unroll
+            for (int i = 0; i < TI; ++i) {
+                const bf16x8 fa = as_bf16x8(*(const uint4 *)&As[buf][wm * WM + i * 16 + (lane & 15)][kr]);
+#pragma unroll
+                for (int j = 0; j < TJ; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, fb[j], acc[i][j], 0, 0, 0);
             }
         }
+        if (s + 1 < steps) stash(buf ^ 1);
+        __syncthreads();
     }
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < TI; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const int c = n0 + wn * 32 + j * 16 + (lane & 15);
+        for (int j = 0; j < TJ; ++j) {
+            const int c = n0 + wn * WN + j * 16 + (lane & 15);
             if (c >= a.ncols) continue;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const long long m = m0 + wm * 32 + i * 16 + (lane >> 4) * 4 + q;
+                const long long m = m0 + wm * WM + i * 16 + (lane >> 4) * 4 + q;
                 if (m >= a.M) continue;
                 int bc;
                 const long long o = out_index(a, m, c, bc);
@@ -192,8 +259,7 @@ __global__ void __launch_bounds__(256) k_wgrad(ConvArgs a, const uint16_t *__res
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     const bool s2d_g = (a.flags & FLAG_S2D_G) != 0;
     // the thread's im2col column (tap, channel) is fixed over the pixel loop
-    const bool kvalid = c0 + ls < a.K;
-    const Tap tap = tap_of(a, kvalid ? c0 + ls : 0);
+    const KOff ko = koff_of(a, c0 + ls);
     for (long long mm = mb; mm < me; mm += BK) {
         const long long m = mm + lm;
         uint4 gv = make_uint4(0, 0, 0, 0);
@@ -213,7 +279,7 @@ __global__ void __launch_bounds__(256) k_wgrad(ConvArgs a, const uint16_t *__res
             }
             gv = *(const uint4 *)(g + src * g_cs + g_co + ch);
         }
-        const uint4 tv = m < me && kvalid ? im2col_at(a, pix_of(m, a.d, a.h, a.w), tap) : make_uint4(0, 0, 0, 0);
+        const uint4 tv = m < me ? im2col_load(a, row_of(a, m), ko) : make_uint4(0, 0, 0, 0);
         __syncthreads();
         const uint16_t *gp = (const uint16_t *)&gv, *tp = (const uint16_t *)&tv;
 #pragma unroll
@@ -494,8 +560,13 @@ __global__ void k_denormalize(const float *__restrict__ pred, int pcs, const uin
 static inline unsigned blocks(long long n, int b) { return (unsigned)((n + b - 1) / b); }
 
 hipError_t conv(const ConvArgs &a, hipStream_t s) {
-    dim3 grid(blocks(a.M, BM), (unsigned)((a.ncols + BN - 1) / BN));
-    hipLaunchKernelGGL(k_conv, grid, dim3(256), 0, s, a);
+    if (a.ncols <= 32) {
+        dim3 grid(blocks(a.M, 128), (unsigned)((a.ncols + 31) / 32));
+        hipLaunchKernelGGL((k_conv<128, 32>), grid, dim3(256), 0, s, a);
+    } else {
+        dim3 grid(blocks(a.M, 64), (unsigned)((a.ncols + 63) / 64));
+        hipLaunchKernelGGL((k_conv<64, 64>), grid, dim3(256), 0, s, a);
+    }
     return hipGetLastError();
 }
 

@@ -27,7 +27,11 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(HERE, "liblbm_oracle.so")
 
-BC_PRESSURE, BC_PERIODIC, BC_WALL, BC_ABB = 0, 1, 2, 3
+BC_PRESSURE, BC_PERIODIC, BC_WALL, BC_ABB, BC_VELOCITY = 0, 1, 2, 3, 4
+# D2Q9 multiple-relaxation-time rates (rho, e, eps, jx, qx, jy, qy, pxx, pxy);
+# the stress rates are replaced by 1/tau.  Conserved moments 1.0; the others
+# from the commonly used set of Lallemand & Luo.
+MRT_RATES = (1.0, 1.64, 1.54, 1.0, 1.9, 1.0, 1.9, 1.0, 1.0)
 LOSS_VEC, LOSS_NORM = 0, 1
 
 C2 = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [-1, 0, 0], [0, -1, 0],
@@ -71,15 +75,17 @@ def _f64(a):
 
 class Lattice:
     """Geometry of one lattice: q in {9, 19}, shape (nz, ny, nx), per-axis
-    boundary kind (x, y, z) and an optional solid mask."""
+    boundary kind (x, y, z), an optional solid mask and, for D2Q9, optional
+    multiple-relaxation-time rates (None = BGK)."""
 
-    def __init__(self, q, nx, ny, nz=1, bc=(BC_PRESSURE, BC_WALL, BC_PERIODIC), solid=None):
+    def __init__(self, q, nx, ny, nz=1, bc=(BC_PRESSURE, BC_WALL, BC_PERIODIC), solid=None, mrt=None):
         self.q, self.nx, self.ny, self.nz = int(q), int(nx), int(ny), int(nz)
         self.bc = (ctypes.c_int * 3)(*bc)
         self.bc_tuple = tuple(bc)
         if solid is None:
             solid = np.zeros((nz, ny, nx), np.uint8)
         self.solid = np.ascontiguousarray(solid.reshape(nz, ny, nx), dtype=np.uint8)
+        self.mrt = None if mrt is None else _f64(np.asarray(mrt, np.float64).reshape(9))
 
     @property
     def shape(self):
@@ -87,7 +93,7 @@ class Lattice:
 
     def args(self):
         return (self.q, self.nx, self.ny, self.nz, self.bc,
-                self.solid.ctypes.data_as(ctypes.POINTER(ctypes.c_ubyte)))
+                self.solid.ctypes.data_as(ctypes.POINTER(ctypes.c_ubyte)), _p(self.mrt))
 
     def face(self, value):
         """Broadcast a scalar or (nz, ny) array to a face density array."""
@@ -196,13 +202,23 @@ def stream_adj(lat, gbar):
     return fsbar
 
 
-def zouhe_adj(lat, gbar):
-    """(gbar after the Zou-He transpose, d/drho_in, d/drho_out) per face node."""
+def zouhe_adj(lat, gbar, g=None, rho_in=None):
+    """(gbar after the Zou-He transpose, d/drho_in, d/drho_out) per face node.
+    A velocity inlet also needs the completed state g and the inlet values."""
     gbar = _f64(gbar).copy()
     din = np.zeros((lat.nz, lat.ny))
     dout = np.zeros((lat.nz, lat.ny))
-    lib().orc_zouhe_adj(*lat.args(), _p(gbar), _p(din), _p(dout))
+    gp = _p(_f64(g)) if g is not None else None
+    rp = _p(lat.face(rho_in)) if rho_in is not None else None
+    lib().orc_zouhe_adj(*lat.args(), gp, rp, _p(gbar), _p(din), _p(dout))
     return gbar, din, dout
+
+
+def mrt_matrix():
+    """The D2Q9 moment basis M (9 x 9) as the oracle builds it."""
+    m = np.zeros((9, 9))
+    lib().orc_mrt_matrix(_p(m))
+    return m
 
 
 def grad(lat, tau, rho_in, rho_out, f0, T, target_u, weight=None, kind=LOSS_VEC,

@@ -33,7 +33,7 @@
 
 #define ORC_QMAX 19
 
-enum { ORC_BC_PRESSURE = 0, ORC_BC_PERIODIC = 1, ORC_BC_WALL = 2, ORC_BC_ABB = 3 };
+enum { ORC_BC_PRESSURE = 0, ORC_BC_PERIODIC = 1, ORC_BC_WALL = 2, ORC_BC_ABB = 3, ORC_BC_VELOCITY = 4 };
 enum { ORC_LOSS_VEC = 0, ORC_LOSS_NORM = 1 };
 enum { ORC_LINK_NORMAL = 0, ORC_LINK_BOUNCE = 1, ORC_LINK_DROP = 2 };
 
@@ -44,12 +44,16 @@ typedef struct {
     int opp[ORC_QMAX];
 } orc_velset;
 
-/* Geometry of one lattice.  solid may be NULL (all fluid). */
+/* Geometry of one lattice.  solid may be NULL (all fluid).  mrt: NULL for
+ * BGK; else the nine D2Q9 multiple-relaxation-time rates in the order of
+ * the moments (rho, e, eps, jx, qx, jy, qy, pxx, pxy); the two stress rates
+ * (entries 7, 8) are ignored and set to 1/tau. */
 typedef struct {
     int q;                       /* 9 or 19 */
     int nx, ny, nz;              /* nz = 1 for D2Q9 */
-    int bc[3];                   /* per axis, ORC_BC_*; PRESSURE and ABB only on x */
+    int bc[3];                   /* per axis, ORC_BC_*; PRESSURE, ABB and VELOCITY only on x */
     const unsigned char *solid;  /* [nz][ny][nx], nonzero = solid */
+    const double *mrt;
 } orc_lattice;
 
 /* D2Q9: rest, 4 axis links, 4 diagonals; w = 4/9, 1/9, 1/36. */
@@ -122,7 +126,7 @@ static int orc_link_target(const orc_lattice *L, const int x[3], const int c[3],
         if (y[a] >= 0 && y[a] < n[a]) continue;
         if (L->bc[a] == ORC_BC_PERIODIC) {
             y[a] = (y[a] + n[a]) % n[a];
-        } else if (L->bc[a] == ORC_BC_PRESSURE || L->bc[a] == ORC_BC_ABB) {
+        } else if (L->bc[a] == ORC_BC_PRESSURE || L->bc[a] == ORC_BC_ABB || L->bc[a] == ORC_BC_VELOCITY) {
             outside_pressure = 1;
         } else {
             outside_wall = 1;
@@ -133,6 +137,45 @@ static int orc_link_target(const orc_lattice *L, const int x[3], const int c[3],
     if (outside_pressure) return ORC_LINK_DROP;
     if (outside_wall) return ORC_LINK_BOUNCE;
     return ORC_LINK_NORMAL;
+}
+
+/* ---- D2Q9 moment basis for the multiple-relaxation-time collision -------
+ * (Section 3.4, after Lallemand & Luo): rows are polynomials of the lattice
+ * velocity, evaluated on the D2Q9 set:
+ *   rho: 1,  e: -4 + 3|c|^2,  eps: 4 - 21/2 |c|^2 + 9/2 |c|^4,
+ *   jx: c_x,  qx: (-5 + 3|c|^2) c_x,  jy: c_y,  qy: (-5 + 3|c|^2) c_y,
+ *   pxx: c_x^2 - c_y^2,  pxy: c_x c_y.
+ * The rows are mutually orthogonal, so M^-1 = M^T diag(1 / |row|^2). */
+static double ORC_M[9][9], ORC_MNORM[9];
+static void orc_mrt_basis(void)
+{
+    static int ready = 0;
+    if (ready) return;
+    const orc_velset *V = orc_vel(9);
+    for (int i = 0; i < 9; i++) {
+        const double cx = V->c[i][0], cy = V->c[i][1], c2 = cx * cx + cy * cy;
+        ORC_M[0][i] = 1;
+        ORC_M[1][i] = -4 + 3 * c2;
+        ORC_M[2][i] = 4 - 10.5 * c2 + 4.5 * c2 * c2;
+        ORC_M[3][i] = cx;
+        ORC_M[4][i] = (-5 + 3 * c2) * cx;
+        ORC_M[5][i] = cy;
+        ORC_M[6][i] = (-5 + 3 * c2) * cy;
+        ORC_M[7][i] = cx * cx - cy * cy;
+        ORC_M[8][i] = cx * cy;
+    }
+    for (int r = 0; r < 9; r++) {
+        ORC_MNORM[r] = 0;
+        for (int i = 0; i < 9; i++) ORC_MNORM[r] += ORC_M[r][i] * ORC_M[r][i];
+    }
+    ready = 1;
+}
+
+void orc_mrt_matrix(double *m)
+{
+    orc_mrt_basis();
+    for (int r = 0; r < 9; r++)
+        for (int i = 0; i < 9; i++) m[r * 9 + i] = ORC_M[r][i];
 }
 
 /* ---------------- real and complex builds of the forward map ------------- */
@@ -154,15 +197,18 @@ static int orc_link_target(const orc_lattice *L, const int x[3], const int c[3],
 
 /* ---------------- exported forward entry points (real) ------------------- */
 static void orc_make(orc_lattice *L, int q, int nx, int ny, int nz, const int *bc,
-                     const unsigned char *solid)
+                     const unsigned char *solid, const double *mrt)
 {
     L->q = q; L->nx = nx; L->ny = ny; L->nz = nz;
     L->bc[0] = bc[0]; L->bc[1] = bc[1]; L->bc[2] = bc[2];
     L->solid = solid;
+    L->mrt = q == 9 ? mrt : NULL;
+    orc_mrt_basis();
 }
 
-#define ORC_ARGS int q, int nx, int ny, int nz, const int *bc, const unsigned char *solid
-#define ORC_MAKE orc_lattice L; orc_make(&L, q, nx, ny, nz, bc, solid)
+#define ORC_ARGS int q, int nx, int ny, int nz, const int *bc, const unsigned char *solid, const double *mrt
+#define ORC_MAKE orc_lattice L; orc_make(&L, q, nx, ny, nz, bc, solid, mrt)
+#define ORC_PASS q, nx, ny, nz, bc, solid, mrt
 
 void orc_equilibrium(int q, double rho, const double *u, double *feq)
 {
@@ -286,6 +332,56 @@ static void orc_collide_adj_node(int q, double tau, const double *f, const doubl
     }
 }
 
+/* Transpose of the MRT collision at one node.  With A = M^-1 S M and J the
+ * Jacobian of feq(f), fs = f - A (f - feq) has the Jacobian I - A (I - J), so
+ *   fbar = fsbar - mu + J^T mu,   mu = A^T fsbar = M^T S M^-T fsbar,
+ * and only the stress rates depend on tau (d s / d tau = -1/tau^2):
+ *   d L / d tau = sum_{r stress} (M^-T fsbar)_r (M (f - feq))_r / tau^2. */
+static void orc_collide_adj_node_mrt(const double *rates, double tau, const double *f, const double *fsbar,
+                                     double *fbar, double *dtau)
+{
+    const orc_velset *V = orc_vel(9);
+    const double cs2 = 1.0 / 3.0;
+    double rho = 0, j[3] = {0, 0, 0};
+    for (int i = 0; i < 9; i++) {
+        rho += f[i];
+        for (int a = 0; a < 3; a++) j[a] += f[i] * V->c[i][a];
+    }
+    double u[3] = {j[0] / rho, j[1] / rho, j[2] / rho};
+    double feq[9];
+    orc_equilibrium_d(9, rho, u, feq);
+    double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    double y[9], mu[9], md[9];
+    for (int r = 0; r < 9; r++) {                 /* y = M^-T fsbar, md = M (f - feq) */
+        double a = 0, b = 0;
+        for (int i = 0; i < 9; i++) {
+            a += ORC_M[r][i] * fsbar[i];
+            b += ORC_M[r][i] * (f[i] - feq[i]);
+        }
+        y[r] = a / ORC_MNORM[r];
+        md[r] = b;
+    }
+    for (int r = 7; r < 9; r++) *dtau += y[r] * md[r] / (tau * tau);
+    for (int i = 0; i < 9; i++) {                 /* mu = M^T S y */
+        double a = 0;
+        for (int r = 0; r < 9; r++) a += ORC_M[r][i] * (r >= 7 ? 1.0 / tau : rates[r]) * y[r];
+        mu[i] = a;
+    }
+    for (int i = 0; i < 9; i++) fbar[i] = fsbar[i] - mu[i];
+    for (int k = 0; k < 9; k++) {                 /* + J^T mu, J_ki = d feq_k / d f_i */
+        double uc = u[0] * V->c[k][0] + u[1] * V->c[k][1];
+        double dfeq_drho = V->w[k] * (1.0 + uc / cs2 + uc * uc / (2 * cs2 * cs2) - uu / (2 * cs2));
+        double dfeq_du[3];
+        for (int a = 0; a < 3; a++)
+            dfeq_du[a] = V->w[k] * rho * (V->c[k][a] / cs2 + uc * V->c[k][a] / (cs2 * cs2) - u[a] / cs2);
+        for (int i = 0; i < 9; i++) {
+            double d = dfeq_drho;
+            for (int a = 0; a < 3; a++) d += dfeq_du[a] * (V->c[i][a] - u[a]) / rho;
+            fbar[i] += mu[k] * d;
+        }
+    }
+}
+
 void orc_collide_adj(ORC_ARGS, double tau, const double *f, const double *fsbar,
                      double *fbar, double *dtau)
 {
@@ -297,7 +393,10 @@ void orc_collide_adj(ORC_ARGS, double tau, const double *f, const double *fsbar,
             for (int i = 0; i < q; i++) fbar[k * q + i] = 0;
             continue;
         }
-        orc_collide_adj_node(q, tau, &f[k * q], &fsbar[k * q], &fbar[k * q], &acc);
+        if (L.mrt)
+            orc_collide_adj_node_mrt(L.mrt, tau, &f[k * q], &fsbar[k * q], &fbar[k * q], &acc);
+        else
+            orc_collide_adj_node(q, tau, &f[k * q], &fsbar[k * q], &fbar[k * q], &acc);
     }
     *dtau += acc;
 }
@@ -339,8 +438,8 @@ void orc_stream_adj(ORC_ARGS, const double *gbar, double *fsbar)
  * from J to rho_b with +1 and to the known populations with -1 or -2), and
  * to the tangential sums. The unknowns' incoming values were overwritten,
  * so their adjoint is zero afterwards. */
-static void orc_zouhe_face_adj(const orc_lattice *L, int face_x, int s, double *gbar,
-                               double *drho_b)
+static void orc_zouhe_face_adj(const orc_lattice *L, int face_x, int s, const double *g,
+                               const double *rho_b, double *gbar, double *drho_b, int velocity)
 {
     const orc_velset *V = orc_vel(L->q);
     const int q = L->q;
@@ -360,25 +459,41 @@ static void orc_zouhe_face_adj(const orc_lattice *L, int face_x, int s, double *
                 Nzbar -= V->c[i][2] * gb[i];
                 gb[i] = 0;
             }
-            drho_b[z * L->ny + y] += Jbar;
+            /* J = rho_b - K (density), or J = K u / (1 - u) (velocity) */
+            double dJdK = -1.0;
+            if (velocity) {
+                double K = 0;
+                for (int i = 0; i < q; i++) {
+                    if (V->c[i][0] == 0) K += g[k * q + i];
+                    else if (V->c[i][0] == -s) K += 2.0 * g[k * q + i];
+                }
+                const double ub = rho_b[z * L->ny + y];
+                dJdK = ub / (1.0 - ub);
+                drho_b[z * L->ny + y] += Jbar * K / ((1.0 - ub) * (1.0 - ub));
+            } else {
+                drho_b[z * L->ny + y] += Jbar;
+            }
             for (int i = 0; i < q; i++) {
                 if (V->c[i][0] == 0) {
-                    gb[i] += -Jbar + 0.5 * V->c[i][1] * Nybar + 0.5 * V->c[i][2] * Nzbar;
+                    gb[i] += dJdK * Jbar + 0.5 * V->c[i][1] * Nybar + 0.5 * V->c[i][2] * Nzbar;
                 } else if (V->c[i][0] == -s) {
-                    gb[i] += -2.0 * Jbar;
+                    gb[i] += 2.0 * dJdK * Jbar;
                 }
             }
         }
     }
 }
 
-void orc_zouhe_adj(ORC_ARGS, double *gbar, double *drho_in, double *drho_out)
+/* g: the state the closure completed (its known populations are read by the
+ * velocity face; may be NULL for density faces); rho_in: the inlet values. */
+void orc_zouhe_adj(ORC_ARGS, const double *g, const double *rho_in, double *gbar, double *drho_in,
+                   double *drho_out)
 {
     ORC_MAKE;
-    if (L.bc[0] != ORC_BC_PRESSURE) return;
+    if (L.bc[0] != ORC_BC_PRESSURE && L.bc[0] != ORC_BC_VELOCITY) return;
     /* reverse order of the forward pass (inlet, then outlet) */
-    orc_zouhe_face_adj(&L, nx - 1, -1, gbar, drho_out);
-    orc_zouhe_face_adj(&L, 0, +1, gbar, drho_in);
+    orc_zouhe_face_adj(&L, nx - 1, -1, g, NULL, gbar, drho_out, 0);
+    orc_zouhe_face_adj(&L, 0, +1, g, rho_in, gbar, drho_in, L.bc[0] == ORC_BC_VELOCITY);
 }
 
 /* Transpose of one anti-bounce-back face.  The forward pass wrote
@@ -499,7 +614,7 @@ double orc_grad(ORC_ARGS, double tau, const double *rho_in, const double *rho_ou
     double loss = orc_loss_d(&L, f, target_u, weight, kind, scale);
     for (long k = 0; k < nf; k++) drho_in[k] = drho_out[k] = 0;
     *dtau = 0;
-    orc_loss_seed(q, nx, ny, nz, bc, solid, f, target_u, weight, kind, scale, a);
+    orc_loss_seed(ORC_PASS, f, target_u, weight, kind, scale, a);
     for (int c = nseg - 1; c >= 0; c--) {
         int t0 = c * K, t1 = (c + 1) * K < T ? (c + 1) * K : T;
         memcpy(&seg[0], &ckpt[c * nq], sizeof(double) * (size_t)nq);
@@ -515,14 +630,22 @@ double orc_grad(ORC_ARGS, double tau, const double *rho_in, const double *rho_ou
                 memcpy(scratch, fprev, sizeof(double) * (size_t)nq);
                 orc_collide_d(&L, tau, scratch);
                 for (long k = 0; k < nq; k++) fsb[k] = 0;
-                orc_abb_adj(q, nx, ny, nz, bc, solid, rho_in, rho_out, scratch, a, fsb, drho_in, drho_out);
-                orc_stream_adj(q, nx, ny, nz, bc, solid, a, b);
+                orc_abb_adj(ORC_PASS, rho_in, rho_out, scratch, a, fsb, drho_in, drho_out);
+                orc_stream_adj(ORC_PASS, a, b);
                 for (long k = 0; k < nq; k++) b[k] += fsb[k];
             } else {
-                orc_zouhe_adj(q, nx, ny, nz, bc, solid, a, drho_in, drho_out);
-                orc_stream_adj(q, nx, ny, nz, bc, solid, a, b);
+                const double *gt = NULL;
+                if (L.bc[0] == ORC_BC_VELOCITY) {
+                    /* the closure's known populations at step t */
+                    memcpy(scratch, fprev, sizeof(double) * (size_t)nq);
+                    orc_collide_d(&L, tau, scratch);
+                    orc_stream_d(&L, scratch, fsb);
+                    gt = fsb;
+                }
+                orc_zouhe_adj(ORC_PASS, gt, rho_in, a, drho_in, drho_out);
+                orc_stream_adj(ORC_PASS, a, b);
             }
-            orc_collide_adj(q, nx, ny, nz, bc, solid, tau, fprev, b, a, dtau);
+            orc_collide_adj(ORC_PASS, tau, fprev, b, a, dtau);
         }
     }
     if (fbar0) memcpy(fbar0, a, sizeof(double) * (size_t)nq);

@@ -63,7 +63,10 @@ static void FN(init_eq)(const orc_lattice *L, const R *rho, const R *u, R *f)
     }
 }
 
-/* ---- BGK collision, Eq. 4 with the relaxing sign: f* = f - (f - feq)/tau */
+/* ---- collision ----------------------------------------------------------
+ * BGK, Eq. 4 with the relaxing sign:  f* = f - (f - feq)/tau.
+ * MRT (D2Q9, Section 3.4):  f* = f - M^-1 S M (f - feq), with m_eq = M feq,
+ * S = diag(rates) and the two stress rates equal to 1/tau. */
 static void FN(collide)(const orc_lattice *L, R tau, R *f)
 {
     const int q = L->q;
@@ -75,6 +78,20 @@ static void FN(collide)(const orc_lattice *L, R tau, R *f)
         FN(moments)(L, &f[k * q], &rho, j);
         u[0] = j[0] / rho; u[1] = j[1] / rho; u[2] = j[2] / rho;
         FN(equilibrium)(q, rho, u, feq);
+        if (L->mrt) {
+            R m[9];
+            for (int r = 0; r < 9; r++) {
+                R acc = 0;
+                for (int i = 0; i < 9; i++) acc += ORC_M[r][i] * (f[k * q + i] - feq[i]);
+                m[r] = acc * (r >= 7 ? 1.0 / tau : (R)L->mrt[r]);
+            }
+            for (int i = 0; i < 9; i++) {
+                R acc = 0;
+                for (int r = 0; r < 9; r++) acc += ORC_M[r][i] * m[r] / ORC_MNORM[r];
+                f[k * q + i] -= acc;
+            }
+            continue;
+        }
         for (int i = 0; i < q; i++)
             f[k * q + i] = f[k * q + i] - (f[k * q + i] - feq[i]) / tau;
     }
@@ -129,8 +146,10 @@ static void FN(stream)(const orc_lattice *L, const R *fs, R *g)
  *   N_t = 1/2 sum_{c_x = 0} g c_t                     (t = y, z)
  * every unknown population is
  *   g_i = g_opp(i) + 2 w_i J / cs^2 - sum_t c_it N_t.
- * rho_b holds one value per (z, y) face node. */
-static void FN(zouhe_face)(const orc_lattice *L, int face_x, int s, const R *rho_b, R *g)
+ * rho_b holds one value per (z, y) face node.  With velocity != 0 the face
+ * imposes the normal velocity u = rho_b[..] instead of the density (Zou-He
+ * velocity inlet, s = +1): rho = K / (1 - u) and J = rho - K. */
+static void FN(zouhe_face)(const orc_lattice *L, int face_x, int s, const R *rho_b, R *g, int velocity)
 {
     const orc_velset *V = orc_vel(L->q);
     const int q = L->q;
@@ -151,7 +170,7 @@ static void FN(zouhe_face)(const orc_lattice *L, int face_x, int s, const R *rho
                     K += 2.0 * gk[i];
                 }
             }
-            R J = rho_b[z * L->ny + y] - K;
+            R J = velocity ? K / (1.0 - rho_b[z * L->ny + y]) - K : rho_b[z * L->ny + y] - K;
             for (int i = 0; i < q; i++) {
                 if (V->c[i][0] != s) continue;
                 gk[i] = gk[V->opp[i]] + 2.0 * V->w[i] * J / cs2
@@ -161,11 +180,13 @@ static void FN(zouhe_face)(const orc_lattice *L, int face_x, int s, const R *rho
     }
 }
 
+/* x faces: PRESSURE imposes both densities; VELOCITY imposes the inlet's
+ * normal velocity (rho_in holds it) and the outlet's density. */
 static void FN(zouhe)(const orc_lattice *L, const R *rho_in, const R *rho_out, R *g)
 {
-    if (L->bc[0] != ORC_BC_PRESSURE) return;
-    FN(zouhe_face)(L, 0, +1, rho_in, g);
-    FN(zouhe_face)(L, L->nx - 1, -1, rho_out, g);
+    if (L->bc[0] != ORC_BC_PRESSURE && L->bc[0] != ORC_BC_VELOCITY) return;
+    FN(zouhe_face)(L, 0, +1, rho_in, g, L->bc[0] == ORC_BC_VELOCITY);
+    FN(zouhe_face)(L, L->nx - 1, -1, rho_out, g, 0);
 }
 
 /* ---- anti-bounce-back density boundaries on the x faces (Eq. 6) ---------

@@ -75,7 +75,17 @@ enum lbm_lattice { LBM_D2Q9 = 9, LBM_D3Q19 = 19 };
  *             the negated outgoing post-collision population plus twice the
  *             even part of the equilibrium at the imposed density and the
  *             face node's own velocity (density imposed half a link outside). */
-enum lbm_bc { LBM_BC_PRESSURE = 0, LBM_BC_PERIODIC = 1, LBM_BC_WALL = 2, LBM_BC_ABB = 3 };
+/*   VELOCITY: Zou-He velocity inlet at x = 0 (normal velocity u_in taken from
+ *             the drho_in parameters, zero tangential velocity; the node's
+ *             density follows as K / (1 - u_in)) and a Zou-He density outlet
+ *             at x = nx-1 (the free-stream inflow of Section 3.4's cylinder
+ *             wake); lbm_grad's d_rho_in then holds dL/du_in. */
+enum lbm_bc { LBM_BC_PRESSURE = 0, LBM_BC_PERIODIC = 1, LBM_BC_WALL = 2, LBM_BC_ABB = 3, LBM_BC_VELOCITY = 4 };
+/* Collision operator: BGK (Eq. 4), or for D2Q9 the multiple-relaxation-time
+ * operator of Section 3.4, f* = f - M^-1 S M (f - f_eq) with the moment basis
+ * (rho, e, eps, jx, qx, jy, qy, pxx, pxy) and S = diag(mrt_rates), the two
+ * stress rates being 1/tau. */
+enum lbm_collision { LBM_COLL_BGK = 0, LBM_COLL_MRT = 1 };
 enum lbm_loss_kind { LBM_LOSS_VEC = 0, LBM_LOSS_NORM = 1 };
 enum lbm_loss_scale { LBM_SCALE_SUM = 0, LBM_SCALE_MEAN_FLUID = 1 };
 enum lbm_inlet_mode { LBM_INLET_CONST = 0, LBM_INLET_PROFILE = 1 };
@@ -95,13 +105,16 @@ typedef struct lbm_problem {
     int lattice;             /* LBM_D2Q9 or LBM_D3Q19 */
     int n_inst;              /* number of independent instances (>= 1) */
     const lbm_instance *inst;
-    int bc_x, bc_y, bc_z;    /* lbm_bc per axis; LBM_BC_PRESSURE and LBM_BC_ABB only on x */
+    int bc_x, bc_y, bc_z;    /* lbm_bc per axis; PRESSURE, ABB and VELOCITY only on x */
     int steps;               /* T, number of time steps of lbm_forward() (>= 1) */
     int ckpt_interval;       /* K, checkpoint interval of the taped forward; 0 = ceil(sqrt(T)) */
     int tape;                /* nonzero: reserve checkpoints and a segment store for lbm_adjoint() */
     int loss_kind;           /* lbm_loss_kind: VEC |u - u_t|^2 or NORM (|u| - |u_t|)^2 */
     int loss_scale;          /* lbm_loss_scale: SUM, or MEAN_FLUID = 1 / (number of fluid nodes) (Eq. 15) */
     int inlet_mode;          /* lbm_inlet_mode: one inlet density per instance, or one per inlet node */
+    int collision;           /* lbm_collision (0 = BGK; MRT needs LBM_D2Q9) */
+    double mrt_rates[9];     /* MRT: rates of (rho, e, eps, jx, qx, jy, qy, pxx, pxy) in (0, 2);
+                                the stress entries are ignored (1/tau) */
 } lbm_problem;
 
 /* Parameters of one forward evaluation (host arrays, read during the call). */

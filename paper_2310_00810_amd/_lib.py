@@ -13,7 +13,8 @@ LIBPATH = os.environ.get("LBM_LIBRARY") or os.path.join(PKG, "liblbm.so")
 
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_ESTATE, LBM_EUNSTABLE, LBM_ECORRUPT, LBM_EDEVICE = 0, -1, -2, -3, -4, -5, -6
 LBM_D2Q9, LBM_D3Q19 = 9, 19
-BC_PRESSURE, BC_PERIODIC, BC_WALL, BC_ABB = 0, 1, 2, 3
+BC_PRESSURE, BC_PERIODIC, BC_WALL, BC_ABB, BC_VELOCITY = 0, 1, 2, 3, 4
+COLL_BGK, COLL_MRT = 0, 1
 LOSS_VEC, LOSS_NORM = 0, 1
 SCALE_SUM, SCALE_MEAN_FLUID = 0, 1
 INLET_CONST, INLET_PROFILE = 0, 1
@@ -43,7 +44,8 @@ class lbm_problem(ctypes.Structure):
                 ("inst", ctypes.POINTER(lbm_instance)),
                 ("bc_x", ctypes.c_int), ("bc_y", ctypes.c_int), ("bc_z", ctypes.c_int),
                 ("steps", ctypes.c_int), ("ckpt_interval", ctypes.c_int), ("tape", ctypes.c_int),
-                ("loss_kind", ctypes.c_int), ("loss_scale", ctypes.c_int), ("inlet_mode", ctypes.c_int)]
+                ("loss_kind", ctypes.c_int), ("loss_scale", ctypes.c_int), ("inlet_mode", ctypes.c_int),
+                ("collision", ctypes.c_int), ("mrt_rates", ctypes.c_double * 9)]
 
 
 class lbm_params(ctypes.Structure):

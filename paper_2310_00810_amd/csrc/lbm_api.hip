@@ -64,12 +64,19 @@ int validate_problem(const lbm_problem *p) {
     if (p->n_inst < 1 || !p->inst) return fail(LBM_EINVAL, "n_inst must be >= 1 with a descriptor array");
     const int bcs[3] = {p->bc_x, p->bc_y, p->bc_z};
     for (int a = 0; a < 3; ++a)
-        if (bcs[a] < LBM_BC_PRESSURE || bcs[a] > LBM_BC_ABB)
+        if (bcs[a] < LBM_BC_PRESSURE || bcs[a] > LBM_BC_VELOCITY)
             return fail(LBM_EINVAL, "boundary kind of axis %d is invalid (%d)", a, bcs[a]);
-    if (p->bc_y == LBM_BC_PRESSURE || p->bc_z == LBM_BC_PRESSURE || p->bc_y == LBM_BC_ABB ||
-        p->bc_z == LBM_BC_ABB)
-        return fail(LBM_EINVAL, "density faces (Zou-He or anti-bounce-back) are supported on the x axis only");
-    const bool faces = p->bc_x == LBM_BC_PRESSURE || p->bc_x == LBM_BC_ABB;
+    for (int a = 1; a < 3; ++a)
+        if (bcs[a] != LBM_BC_PERIODIC && bcs[a] != LBM_BC_WALL)
+            return fail(LBM_EINVAL, "inlet / outlet faces (Zou-He, anti-bounce-back, velocity) are on the x axis only");
+    const bool faces = p->bc_x == LBM_BC_PRESSURE || p->bc_x == LBM_BC_ABB || p->bc_x == LBM_BC_VELOCITY;
+    if (p->collision != LBM_COLL_BGK && p->collision != LBM_COLL_MRT) return fail(LBM_EINVAL, "bad collision");
+    if (p->collision == LBM_COLL_MRT) {
+        if (p->lattice != LBM_D2Q9) return fail(LBM_EINVAL, "the MRT collision is implemented for D2Q9 only");
+        for (int r = 0; r < 7; ++r)
+            if (!(p->mrt_rates[r] > 0.0 && p->mrt_rates[r] < 2.0))
+                return fail(LBM_EINVAL, "MRT rate %d must lie in (0, 2) (got %g)", r, p->mrt_rates[r]);
+    }
     if (p->steps < 1) return fail(LBM_EINVAL, "steps must be >= 1 (got %d)", p->steps);
     if (p->ckpt_interval < 0) return fail(LBM_EINVAL, "ckpt_interval must be >= 0");
     if (p->loss_kind != LBM_LOSS_VEC && p->loss_kind != LBM_LOSS_NORM) return fail(LBM_EINVAL, "bad loss_kind");
@@ -234,7 +241,12 @@ int upload_params(lbm_handle *h, const lbm_params *prm) {
         if (!isfinite(dout) || dout <= -1.0) return fail(LBM_EINVAL, "instance %d: drho_out must be finite and > -1", b);
         for (long long k = 0; k < nf; ++k) {
             double din = h->P.inlet_mode == LBM_INLET_PROFILE ? prm->drho_in[prof + k] : prm->drho_in[b];
-            if (!isfinite(din) || din <= -1.0) return fail(LBM_EINVAL, "instance %d: drho_in must be finite and > -1", b);
+            if (h->P.bc_x == LBM_BC_VELOCITY) {
+                if (!isfinite(din) || !(din > -1.0 && din < 1.0))
+                    return fail(LBM_EINVAL, "instance %d: inlet velocity must lie in (-1, 1)", b);
+            } else if (!isfinite(din) || din <= -1.0) {
+                return fail(LBM_EINVAL, "instance %d: drho_in must be finite and > -1", b);
+            }
             h->h_face_in[I.face_off + k] = (float)din;
             h->h_face_out[I.face_off + k] = (float)dout;
         }
@@ -433,6 +445,8 @@ int lbm_init(lbm_handle **out, const lbm_problem *p, void *d_workspace, size_t b
     h->G.n_inst = L.n_inst;
     h->G.n_tiles = L.n_tiles;
     h->G.bcx = p->bc_x; h->G.bcy = p->bc_y; h->G.bcz = p->bc_z;
+    h->G.coll = p->collision;
+    for (int r = 0; r < 9; ++r) h->G.mrt[r] = (float)p->mrt_rates[r];
     h->G.rw = h->at<uint2>(L.off_mask);
     h->G.n_ftiles = L.n_ftiles;
     h->G.fblk = h->at<int2>(L.off_fblk);

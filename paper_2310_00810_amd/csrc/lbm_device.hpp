@@ -8,9 +8,16 @@
 
 namespace lbm {
 
-enum { BC_PRESSURE = 0, BC_PERIODIC = 1, BC_WALL = 2, BC_ABB = 3 };
-// x boundary kinds with density faces: Zou-He (PRESSURE) or anti-bounce-back (ABB)
-__host__ __device__ constexpr bool density_faces(int bcx) { return bcx == BC_PRESSURE || bcx == BC_ABB; }
+enum { BC_PRESSURE = 0, BC_PERIODIC = 1, BC_WALL = 2, BC_ABB = 3, BC_VELOCITY = 4 };
+enum { COLL_BGK = 0, COLL_MRT = 1 };
+// x boundary kinds with inlet / outlet faces: Zou-He densities (PRESSURE),
+// anti-bounce-back densities (ABB), Zou-He velocity inlet + density outlet
+// (VELOCITY)
+__host__ __device__ constexpr bool density_faces(int bcx) {
+    return bcx == BC_PRESSURE || bcx == BC_ABB || bcx == BC_VELOCITY;
+}
+// x kinds whose faces use the Zou-He closure
+__host__ __device__ constexpr bool zouhe_faces(int bcx) { return bcx == BC_PRESSURE || bcx == BC_VELOCITY; }
 enum { LOSS_VEC = 0, LOSS_NORM = 1 };
 
 constexpr int TILE_X = 64;       // one wavefront spans 64 consecutive x
@@ -100,6 +107,8 @@ struct Geo {
     const uint2 *rw;       // row-word tables
     int n_ftiles;
     const int2 *fblk;      // per fluid tile: instance-local row words {w0, w1}
+    int coll;              // COLL_BGK or COLL_MRT (D2Q9)
+    float mrt[9];          // MRT rates of the D2Q9 moments; stress entries unused (1/tau)
 };
 
 // Block index -> tile index such that the blocks the hardware places on one
@@ -453,7 +462,7 @@ __device__ inline void gather_fwd(__amdgpu_buffer_rsrc_t r, int plane, const Lin
         const int i = V::opp(q);
         const bool back = BCX == BC_ABB && V::cx(q) != 0 ? (k.wall[q] || k.open[q]) : k.wall[q];
         unsigned off = back ? own + (unsigned)(q * plane) * 4u : (unsigned)(i * plane + k.fid[q]) * 4u;
-        if (BCX == BC_PRESSURE && V::cx(q) != 0) off = k.open[q] ? OOB : off;
+        if (zouhe_faces(BCX) && V::cx(q) != 0) off = k.open[q] ? OOB : off;
         g[i] = bload(r, off);
     }
 }
@@ -478,9 +487,11 @@ __device__ inline void gather_adj(__amdgpu_buffer_rsrc_t r, int plane, const Lin
 // that the imposed density enters as a deviation).  in / out select the
 // inlet (unknowns c_x = +1) or outlet (c_x = -1); other nodes keep g
 // exactly.  Written without branches: in a wavefront of consecutive fluid
-// ids nearly every wavefront holds inlet and outlet nodes.
+// ids nearly every wavefront holds inlet and outlet nodes.  vin: the inlet
+// imposes the normal velocity u = b instead of a density: rho = K / (1 - u)
+// and J = rho - K = (Kbar + 1) u / (1 - u) (Kbar the shifted known sum).
 template <int Q>
-__device__ inline void zouhe(float (&g)[Q], bool in, bool out, float drho_b) {
+__device__ inline void zouhe(float (&g)[Q], bool in, bool out, float drho_b, bool vin = false) {
     using V = Vel<Q>;
     float K0 = 0.f, Kp = 0.f, Km = 0.f, Ny = 0.f, Nz = 0.f;
 #pragma unroll
@@ -495,7 +506,8 @@ __device__ inline void zouhe(float (&g)[Q], bool in, bool out, float drho_b) {
             Km += g[i];
         }
     }
-    const float J = drho_b - (K0 + 2.0f * (in ? Km : Kp));
+    const float Kb = K0 + 2.0f * (in ? Km : Kp);
+    const float J = in && vin ? (Kb + 1.0f) * drho_b / (1.0f - drho_b) : drho_b - Kb;
 #pragma unroll
     for (int p = 1; p < Q; ++p) {
         if (V::cx(p) != 1) continue;
@@ -509,9 +521,12 @@ __device__ inline void zouhe(float (&g)[Q], bool in, bool out, float drho_b) {
 }
 
 // Transpose of the closure above applied to an adjoint vector a (in place):
-// returns dL/d(drho_b) (0 away from the faces, where a is left exactly).
+// returns dL/d(drho_b), or dL/du for a velocity inlet (0 away from the
+// faces, where a is left exactly).  g: the completed populations (their
+// known part gives Kbar for the velocity inlet).
 template <int Q>
-__device__ inline float zouhe_adj(float (&a)[Q], bool in, bool out) {
+__device__ inline float zouhe_adj(float (&a)[Q], bool in, bool out, const float (&g)[Q], float b = 0.f,
+                                  bool vin = false) {
     using V = Vel<Q>;
     float Jb = 0.f, Nyb = 0.f, Nzb = 0.f;
 #pragma unroll
@@ -527,18 +542,28 @@ __device__ inline float zouhe_adj(float (&a)[Q], bool in, bool out) {
         if (V::cy(p)) Nyb -= V::cy(p) * (up - um);
         if (V::cz(p)) Nzb -= V::cz(p) * (up - um);
     }
-    const float Jb2 = 2.0f * Jb;
+    // dJ/dKbar: -1 for a density face, u / (1 - u) for the velocity inlet
+    float dJ = -1.0f, db = 1.0f;
+    if (vin && in) {
+        float Kb = 0.f;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) Kb += V::cx(i) == 0 ? g[i] : (V::cx(i) < 0 ? 2.0f * g[i] : 0.f);
+        const float r = 1.0f / (1.0f - b);
+        dJ = b * r;
+        db = (Kb + 1.0f) * r * r;
+    }
+    const float Jk = dJ * Jb, Jk2 = 2.0f * Jk;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         if (V::cx(i) == 0) {
-            a[i] += -Jb + 0.5f * ((V::cy(i) ? V::cy(i) * Nyb : 0.f) + (V::cz(i) ? V::cz(i) * Nzb : 0.f));
+            a[i] += Jk + 0.5f * ((V::cy(i) ? V::cy(i) * Nyb : 0.f) + (V::cz(i) ? V::cz(i) * Nzb : 0.f));
         } else if (V::cx(i) < 0) {
-            a[i] -= in ? Jb2 : 0.f;
+            a[i] += in ? Jk2 : 0.f;
         } else {
-            a[i] -= out ? Jb2 : 0.f;
+            a[i] += out ? Jk2 : 0.f;
         }
     }
-    return Jb;
+    return Jb * db;
 }
 
 struct Moments {
@@ -571,6 +596,44 @@ __device__ inline float feq_shifted(int i, const Moments &m) {
     const float cu = V::cx(i) * m.ux + V::cy(i) * m.uy + V::cz(i) * m.uz;
     const float usq = m.ux * m.ux + m.uy * m.uy + m.uz * m.uz;
     return V::w(i) * (m.drho + m.rho * (3.0f * cu + 4.5f * cu * cu - 1.5f * usq));
+}
+
+// D2Q9 moment basis of the multiple-relaxation-time collision: row r of M
+// is a polynomial of the lattice velocity (rho, e, eps, jx, qx, jy, qy, pxx,
+// pxy); the rows are orthogonal with squared norms mrt_norm.
+__host__ __device__ constexpr int mrt_m(int r, int i) {
+    using V = Vel<9>;
+    const int cx = V::cx(i), cy = V::cy(i), c2 = cx * cx + cy * cy;
+    return r == 0 ? 1 : r == 1 ? -4 + 3 * c2 : r == 2 ? (8 - 21 * c2 + 9 * c2 * c2) / 2 : r == 3 ? cx
+         : r == 4 ? (-5 + 3 * c2) * cx : r == 5 ? cy : r == 6 ? (-5 + 3 * c2) * cy : r == 7 ? cx * cx - cy * cy
+         : cx * cy;
+}
+__host__ __device__ constexpr int mrt_norm(int r) {
+    int s = 0;
+    for (int i = 0; i < 9; ++i) s += mrt_m(r, i) * mrt_m(r, i);
+    return s;
+}
+
+// MRT relaxation of d = g - feq: returns M^-1 S M d in out (S: rates, the
+// two stress rates being omega).
+__device__ inline void mrt_relax(const float (&d)[9], const float *rates, float omega, float (&out)[9]) {
+    float m[9];
+#pragma unroll
+    for (int r = 0; r < 9; ++r) {
+        float acc = 0.f;
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+            if (mrt_m(r, i)) acc += (float)mrt_m(r, i) * d[i];
+        m[r] = acc * ((r >= 7 ? omega : rates[r]) / (float)mrt_norm(r));
+    }
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        float acc = 0.f;
+#pragma unroll
+        for (int r = 0; r < 9; ++r)
+            if (mrt_m(r, i)) acc += (float)mrt_m(r, i) * m[r];
+        out[i] = acc;
+    }
 }
 
 // Moments of a node's own populations (face nodes of anti-bounce-back faces).

@@ -68,12 +68,23 @@ __global__ void __launch_bounds__(FT) k_step(Geo G, const float *__restrict__ sr
     links<Q, BCX>(G, I, t, L, n, k);
     float g[Q];
     gather_fwd<Q, BCX>(rs, plane, k, g);
-    if (BCX == BC_PRESSURE) zouhe<Q>(g, in, out, drho_b);
+    if (zouhe_faces(BCX)) zouhe<Q>(g, in, out, drho_b, BCX == BC_VELOCITY);
     if (BCX == BC_ABB) abb<Q>(g, in, out, drho_b, uF);
     const Moments m = moments<Q>(g);
     const float om = I.omega;
     const __amdgpu_buffer_rsrc_t rd = planes_rsrc(dst + I.st_off, Q, I.plane);
     const unsigned own = (unsigned)n.id * 4u;
+    if constexpr (Q == 9) {
+        if (G.coll == COLL_MRT) {
+            float d[9], r[9];
+#pragma unroll
+            for (int i = 0; i < 9; ++i) d[i] = g[i] - feq_shifted<Q>(i, m);
+            mrt_relax(d, G.mrt, om, r);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) bstore(rd, g[i] - r[i], own, i * plane * 4);
+            return;
+        }
+    }
 #pragma unroll
     for (int i = 0; i < Q; ++i) bstore(rd, g[i] + om * (feq_shifted<Q>(i, m) - g[i]), own, i * plane * 4);
 }
@@ -163,7 +174,7 @@ __global__ void __launch_bounds__(FT) k_adj_seed(Geo G, const float *__restrict_
     links<Q, BCX>(G, I, t, L, n, k);
     float g[Q];
     gather_fwd<Q, BCX>(rs, plane, k, g);
-    if (BCX == BC_PRESSURE) zouhe<Q>(g, in, out, drho_b);
+    if (zouhe_faces(BCX)) zouhe<Q>(g, in, out, drho_b, BCX == BC_VELOCITY);
     if (BCX == BC_ABB) abb<Q>(g, in, out, drho_b, uF);
     const Moments m = moments<Q>(g);
     const float u[3] = {m.ux, m.uy, m.uz};
@@ -184,8 +195,8 @@ __global__ void __launch_bounds__(FT) k_adj_seed(Geo G, const float *__restrict_
     for (int i = 0; i < Q; ++i)
         a[i] = inv * (dldu[0] * (V::cx(i) - m.ux) + dldu[1] * (V::cy(i) - m.uy) +
                       (D == 3 ? dldu[2] * (V::cz(i) - m.uz) : 0.f));
-    if (BCX == BC_PRESSURE) {
-        const float jb = zouhe_adj<Q>(a, in, out);
+    if (zouhe_faces(BCX)) {
+        const float jb = zouhe_adj<Q>(a, in, out, g, drho_b, BCX == BC_VELOCITY);
         if (in) grad_in[I.face_off + n.r] += (double)jb;
         else if (out) grad_out[I.face_off + n.r] += (double)jb;
     }
@@ -236,7 +247,7 @@ __global__ void __launch_bounds__(FT) k_adj_step(Geo G, const float *__restrict_
         float g[Q], lam[Q];
         gather_fwd<Q, BCX>(rs, plane, k, g);
         gather_adj<Q>(rn, plane, k, lam);
-        if (BCX == BC_PRESSURE) zouhe<Q>(g, in, out, drho_b);
+        if (zouhe_faces(BCX)) zouhe<Q>(g, in, out, drho_b, BCX == BC_VELOCITY);
         if (BCX == BC_ABB) abb<Q>(g, in, out, drho_b, uF);
         const Moments m = moments<Q>(g);
         if (BCX == BC_ABB) {
@@ -247,12 +258,35 @@ __global__ void __launch_bounds__(FT) k_adj_step(Geo G, const float *__restrict_
             if (in) grad_in[I.face_off + n.r] += (double)jb;
             else if (out) grad_out[I.face_off + n.r] += (double)jb;
         }
+        // the equilibrium part of the collision transpose acts on mu:
+        // BGK mu = omega lam; MRT mu = M^-1 S M lam (the update matrix is
+        // symmetric), with dL/dtau from the two stress rates only
+        float mu[Q];
+        bool mrt = false;
+        if constexpr (Q == 9) mrt = G.coll == COLL_MRT;
+        if constexpr (Q == 9) {
+            if (mrt) {
+                mrt_relax(lam, G.mrt, I.omega, mu);
+                float y7 = 0.f, y8 = 0.f, d7 = 0.f, d8 = 0.f;
+#pragma unroll
+                for (int i = 0; i < 9; ++i) {
+                    const float dq = g[i] - feq_shifted<Q>(i, m);
+                    if (mrt_m(7, i)) { y7 += mrt_m(7, i) * lam[i]; d7 += mrt_m(7, i) * dq; }
+                    if (mrt_m(8, i)) { y8 += mrt_m(8, i) * lam[i]; d8 += mrt_m(8, i) * dq; }
+                }
+                dtau = (y7 * d7 / (float)mrt_norm(7) + y8 * d8 / (float)mrt_norm(8)) * I.inv_tau2;
+            }
+        }
+        if (!mrt) {
+#pragma unroll
+            for (int q = 0; q < Q; ++q) mu[q] = lam[q];
+        }
         float S0 = 0.f, Sx = 0.f, Sy = 0.f, Sz = 0.f;
         float Sxx = 0.f, Syy = 0.f, Szz = 0.f, Sxy = 0.f, Sxz = 0.f, Syz = 0.f;
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             const int cx = V::cx(q), cy = V::cy(q), cz = V::cz(q);
-            const float wl = V::w(q) * lam[q];
+            const float wl = V::w(q) * mu[q];
             S0 += wl;
             if (cx) { Sx += cx * wl; Sxx += wl; }
             if (cy) { Sy += cy * wl; Syy += wl; }
@@ -260,9 +294,9 @@ __global__ void __launch_bounds__(FT) k_adj_step(Geo G, const float *__restrict_
             if (cx && cy) Sxy += cx * cy * wl;
             if (cx && cz) Sxz += cx * cz * wl;
             if (cy && cz) Syz += cy * cz * wl;
-            dtau += lam[q] * (g[q] - feq_shifted<Q>(q, m));
+            if (!mrt) dtau += lam[q] * (g[q] - feq_shifted<Q>(q, m));
         }
-        dtau *= I.inv_tau2;
+        if (!mrt) dtau *= I.inv_tau2;
         const float ux = m.ux, uy = m.uy, uz = m.uz;
         const float usq = ux * ux + uy * uy + uz * uz;
         const float S2ux = Sxx * ux + Sxy * uy + Sxz * uz;
@@ -272,14 +306,17 @@ __global__ void __launch_bounds__(FT) k_adj_step(Geo G, const float *__restrict_
         const float Bx = 3.0f * Sx + 9.0f * S2ux - 3.0f * ux * S0;
         const float By = 3.0f * Sy + 9.0f * S2uy - 3.0f * uy * S0;
         const float Bz = 3.0f * Sz + 9.0f * S2uz - 3.0f * uz * S0;
-        const float om = I.omega, om1 = 1.0f - I.omega;
+        const float om = mrt ? 1.0f : I.omega, om1 = 1.0f - I.omega;
         float a[Q];
 #pragma unroll
-        for (int i = 0; i < Q; ++i)
-            a[i] = om1 * lam[i] + om * (A + (V::cx(i) ? V::cx(i) * Bx : 0.f) + (V::cy(i) ? V::cy(i) * By : 0.f) +
-                                        (V::cz(i) ? V::cz(i) * Bz : 0.f));
-        if (BCX == BC_PRESSURE) {
-            const float jb = zouhe_adj<Q>(a, in, out);
+        for (int i = 0; i < Q; ++i) {
+            const float eq = A + (V::cx(i) ? V::cx(i) * Bx : 0.f) + (V::cy(i) ? V::cy(i) * By : 0.f) +
+                             (V::cz(i) ? V::cz(i) * Bz : 0.f);
+            // BGK: (1 - omega) lam + omega J^T lam;  MRT: lam - mu + J^T mu
+            a[i] = mrt ? lam[i] - mu[i] + eq : om1 * lam[i] + om * eq;
+        }
+        if (zouhe_faces(BCX)) {
+            const float jb = zouhe_adj<Q>(a, in, out, g, drho_b, BCX == BC_VELOCITY);
             if (in) grad_in[I.face_off + n.r] += (double)jb;
             else if (out) grad_out[I.face_off + n.r] += (double)jb;
         }
@@ -492,12 +529,14 @@ static inline dim3 fgrid_of(const Geo &G) { return dim3((unsigned)G.n_ftiles); }
             if (bcx == BC_PRESSURE) CALL(9, BC_PRESSURE);                                  \
             else if (bcx == BC_PERIODIC) CALL(9, BC_PERIODIC);                             \
             else if (bcx == BC_WALL) CALL(9, BC_WALL);                                     \
-            else CALL(9, BC_ABB);                                                          \
+            else if (bcx == BC_ABB) CALL(9, BC_ABB);                                       \
+            else CALL(9, BC_VELOCITY);                                                     \
         } else {                                                                           \
             if (bcx == BC_PRESSURE) CALL(19, BC_PRESSURE);                                 \
             else if (bcx == BC_PERIODIC) CALL(19, BC_PERIODIC);                            \
             else if (bcx == BC_WALL) CALL(19, BC_WALL);                                    \
-            else CALL(19, BC_ABB);                                                         \
+            else if (bcx == BC_ABB) CALL(19, BC_ABB);                                      \
+            else CALL(19, BC_VELOCITY);                                                    \
         }                                                                                  \
     } while (0)
 

@@ -18,7 +18,12 @@ from . import _lib as C
 _LOSS = {"vec": C.LOSS_VEC, "norm": C.LOSS_NORM}
 _SCALE = {"sum": C.SCALE_SUM, "mean": C.SCALE_MEAN_FLUID}
 _INLET = {"const": C.INLET_CONST, "profile": C.INLET_PROFILE}
-_BC = {"pressure": C.BC_PRESSURE, "periodic": C.BC_PERIODIC, "wall": C.BC_WALL, "abb": C.BC_ABB}
+_BC = {"pressure": C.BC_PRESSURE, "periodic": C.BC_PERIODIC, "wall": C.BC_WALL, "abb": C.BC_ABB,
+       "velocity": C.BC_VELOCITY}
+# D2Q9 multiple-relaxation-time rates of (rho, e, eps, jx, qx, jy, qy, pxx, pxy):
+# conserved moments 1.0, the energy / flux rates of Lallemand & Luo; the two
+# stress rates are 1/tau.
+MRT_RATES = (1.0, 1.64, 1.54, 1.0, 1.9, 1.0, 1.9, 1.0, 1.0)
 
 
 @dataclass
@@ -54,11 +59,12 @@ class Solver:
 
     lattice: 9 or 19.  instances: list of Instance (a batch of independent
     lattices).  bc: boundary kind per axis (x, y, z).  steps: T.
-    ckpt_interval: K (0 = ceil(sqrt(T))).  tape: reserve the adjoint tape."""
+    ckpt_interval: K (0 = ceil(sqrt(T))).  tape: reserve the adjoint tape.
+    collision: "bgk" or (D2Q9) "mrt" with mrt_rates."""
 
     def __init__(self, lattice, instances, bc=("pressure", "wall", "periodic"), steps=1,
                  ckpt_interval=0, tape=False, loss_kind="vec", loss_scale="sum",
-                 inlet_mode="const", device="cuda", stream=None):
+                 inlet_mode="const", device="cuda", stream=None, collision="bgk", mrt_rates=MRT_RATES):
         self.q = int(lattice)
         self.D = 2 if self.q == 9 else 3
         self.instances = list(instances)
@@ -76,7 +82,9 @@ class Solver:
         self._inst_arr = arr
         self.problem = C.lbm_problem(self.q, self.n_inst, arr, _bc(bc[0]), _bc(bc[1]), _bc(bc[2]),
                                      self.steps, int(ckpt_interval), int(bool(tape)), _LOSS[loss_kind],
-                                     _SCALE[loss_scale], _INLET[inlet_mode])
+                                     _SCALE[loss_scale], _INLET[inlet_mode],
+                                     C.COLL_MRT if collision == "mrt" else C.COLL_BGK,
+                                     (ctypes.c_double * 9)(*[float(r) for r in mrt_rates]))
         L = C.lib()
         nbytes = ctypes.c_size_t(0)
         C.check(L.lbm_workspace_bytes(ctypes.byref(self.problem), ctypes.byref(nbytes)), "lbm_workspace_bytes")

@@ -103,3 +103,23 @@ def abb_lattices():
         out.append((name.replace("d2q9", "abb_d2q9").replace("d3q19", "abb_d3q19"),
                     O.Lattice(lat.q, lat.nx, lat.ny, lat.nz, bc, lat.solid.copy())))
     return out
+
+
+def mrt_velocity_lattices():
+    """D2Q9 lattices with the multiple-relaxation-time collision and / or the
+    Zou-He velocity inlet (grains at the faces, walls, periodic y), and a
+    many-tile MRT lattice."""
+    import oracle as O
+    out = []
+    tiny = [(n, l) for n, l in tiny_lattices() if l.q == 9]
+    for name, lat in tiny:
+        for bcx, mrt, tag in ((O.BC_PRESSURE, O.MRT_RATES, "mrt"), (O.BC_VELOCITY, None, "vel"),
+                              (O.BC_VELOCITY, O.MRT_RATES, "mrt_vel")):
+            out.append((f"{tag}_{name}", O.Lattice(9, lat.nx, lat.ny, 1, (bcx,) + tuple(lat.bc_tuple[1:]),
+                                                   lat.solid.copy(), mrt=mrt)))
+    rng = np.random.default_rng(78)
+    s = (rng.random((1, 40, 300)) < 0.4).astype(np.uint8)
+    s[:, :, 0] = 0
+    out.append(("mrt_vel_multi_tile", O.Lattice(9, 300, 40, 1, (O.BC_VELOCITY, O.BC_WALL, O.BC_PERIODIC), s,
+                                                mrt=O.MRT_RATES)))
+    return out

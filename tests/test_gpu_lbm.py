@@ -9,7 +9,7 @@ import pytest
 
 import oracle as O
 from paper_2310_00810_amd import geometry as G
-from tests.conftest import abb_lattices, multi_tile_lattices, tiny_lattices
+from tests.conftest import abb_lattices, mrt_velocity_lattices, multi_tile_lattices, tiny_lattices
 
 pytestmark = pytest.mark.gpu
 
@@ -21,7 +21,8 @@ def _lbm():
     return lbm
 
 
-BC_NAMES = {O.BC_PRESSURE: "pressure", O.BC_PERIODIC: "periodic", O.BC_WALL: "wall", O.BC_ABB: "abb"}
+BC_NAMES = {O.BC_PRESSURE: "pressure", O.BC_PERIODIC: "periodic", O.BC_WALL: "wall", O.BC_ABB: "abb",
+            O.BC_VELOCITY: "velocity"}
 
 
 def oracle_pull_step(lat, tau, rin, rout, F):
@@ -40,9 +41,16 @@ def solver_for(lat, steps, tape=False, K=0, roi=None, target=None, loss_kind="ve
     tgt = None if target is None else np.asarray(target)[..., :D].astype(np.float32)
     ins = lbm.Instance(lat.nx, lat.ny, lat.nz, solid=lat.solid.copy(),
                        roi=None if roi is None else roi.astype(np.float32), target_u=tgt)
+    kw = {} if lat.mrt is None else dict(collision="mrt", mrt_rates=tuple(lat.mrt))
     return lbm.Solver(lat.q, [ins], bc=tuple(BC_NAMES[b] for b in lat.bc_tuple), steps=steps,
                       ckpt_interval=K, tape=tape, loss_kind=loss_kind, loss_scale=loss_scale,
-                      inlet_mode=inlet_mode)
+                      inlet_mode=inlet_mode, **kw)
+
+
+def _inlet(lat, d):
+    """The oracle's inlet face value for a GPU inlet parameter d: the density
+    1 + d, or the velocity d itself for a velocity inlet."""
+    return d if lat.bc_tuple[0] == O.BC_VELOCITY else 1 + d
 
 
 def rel_l2(a, b):
@@ -74,7 +82,8 @@ def f32(x):
 
 
 # ---------------------------------------------------------------- forward --
-@pytest.mark.parametrize("name,lat", tiny_lattices() + multi_tile_lattices() + abb_lattices())
+@pytest.mark.parametrize("name,lat", tiny_lattices() + multi_tile_lattices() + abb_lattices() +
+                         mrt_velocity_lattices())
 @pytest.mark.parametrize("T", [1, 3])
 def test_steps_from_random_state(name, lat, T):
     """T steps from a random non-equilibrium state, all boundary kinds."""
@@ -83,7 +92,7 @@ def test_steps_from_random_state(name, lat, T):
     F0 = (w + G.random_perturbation(lat.shape, lat.q, 0.01, seed=21)) * fl
     fb = dense_shifted(lat, F0)
     F0 = (np.moveaxis(fb.astype(np.float64), 0, -1) + w) * fl      # the same FP32 values
-    rin = 1 + f32(0.004) + np.zeros((lat.nz, lat.ny))
+    rin = _inlet(lat, f32(0.004)) + np.zeros((lat.nz, lat.ny))
     rout = 1 + f32(-0.002) + np.zeros((lat.nz, lat.ny))
     tau = 0.7
     s = solver_for(lat, T)
@@ -170,11 +179,12 @@ def test_c1_gradient_parity(kind):
 
 
 def _driven(lats):
-    """Lattices with density faces (the others stay at rest: zero gradients)."""
-    return [(n, l) for n, l in lats if l.bc_tuple[0] in (O.BC_PRESSURE, O.BC_ABB)]
+    """Lattices with inlet / outlet faces (the others stay at rest: zero gradients)."""
+    return [(n, l) for n, l in lats if l.bc_tuple[0] in (O.BC_PRESSURE, O.BC_ABB, O.BC_VELOCITY)]
 
 
-@pytest.mark.parametrize("name,lat", _driven(tiny_lattices() + multi_tile_lattices() + abb_lattices()))
+@pytest.mark.parametrize("name,lat", _driven(tiny_lattices() + multi_tile_lattices() + abb_lattices() +
+                                             mrt_velocity_lattices()))
 def test_tiny_profile_gradients(name, lat):
     """Per-node inlet profile gradients, dL/dtau and dL/drho_out on the tiny
     lattices (walls, periodic axes, grains touching the faces), T = 40."""
@@ -192,7 +202,7 @@ def test_tiny_profile_gradients(name, lat):
     s.forward(tau, dparam, f32(-0.001), record_tape=True)
     s.adjoint()
     g = s.grad()
-    rin = 1 + (din.astype(np.float64) if mode == "profile" else f32(0.01))
+    rin = _inlet(lat, din.astype(np.float64) if mode == "profile" else f32(0.01))
     go = O.grad(lat, tau, rin, 1 + f32(-0.001), O.init_eq(lat, 1.0, 0.0), T, tgt, wgt, K=7)
     if mode == "profile":
         assert rel_l2(g["drho_in"], go["drho_in"].ravel()) <= 1e-3
@@ -202,7 +212,8 @@ def test_tiny_profile_gradients(name, lat):
     assert rel_l2(g["drho_out"], [go["drho_out"].sum()]) <= 1e-3
 
 
-@pytest.mark.parametrize("name,lat", tiny_lattices() + multi_tile_lattices() + abb_lattices())
+@pytest.mark.parametrize("name,lat", tiny_lattices() + multi_tile_lattices() + abb_lattices() +
+                         mrt_velocity_lattices())
 @pytest.mark.parametrize("T", [1, 2, 3])
 def test_adjoint_of_initial_state(name, lat, T):
     """dL/dF^0 from the GPU reverse sweep against the oracle's stage
@@ -216,7 +227,7 @@ def test_adjoint_of_initial_state(name, lat, T):
     tgt = (0.01 * rng.standard_normal(lat.shape + (3,))).astype(np.float32).astype(np.float64)
     if lat.q == 9:
         tgt[..., 2] = 0
-    tau, rin, rout = 0.8, 1 + f32(0.003), 1 + f32(-0.001)
+    tau, rin, rout = 0.8, _inlet(lat, f32(0.003)), 1 + f32(-0.001)
     s = solver_for(lat, T, tape=True, K=2, target=tgt)
     s.set_populations(torch.from_numpy(fb.ravel()).cuda())
     s.forward(tau, f32(0.003), f32(-0.001), record_tape=True)
@@ -235,7 +246,7 @@ def test_adjoint_of_initial_state(name, lat, T):
             a, fsb, _, _ = O.abb_adj(lat, rin, rout, Fs[t - 1], a)
             a = O.stream_adj(lat, a) + fsb
         else:
-            a, _, _ = O.zouhe_adj(lat, a)
+            a, _, _ = O.zouhe_adj(lat, a, g=gs[t - 1], rho_in=rin)
             a = O.stream_adj(lat, a)
         if t > 1:
             a, _ = O.collide_adj(lat, tau, gs[t - 2], a)

@@ -235,3 +235,11 @@ def obstructed_pipe(nx=300, ny=50, x_plate=80, plate_len=30):
     y0 = (ny - plate_len) // 2
     solid[0, y0:y0 + plate_len, x_plate] = 1
     return solid
+
+
+def cylinder_channel(nx=800, ny=320, diameter=20, xc=300, yc=160):
+    """2D domain with one circular cylinder (Section 3.4's wake): a node is
+    solid iff its distance to (xc, yc) is at most diameter / 2.  Returns a
+    (1, ny, nx) uint8 solid mask."""
+    yy, xx = np.mgrid[0:ny, 0:nx]
+    return (((xx - xc) ** 2 + (yy - yc) ** 2) <= (diameter / 2) ** 2).astype(np.uint8)[None]

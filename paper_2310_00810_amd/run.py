@@ -1,6 +1,6 @@
 """Drivers of the workloads: inverse runs, batched throughput, warm start.
 
-    python -m paper_2310_00810_amd.run c1|c2|c3|c4|c5|e1 [--quick]
+    python -m paper_2310_00810_amd.run c1|c2|c3|c4|c5|e1|e7 [--quick]
 
 Each prints one JSON line with its results.  The workloads are synthetic
 stand-ins for the paper's experiments (Section 3): channel and granular
@@ -21,6 +21,7 @@ import torch
 
 from . import geometry as G
 from . import inverse
+from ._lib import LBMError
 from .lbm import Instance, Solver
 
 
@@ -226,6 +227,90 @@ def e1(quick=False):
                 fluid_nodes=n_fluid)
 
 
+def e7(quick=False, iters=50, nu0=0.06, scan=False, horizon=0):
+    """Viscosity from a cylinder wake (Section 3.4): D2Q9 MRT, Re = 100,
+    nu = 0.02 (tau = 0.56), Zou-He velocity inlet, density outlet, periodic
+    y.  At the paper's u = 0.2 lu/ts and D = 10 the density outlet does not
+    survive the start-up waves, so the same Re and nu are run at half the
+    Mach number: u = 0.1, D = 20, 800 x 320 nodes, cylinder 25 diameters
+    before the outlet.  Uniform flow at t = 0; shedding is developed by
+    20000 steps.  The target is the velocity at T = 20000 in Raissi's window
+    (1 to 8 diameters downstream, +-2 diameters across); Adam on nu
+    (learning rate 0.01) from nu = 0.06 by default; a step into a viscosity
+    that the start-up does not survive is halved back toward the last stable
+    one.  With a horizon, the flow at T is the start state and the target is
+    the window that many steps later (the wake observed while it sheds)."""
+    nx, ny, D, U, T = 800, 320, 20, 0.1, 20000
+    if quick:
+        T, iters = 2000, 5
+    nu_true = 0.02
+    tau_of = lambda nu: 3.0 * nu + 0.5
+    solid = G.cylinder_channel(nx, ny, D, 300, 160)
+    bc = ("velocity", "periodic", "periodic")
+    u0 = torch.zeros(nx * ny * 2, device="cuda")
+    u0[0::2] = U
+    zero = torch.zeros(nx * ny, device="cuda")
+    s0 = Solver(9, [Instance(nx, ny, solid=solid)], bc=bc, steps=T, collision="mrt")
+    s0.set_initial(zero, u0)
+    s0.forward(tau_of(nu_true), U, 0.0, want_loss=False)
+    developed = None
+    if horizon:
+        # observed from a developed wake: the start state is the shedding flow at T,
+        # the target is the window `horizon` steps later
+        developed = s0.get_populations()
+        s0 = Solver(9, [Instance(nx, ny, solid=solid)], bc=bc, steps=horizon, collision="mrt")
+        s0.set_populations(developed)
+        s0.forward(tau_of(nu_true), U, 0.0, want_loss=False)
+        T = horizon
+    _, ut = s0.macro()
+    tgt = ut.cpu().numpy().reshape(1, ny, nx, 2)
+    del s0
+    roi = np.zeros((1, ny, nx), np.float32)
+    roi[:, 160 - 2 * D:160 + 2 * D, 300 + D:300 + 8 * D] = 1.0
+    s = Solver(9, [Instance(nx, ny, solid=solid, roi=roi, target_u=tgt)], bc=bc, steps=T, tape=True,
+               collision="mrt")
+    if developed is None:
+        s.set_initial(zero, u0)
+    else:
+        s.set_populations(developed)
+    if scan:
+        # the loss along nu: a final-time snapshot of a shedding wake depends on its phase
+        pts = []
+        for nu in np.linspace(0.016, 0.10, 43):
+            try:
+                L = float(s.forward(tau_of(float(nu)), U, 0.0, want_loss=True)[0])
+            except LBMError:
+                L = None  # this viscosity does not survive the start-up at this resolution
+            pts.append({"nu": float(nu), "loss": L})
+            log(f"[e7 scan] nu {nu:.4f} loss {L}")
+        return dict(config="E7 scan", T=T, horizon=horizon, scan=pts)
+    opt = inverse.Adam(0.01)
+    nu = np.array([nu0])
+    hist = []
+    t0 = time.time()
+    prev = nu.copy()
+    for it in range(iters):
+        try:
+            L = s.forward(tau_of(float(nu[0])), U, 0.0, record_tape=True)[0]
+        except LBMError:
+            # too small a viscosity for this resolution: back off halfway to the last stable one
+            log(f"[e7] it {it} nu {nu[0]:.5f} unstable")
+            nu = 0.5 * (nu + prev)
+            continue
+        prev = nu.copy()
+        s.adjoint()
+        g = s.grad()
+        dnu = 3.0 * g["dtau"][0]
+        hist.append((float(nu[0]), float(L), float(dnu)))
+        log(f"[e7] it {it} nu {nu[0]:.5f} loss {L:.4e} dL/dnu {dnu:.4e}")
+        nu = np.maximum(opt.step(nu, np.array([dnu])), 0.002)
+    dt = time.time() - t0
+    best = min(hist, key=lambda h: h[1])
+    return dict(config="E7", T=T, horizon=horizon, iterations=iters, seconds=dt, true_nu=nu_true, initial_nu=nu0,
+                final_nu=float(nu[0]), best_nu=best[0], best_loss=best[1],
+                trajectory=[{"nu": h[0], "loss": h[1], "dL_dnu": h[2]} for h in hist])
+
+
 def c5(quick=False):
     from . import warmstart
     sys.argv = [sys.argv[0], "--dims", "2", "--train", "64" if quick else "2000", "--val", "16" if quick else "200",
@@ -236,10 +321,15 @@ def c5(quick=False):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("config", choices=["c1", "c2", "c3", "c4", "c5", "e1"])
+    ap.add_argument("config", choices=["c1", "c2", "c3", "c4", "c5", "e1", "e7"])
     ap.add_argument("--quick", action="store_true")
+    ap.add_argument("--nu0", type=float, default=0.06, help="e7: initial viscosity")
+    ap.add_argument("--scan", action="store_true", help="e7: loss along nu instead of the inversion")
+    ap.add_argument("--horizon", type=int, default=0,
+                    help="e7: start from the developed wake and match the window this many steps later")
     a = ap.parse_args()
-    res = globals()[a.config](quick=a.quick)
+    kw = dict(nu0=a.nu0, scan=a.scan, horizon=a.horizon) if a.config == "e7" else {}
+    res = globals()[a.config](quick=a.quick, **kw)
     if res is not None:
         print(json.dumps(res), flush=True)
 

@@ -479,3 +479,28 @@ def test_e1_gradient_parity():
     go = O.grad(lat, tau, 1 + f32(0.1), 1.0, O.init_eq(lat, 1.0, 0.0), T, tgt, roi, O.LOSS_NORM)
     assert rel_l2(g["drho_in"], [go["drho_in"].sum()]) <= 1e-3
     assert rel_l2(g["dtau"], [go["dtau"]]) <= 1e-3
+
+
+# ----------------------------------------- cylinder wake, MRT + velocity inlet --
+def test_cylinder_wake_forward_parity():
+    """D2Q9 MRT cylinder wake (800 x 320, D = 20, Zou-He velocity inlet
+    u = 0.1, density outlet, periodic y, tau = 0.56, uniform start), 2000
+    steps: GPU velocity against the oracle."""
+    lbm = _lbm()
+    nx, ny, U, T = 800, 320, 0.1, 2000
+    solid = G.cylinder_channel(nx, ny, 20, 300, 160)
+    s = lbm.Solver(9, [lbm.Instance(nx, ny, solid=solid)], bc=("velocity", "periodic", "periodic"), steps=T,
+                   collision="mrt", mrt_rates=O.MRT_RATES)
+    u0 = torch.zeros(nx * ny * 2, device="cuda")
+    u0[0::2] = U
+    s.set_initial(torch.zeros(nx * ny, device="cuda"), u0)
+    s.forward(0.56, U, 0.0, want_loss=False)
+    _, ug = s.macro()
+    ug = ug.cpu().numpy().reshape(ny, nx, 2)
+    lat = O.Lattice(9, nx, ny, 1, (O.BC_VELOCITY, O.BC_PERIODIC, O.BC_PERIODIC), solid, mrt=O.MRT_RATES)
+    ua = np.zeros(lat.shape + (3,))
+    ua[..., 0] = U
+    fo = O.run(lat, 0.56, U, 1.0, O.init_eq(lat, 1.0, ua) * lat.fluid()[..., None], T)
+    _, uo = O.macro(lat, fo)
+    m = lat.fluid()[0]
+    assert rel_l2(ug[m], uo[0][m][:, :2]) <= 1e-4

@@ -12,6 +12,11 @@ Workload (synthetic stand-in for the paper's 3D granular media): D3Q19,
 VEC loss against the velocity of a second run at tau = 0.9, mean over
 fluid nodes.
 
+The taped forward keeps the states of as many trailing K-step segments as fit
+in device memory (288 GB on MI355X: 11 of the 20 segments here), so the
+reverse sweep recomputes only the others; `--resident 1` keeps only the last
+one.  The gradient is bit for bit the same either way.
+
 Prints ONE JSON line.  value = forward+adjoint MLUPS (all lattice nodes x T
 per second of the whole gradient evaluation).  roofline = the dominant kernel
 of that evaluation, k_step (forward pass and segment recomputes: about 60 % of
@@ -151,6 +156,9 @@ def main():
     ap.add_argument("--workload", choices=["spheres", "channel"], default="spheres")
     ap.add_argument("--T", type=int, default=8000)
     ap.add_argument("--K", type=int, default=400)
+    ap.add_argument("--resident", default="max",
+                    help="tape segments kept resident by the taped forward (an integer, or 'max': as many as "
+                         "fit in device memory); the others are recomputed in the reverse sweep")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-copy", action="store_true", help="skip the copy-bandwidth calibration")
     ap.add_argument("--no-warm", action="store_true", help="skip the warm-versus-cold start comparison")
@@ -179,8 +187,10 @@ def main():
 
     ins = lbm.Instance(n, n, n, solid=w["solid"], target_u=target)
     s = lbm.Solver(19, [ins], bc=w["bc"], steps=T, ckpt_interval=K, tape=True,
-                   loss_scale="mean", inlet_mode="profile")
-    print(f"[bench] workspace {s.workspace_bytes / 2**30:.1f} GiB", file=sys.stderr, flush=True)
+                   loss_scale="mean", inlet_mode="profile",
+                   resident_segments=args.resident if args.resident == "max" else int(args.resident))
+    print(f"[bench] workspace {s.workspace_bytes / 2**30:.1f} GiB, {s.resident_segments} resident tape segments",
+          file=sys.stderr, flush=True)
 
     def one():
         s.forward(w["tau"], w["din"].ravel(), 0.0, record_tape=True)
@@ -237,7 +247,9 @@ def main():
                                 if w["kind"] == "spheres" else f"D3Q19 {n}^3 plane channel, walls y, periodic z, ")
                                + f"Zou-He profile inlet (8 Fourier modes) + tau gradient, T={T}, K={K}, "
                                f"one step = taped forward + reverse sweep",
-                   "lattice": "D3Q19", "nodes": n ** 3, "fluid_nodes": n_fluid, "T": T, "K": K},
+                   "lattice": "D3Q19", "nodes": n ** 3, "fluid_nodes": n_fluid, "T": T, "K": K,
+                   "resident_segments": s.resident_segments, "recomputed_steps": tm["recompute_launches"],
+                   "workspace_gib": round(s.workspace_bytes / 2 ** 30, 1)},
         "roofline": {"bound": "hbm", "achieved": round(step_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(step_gbs / HBM_PEAK_GBS, 4), "traffic": load_traffic(FWD_KERNEL),
                      "kernel": FWD_KERNEL, "bytes_per_launch": fwd_bytes, "avg_launch_ms": round(step_ms, 5),

@@ -115,6 +115,10 @@ typedef struct lbm_problem {
     int collision;           /* lbm_collision (0 = BGK; MRT needs LBM_D2Q9) */
     double mrt_rates[9];     /* MRT: rates of (rho, e, eps, jx, qx, jy, qy, pxx, pxy) in (0, 2);
                                 the stress entries are ignored (1/tau) */
+    int resident_segments;   /* tape: the taped forward keeps the states of its last R segments
+                                (0 or 1 = the last one; clamped to the number of segments), and
+                                lbm_adjoint() recomputes only the others.  Each costs K-1 states
+                                of workspace; the gradient does not depend on R */
 } lbm_problem;
 
 /* Parameters of one forward evaluation (host arrays, read during the call). */

@@ -47,6 +47,7 @@ inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 struct Layout {
     int q = 9, D = 2, n_inst = 0;
     int T = 1, K = 1, n_seg = 1, tape = 0;
+    int R = 1;                // resident segments: the last R segments' states are kept by the forward
     int n_tiles = 0, n_ftiles = 0;
     long long total_poff = 0, total_nodes = 0, total_face = 0, total_words = 0;
     long long S = 0;          // floats per state buffer
@@ -62,6 +63,8 @@ int validate_problem(const lbm_problem *p) {
     if (p->lattice != LBM_D2Q9 && p->lattice != LBM_D3Q19)
         return fail(LBM_EINVAL, "lattice must be LBM_D2Q9 or LBM_D3Q19 (got %d)", p->lattice);
     if (p->n_inst < 1 || !p->inst) return fail(LBM_EINVAL, "n_inst must be >= 1 with a descriptor array");
+    if (p->resident_segments < 0)
+        return fail(LBM_EINVAL, "resident_segments must be >= 0 (got %d)", p->resident_segments);
     const int bcs[3] = {p->bc_x, p->bc_y, p->bc_z};
     for (int a = 0; a < 3; ++a)
         if (bcs[a] < LBM_BC_PRESSURE || bcs[a] > LBM_BC_VELOCITY)
@@ -121,6 +124,7 @@ void plan(const lbm_problem *p, Layout &L) {
     if (L.K > L.T) L.K = L.T;
     L.n_seg = (L.T + L.K - 1) / L.K;
     L.tape = p->tape ? 1 : 0;
+    L.R = std::min(std::max(p->resident_segments, 1), L.n_seg);
     L.inst.assign(p->n_inst, InstDev{});
     long long poff = 0, node = 0, face = 0, words = 0;
     int tile = 0, ftile = 0;
@@ -160,7 +164,7 @@ void plan(const lbm_problem *p, Layout &L) {
     L.total_face = face;
     L.total_words = words;
     L.S = (long long)L.q * poff;
-    L.n_states = 3 + (L.tape ? (L.n_seg - 1) + (L.K - 1) + 2 : 0);
+    L.n_states = 3 + (L.tape ? (L.n_seg - 1) + L.R * (L.K - 1) + 2 : 0);
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + bytes, 256); return r; };
     L.off_inst = take(sizeof(InstDev) * p->n_inst);
@@ -197,7 +201,7 @@ struct lbm_handle {
     // state bookkeeping
     float *cur = nullptr, *prev = nullptr;
     long long cur_steps = 0;          // steps taken since the initial state
-    bool fwd_taped = false, adjoint_done = false, seg_holds_last = false;
+    bool fwd_taped = false, adjoint_done = false, resident_valid = false;
     float *nu_last = nullptr;         // nu^1 after the adjoint
     std::vector<double> tau;          // parameters of the taped forward
     // timing
@@ -208,7 +212,7 @@ struct lbm_handle {
     bool graphs = true;
     hipStream_t cap = nullptr;
     hipGraphExec_t g_fwd[2] = {nullptr, nullptr};            // [record_tape]
-    hipGraphExec_t g_rev[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [recompute_last][seed]
+    hipGraphExec_t g_rev[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [!resident][seed]
     hipGraphExec_t g_chunk[2] = {nullptr, nullptr};          // [starts from the initial state]
     int chunk_len = 0;
 
@@ -216,8 +220,10 @@ struct lbm_handle {
     float *init() const { return state(0); }
     float *pp(int k) const { return state(1 + k); }
     float *ckpt(int c) const { return c == 0 ? init() : state(3 + (c - 1)); }
-    float *seg(int j) const { return state(3 + (L.n_seg - 1) + (j - 1)); }
-    float *nu(int k) const { return state(3 + (L.n_seg - 1) + (L.K - 1) + k); }
+    // state j (1 .. K-1) of segment region r (0 .. R-1); region r holds segment n_seg - R + r
+    // after a taped forward, and region 0 is where the reverse sweep recomputes the others
+    float *seg(int r, int j) const { return state(3 + (L.n_seg - 1) + r * (L.K - 1) + (j - 1)); }
+    float *nu(int k) const { return state(3 + (L.n_seg - 1) + L.R * (L.K - 1) + k); }
     template <class T> T *at(size_t off) const { return (T *)(ws + off); }
 };
 
@@ -478,7 +484,7 @@ static void reset_state(lbm_handle *h) {
     h->cur = h->init();
     h->prev = nullptr;
     h->cur_steps = 0;
-    h->fwd_taped = h->adjoint_done = h->seg_holds_last = false;
+    h->fwd_taped = h->adjoint_done = h->resident_valid = false;
 }
 
 int lbm_set_initial(lbm_handle *h, const float *d_drho, const float *d_u) {
@@ -512,13 +518,13 @@ int lbm_get_populations(lbm_handle *h, int which, float *d_out) {
 }
 
 // Destination of step t of the forward pass.  With a tape, F^{cK} goes to
-// checkpoint c and the states of the last segment go straight to the
-// segment store, so the reverse sweep does not recompute that segment.
+// checkpoint c and the states of the last R segments go straight to their
+// regions of the segment store, so the reverse sweep does not recompute them.
 static float *fwd_dst(lbm_handle *h, int t, int record_tape) {
     const Layout &L = h->L;
     if (record_tape && t < L.T) {
-        const int c = t / L.K, j = t % L.K;
-        return j == 0 ? h->ckpt(c) : (c == L.n_seg - 1 ? h->seg(j) : h->pp(t & 1));
+        const int c = t / L.K, j = t % L.K, r = c - (L.n_seg - L.R);
+        return j == 0 ? h->ckpt(c) : (r >= 0 ? h->seg(r, j) : h->pp(t & 1));
     }
     return h->pp(t & 1);
 }
@@ -553,7 +559,7 @@ int lbm_forward(lbm_handle *h, const lbm_params *prm, int record_tape, double *l
     h->cur_steps = T;
     if (record_tape) {
         h->fwd_taped = true;
-        h->seg_holds_last = true;
+        h->resident_valid = true;
         h->tau.assign(prm->tau, prm->tau + L.n_inst);
     }
     if (loss_out) {
@@ -576,9 +582,12 @@ int lbm_forward(lbm_handle *h, const lbm_params *prm, int record_tape, double *l
 }
 
 // The reverse sweep: zero the accumulators, then per segment (last first)
-// recompute its states from the checkpoint and run the adjoint steps.
-// Event marks (timing mode only) bracket each segment's two phases.
-static int enqueue_reverse(lbm_handle *h, bool recompute_last, const float *seed, hipStream_t s,
+// recompute its states from the checkpoint and run the adjoint steps.  While
+// the taped forward's states are intact (resident), the last R segments are
+// read from their own regions; every other segment is recomputed into region
+// 0, whose resident states have been consumed by then.  Event marks (timing
+// mode only) bracket each segment's two phases.
+static int enqueue_reverse(lbm_handle *h, bool resident, const float *seed, hipStream_t s,
                            std::vector<int> *marks) {
     const Layout &L = h->L;
     const int q = L.q, T = L.T, K = L.K;
@@ -591,11 +600,13 @@ static int enqueue_reverse(lbm_handle *h, bool recompute_last, const float *seed
     int ev = 0, rc;
     for (int c = L.n_seg - 1; c >= 0; --c) {
         const int t0 = c * K, t1 = std::min(t0 + K, T);
-        auto F = [&](int j) -> const float * { return j == 0 ? h->ckpt(c) : h->seg(j); };
+        const bool keep = resident && c >= L.n_seg - L.R;
+        const int r = keep ? c - (L.n_seg - L.R) : 0;
+        auto F = [&](int j) -> const float * { return j == 0 ? h->ckpt(c) : h->seg(r, j); };
         if (marks) { if ((rc = record(h, ev))) return rc; marks->push_back(ev++); }
-        if (c != L.n_seg - 1 || recompute_last) {
+        if (!keep) {
             for (int j = 1; j < t1 - t0; ++j)
-                if ((rc = step(h, F(j - 1), h->seg(j), s))) return rc;
+                if ((rc = step(h, F(j - 1), h->seg(r, j), s))) return rc;
             if (marks) h->tm.recompute_launches += t1 - t0 - 1;
         }
         if (marks) { if ((rc = record(h, ev))) return rc; marks->push_back(ev++); }
@@ -631,10 +642,10 @@ int lbm_adjoint(lbm_handle *h, const float *d_seed_du) {
                                hipMemcpyDeviceToDevice, h->stream));
         seed = h->at<float>(L.off_seed);
     }
-    const bool recompute_last = !h->seg_holds_last;
+    const bool resident = h->resident_valid;
     if (h->timing) {
         std::vector<int> marks;
-        if ((rc = enqueue_reverse(h, recompute_last, seed, h->stream, &marks))) return rc;
+        if ((rc = enqueue_reverse(h, resident, seed, h->stream, &marks))) return rc;
         HIP_TRY(hipEventSynchronize(h->ev[marks.back()]));
         for (int c = L.n_seg - 1, k = 0; c >= 0; --c, k += 3) {
             const int t0 = c * L.K, t1 = std::min(t0 + L.K, L.T);
@@ -643,11 +654,12 @@ int lbm_adjoint(lbm_handle *h, const float *d_seed_du) {
             h->tm.adjoint_launches += t1 - t0;
         }
     } else {
-        rc = with_graph(h, h->g_rev[recompute_last ? 1 : 0][seed ? 1 : 0],
-                        [&](hipStream_t s) { return enqueue_reverse(h, recompute_last, seed, s, nullptr); });
+        rc = with_graph(h, h->g_rev[resident ? 0 : 1][seed ? 1 : 0],
+                        [&](hipStream_t s) { return enqueue_reverse(h, resident, seed, s, nullptr); });
         if (rc) return rc;
     }
-    h->seg_holds_last = L.n_seg == 1;  // earlier segments' recompute reuses the store
+    // recomputed segments overwrite region 0; with every segment resident nothing is recomputed
+    h->resident_valid = (resident && L.R == L.n_seg) || L.n_seg == 1;
     h->nu_last = h->nu(1);
     h->adjoint_done = true;
     h->prev = nullptr;  // the segment store that held F^{T-1} has been reused

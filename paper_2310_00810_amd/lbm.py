@@ -60,11 +60,15 @@ class Solver:
     lattice: 9 or 19.  instances: list of Instance (a batch of independent
     lattices).  bc: boundary kind per axis (x, y, z).  steps: T.
     ckpt_interval: K (0 = ceil(sqrt(T))).  tape: reserve the adjoint tape.
-    collision: "bgk" or (D2Q9) "mrt" with mrt_rates."""
+    collision: "bgk" or (D2Q9) "mrt" with mrt_rates.  resident_segments: the
+    taped forward keeps the states of its last R segments (K-1 states each), so
+    the reverse sweep recomputes only the others; "max" takes as many as fit in
+    the free device memory less `reserve_bytes`."""
 
     def __init__(self, lattice, instances, bc=("pressure", "wall", "periodic"), steps=1,
                  ckpt_interval=0, tape=False, loss_kind="vec", loss_scale="sum",
-                 inlet_mode="const", device="cuda", stream=None, collision="bgk", mrt_rates=MRT_RATES):
+                 inlet_mode="const", device="cuda", stream=None, collision="bgk", mrt_rates=MRT_RATES,
+                 resident_segments=1, reserve_bytes=8 << 30):
         self.q = int(lattice)
         self.D = 2 if self.q == 9 else 3
         self.instances = list(instances)
@@ -84,10 +88,26 @@ class Solver:
                                      self.steps, int(ckpt_interval), int(bool(tape)), _LOSS[loss_kind],
                                      _SCALE[loss_scale], _INLET[inlet_mode],
                                      C.COLL_MRT if collision == "mrt" else C.COLL_BGK,
-                                     (ctypes.c_double * 9)(*[float(r) for r in mrt_rates]))
+                                     (ctypes.c_double * 9)(*[float(r) for r in mrt_rates]), 1)
         L = C.lib()
         nbytes = ctypes.c_size_t(0)
         C.check(L.lbm_workspace_bytes(ctypes.byref(self.problem), ctypes.byref(nbytes)), "lbm_workspace_bytes")
+        if resident_segments == "max":
+            # one more resident segment costs the difference of two workspace sizes
+            base_bytes = int(nbytes.value)
+            self.problem.resident_segments = 2
+            C.check(L.lbm_workspace_bytes(ctypes.byref(self.problem), ctypes.byref(nbytes)), "lbm_workspace_bytes")
+            per_seg = int(nbytes.value) - base_bytes
+            free = torch.cuda.mem_get_info(self.device)[0]
+            r = 1 if per_seg <= 0 else 1 + max(0, (free - reserve_bytes - base_bytes) // per_seg)
+            self.problem.resident_segments = int(max(1, r))
+        else:
+            self.problem.resident_segments = int(resident_segments)
+        K = int(ckpt_interval) if int(ckpt_interval) > 0 else int(np.ceil(np.sqrt(self.steps)))
+        n_seg = -(-self.steps // min(K, self.steps))
+        self.problem.resident_segments = min(max(self.problem.resident_segments, 1), n_seg)
+        C.check(L.lbm_workspace_bytes(ctypes.byref(self.problem), ctypes.byref(nbytes)), "lbm_workspace_bytes")
+        self.resident_segments = self.problem.resident_segments
         self.workspace_bytes = int(nbytes.value)
         self.workspace = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device=self.device)
         base = self.workspace.data_ptr()

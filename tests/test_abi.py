@@ -53,6 +53,7 @@ def _problem(nx=64, ny=32, nz=1, q=9, steps=100, K=0, tape=0, solid=None, n=1, *
             arr[k].solid = s.ctypes.data_as(ctypes.c_void_p)
     p = C.lbm_problem(q, n, arr, kw.get("bcx", 0), kw.get("bcy", 2), kw.get("bcz", 1), steps, K, tape,
                       kw.get("loss_kind", 0), kw.get("loss_scale", 0), kw.get("inlet_mode", 0))
+    p.resident_segments = kw.get("resident", 0)
     p._keep = (arr, keep)
     return p
 
@@ -77,8 +78,23 @@ def test_workspace_size_matches_the_plan(L):
     assert rc == 0 and abs(b3 / (423 * 19 * 128 ** 3 * 4) - 1) < 3e-3
 
 
+def test_resident_segments_cost_k_minus_one_states_each(L):
+    state = 9 * 32 * 64 * 4
+    n_seg = -(-2000 // 45)
+    _, b1 = _bytes(L, _problem(steps=2000, K=45, tape=1))
+    for R in (0, 1):
+        assert _bytes(L, _problem(steps=2000, K=45, tape=1, resident=R))[1] == b1
+    for R in (2, 7, n_seg):
+        assert _bytes(L, _problem(steps=2000, K=45, tape=1, resident=R))[1] - b1 == (R - 1) * 44 * state
+    # more than the number of segments is clamped; without a tape nothing is reserved
+    assert _bytes(L, _problem(steps=2000, K=45, tape=1, resident=n_seg + 5))[1] == \
+        _bytes(L, _problem(steps=2000, K=45, tape=1, resident=n_seg))[1]
+    assert _bytes(L, _problem(steps=2000, resident=9))[1] == _bytes(L, _problem(steps=2000))[1]
+
+
 @pytest.mark.parametrize("kw,code", [
     (dict(q=7), C.LBM_EINVAL),
+    (dict(resident=-1), C.LBM_EINVAL),
     (dict(nz=2), C.LBM_EINVAL),                 # D2Q9 with nz != 1
     (dict(nx=1), C.LBM_EINVAL),                 # pressure axis needs nx >= 2
     (dict(steps=0), C.LBM_EINVAL),

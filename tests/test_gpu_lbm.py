@@ -35,7 +35,7 @@ def oracle_pull_step(lat, tau, rin, rout, F):
 
 
 def solver_for(lat, steps, tape=False, K=0, roi=None, target=None, loss_kind="vec",
-               loss_scale="sum", inlet_mode="const"):
+               loss_scale="sum", inlet_mode="const", resident=1):
     lbm = _lbm()
     D = 2 if lat.q == 9 else 3
     tgt = None if target is None else np.asarray(target)[..., :D].astype(np.float32)
@@ -44,7 +44,7 @@ def solver_for(lat, steps, tape=False, K=0, roi=None, target=None, loss_kind="ve
     kw = {} if lat.mrt is None else dict(collision="mrt", mrt_rates=tuple(lat.mrt))
     return lbm.Solver(lat.q, [ins], bc=tuple(BC_NAMES[b] for b in lat.bc_tuple), steps=steps,
                       ckpt_interval=K, tape=tape, loss_kind=loss_kind, loss_scale=loss_scale,
-                      inlet_mode=inlet_mode, **kw)
+                      inlet_mode=inlet_mode, resident_segments=resident, **kw)
 
 
 def _inlet(lat, d):
@@ -267,6 +267,44 @@ def test_checkpoint_interval_invariance_bitwise():
     for r in res[1:]:
         for k in ("drho_in", "dtau", "drho_out"):
             assert np.array_equal(r[k], res[0][k])
+
+
+def test_resident_segments_bitwise():
+    """Keeping the taped forward's last R segments resident, so that the
+    reverse sweep recomputes only the others, gives bit for bit the gradient
+    of a sweep that recomputes every segment: for several R (one of them
+    above the number of segments), on a second adjoint without a new forward
+    (which must recompute), with graphs, direct launches and timing."""
+    n = (24, 16, 12)
+    solid = G.boolean_spheres(n, (2.5, 4.0), 0.6, seed=3, x_margin=3)
+    lat = O.Lattice(19, n[0], n[1], n[2], (O.BC_PRESSURE, O.BC_PERIODIC, O.BC_PERIODIC), solid)
+    T, K, tau = 50, 7, 0.75                      # 8 segments, the last one a single step
+    din = (0.004 * G.fourier_profile(n[1], n[2], seed=33)).astype(np.float32).ravel()
+    rng = np.random.default_rng(8)
+    tgt = (1e-4 * rng.standard_normal(lat.shape + (3,))).astype(np.float32)
+
+    def run(R, mode):
+        s = solver_for(lat, T, tape=True, K=K, target=tgt, inlet_mode="profile", resident=R)
+        assert s.resident_segments == min(R, 8)
+        if mode == "direct":
+            s.set_graphs(False)
+        if mode == "timing":
+            s.set_timing(True)
+        out = []
+        loss = s.forward(tau, din, 0.0, record_tape=True)
+        for _ in range(2):
+            s.adjoint()
+            out.append((s.grad(), s.get_populations("adjoint").cpu().numpy()))
+        return loss[0], out
+
+    l0, ref = run(1, "graphs")
+    for R, mode in [(1, "direct"), (2, "graphs"), (5, "direct"), (5, "timing"), (8, "graphs"), (12, "direct")]:
+        l, out = run(R, mode)
+        assert l == l0, (R, mode)
+        for (g, a), (g0, a0) in zip(out, ref):
+            for k in ("drho_in", "dtau", "drho_out"):
+                assert np.array_equal(g[k], g0[k]), (R, mode, k)
+            assert np.array_equal(a, a0), (R, mode)
 
 
 def test_repeat_runs_are_bitwise_identical():

@@ -95,6 +95,7 @@ def test_resident_segments_cost_k_minus_one_states_each(L):
 @pytest.mark.parametrize("kw,code", [
     (dict(q=7), C.LBM_EINVAL),
     (dict(resident=-1), C.LBM_EINVAL),
+    (dict(nx=1 << 20, ny=2), C.LBM_EINVAL),     # x positions are packed into 20 bits
     (dict(nz=2), C.LBM_EINVAL),                 # D2Q9 with nz != 1
     (dict(nx=1), C.LBM_EINVAL),                 # pressure axis needs nx >= 2
     (dict(steps=0), C.LBM_EINVAL),
@@ -107,6 +108,11 @@ def test_invalid_problems_are_rejected(L, kw, code):
     rc, _ = _bytes(L, _problem(**kw))
     assert rc == code
     assert len(L.lbm_last_error()) > 0
+
+
+def test_largest_row_length_is_accepted(L):
+    rc, b = _bytes(L, _problem(nx=(1 << 20) - 1, ny=2))
+    assert rc == 0 and b >= 3 * 9 * 2 * ((1 << 20) - 1) * 4
 
 
 def test_solid_inlet_rejected_in_profile_mode(L):

@@ -87,6 +87,27 @@ def f32(x):
 @pytest.mark.parametrize("T", [1, 3])
 def test_steps_from_random_state(name, lat, T):
     """T steps from a random non-equilibrium state, all boundary kinds."""
+    _check_random_steps(lat, T)
+
+
+def _long_rows(q):
+    nx = (1 << 20) - 1                     # the longest row the ABI accepts
+    ny, nz = (3, 1) if q == 9 else (2, 2)
+    rng = np.random.default_rng(61 + q)
+    solid = (rng.random((nz, ny, nx)) < 0.3).astype(np.uint8)
+    solid[:, :, [0, -1]] = 0
+    bc = (O.BC_PRESSURE, O.BC_WALL, O.BC_PERIODIC)
+    return O.Lattice(q, nx, ny, nz, bc, solid)
+
+
+@pytest.mark.parametrize("q", [9, 19])
+def test_steps_on_the_longest_rows(q):
+    """Rows of 2^20 - 1 nodes (x positions fill their 20-bit field): two
+    steps from a random state against the oracle."""
+    _check_random_steps(_long_rows(q), 2)
+
+
+def _check_random_steps(lat, T):
     _, w, _ = O.velset(lat.q)
     fl = lat.fluid()[..., None]
     F0 = (w + G.random_perturbation(lat.shape, lat.q, 0.01, seed=21)) * fl
@@ -372,6 +393,47 @@ def test_batched_instances_match_single_runs():
         assert l1[0] == lb[k]
         assert g1["dtau"][0] == gb["dtau"][k] and g1["drho_in"][0] == gb["drho_in"][k]
         assert np.array_equal(s.macro()[1].cpu().numpy(), ub[k])
+
+
+def test_all_solid_instances():
+    """An instance without a fluid node, alone or between two others in a
+    batch: no tile is launched for it, its loss and gradients are zero, its
+    velocity reads zero, and its neighbours in the batch are unaffected (bit
+    for bit what they give alone)."""
+    lbm = _lbm()
+    shapes = [(64, 32), (40, 24), (96, 40)]
+    insts = []
+    for k, (nx, ny) in enumerate(shapes):
+        solid = np.ones((1, ny, nx), np.uint8) if k == 1 else G.rsa_disks(nx, ny, (3.0, 6.0), 0.8, seed=200 + k)[None]
+        tgt = np.full((1, ny, nx, 2), 1e-3, np.float32)
+        insts.append(lbm.Instance(nx, ny, 1, solid=solid, target_u=tgt))
+    taus, dins = [0.7, 0.9, 1.1], [0.002, 0.004, 0.006]
+    for scale in ("sum", "mean"):
+        bs = lbm.Solver(9, insts, steps=60, tape=True, ckpt_interval=7, loss_scale=scale)
+        lb = bs.forward(taus, dins, 0.0, record_tape=True)
+        bs.adjoint()
+        gb = bs.grad()
+        ub = bs.split(bs.macro()[1].cpu().numpy())
+        assert lb[1] == 0.0 and gb["dtau"][1] == 0.0 and gb["drho_in"][1] == 0.0 and gb["drho_out"][1] == 0.0
+        assert not np.any(ub[1])
+        pa = bs.get_populations("adjoint").cpu().numpy()       # [inst][i][nz][ny][nx]
+        o = 9 * insts[0].nodes
+        assert not np.any(pa[o:o + 9 * insts[1].nodes])
+        for k in (0, 2):
+            s = lbm.Solver(9, [insts[k]], steps=60, tape=True, ckpt_interval=7, loss_scale=scale)
+            l1 = s.forward(taus[k], dins[k], 0.0, record_tape=True)
+            s.adjoint()
+            g1 = s.grad()
+            assert l1[0] == lb[k]
+            assert g1["dtau"][0] == gb["dtau"][k] and g1["drho_in"][0] == gb["drho_in"][k]
+            assert np.array_equal(s.macro()[1].cpu().numpy(), ub[k])
+        # the solid instance alone: nothing to launch, zero loss and gradients
+        s = lbm.Solver(9, [insts[1]], steps=60, tape=True, ckpt_interval=7, loss_scale=scale)
+        assert s.forward(0.9, 0.004, 0.0, record_tape=True)[0] == 0.0
+        s.adjoint()
+        g = s.grad()
+        assert g["dtau"][0] == 0.0 and g["drho_in"][0] == 0.0
+        assert not torch.any(s.macro()[1]).item()
 
 
 def test_error_paths():

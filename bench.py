@@ -19,7 +19,7 @@ one.  The gradient is bit for bit the same either way.
 
 Prints ONE JSON line.  value = forward+adjoint MLUPS (all lattice nodes x T
 per second of the whole gradient evaluation).  roofline = the dominant kernel
-of that evaluation, k_step (forward pass and segment recomputes: about 60 % of
+of that evaluation, k_step (forward pass and segment recomputes: about 57 % of
 the GPU time), averaged over all its launches; adj_roofline = k_adj_step.
 Both use algorithmic bytes (152 B and 228 B per fluid node) over HIP-event
 kernel times on the library stream.

@@ -79,7 +79,7 @@ def _paint_disk(solid, cx, cy, r):
 
 
 def rsa_disks(nx: int, ny: int, r_range=(6.0, 14.0), target_porosity=0.7, seed=0,
-              x_margin=4, gap=2.0, max_reject=100_000, max_reseed=20, batch=512):
+              x_margin=4, gap=2.0, max_reject=100_000, max_reseed=20, batch=512, hydro=1.0):
     """2D solid mask (ny, nx) uint8 of non-overlapping disks.
 
     Disks are drawn with radius ~ U[r_range] and a real-valued centre such
@@ -91,10 +91,16 @@ def rsa_disks(nx: int, ny: int, r_range=(6.0, 14.0), target_porosity=0.7, seed=0
     in batches and the first acceptable one of a batch is placed (the others
     are discarded), which is random sequential addition with a different use
     of the random stream.  The mask must let fluid percolate from inlet to
-    outlet; otherwise the next seed of the stream is used."""
+    outlet; otherwise the next seed of the stream is used.
+
+    hydro < 1: the grains are placed (and the porosity target is met) with
+    their radius R, but the returned mask paints them with the hydrodynamic
+    radius hydro * R (Section 3.1.2 uses 0.9 R), which opens the contacts
+    that would close the 2D pore space."""
     rng = np.random.default_rng(seed)
     for _ in range(max_reseed):
         solid = np.zeros((ny, nx), np.uint8)
+        hsolid = solid if hydro == 1.0 else np.zeros((ny, nx), np.uint8)
         placed = np.zeros((0, 3))
         rejects = 0
         overlap_ok = False
@@ -120,8 +126,10 @@ def rsa_disks(nx: int, ny: int, r_range=(6.0, 14.0), target_porosity=0.7, seed=0
                 rejects = 0 if j == 0 else rejects + j
             placed = np.vstack([placed, [cx[j], cy[j], r[j]]])
             _paint_disk(solid, cx[j], cy[j], r[j])
-        if percolates(solid):
-            return solid
+            if hsolid is not solid:
+                _paint_disk(hsolid, cx[j], cy[j], hydro * r[j])
+        if percolates(hsolid):
+            return hsolid
     raise RuntimeError("no percolating packing found")
 
 
@@ -171,25 +179,26 @@ def _paint_sphere(solid, c, r, periodic):
 
 
 def boolean_disks(nx, ny, r_range=(6.0, 14.0), target_porosity=0.6, seed=0, periodic_y=False, x_margin=4,
-                  max_reseed=20):
+                  max_reseed=20, hydro=1.0):
     """2D solid mask (ny, nx) uint8 of overlapping disks (Boolean model), for
     porosities below what non-overlapping placement reaches.  Centres have
     x in [x_margin + r, nx-1-x_margin-r] and y uniform (periodic_y) or inside
-    [r, ny-1-r]; the pore space must percolate from inlet to outlet."""
+    [r, ny-1-r]; the pore space must percolate from inlet to outlet.
+    hydro: as in rsa_disks (placement with R, mask painted with hydro * R)."""
     rng = np.random.default_rng(seed)
     for _ in range(max_reseed):
         solid = np.zeros((ny, nx), np.uint8)
+        hsolid = solid if hydro == 1.0 else np.zeros((ny, nx), np.uint8)
         while porosity(solid) > target_porosity:
             r = rng.uniform(*r_range)
             cx = rng.uniform(x_margin + r, nx - 1 - x_margin - r)
             cy = rng.uniform(0, ny) if periodic_y else rng.uniform(r, ny - 1 - r)
-            if periodic_y:
-                for sh in (-ny, 0, ny):
-                    _paint_disk(solid, cx, cy + sh, r)
-            else:
-                _paint_disk(solid, cx, cy, r)
-        if percolates(solid):
-            return solid
+            for sh in ((-ny, 0, ny) if periodic_y else (0,)):
+                _paint_disk(solid, cx, cy + sh, r)
+                if hsolid is not solid:
+                    _paint_disk(hsolid, cx, cy + sh, hydro * r)
+        if percolates(hsolid):
+            return hsolid
     raise RuntimeError("no percolating packing found")
 
 

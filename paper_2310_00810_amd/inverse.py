@@ -133,6 +133,64 @@ def reynolds(U, D, nu):
     return U * D / (2.0 * nu)
 
 
+def carman_kozeny(porosity, d_p, phi_s=1.0, phi_ck=180.0):
+    """Carman-Kozeny permeability (Eq. 8): k = phi_s^2 eps^3 D_p^2 / (Phi_CK (1 - eps)^2),
+    with eps the porosity, D_p the mean grain diameter, phi_s the sphericity
+    and Phi_CK the Kozeny factor (180 for a packing of spheres)."""
+    e = float(porosity)
+    return phi_s ** 2 * e ** 3 * d_p ** 2 / (phi_ck * (1.0 - e) ** 2)
+
+
+def kozeny_factor(tortuosity, phi=90.0):
+    """Kozeny factor from the tortuosity L_e / L of the streamlines (Section
+    3.3): Phi_CK = Phi (L_e / L)^2, Phi = 90 for spherical grains."""
+    return phi * tortuosity ** 2
+
+
+def physical_permeability(k_lattice, dx):
+    """Lattice permeability (lu^2) in m^2 for a lattice spacing dx (m per lu)."""
+    return k_lattice * dx ** 2
+
+
+def lattice_time_step(nu_lattice, dx, nu_physical=1e-6):
+    """Seconds per time step that make the lattice viscosity the physical one:
+    nu_phys = nu_lattice dx^2 / dt (water: 1e-6 m^2/s)."""
+    return nu_lattice * dx ** 2 / nu_physical
+
+
+def spline_basis(n_nodes, n_knots):
+    """Matrix B (n_nodes x n_knots) of the natural cubic spline through
+    n_knots equally spaced knots spanning the n_nodes inlet nodes: the
+    profile is B @ knot_values, and a gradient with respect to the profile
+    maps to the knots as B.T @ g (Section 3.2 draws the inlet pressure as a
+    cubic spline).  Natural: zero second derivative at the end knots."""
+    if n_knots < 2 or n_nodes < 1:
+        raise ValueError("need at least two knots and one node")
+    xk = np.linspace(0.0, n_nodes - 1.0, n_knots)
+    h = np.diff(xk)
+    n = n_knots
+    # second derivatives M of the spline through unit knot vectors: A M = R v
+    A = np.zeros((n, n))
+    R = np.zeros((n, n))
+    A[0, 0] = A[-1, -1] = 1.0
+    for i in range(1, n - 1):
+        A[i, i - 1], A[i, i], A[i, i + 1] = h[i - 1] / 6.0, (h[i - 1] + h[i]) / 3.0, h[i] / 6.0
+        R[i, i - 1], R[i, i], R[i, i + 1] = 1.0 / h[i - 1], -1.0 / h[i - 1] - 1.0 / h[i], 1.0 / h[i]
+    Mv = np.linalg.solve(A, R)                       # n x n: second derivatives per unit knot
+    x = np.arange(n_nodes, dtype=np.float64)
+    j = np.clip(np.searchsorted(xk, x, side="right") - 1, 0, n - 2)
+    a = (xk[j + 1] - x) / h[j]
+    b = (x - xk[j]) / h[j]
+    B = np.zeros((n_nodes, n))
+    rows = np.arange(n_nodes)
+    B[rows, j] += a
+    B[rows, j + 1] += b
+    c2 = h[j] ** 2 / 6.0
+    B += ((a ** 3 - a) * c2)[:, None] * Mv[j] + ((b ** 3 - b) * c2)[:, None] * Mv[j + 1]
+    return B
+
+
 __all__ = ["Adam", "History", "recover_constant_head", "recover_profile_and_tau", "darcy_permeability",
            "superficial_velocity", "pressure_gradient", "viscosity", "tau_from_viscosity", "reynolds",
+           "carman_kozeny", "kozeny_factor", "physical_permeability", "lattice_time_step", "spline_basis",
            "math"]

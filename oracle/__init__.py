@@ -222,8 +222,10 @@ def mrt_matrix():
 
 
 def grad(lat, tau, rho_in, rho_out, f0, T, target_u, weight=None, kind=LOSS_VEC,
-         scale=1.0, K=0, want_f0_bar=False):
-    """Reverse-mode gradient of the loss after T steps.
+         scale=1.0, K=0, want_f0_bar=False, frames=1, stride=1):
+    """Reverse-mode gradient of the loss after T steps.  frames > 1: the loss
+    sums over the states after steps T - (frames - 1 - m) * stride, target_u
+    holding one target per frame (frames, *shape, 3).
 
     Returns dict(loss, drho_in (nz, ny), drho_out (nz, ny), dtau[, df0])."""
     din = np.zeros((lat.nz, lat.ny))
@@ -235,8 +237,8 @@ def grad(lat, tau, rho_in, rho_out, f0, T, target_u, weight=None, kind=LOSS_VEC,
     fn.restype = ctypes.c_double
     L = fn(*lat.args(), ctypes.c_double(tau), _p(lat.face(rho_in)), _p(lat.face(rho_out)),
            _p(_f64(f0)), ctypes.c_int(T), ctypes.c_int(K), _p(_f64(target_u)), _p(w),
-           ctypes.c_int(kind), ctypes.c_double(scale), _p(din), _p(dout),
-           ctypes.byref(dtau), _p(fb))
+           ctypes.c_int(kind), ctypes.c_double(scale), ctypes.c_int(frames), ctypes.c_int(stride),
+           _p(din), _p(dout), ctypes.byref(dtau), _p(fb))
     out = dict(loss=L, drho_in=din, drho_out=dout, dtau=dtau.value)
     if want_f0_bar:
         out["df0"] = fb
@@ -245,16 +247,17 @@ def grad(lat, tau, rho_in, rho_out, f0, T, target_u, weight=None, kind=LOSS_VEC,
 
 def loss_complex_step(lat, tau, rho_in, rho_out, f0, T, target_u, weight=None,
                       kind=LOSS_VEC, scale=1.0, dtau=0.0, drho_in=0.0, drho_out=0.0,
-                      h=1e-30):
+                      h=1e-30, frames=1, stride=1):
     """(loss, directional derivative) along (dtau, drho_in, drho_out) by the
-    complex-step method: Im L(p + i h v) / h."""
+    complex-step method: Im L(p + i h v) / h.  frames, stride: as in grad."""
     res = np.zeros(2)
     w = _f64(weight) if weight is not None else None
     lib().orc_run_loss_cs(*lat.args(), ctypes.c_double(tau), ctypes.c_double(h * dtau),
                           _p(lat.face(rho_in)), _p(lat.face(np.asarray(drho_in) * h)),
                           _p(lat.face(rho_out)), _p(lat.face(np.asarray(drho_out) * h)),
                           _p(_f64(f0)), ctypes.c_int(T), _p(_f64(target_u)), _p(w),
-                          ctypes.c_int(kind), ctypes.c_double(scale), _p(res))
+                          ctypes.c_int(kind), ctypes.c_double(scale), ctypes.c_int(frames),
+                          ctypes.c_int(stride), _p(res))
     return res[0], res[1] / h
 
 

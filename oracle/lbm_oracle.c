@@ -102,6 +102,16 @@ static const orc_velset *orc_vel(int q)
 
 static long orc_nodes(const orc_lattice *L) { return (long)L->nx * L->ny * L->nz; }
 
+/* Loss frame of the state after step t (1 <= t <= T), or -1: the frames sit
+ * at T - (frames - 1 - m) * stride for m = 0 .. frames - 1, the last one at T. */
+static int orc_frame_of(int t, int T, int frames, int stride)
+{
+    if (frames <= 1) return t == T ? 0 : -1;
+    const int back = T - t;
+    if (back < 0 || back % stride != 0 || back / stride > frames - 1) return -1;
+    return frames - 1 - back / stride;
+}
+
 static long orc_index(const orc_lattice *L, const int x[3])
 {
     return ((long)x[2] * L->ny + x[1]) * L->nx + x[0];
@@ -249,7 +259,7 @@ void orc_run(ORC_ARGS, double tau, const double *rho_in, const double *rho_out,
              double *f, int T)
 {
     ORC_MAKE;
-    orc_run_loss_d(&L, tau, rho_in, rho_out, f, T, NULL, NULL, 0, 1.0);
+    orc_run_loss_d(&L, tau, rho_in, rho_out, f, T, NULL, NULL, 0, 1.0, 1, 1);
 }
 
 void orc_macro(ORC_ARGS, const double *f, double *rho, double *u)
@@ -271,7 +281,8 @@ void orc_run_loss_cs(ORC_ARGS, double tau_re, double tau_im,
                      const double *rho_in_re, const double *rho_in_im,
                      const double *rho_out_re, const double *rho_out_im,
                      const double *f0, int T, const double *target_u,
-                     const double *weight, int kind, double scale, double *loss_re_im)
+                     const double *weight, int kind, double scale, int frames, int stride,
+                     double *loss_re_im)
 {
     ORC_MAKE;
     const long n = orc_nodes(&L);
@@ -285,7 +296,7 @@ void orc_run_loss_cs(ORC_ARGS, double tau_re, double tau_im,
         ro[k] = rho_out_re[k] + I * rho_out_im[k];
     }
     double _Complex l = orc_run_loss_z(&L, tau_re + I * tau_im, ri, ro, f, T, target_u,
-                                       weight, kind, scale);
+                                       weight, kind, scale, frames, stride);
     loss_re_im[0] = creal(l);
     loss_re_im[1] = cimag(l);
     free(f); free(ri); free(ro);
@@ -588,11 +599,14 @@ void orc_loss_seed(ORC_ARGS, const double *f, const double *target_u, const doub
  * recomputed from its checkpoint in reverse order and then swept backwards
  * stage by stage: boundary transpose (Zou-He, or anti-bounce-back whose
  * contribution joins the streaming transpose's), streaming transpose,
- * collision transpose.  fbar0 (nullable) receives dL/df^0.  Returns the loss. */
+ * collision transpose.  With several loss frames (see orc_run_loss), the
+ * derivative of a frame's loss with respect to the state it is taken on
+ * joins dL/df^t before that step's transposes.  fbar0 (nullable) receives
+ * dL/df^0.  Returns the loss. */
 double orc_grad(ORC_ARGS, double tau, const double *rho_in, const double *rho_out,
                 const double *f0, int T, int K, const double *target_u,
-                const double *weight, int kind, double scale, double *drho_in,
-                double *drho_out, double *dtau, double *fbar0)
+                const double *weight, int kind, double scale, int frames, int stride,
+                double *drho_in, double *drho_out, double *dtau, double *fbar0)
 {
     ORC_MAKE;
     const long nq = orc_nodes(&L) * q;
@@ -606,15 +620,19 @@ double orc_grad(ORC_ARGS, double tau, const double *rho_in, const double *rho_ou
     double *a = malloc(sizeof(double) * (size_t)nq);
     double *b = malloc(sizeof(double) * (size_t)nq);
     double *fsb = malloc(sizeof(double) * (size_t)nq);
+    const long n = orc_nodes(&L);
+    if (frames < 1) frames = 1;
     memcpy(f, f0, sizeof(double) * (size_t)nq);
+    double loss = 0;
     for (int t = 0; t < T; t++) {
         if (t % K == 0) memcpy(&ckpt[(t / K) * nq], f, sizeof(double) * (size_t)nq);
         orc_step_d(&L, tau, rho_in, rho_out, f, scratch);
+        const int m = orc_frame_of(t + 1, T, frames, stride);
+        if (m >= 0) loss += orc_loss_d(&L, f, target_u + 3 * n * (long)m, weight, kind, scale);
     }
-    double loss = orc_loss_d(&L, f, target_u, weight, kind, scale);
     for (long k = 0; k < nf; k++) drho_in[k] = drho_out[k] = 0;
     *dtau = 0;
-    orc_loss_seed(ORC_PASS, f, target_u, weight, kind, scale, a);
+    orc_loss_seed(ORC_PASS, f, target_u + 3 * n * (long)(frames - 1), weight, kind, scale, a);
     for (int c = nseg - 1; c >= 0; c--) {
         int t0 = c * K, t1 = (c + 1) * K < T ? (c + 1) * K : T;
         memcpy(&seg[0], &ckpt[c * nq], sizeof(double) * (size_t)nq);
@@ -625,6 +643,13 @@ double orc_grad(ORC_ARGS, double tau, const double *rho_in, const double *rho_ou
         for (int t = t1; t > t0; t--) {
             /* a = dL/df^t  ->  a = dL/df^{t-1} */
             const double *fprev = &seg[(t - 1 - t0) * nq];
+            const int m = t < T ? orc_frame_of(t, T, frames, stride) : -1;
+            if (m >= 0) {
+                /* the frame's loss on f^t: f^t is the next segment's checkpoint at t1 */
+                const double *ft = t == t1 ? &ckpt[(c + 1) * nq] : &seg[(t - t0) * nq];
+                orc_loss_seed(ORC_PASS, ft, target_u + 3 * n * (long)m, weight, kind, scale, fsb);
+                for (long k = 0; k < nq; k++) a[k] += fsb[k];
+            }
             if (L.bc[0] == ORC_BC_ABB) {
                 /* the boundary pass read the post-collision state of step t-1 */
                 memcpy(scratch, fprev, sizeof(double) * (size_t)nq);

@@ -289,15 +289,23 @@ static R FN(loss)(const orc_lattice *L, const R *f, const double *target_u,
     return scale * acc;
 }
 
-/* Runs T steps from f (in place) and returns the loss of the final state. */
+/* Runs T steps from f (in place) and returns the loss: with frames <= 1 the
+ * loss of the final state; otherwise the sum over the states after steps
+ * T - (frames - 1 - m) * stride, m = 0 .. frames - 1, each against its own
+ * target frame (target_u is [frames][node][3]), added in time order. */
 static R FN(run_loss)(const orc_lattice *L, R tau, const R *rho_in, const R *rho_out,
                       R *f, int T, const double *target_u, const double *weight,
-                      int kind, double scale)
+                      int kind, double scale, int frames, int stride)
 {
-    const long nq = orc_nodes(L) * L->q;
+    const long n = orc_nodes(L), nq = n * L->q;
     R *scratch = (R *)malloc(sizeof(R) * (size_t)nq);
-    for (int t = 0; t < T; t++) FN(step)(L, tau, rho_in, rho_out, f, scratch);
+    R acc = 0;
+    if (frames < 1) frames = 1;
+    for (int t = 1; t <= T; t++) {
+        FN(step)(L, tau, rho_in, rho_out, f, scratch);
+        const int m = orc_frame_of(t, T, frames, stride);
+        if (target_u && m >= 0) acc += FN(loss)(L, f, target_u + 3 * n * (long)m, weight, kind, scale);
+    }
     free(scratch);
-    if (!target_u) return 0;
-    return FN(loss)(L, f, target_u, weight, kind, scale);
+    return acc;
 }

@@ -97,7 +97,8 @@ typedef struct lbm_instance {
     int nx, ny, nz;          /* nz = 1 for D2Q9; nx >= 2 with density faces; nx < 2^20 */
     const uint8_t *solid;    /* [nz][ny][nx], nonzero = solid node; NULL = all fluid */
     const float *roi;        /* [nz][ny][nx] loss weights (Eq. 7 region of interest); NULL = 1 */
-    const float *target_u;   /* [nz][ny][nx][D] target velocity; NULL = 0 */
+    const float *target_u;   /* [frames][nz][ny][nx][D] target velocity (frames = loss_frames, at
+                                least 1); NULL = 0 */
 } lbm_instance;
 
 /* The problem: lattice, instances, boundary kinds, horizon and loss. */
@@ -119,6 +120,11 @@ typedef struct lbm_problem {
                                 (0 or 1 = the last one; clamped to the number of segments), and
                                 lbm_adjoint() recomputes only the others.  Each costs K-1 states
                                 of workspace; the gradient does not depend on R */
+    int loss_frames;         /* time-windowed loss (Section 3.4 observes the periodic wake over
+                                time): the loss is summed over the states after steps
+                                T - (loss_frames - 1 - m) * loss_stride, m = 0 .. loss_frames - 1,
+                                each against its own target frame.  0 or 1: the final state only */
+    int loss_stride;         /* steps between loss frames (>= 1; (loss_frames - 1) * loss_stride < T) */
 } lbm_problem;
 
 /* Parameters of one forward evaluation (host arrays, read during the call). */

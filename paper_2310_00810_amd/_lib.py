@@ -46,7 +46,8 @@ class lbm_problem(ctypes.Structure):
                 ("steps", ctypes.c_int), ("ckpt_interval", ctypes.c_int), ("tape", ctypes.c_int),
                 ("loss_kind", ctypes.c_int), ("loss_scale", ctypes.c_int), ("inlet_mode", ctypes.c_int),
                 ("collision", ctypes.c_int), ("mrt_rates", ctypes.c_double * 9),
-                ("resident_segments", ctypes.c_int)]
+                ("resident_segments", ctypes.c_int), ("loss_frames", ctypes.c_int),
+                ("loss_stride", ctypes.c_int)]
 
 
 class lbm_params(ctypes.Structure):

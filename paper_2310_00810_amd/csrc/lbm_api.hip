@@ -48,6 +48,7 @@ struct Layout {
     int q = 9, D = 2, n_inst = 0;
     int T = 1, K = 1, n_seg = 1, tape = 0;
     int R = 1;                // resident segments: the last R segments' states are kept by the forward
+    int frames = 1, stride = 1;   // loss frames: the states after steps T - (frames - 1 - m) stride
     int n_tiles = 0, n_ftiles = 0;
     long long total_poff = 0, total_nodes = 0, total_face = 0, total_words = 0;
     long long S = 0;          // floats per state buffer
@@ -65,6 +66,11 @@ int validate_problem(const lbm_problem *p) {
     if (p->n_inst < 1 || !p->inst) return fail(LBM_EINVAL, "n_inst must be >= 1 with a descriptor array");
     if (p->resident_segments < 0)
         return fail(LBM_EINVAL, "resident_segments must be >= 0 (got %d)", p->resident_segments);
+    if (p->loss_frames < 0) return fail(LBM_EINVAL, "loss_frames must be >= 0 (got %d)", p->loss_frames);
+    if (p->loss_frames > 1 && (p->loss_stride < 1 || (long long)(p->loss_frames - 1) * p->loss_stride >= p->steps))
+        return fail(LBM_EINVAL, "loss frames must lie on steps 1 .. T: need loss_stride >= 1 and "
+                                "(loss_frames - 1) loss_stride < T (got %d frames, stride %d, T %d)",
+                    p->loss_frames, p->loss_stride, p->steps);
     const int bcs[3] = {p->bc_x, p->bc_y, p->bc_z};
     for (int a = 0; a < 3; ++a)
         if (bcs[a] < LBM_BC_PRESSURE || bcs[a] > LBM_BC_VELOCITY)
@@ -125,6 +131,8 @@ void plan(const lbm_problem *p, Layout &L) {
     L.n_seg = (L.T + L.K - 1) / L.K;
     L.tape = p->tape ? 1 : 0;
     L.R = std::min(std::max(p->resident_segments, 1), L.n_seg);
+    L.frames = std::max(p->loss_frames, 1);
+    L.stride = L.frames > 1 ? p->loss_stride : 1;
     L.inst.assign(p->n_inst, InstDev{});
     long long poff = 0, node = 0, face = 0, words = 0;
     int tile = 0, ftile = 0;
@@ -170,7 +178,7 @@ void plan(const lbm_problem *p, Layout &L) {
     L.off_inst = take(sizeof(InstDev) * p->n_inst);
     L.off_mask = take(sizeof(uint2) * words);
     L.off_roi = take(sizeof(float) * poff);
-    L.off_target = take(sizeof(float) * poff * L.D);
+    L.off_target = take(sizeof(float) * poff * L.D * L.frames);
     L.off_face_in = take(sizeof(float) * face);
     L.off_face_out = take(sizeof(float) * face);
     L.off_grad_in = take(sizeof(double) * face);
@@ -384,7 +392,8 @@ int lbm_init(lbm_handle **out, const lbm_problem *p, void *d_workspace, size_t b
     const Layout &L = h->L;
     // host copies of the row-word tables, weights and targets in the device layouts
     std::vector<uint2> rw(L.total_words);
-    std::vector<float> roi(L.total_poff, 0.f), target((size_t)L.total_poff * L.D, 0.f);
+    const size_t frame_floats = (size_t)L.total_poff * L.D;
+    std::vector<float> roi(L.total_poff, 0.f), target(frame_floats * L.frames, 0.f);
     for (int b = 0; b < L.n_inst; ++b) {
         const lbm_instance &S = p->inst[b];
         InstDev &I = h->hinst[b];
@@ -404,7 +413,12 @@ int lbm_init(lbm_handle **out, const lbm_problem *p, void *d_workspace, size_t b
                         }
                         roi[I.poff + id] = S.roi ? S.roi[dn] : 1.0f;
                         if (S.target_u)
-                            for (int a = 0; a < L.D; ++a) target[I.poff * L.D + a * I.plane + id] = S.target_u[dn * L.D + a];
+                            for (int f = 0; f < L.frames; ++f) {
+                                const long long fdn = (long long)f * S.nz * S.ny * S.nx + dn;
+                                for (int a = 0; a < L.D; ++a)
+                                    target[f * frame_floats + I.poff * L.D + a * I.plane + id] =
+                                        S.target_u[fdn * L.D + a];
+                            }
                         ++id;
                     }
                 }
@@ -529,12 +543,33 @@ static float *fwd_dst(lbm_handle *h, int t, int record_tape) {
     return h->pp(t & 1);
 }
 
+// Loss frame of the state after step t, or -1: frames sit at
+// T - (frames - 1 - m) stride, m = 0 .. frames - 1.
+static int frame_of(const Layout &L, int t) {
+    const int back = L.T - t;
+    if (back < 0 || back % L.stride) return -1;
+    const int m = L.frames - 1 - back / L.stride;
+    return m >= 0 ? m : -1;
+}
+
+static const float *frame_target(lbm_handle *h, int m) {
+    return h->at<float>(h->L.off_target) + (size_t)m * h->L.total_poff * h->L.D;
+}
+
+// The steps of a forward pass; the frames of a time-windowed loss before T
+// add their partial sums as the pass goes (the frame at T is added by
+// lbm_forward when a loss is asked for).
 static int enqueue_forward(lbm_handle *h, int record_tape, hipStream_t s) {
+    const Layout &L = h->L;
     const float *src = h->init();
-    for (int t = 1; t <= h->L.T; ++t) {
+    for (int t = 1; t <= L.T; ++t) {
         float *dst = fwd_dst(h, t, record_tape);
         int rc = step(h, src, dst, s);
         if (rc) return rc;
+        const int m = t < L.T ? frame_of(L, t) : -1;
+        if (m >= 0)
+            HIP_TRY(lbm::launch_loss(L.q, h->G, dst, h->at<float>(L.off_roi), frame_target(h, m), h->P.loss_kind,
+                                     h->at<double>(L.off_part_loss), m > 0, s));
         src = dst;
     }
     return LBM_OK;
@@ -563,8 +598,8 @@ int lbm_forward(lbm_handle *h, const lbm_params *prm, int record_tape, double *l
         h->tau.assign(prm->tau, prm->tau + L.n_inst);
     }
     if (loss_out) {
-        HIP_TRY(lbm::launch_loss(L.q, h->G, h->cur, h->at<float>(L.off_roi), h->at<float>(L.off_target),
-                                 h->P.loss_kind, h->at<double>(L.off_part_loss), h->stream));
+        HIP_TRY(lbm::launch_loss(L.q, h->G, h->cur, h->at<float>(L.off_roi), frame_target(h, L.frames - 1),
+                                 h->P.loss_kind, h->at<double>(L.off_part_loss), L.frames > 1, h->stream));
         if ((rc = reduce_to_host(h, L.off_part_loss, 1, 0))) return rc;
         bool finite = true;
         for (int b = 0; b < L.n_inst; ++b) {
@@ -615,11 +650,13 @@ static int enqueue_reverse(lbm_handle *h, bool resident, const float *seed, hipS
             float *nu_out = h->nu(k & 1);
             if (k == T) {
                 HIP_TRY(lbm::launch_adj_seed(q, h->G, Fprev, nu_out, fin, fout, gin, gout,
-                                             h->at<float>(L.off_roi), h->at<float>(L.off_target),
+                                             h->at<float>(L.off_roi), frame_target(h, L.frames - 1),
                                              h->P.loss_kind, seed, s));
             } else {
+                const int m = frame_of(L, k);
                 HIP_TRY(lbm::launch_adj_step(q, h->G, Fprev, h->nu((k + 1) & 1), nu_out, fin, fout, gin, gout,
-                                             dpart, s));
+                                             dpart, h->at<float>(L.off_roi), m >= 0 ? frame_target(h, m) : nullptr,
+                                             h->P.loss_kind, s));
             }
         }
         if (marks) { if ((rc = record(h, ev))) return rc; marks->push_back(ev++); }
@@ -636,6 +673,8 @@ int lbm_adjoint(lbm_handle *h, const float *d_seed_du) {
     const Layout &L = h->L;
     int rc;
     const float *seed = nullptr;
+    if (d_seed_du && L.frames > 1)
+        return fail(LBM_EINVAL, "a caller seed replaces the loss at T only; loss_frames > 1 needs the built-in loss");
     if (d_seed_du) {
         // a fixed internal copy keeps captured graphs valid for any caller buffer
         HIP_TRY(hipMemcpyAsync(h->at<float>(L.off_seed), d_seed_du, sizeof(float) * L.total_nodes * L.D,

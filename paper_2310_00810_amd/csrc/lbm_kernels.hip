@@ -122,13 +122,14 @@ __device__ inline Moments load_moments(const float *__restrict__ F, const InstDe
     return moments<Q>(g);
 }
 
-// Loss on the final state (moments of F^T equal those of g^T: collision
-// conserves rho and j).  part[tile] = block sum.
+// Loss on a state F^t (its moments equal those of g^t: collision conserves
+// rho and j).  part[tile] = block sum, or += with acc (the frames of a
+// time-windowed loss, added in time order).
 template <int Q>
 __global__ void __launch_bounds__(BLOCK) k_loss(Geo G, const float *__restrict__ F,
                                                 const float *__restrict__ roi,
                                                 const float *__restrict__ target, int kind,
-                                                double *__restrict__ part) {
+                                                double *__restrict__ part, int acc) {
     __shared__ double lds[4];
     constexpr int D = Vel<Q>::D;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -144,7 +145,7 @@ __global__ void __launch_bounds__(BLOCK) k_loss(Geo G, const float *__restrict__
         l = loss_node<D>(kind, roi[I.poff + n.id] * I.loss_scale, u, t, d);
     }
     const double s = block_sum(l, lds);
-    if (threadIdx.x == 0) part[tile] = s;
+    if (threadIdx.x == 0) part[tile] = acc ? part[tile] + s : s;
 }
 
 // -------------------------------------------------------------- adjoint --
@@ -207,12 +208,14 @@ __global__ void __launch_bounds__(FT) k_adj_seed(Geo G, const float *__restrict_
 }
 
 // Adjoint step k: reads F^{k-1} (to rebuild g^k) and nu^{k+1}, writes nu^k;
-// accumulates dL/dtau per tile and dL/d(drho_b) per face node.  With
+// accumulates dL/dtau per tile and dL/d(drho_b) per face node.  SEED: g^k
+// carries a frame of a time-windowed loss (target), whose dl/dg^k joins the
+// collision transpose's output before the boundary transpose.  With
 // lam = S^T nu^{k+1} and the moments of w lam (S0, S_a, S_ab), the
 // collision transpose is  a_i = (1 - omega) lam_i + omega (A + B . c_i)  with
 //   A   = sum_k lam_k dfeq_k/drho = S0 (1 + 1.5 u.u) - 4.5 u.S2.u,
 //   B_a = sum_k lam_k dfeq_k/dj_a = 3 S_a + 9 (S2 u)_a - 3 u_a S0.
-template <int Q, int BCX>
+template <int Q, int BCX, bool SEED>
 __global__ void __launch_bounds__(FT) k_adj_step(Geo G, const float *__restrict__ Fprev,
                                                  const float *__restrict__ nu_in,
                                                  float *__restrict__ nu_out,
@@ -220,7 +223,9 @@ __global__ void __launch_bounds__(FT) k_adj_step(Geo G, const float *__restrict_
                                                  const float *__restrict__ face_out,
                                                  double *__restrict__ grad_in,
                                                  double *__restrict__ grad_out,
-                                                 double *__restrict__ dtau_part) {
+                                                 double *__restrict__ dtau_part,
+                                                 const float *__restrict__ roi,
+                                                 const float *__restrict__ target, int kind) {
     using V = Vel<Q>;
     __shared__ double red[4];
     FLUID_PROLOGUE();
@@ -314,6 +319,18 @@ __global__ void __launch_bounds__(FT) k_adj_step(Geo G, const float *__restrict_
                              (V::cz(i) ? V::cz(i) * Bz : 0.f);
             // BGK: (1 - omega) lam + omega J^T lam;  MRT: lam - mu + J^T mu
             a[i] = mrt ? lam[i] - mu[i] + eq : om1 * lam[i] + om * eq;
+        }
+        if constexpr (SEED) {
+            const float u[3] = {ux, uy, uz};
+            float tg[3] = {0.f, 0.f, 0.f}, dldu[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+            for (int d = 0; d < D; ++d) tg[d] = target[I.poff * D + (long long)d * I.plane + n.id];
+            loss_node<D>(kind, roi[I.poff + n.id] * I.loss_scale, u, tg, dldu);
+            const float inv = 1.0f / m.rho;
+#pragma unroll
+            for (int i = 0; i < Q; ++i)
+                a[i] += inv * (dldu[0] * (V::cx(i) - ux) + dldu[1] * (V::cy(i) - uy) +
+                               (D == 3 ? dldu[2] * (V::cz(i) - uz) : 0.f));
         }
         if (zouhe_faces(BCX)) {
             const float jb = zouhe_adj<Q>(a, in, out, g, drho_b, BCX == BC_VELOCITY);
@@ -550,9 +567,9 @@ hipError_t launch_step(int q, const Geo &G, const float *src, float *dst, const 
 }
 
 hipError_t launch_loss(int q, const Geo &G, const float *F, const float *roi, const float *target,
-                       int kind, double *part, hipStream_t s) {
-    if (q == 9) hipLaunchKernelGGL(k_loss<9>, grid_of(G), dim3(BLOCK), 0, s, G, F, roi, target, kind, part);
-    else hipLaunchKernelGGL(k_loss<19>, grid_of(G), dim3(BLOCK), 0, s, G, F, roi, target, kind, part);
+                       int kind, double *part, int acc, hipStream_t s) {
+    if (q == 9) hipLaunchKernelGGL(k_loss<9>, grid_of(G), dim3(BLOCK), 0, s, G, F, roi, target, kind, part, acc);
+    else hipLaunchKernelGGL(k_loss<19>, grid_of(G), dim3(BLOCK), 0, s, G, F, roi, target, kind, part, acc);
     return hipGetLastError();
 }
 
@@ -570,11 +587,17 @@ hipError_t launch_adj_seed(int q, const Geo &G, const float *Fprev, float *nu_ou
 
 hipError_t launch_adj_step(int q, const Geo &G, const float *Fprev, const float *nu_in, float *nu_out,
                            const float *fin, const float *fout, double *gin, double *gout,
-                           double *dtau_part, hipStream_t s) {
+                           double *dtau_part, const float *roi, const float *target, int kind, hipStream_t s) {
     if (G.n_ftiles == 0) return hipSuccess;
 #define CALL(Q, B)                                                                                 \
-    hipLaunchKernelGGL((k_adj_step<Q, B>), fgrid_of(G), dim3(FT), 0, s, G, Fprev, nu_in, nu_out, fin, fout, gin, \
-                       gout, dtau_part)
+    do {                                                                                           \
+        if (target)                                                                                \
+            hipLaunchKernelGGL((k_adj_step<Q, B, true>), fgrid_of(G), dim3(FT), 0, s, G, Fprev, nu_in, nu_out, \
+                               fin, fout, gin, gout, dtau_part, roi, target, kind);                 \
+        else                                                                                       \
+            hipLaunchKernelGGL((k_adj_step<Q, B, false>), fgrid_of(G), dim3(FT), 0, s, G, Fprev, nu_in, nu_out, \
+                               fin, fout, gin, gout, dtau_part, roi, target, kind);                 \
+    } while (0)
     DISPATCH_BCX(q, G.bcx, CALL);
 #undef CALL
     return hipGetLastError();

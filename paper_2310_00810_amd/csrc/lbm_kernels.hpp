@@ -7,14 +7,16 @@ namespace lbm {
 
 hipError_t launch_step(int q, const Geo &G, const float *src, float *dst, const float *fin,
                        const float *fout, hipStream_t s);
+// acc: add to the partials (the later frames of a time-windowed loss).
 hipError_t launch_loss(int q, const Geo &G, const float *F, const float *roi, const float *target,
-                       int kind, double *part, hipStream_t s);
+                       int kind, double *part, int acc, hipStream_t s);
 hipError_t launch_adj_seed(int q, const Geo &G, const float *Fprev, float *nu_out, const float *fin,
                            const float *fout, double *gin, double *gout, const float *roi,
                            const float *target, int kind, const float *seed, hipStream_t s);
+// target (nullable): the loss frame taken on g^k, whose derivative joins nu^k.
 hipError_t launch_adj_step(int q, const Geo &G, const float *Fprev, const float *nu_in, float *nu_out,
                            const float *fin, const float *fout, double *gin, double *gout,
-                           double *dtau_part, hipStream_t s);
+                           double *dtau_part, const float *roi, const float *target, int kind, hipStream_t s);
 // Zeroes the n_dense floats of dense, then writes the fluid entries
 // (F0 and the face densities serve the anti-bounce-back transpose).
 hipError_t launch_adj_final(int q, const Geo &G, const float *nu_in, const float *F0, const float *fin,

@@ -29,7 +29,8 @@ MRT_RATES = (1.0, 1.64, 1.54, 1.0, 1.9, 1.0, 1.9, 1.0, 1.0)
 @dataclass
 class Instance:
     """One lattice: shape (nx, ny, nz), optional solid mask (nz, ny, nx),
-    loss weights (nz, ny, nx) and target velocity (nz, ny, nx, D)."""
+    loss weights (nz, ny, nx) and target velocity (nz, ny, nx, D), or one
+    target per loss frame (frames, nz, ny, nx, D) for a time-windowed loss."""
     nx: int
     ny: int
     nz: int = 1
@@ -63,12 +64,14 @@ class Solver:
     collision: "bgk" or (D2Q9) "mrt" with mrt_rates.  resident_segments: the
     taped forward keeps the states of its last R segments (K-1 states each), so
     the reverse sweep recomputes only the others; "max" takes as many as fit in
-    the free device memory less `reserve_bytes`."""
+    the free device memory less `reserve_bytes`.  loss_frames, loss_stride:
+    time-windowed loss over the states after steps T - (frames - 1 - m)
+    stride (the instances then carry one target per frame)."""
 
     def __init__(self, lattice, instances, bc=("pressure", "wall", "periodic"), steps=1,
                  ckpt_interval=0, tape=False, loss_kind="vec", loss_scale="sum",
                  inlet_mode="const", device="cuda", stream=None, collision="bgk", mrt_rates=MRT_RATES,
-                 resident_segments=1, reserve_bytes=8 << 30):
+                 resident_segments=1, reserve_bytes=8 << 30, loss_frames=1, loss_stride=1):
         self.q = int(lattice)
         self.D = 2 if self.q == 9 else 3
         self.instances = list(instances)
@@ -82,13 +85,15 @@ class Solver:
             arr[k].nx, arr[k].ny, arr[k].nz = ins.nx, ins.ny, ins.nz
             arr[k].solid = self._host(ins.solid, np.uint8, (ins.nz, ins.ny, ins.nx))
             arr[k].roi = self._host(ins.roi, np.float32, (ins.nz, ins.ny, ins.nx))
-            arr[k].target_u = self._host(ins.target_u, np.float32, (ins.nz, ins.ny, ins.nx, self.D))
+            arr[k].target_u = self._host(ins.target_u, np.float32,
+                                         (max(int(loss_frames), 1), ins.nz, ins.ny, ins.nx, self.D))
         self._inst_arr = arr
         self.problem = C.lbm_problem(self.q, self.n_inst, arr, _bc(bc[0]), _bc(bc[1]), _bc(bc[2]),
                                      self.steps, int(ckpt_interval), int(bool(tape)), _LOSS[loss_kind],
                                      _SCALE[loss_scale], _INLET[inlet_mode],
                                      C.COLL_MRT if collision == "mrt" else C.COLL_BGK,
-                                     (ctypes.c_double * 9)(*[float(r) for r in mrt_rates]), 1)
+                                     (ctypes.c_double * 9)(*[float(r) for r in mrt_rates]), 1,
+                                     int(loss_frames), int(loss_stride))
         L = C.lib()
         nbytes = ctypes.c_size_t(0)
         C.check(L.lbm_workspace_bytes(ctypes.byref(self.problem), ctypes.byref(nbytes)), "lbm_workspace_bytes")

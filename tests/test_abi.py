@@ -54,6 +54,7 @@ def _problem(nx=64, ny=32, nz=1, q=9, steps=100, K=0, tape=0, solid=None, n=1, *
     p = C.lbm_problem(q, n, arr, kw.get("bcx", 0), kw.get("bcy", 2), kw.get("bcz", 1), steps, K, tape,
                       kw.get("loss_kind", 0), kw.get("loss_scale", 0), kw.get("inlet_mode", 0))
     p.resident_segments = kw.get("resident", 0)
+    p.loss_frames, p.loss_stride = kw.get("frames", 0), kw.get("stride", 0)
     p._keep = (arr, keep)
     return p
 
@@ -95,6 +96,9 @@ def test_resident_segments_cost_k_minus_one_states_each(L):
 @pytest.mark.parametrize("kw,code", [
     (dict(q=7), C.LBM_EINVAL),
     (dict(resident=-1), C.LBM_EINVAL),
+    (dict(frames=-1), C.LBM_EINVAL),
+    (dict(frames=3, stride=0), C.LBM_EINVAL),
+    (dict(frames=3, stride=50, steps=100), C.LBM_EINVAL),   # the first frame would be step 0
     (dict(nx=1 << 20, ny=2), C.LBM_EINVAL),     # x positions are packed into 20 bits
     (dict(nz=2), C.LBM_EINVAL),                 # D2Q9 with nz != 1
     (dict(nx=1), C.LBM_EINVAL),                 # pressure axis needs nx >= 2
@@ -108,6 +112,14 @@ def test_invalid_problems_are_rejected(L, kw, code):
     rc, _ = _bytes(L, _problem(**kw))
     assert rc == code
     assert len(L.lbm_last_error()) > 0
+
+
+def test_loss_frames_hold_one_target_each(L):
+    _, b1 = _bytes(L, _problem(steps=100))
+    rc, b3 = _bytes(L, _problem(steps=100, frames=3, stride=49))
+    assert rc == 0
+    # two more target frames of D planes over the fluid nodes (64 x 32, all fluid)
+    assert b3 - b1 == 2 * 2 * 64 * 32 * 4
 
 
 def test_largest_row_length_is_accepted(L):

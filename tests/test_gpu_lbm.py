@@ -35,7 +35,7 @@ def oracle_pull_step(lat, tau, rin, rout, F):
 
 
 def solver_for(lat, steps, tape=False, K=0, roi=None, target=None, loss_kind="vec",
-               loss_scale="sum", inlet_mode="const", resident=1):
+               loss_scale="sum", inlet_mode="const", resident=1, frames=1, stride=1):
     lbm = _lbm()
     D = 2 if lat.q == 9 else 3
     tgt = None if target is None else np.asarray(target)[..., :D].astype(np.float32)
@@ -44,7 +44,8 @@ def solver_for(lat, steps, tape=False, K=0, roi=None, target=None, loss_kind="ve
     kw = {} if lat.mrt is None else dict(collision="mrt", mrt_rates=tuple(lat.mrt))
     return lbm.Solver(lat.q, [ins], bc=tuple(BC_NAMES[b] for b in lat.bc_tuple), steps=steps,
                       ckpt_interval=K, tape=tape, loss_kind=loss_kind, loss_scale=loss_scale,
-                      inlet_mode=inlet_mode, resident_segments=resident, **kw)
+                      inlet_mode=inlet_mode, resident_segments=resident, loss_frames=frames,
+                      loss_stride=stride, **kw)
 
 
 def _inlet(lat, d):
@@ -231,6 +232,45 @@ def test_tiny_profile_gradients(name, lat):
         assert rel_l2(g["drho_in"], [go["drho_in"].sum()]) <= 1e-3
     assert rel_l2(g["dtau"], [go["dtau"]]) <= 1e-3
     assert rel_l2(g["drho_out"], [go["drho_out"].sum()]) <= 1e-3
+
+
+@pytest.mark.parametrize("name,lat", _driven(tiny_lattices() + multi_tile_lattices() + abb_lattices() +
+                                             mrt_velocity_lattices()))
+@pytest.mark.parametrize("frames,stride,resident", [(4, 5, 1), (3, 1, 2)])
+def test_windowed_loss_gradients(name, lat, frames, stride, resident):
+    """Time-windowed loss (frames at T - (frames - 1 - m) stride, one target
+    per frame): loss, per-node inlet gradients, dL/dtau and dL/drho_out
+    against the oracle.  T = 40, K = 7: frames inside and at the end of
+    segments (step 35), in recomputed and in resident segments."""
+    T, tau = 40, 0.8
+    rng = np.random.default_rng(9)
+    din = (0.01 + 0.002 * rng.standard_normal((lat.nz, lat.ny))).astype(np.float32)
+    solid_in = lat.solid[:, :, 0].astype(bool)
+    tgt = (0.004 * rng.standard_normal((frames,) + lat.shape + (3,))).astype(np.float32).astype(np.float64)
+    if lat.q == 9:
+        tgt[..., 2] = 0
+    wgt = rng.uniform(0.5, 1.5, lat.shape).astype(np.float32).astype(np.float64)
+    mode = "const" if solid_in.any() else "profile"
+    s = solver_for(lat, T, tape=True, K=7, roi=wgt, target=tgt, inlet_mode=mode, resident=resident,
+                   frames=frames, stride=stride)
+    dparam = din.ravel() if mode == "profile" else f32(0.01)
+    loss = s.forward(tau, dparam, f32(-0.001), record_tape=True)
+    s.adjoint()
+    g = s.grad()
+    rin = _inlet(lat, din.astype(np.float64) if mode == "profile" else f32(0.01))
+    go = O.grad(lat, tau, rin, 1 + f32(-0.001), O.init_eq(lat, 1.0, 0.0), T, tgt, wgt, K=7, frames=frames,
+                stride=stride)
+    assert abs(loss[0] - go["loss"]) <= 1e-4 * go["loss"]
+    if mode == "profile":
+        assert rel_l2(g["drho_in"], go["drho_in"].ravel()) <= 1e-3
+    else:
+        assert rel_l2(g["drho_in"], [go["drho_in"].sum()]) <= 1e-3
+    assert rel_l2(g["dtau"], [go["dtau"]]) <= 1e-3
+    assert rel_l2(g["drho_out"], [go["drho_out"].sum()]) <= 1e-3
+    # a caller-given seed covers the final state only
+    from paper_2310_00810_amd._lib import LBMError
+    with pytest.raises(LBMError):
+        s.adjoint(torch.zeros(lat.nx * lat.ny * lat.nz * (2 if lat.q == 9 else 3), device="cuda"))
 
 
 @pytest.mark.parametrize("name,lat", tiny_lattices() + multi_tile_lattices() + abb_lattices() +

@@ -227,21 +227,25 @@ def e1(quick=False):
                 fluid_nodes=n_fluid)
 
 
-def e7(quick=False, iters=50, nu0=0.06, scan=False, horizon=1000):
+def e7(quick=False, iters=50, nu0=0.06, scan=False, horizon=1200, frames=12, stride=100):
     """Viscosity from a cylinder wake (Section 3.4): D2Q9 MRT, Re = 100,
     nu = 0.02 (tau = 0.56), Zou-He velocity inlet, density outlet, periodic
     y.  At the paper's u = 0.2 lu/ts and D = 10 the density outlet does not
     survive the start-up waves, so the same Re and nu are run at half the
     Mach number: u = 0.1, D = 20, 800 x 320 nodes, cylinder 25 diameters
     before the outlet.  Uniform flow at t = 0; shedding is developed by
-    20000 steps.  By default (horizon 1000) that developed flow is the start
-    state and the target is the velocity 1000 steps later in Raissi's window
-    (1 to 8 diameters downstream, +-2 diameters across): the wake observed
-    while it sheds.  With horizon 0 the target is the window at T = 20000
+    20000 steps.  By default that developed flow is the start state and the
+    target is the velocity in Raissi's window (1 to 8 diameters downstream,
+    +-2 diameters across) over the next shedding period: 12 frames, 100
+    steps apart, the last one 1200 steps later (the wake observed while it
+    sheds).  With horizon 0 the target is the window at T = 20000
     from the uniform start, a final-time snapshot whose shedding phase makes
-    the basin of the true viscosity very narrow.  Adam on nu (learning rate
-    0.01) from nu = 0.06 by default; a step into a viscosity that the flow
-    does not survive is halved back toward the last stable one."""
+    the basin of the true viscosity very narrow.  frames > 1: the loss is
+    summed over that many states, `stride` steps apart and ending at the
+    target time (the wake observed over time; the shedding period is about
+    1200 steps).  Adam on nu (learning rate 0.01) from nu = 0.06 by default;
+    a step into a viscosity that the flow does not survive is halved back
+    toward the last stable one."""
     nx, ny, D, U, T = 800, 320, 20, 0.1, 20000
     if quick:
         T, iters = 2000, 5
@@ -260,17 +264,32 @@ def e7(quick=False, iters=50, nu0=0.06, scan=False, horizon=1000):
         # observed from a developed wake: the start state is the shedding flow at T,
         # the target is the window `horizon` steps later
         developed = s0.get_populations()
-        s0 = Solver(9, [Instance(nx, ny, solid=solid)], bc=bc, steps=horizon, collision="mrt")
-        s0.set_populations(developed)
-        s0.forward(tau_of(nu_true), U, 0.0, want_loss=False)
         T = horizon
-    _, ut = s0.macro()
-    tgt = ut.cpu().numpy().reshape(1, ny, nx, 2)
+    # the target frames: the true run's velocity at T - (frames - 1 - m) stride
+    times = [T - (frames - 1 - m) * stride for m in range(frames)]
+    if times[0] < 1:
+        raise ValueError("the loss frames must lie after the start")
+    tgts = []
+    for m, t in enumerate(times):
+        st = Solver(9, [Instance(nx, ny, solid=solid)], bc=bc, steps=t - (times[m - 1] if m else 0),
+                    collision="mrt")
+        if m == 0:
+            if developed is None:
+                st.set_initial(zero, u0)
+            else:
+                st.set_populations(developed)
+        else:
+            st.set_populations(prev)
+        st.forward(tau_of(nu_true), U, 0.0, want_loss=False)
+        prev = st.get_populations()
+        tgts.append(st.macro()[1].cpu().numpy().reshape(ny, nx, 2))
+        del st
+    tgt = np.stack(tgts)[:, None]
     del s0
     roi = np.zeros((1, ny, nx), np.float32)
     roi[:, 160 - 2 * D:160 + 2 * D, 300 + D:300 + 8 * D] = 1.0
     s = Solver(9, [Instance(nx, ny, solid=solid, roi=roi, target_u=tgt)], bc=bc, steps=T, tape=True,
-               collision="mrt")
+               collision="mrt", loss_frames=frames, loss_stride=stride)
     if developed is None:
         s.set_initial(zero, u0)
     else:
@@ -285,7 +304,7 @@ def e7(quick=False, iters=50, nu0=0.06, scan=False, horizon=1000):
                 L = None  # this viscosity does not survive the start-up at this resolution
             pts.append({"nu": float(nu), "loss": L})
             log(f"[e7 scan] nu {nu:.4f} loss {L}")
-        return dict(config="E7 scan", T=T, horizon=horizon, scan=pts)
+        return dict(config="E7 scan", T=T, horizon=horizon, frames=frames, stride=stride, scan=pts)
     opt = inverse.Adam(0.01)
     nu = np.array([nu0])
     hist = []
@@ -308,7 +327,7 @@ def e7(quick=False, iters=50, nu0=0.06, scan=False, horizon=1000):
         nu = np.maximum(opt.step(nu, np.array([dnu])), 0.002)
     dt = time.time() - t0
     best = min(hist, key=lambda h: h[1])
-    return dict(config="E7", T=T, horizon=horizon, iterations=iters, seconds=dt, true_nu=nu_true, initial_nu=nu0,
+    return dict(config="E7", T=T, horizon=horizon, frames=frames, stride=stride, iterations=iters, seconds=dt, true_nu=nu_true, initial_nu=nu0,
                 final_nu=float(nu[0]), best_nu=best[0], best_loss=best[1],
                 trajectory=[{"nu": h[0], "loss": h[1], "dL_dnu": h[2]} for h in hist])
 
@@ -378,10 +397,12 @@ def main():
     ap.add_argument("--quick", action="store_true")
     ap.add_argument("--nu0", type=float, default=0.06, help="e7: initial viscosity")
     ap.add_argument("--scan", action="store_true", help="e7: loss along nu instead of the inversion")
-    ap.add_argument("--horizon", type=int, default=1000,
+    ap.add_argument("--horizon", type=int, default=1200,
                     help="e7: start from the developed wake and match the window this many steps later; 0: final-time snapshot from uniform flow")
+    ap.add_argument("--frames", type=int, default=12, help="e7: loss frames (time-windowed loss)")
+    ap.add_argument("--stride", type=int, default=100, help="e7: steps between loss frames")
     a = ap.parse_args()
-    kw = dict(nu0=a.nu0, scan=a.scan, horizon=a.horizon) if a.config == "e7" else {}
+    kw = dict(nu0=a.nu0, scan=a.scan, horizon=a.horizon, frames=a.frames, stride=a.stride) if a.config == "e7" else {}
     res = globals()[a.config](quick=a.quick, **kw)
     if res is not None:
         print(json.dumps(res), flush=True)

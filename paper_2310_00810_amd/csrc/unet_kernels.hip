@@ -35,7 +35,7 @@ __device__ __host__ inline uint16_t f2bf(float f) {
     return (uint16_t)(r >> 16);
 }
 
-constexpr int BM = 64, BN = 64, BK = 32, LDK = BK + 8;   // LDS rows padded by 16 B
+constexpr int BM = 64, BN = 64;          // weight-gradient output tile (rows x K entries)
 
 // Pixel index -> (b, z, y, x) on a grid of d x h x w per sample (pixel
 // counts stay below 2^31: checked on the host).
@@ -240,62 +240,98 @@ __global__ void __launch_bounds__(256) k_conv(ConvArgs a) {
 
 // Weight gradient: dW[r][k] = sum_m G[m][r] * im2col(in)[m][k], G = dout
 // (S2D: r = sub * Cr + co read at the fine pixel).  blockIdx.z splits the
-// pixel range; partials are summed by k_sum_splits.
+// pixel range; partials are summed by k_sum_splits.  The contraction runs
+// over pixels, which are the slow index of both operands in memory, so each
+// stage of WPB pixels is transposed on its way into LDS: a thread loads 4
+// consecutive pixels x 8 channels of G and of the im2col rows, swaps them in
+// registers and writes one 8-byte run of 4 pixels per channel.  The next
+// stage's global loads are issued before the current stage's MFMAs.
+constexpr int WPB = 128, WLD = WPB + 8;          // pixels per stage; LDS rows padded by 16 B
+
+// v[j] = 8 channels of pixel j (j = 0..3) -> o[e] = channel e of pixels 0..3.
+__device__ inline void transpose_4x8(const uint4 (&v)[4], uint2 (&o)[8]) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int d = e >> 1;
+        const uint32_t a0 = (&v[0].x)[d], a1 = (&v[1].x)[d], a2 = (&v[2].x)[d], a3 = (&v[3].x)[d];
+        if (e & 1)
+            o[e] = make_uint2((a0 >> 16) | (a1 & 0xffff0000u), (a2 >> 16) | (a3 & 0xffff0000u));
+        else
+            o[e] = make_uint2((a0 & 0xffffu) | (a1 << 16), (a2 & 0xffffu) | (a3 << 16));
+    }
+}
+
 __global__ void __launch_bounds__(256) k_wgrad(ConvArgs a, const uint16_t *__restrict__ g, int g_cs,
                                                int g_co, int rows, float *__restrict__ part,
                                                long long chunk) {
-    __shared__ uint16_t Gs[BM][LDK];
-    __shared__ uint16_t Ts[BN][LDK];
+    __shared__ uint16_t Gs[BM][WLD];
+    __shared__ uint16_t Ts[BN][WLD];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int wm = wave & 1, wn = wave >> 1;
     const int r0 = blockIdx.x * BM, c0 = blockIdx.y * BN;
     const long long mb = (long long)blockIdx.z * chunk;
     const long long me = mb + chunk < a.M ? mb + chunk : a.M;
-    const int lm = t >> 3, ls = (t & 7) * 8;
+    const int pg = t >> 3, cg = (t & 7) * 8;        // pixels 4 pg .. 4 pg + 3 of a stage, channels cg .. cg + 7
     f32x4 acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     const bool s2d_g = (a.flags & FLAG_S2D_G) != 0;
-    // the thread's im2col column (tap, channel) is fixed over the pixel loop
-    const KOff ko = koff_of(a, c0 + ls);
-    for (long long mm = mb; mm < me; mm += BK) {
-        const long long m = mm + lm;
-        uint4 gv = make_uint4(0, 0, 0, 0);
-        const int r = r0 + ls;
-        if (m < me && r < rows) {
-            long long src = m;
-            int ch = r;
-            if (s2d_g) {
-                const int cr = rows >> a.dims;
-                const int sub = r / cr;
-                ch = r - sub * cr;
-                const Pix p = pix_of(m, a.d, a.h, a.w);
-                const int sx = sub & 1, sy = (sub >> 1) & 1, sz = (sub >> 2) & 1;
-                const int fd = a.dims == 3 ? 2 * a.d : 1, fh = 2 * a.h, fw = 2 * a.w;
-                const int zf = a.dims == 3 ? 2 * p.z + sz : 0;
-                src = (((long long)p.b * fd + zf) * fh + 2 * p.y + sy) * fw + 2 * p.x + sx;
+    // the thread's im2col column (tap, channel) and G channels are fixed over the pixel loop
+    const KOff ko = koff_of(a, c0 + cg);
+    const int r = r0 + cg;
+    uint4 gv[4], tv[4];
+    auto load = [&](long long mm) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const long long m = mm + 4 * pg + j;
+            gv[j] = tv[j] = make_uint4(0, 0, 0, 0);
+            if (m >= me) continue;
+            if (r < rows) {
+                long long src = m;
+                int ch = r;
+                if (s2d_g) {
+                    const int cr = rows >> a.dims;
+                    const int sub = r / cr;
+                    ch = r - sub * cr;
+                    const Pix p = pix_of(m, a.d, a.h, a.w);
+                    const int sx = sub & 1, sy = (sub >> 1) & 1, sz = (sub >> 2) & 1;
+                    const int fd = a.dims == 3 ? 2 * a.d : 1, fh = 2 * a.h, fw = 2 * a.w;
+                    const int zf = a.dims == 3 ? 2 * p.z + sz : 0;
+                    src = (((long long)p.b * fd + zf) * fh + 2 * p.y + sy) * fw + 2 * p.x + sx;
+                }
+                gv[j] = *(const uint4 *)(g + src * g_cs + g_co + ch);
             }
-            gv = *(const uint4 *)(g + src * g_cs + g_co + ch);
+            tv[j] = im2col_load(a, row_of(a, m), ko);
         }
-        const uint4 tv = m < me ? im2col_load(a, row_of(a, m), ko) : make_uint4(0, 0, 0, 0);
-        __syncthreads();
-        const uint16_t *gp = (const uint16_t *)&gv, *tp = (const uint16_t *)&tv;
+    };
+    load(mb);
+    for (long long mm = mb; mm < me; mm += WPB) {
+        __syncthreads();                              // the previous stage's MFMA reads are done
+        {
+            uint2 og[8], ot[8];
+            transpose_4x8(gv, og);
+            transpose_4x8(tv, ot);
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            Gs[ls + e][lm] = gp[e];
-            Ts[ls + e][lm] = tp[e];
+            for (int e = 0; e < 8; ++e) {
+                *(uint2 *)&Gs[cg + e][4 * pg] = og[e];
+                *(uint2 *)&Ts[cg + e][4 * pg] = ot[e];
+            }
         }
         __syncthreads();
-        const int kr = (lane >> 4) * 8;
+        if (mm + WPB < me) load(mm + WPB);
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            const bf16x8 fa = as_bf16x8(*(const uint4 *)&Gs[wm * 32 + i * 16 + (lane & 15)][kr]);
+        for (int kh = 0; kh < WPB; kh += 32) {
+            const int kr = kh + (lane >> 4) * 8;
+            bf16x8 fb[2];
 #pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                const bf16x8 fb = as_bf16x8(*(const uint4 *)&Ts[wn * 32 + j * 16 + (lane & 15)][kr]);
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, fb, acc[i][j], 0, 0, 0);
+            for (int j = 0; j < 2; ++j) fb[j] = as_bf16x8(*(const uint4 *)&Ts[wn * 32 + j * 16 + (lane & 15)][kr]);
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const bf16x8 fa = as_bf16x8(*(const uint4 *)&Gs[wm * 32 + i * 16 + (lane & 15)][kr]);
+#pragma unroll
+                for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, fb[j], acc[i][j], 0, 0, 0);
             }
         }
     }
@@ -308,19 +344,29 @@ __global__ void __launch_bounds__(256) k_wgrad(ConvArgs a, const uint16_t *__res
             if (c >= a.K) continue;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int r = r0 + wm * 32 + i * 16 + (lane >> 4) * 4 + q;
-                if (r < rows) dst[(long long)r * a.K + c] = acc[i][j][q];
+                const int rr = r0 + wm * 32 + i * 16 + (lane >> 4) * 4 + q;
+                if (rr < rows) dst[(long long)rr * a.K + c] = acc[i][j][q];
             }
         }
 }
 
-__global__ void k_sum_splits(const float *__restrict__ part, int splits, long long n, float *__restrict__ out,
-                             int accumulate) {
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+// Sum of split partials: a block takes 64 outputs, its four wavefronts the
+// splits z = w, w + 4, ... (coalesced 64-float rows), combined in a fixed
+// order (deterministic).
+__global__ void __launch_bounds__(256) k_sum_splits(const float *__restrict__ part, int splits, long long n,
+                                                    float *__restrict__ out, int accumulate) {
+    __shared__ float sh[4][64];
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const long long i = (long long)blockIdx.x * 64 + l;
     float s = 0.f;
-    for (int z = 0; z < splits; ++z) s += part[(long long)z * n + i];
-    out[i] = accumulate ? out[i] + s : s;
+    if (i < n)
+        for (int z = w; z < splits; z += 4) s += part[(long long)z * n + i];
+    sh[w][l] = s;
+    __syncthreads();
+    if (w == 0 && i < n) {
+        const float v = (sh[0][l] + sh[1][l]) + (sh[2][l] + sh[3][l]);
+        out[i] = accumulate ? out[i] + v : v;
+    }
 }
 
 // Sum of split partials when there are few outputs: one block per output,
@@ -572,7 +618,7 @@ hipError_t conv(const ConvArgs &a, hipStream_t s) {
 
 long long wgrad_chunk(long long M, int splits) {
     long long c = (M + splits - 1) / splits;
-    return (c + BK - 1) / BK * BK;
+    return (c + WPB - 1) / WPB * WPB;
 }
 
 // Sum of z split partials into n outputs: a thread per output when there are
@@ -581,7 +627,7 @@ static hipError_t sum_splits(const float *part, int z, long long n, float *out, 
     if (n <= 8192 && z > 16)
         hipLaunchKernelGGL(k_sum_splits_narrow, dim3((unsigned)n), dim3(256), 0, s, part, z, n, out, accumulate);
     else
-        hipLaunchKernelGGL(k_sum_splits, dim3(blocks(n, 256)), dim3(256), 0, s, part, z, n, out, accumulate);
+        hipLaunchKernelGGL(k_sum_splits, dim3(blocks(n, 64)), dim3(256), 0, s, part, z, n, out, accumulate);
     return hipGetLastError();
 }
 

@@ -214,6 +214,81 @@ __global__ void __launch_bounds__(256) k_conv(ConvArgs a) {
         if (s + 1 < steps) stash(buf ^ 1);
         __syncthreads();
     }
+    const bool d2s = (a.flags & FLAG_D2S) != 0;
+    const int cr = d2s ? a.ncols >> a.dims : a.ncols;      // D2S: columns sub * cr + co
+    if (((a.out_cs | a.out_co) & 7) == 0 && (!d2s || (cr & 7) == 0)) {
+        // the tile goes through LDS (the A buffers are free after the last barrier) so that each
+        // thread stores 8 consecutive channels of a pixel (of the fine pixel for D2S, whose
+        // 8-column groups stay inside one sub-pixel) with 16-byte writes
+        constexpr int TL = TBN + 4;
+        static_assert(TBM * TL * 4 <= (int)sizeof(As), "epilogue tile must fit in the A buffers");
+        float *T = reinterpret_cast<float *>(&As[0][0][0]);
+#pragma unroll
+        for (int i = 0; i < TI; ++i)
+#pragma unroll
+            for (int j = 0; j < TJ; ++j) {
+                const int cl = wn * WN + j * 16 + (lane & 15), c = n0 + cl;
+                const float b = a.bias && c < a.ncols ? a.bias[d2s ? c - (c / cr) * cr : c] : 0.f;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    float v = acc[i][j][q] + b;
+                    if (a.flags & FLAG_RELU) v = v > 0.f ? v : 0.f;
+                    T[(wm * WM + i * 16 + (lane >> 4) * 4 + q) * TL + cl] = v;
+                }
+            }
+        __syncthreads();
+        constexpr int CG = TBN / 8;
+        for (int e = t; e < TBM * CG; e += 256) {
+            const int ml = e / CG, cl = (e - ml * CG) * 8;
+            const long long m = m0 + ml;
+            const int c = n0 + cl;
+            if (m >= a.M || c >= a.ncols) continue;
+            const float *src = &T[ml * TL + cl];
+            int bc;
+            const long long o = out_index(a, m, c, bc);
+            if (a.out32) {
+                float *dst = a.out32 + o;
+                const int nk = a.ncols - c < 8 ? a.ncols - c : 8;
+                if (nk == 8) {
+                    float4 v0 = make_float4(src[0], src[1], src[2], src[3]);
+                    float4 v1 = make_float4(src[4], src[5], src[6], src[7]);
+                    if (a.flags & FLAG_ACC) {
+                        const float4 o0 = *(const float4 *)dst, o1 = *(const float4 *)(dst + 4);
+                        v0.x += o0.x; v0.y += o0.y; v0.z += o0.z; v0.w += o0.w;
+                        v1.x += o1.x; v1.y += o1.y; v1.z += o1.z; v1.w += o1.w;
+                    }
+                    *(float4 *)dst = v0;
+                    *(float4 *)(dst + 4) = v1;
+                } else {
+                    for (int k = 0; k < nk; ++k) dst[k] = (a.flags & FLAG_ACC) ? dst[k] + src[k] : src[k];
+                }
+                continue;
+            }
+            uint16_t *dst = a.out + o;
+            if (c + 8 <= a.ncols) {
+                float v[8];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) v[k] = src[k];
+                if (a.flags & FLAG_ACC) {
+                    const uint4 old = *(const uint4 *)dst;
+                    const uint32_t ow[4] = {old.x, old.y, old.z, old.w};
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) v[k] += bf2f((uint16_t)(ow[k >> 1] >> (16 * (k & 1))));
+                }
+                uint32_t pw[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) pw[k] = (uint32_t)f2bf(v[2 * k]) | ((uint32_t)f2bf(v[2 * k + 1]) << 16);
+                *(uint4 *)dst = make_uint4(pw[0], pw[1], pw[2], pw[3]);
+            } else {
+                for (int k = 0; k < a.ncols - c; ++k) {
+                    float v = src[k];
+                    if (a.flags & FLAG_ACC) v += bf2f(dst[k]);
+                    dst[k] = f2bf(v);
+                }
+            }
+        }
+        return;
+    }
 #pragma unroll
     for (int i = 0; i < TI; ++i)
 #pragma unroll

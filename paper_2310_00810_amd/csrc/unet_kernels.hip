@@ -148,8 +148,8 @@ __device__ inline long long out_index(const ConvArgs &a, long long m, int c, int
 // TBM/2 x TBN/2 of 16 x 16 x 32 BF16 MFMA tiles) over K steps of 64.  The
 // LDS tiles are double-buffered: the next step's global loads are issued
 // before the current step's MFMAs and land in the other buffer, so a step
-// needs one barrier.  TBN = 32 serves the 32- and 8-channel layers without
-// computing zero columns.
+// needs one barrier.  64 x 32 tiles serve the 32- and 8-channel layers
+// without computing zero columns (and keep 5 blocks per CU).
 template <int TBM, int TBN>
 __global__ void __launch_bounds__(256) k_conv(ConvArgs a) {
     constexpr int KB = 64, LD = KB + 8;             // LDS rows padded by 16 B
@@ -682,8 +682,8 @@ static inline unsigned blocks(long long n, int b) { return (unsigned)((n + b - 1
 
 hipError_t conv(const ConvArgs &a, hipStream_t s) {
     if (a.ncols <= 32) {
-        dim3 grid(blocks(a.M, 128), (unsigned)((a.ncols + 31) / 32));
-        hipLaunchKernelGGL((k_conv<128, 32>), grid, dim3(256), 0, s, a);
+        dim3 grid(blocks(a.M, 64), (unsigned)((a.ncols + 31) / 32));
+        hipLaunchKernelGGL((k_conv<64, 32>), grid, dim3(256), 0, s, a);
     } else {
         dim3 grid(blocks(a.M, 64), (unsigned)((a.ncols + 63) / 64));
         hipLaunchKernelGGL((k_conv<64, 64>), grid, dim3(256), 0, s, a);

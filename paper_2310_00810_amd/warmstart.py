@@ -81,12 +81,15 @@ def features_of(solid_dev, prm_dev, n, d, h, w):
 
 def generate(dims, seeds, batch=32, tol=1e-6, max_steps=100_000, check_every=100):
     """Runs the batched solver to the residual threshold for every seed and
-    returns a Dataset (features, targets and fluid weights on the GPU)."""
+    returns a Dataset (features, targets and fluid weights on the GPU).  A
+    batch runs until its slowest case converges, and the steps to converge
+    scale with 1 / nu, so the cases are batched in order of tau."""
     D = dims
     feats, tgts, wps, prms, steps, cases = [], [], [], [], [], []
     t0 = time.time()
-    for b0 in range(0, len(seeds), batch):
-        chunk = [sample(dims, s) for s in seeds[b0:b0 + batch]]
+    drawn = sorted((sample(dims, s) for s in seeds), key=lambda c: c[3])
+    for b0 in range(0, len(drawn), batch):
+        chunk = drawn[b0:b0 + batch]
         insts = [Instance(c[0].shape[2], c[0].shape[1], c[0].shape[0], solid=c[0]) for c in chunk]
         s = Solver(9 if dims == 2 else 19, insts, bc=bc_of(dims), steps=1)
         taus = [c[3] for c in chunk]
@@ -110,7 +113,7 @@ def generate(dims, seeds, batch=32, tol=1e-6, max_steps=100_000, check_every=100
         prms.append(prm)
         steps += [nstep] * nb
         cases += chunk
-        log(f"[data] dims={dims} {b0 + nb}/{len(seeds)} samples, batch converged in {nstep} steps "
+        log(f"[data] dims={dims} {b0 + nb}/{len(drawn)} samples, batch converged in {nstep} steps "
             f"(r={r:.2e}), {time.time() - t0:.1f} s")
         del s
     return Dataset(dims, cases, torch.cat(feats), torch.cat(tgts), torch.cat(wps), torch.cat(prms),

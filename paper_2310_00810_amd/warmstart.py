@@ -231,13 +231,16 @@ def main():
     ap.add_argument("--epochs", type=int, default=30)
     ap.add_argument("--batch", type=int, default=0)
     ap.add_argument("--gen-batch", type=int, default=0)
-    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--lr", type=float, default=0.0, help="Adam learning rate (default 2e-3 in 2D, 5e-4 in 3D)")
     ap.add_argument("--out", default="")
     ap.add_argument("--max-steps", type=int, default=100_000)
     args = ap.parse_args()
     dims = args.dims
-    batch = args.batch or (16 if dims == 2 else 2)
-    gb = args.gen_batch or (64 if dims == 2 else 16)
+    # 3D: batch 4 at lr 5e-4; at batch 2 and lr 2e-3 the 1000 Adam steps of an epoch over 2000
+    # samples drove the network into a constant prediction
+    batch = args.batch or (16 if dims == 2 else 4)
+    lr = args.lr or (2e-3 if dims == 2 else 5e-4)
+    gb = args.gen_batch or 64
     t0 = time.time()
     tr = generate(dims, [SEED_TRAIN + i for i in range(args.train)], batch=gb, max_steps=args.max_steps)
     va = generate(dims, [SEED_VAL + i for i in range(args.val)], batch=gb, max_steps=args.max_steps) if args.val else None
@@ -247,7 +250,7 @@ def main():
         f"{int(np.median(tr.steps))}, max {int(tr.steps.max())}")
     net = UNet(dims, seed=0)
     hist = train(net, standardized(tr, scale), standardized(va, scale) if va is not None else None, args.epochs,
-                 batch, args.lr)
+                 batch, lr)
     net.fold_output_scale(scale)
     train_s = time.time() - t0 - gen_s
     res = []

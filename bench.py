@@ -22,7 +22,9 @@ per second of the whole gradient evaluation).  roofline = the dominant kernel
 of that evaluation, k_step (forward pass and segment recomputes: about 57 % of
 the GPU time), averaged over all its launches; adj_roofline = k_adj_step.
 Both use algorithmic bytes (152 B and 228 B per fluid node) over HIP-event
-kernel times on the library stream.
+kernel times on the library stream.  The 128^3 box's working set (63.6 MB per
+state) is partly served by the 256 MB Infinity Cache, so hbm_resident_roofline
+repeats the two kernel figures on a 256^3 plane channel (1.27 GB per state).
 """
 import argparse
 import json
@@ -57,6 +59,33 @@ def workload(n=128, T=8000, K=400, kind="spheres"):
     solid = G.boolean_spheres((n, n, n), (6.0, 10.0), 0.40, seed=3, periodic=(False, True, True), x_margin=4)
     return dict(n=n, T=T, K=K, solid=solid, din=(0.004 * phi).astype(np.float32), tau=0.75, tau_target=0.9,
                 bc=("pressure", "periodic", "periodic"), kind=kind)
+
+
+def channel_roofline(torch, n=256, T=40, K=20):
+    """k_step and k_adj_step against the HBM peak on a working set far larger
+    than the 256 MB Infinity Cache: a D3Q19 n^3 plane channel (1.27 GB per
+    state at n = 256), one timed gradient evaluation after one untimed."""
+    from paper_2310_00810_amd import lbm
+    w = workload(n, T, K, "channel")
+    ins = lbm.Instance(n, n, n, solid=w["solid"], target_u=np.zeros((n, n, n, 3), np.float32))
+    s = lbm.Solver(19, [ins], bc=w["bc"], steps=T, ckpt_interval=K, tape=True, loss_scale="mean",
+                   inlet_mode="profile")
+    for timed in (False, True):
+        s.set_timing(timed, reset=True)
+        s.forward(w["tau"], w["din"].ravel(), 0.0, record_tape=True)
+        s.adjoint()
+        s.grad()
+    torch.cuda.synchronize()
+    tm = s.timing()
+    del s
+    torch.cuda.empty_cache()
+    nodes = n ** 3
+    step_ms = (tm["forward_ms"] + tm["recompute_ms"]) / max(tm["forward_launches"] + tm["recompute_launches"], 1)
+    adj_ms = tm["adjoint_ms"] / max(tm["adjoint_launches"], 1)
+    f = lambda b, ms: round(b * nodes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+    return {"workload": f"D3Q19 {n}^3 plane channel, walls y, periodic z, T={T}, K={K}",
+            "k_step_frac": f(BYTES_FWD, step_ms), "k_step_avg_launch_ms": round(step_ms, 5),
+            "k_adj_step_frac": f(BYTES_ADJ, adj_ms), "k_adj_step_avg_launch_ms": round(adj_ms, 5)}
 
 
 def load_traffic(kernel):
@@ -162,6 +191,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-copy", action="store_true", help="skip the copy-bandwidth calibration")
     ap.add_argument("--no-warm", action="store_true", help="skip the warm-versus-cold start comparison")
+    ap.add_argument("--no-channel", action="store_true", help="skip the 256^3 channel roofline")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1"}))
@@ -268,6 +298,9 @@ def main():
     }
     del s
     torch.cuda.empty_cache()
+    if args.workload == "spheres" and not args.no_channel:
+        print("[bench] 256^3 channel roofline ...", file=sys.stderr, flush=True)
+        out["hbm_resident_roofline"] = channel_roofline(torch)
     if not args.no_copy:
         out["copy_peak_gbs"] = round(copy_peak_gbs(torch), 1)
     if not args.no_warm:

@@ -442,3 +442,47 @@ def test_complex_build_matches_real_build():
     L_re, _ = O.loss_complex_step(lat, 0.8, rin, rout, f0, 25, tgt, wgt, dtau=1.0)
     L = O.loss(lat, O.run(lat, 0.8, rin, rout, f0, 25), tgt, wgt)
     assert abs(L_re - L) <= 1e-15 * abs(L)
+
+
+def test_adjoint_matches_complex_step_at_c1_size():
+    """The C1 case at full size (D2Q9 64 x 32 channel, walls, tau 0.8, 2000
+    steps, checkpoints every 45, NORM and VEC losses against a target made at
+    rho_in = 1.003): dL/drho_in (constant head), dL/drho_out and dL/dtau of the
+    reverse pass against complex-step directional derivatives."""
+    lat = O.Lattice(9, 64, 32, 1, (O.BC_PRESSURE, O.BC_WALL, O.BC_PERIODIC))
+    f0 = O.init_eq(lat, 1.0, 0.0)
+    T, tau = 2000, 0.8
+    _, tgt = O.macro(lat, O.run(lat, tau, 1.003, 1.0, f0, T))
+    one = np.ones((1, 32))
+    for kind in (O.LOSS_VEC, O.LOSS_NORM):
+        g = O.grad(lat, tau, 1.005, 1.0, f0, T, tgt, None, kind, 1.0, K=45)
+        L, d_in = O.loss_complex_step(lat, tau, 1.005, 1.0, f0, T, tgt, None, kind, 1.0, drho_in=one)
+        _, d_out = O.loss_complex_step(lat, tau, 1.005, 1.0, f0, T, tgt, None, kind, 1.0, drho_out=one)
+        _, d_tau = O.loss_complex_step(lat, tau, 1.005, 1.0, f0, T, tgt, None, kind, 1.0, dtau=1.0)
+        assert abs(L - g["loss"]) <= 1e-12 * L
+        assert abs(g["drho_in"].sum() - d_in) <= 1e-9 * abs(d_in)
+        assert abs(g["drho_out"].sum() - d_out) <= 1e-9 * abs(d_out)
+        assert abs(g["dtau"] - d_tau) <= 1e-9 * abs(d_tau)
+
+
+def test_adjoint_matches_complex_step_on_a_reduced_c3():
+    """C3 reduced to 32^3 and 800 steps (D3Q19 Boolean spheres r ~ U[2, 3.5],
+    porosity 0.4, periodic y/z, per-node Fourier inlet profile, tau 0.75,
+    checkpoints every 40, MEAN_FLUID VEC loss): the profile gradient along
+    random directions and dL/dtau against complex-step derivatives."""
+    n = 32
+    solid = G.boolean_spheres((n, n, n), (2.0, 3.5), 0.4, seed=3, x_margin=3)
+    lat = O.Lattice(19, n, n, n, (O.BC_PRESSURE, O.BC_PERIODIC, O.BC_PERIODIC), solid)
+    f0 = O.init_eq(lat, 1.0, 0.0)
+    T, tau = 800, 0.75
+    rin = 1.0 + 0.004 * G.fourier_profile(n, n, seed=33)
+    rng = np.random.default_rng(12)
+    tgt = 1e-4 * rng.standard_normal(lat.shape + (3,))
+    scale = 1.0 / lat.fluid().sum()
+    g = O.grad(lat, tau, rin, 1.0, f0, T, tgt, None, O.LOSS_VEC, scale, K=40)
+    for k in range(2):
+        v = rng.standard_normal((n, n))
+        _, d = O.loss_complex_step(lat, tau, rin, 1.0, f0, T, tgt, None, O.LOSS_VEC, scale, drho_in=v)
+        assert abs(np.sum(g["drho_in"] * v) - d) <= 1e-9 * np.abs(g["drho_in"]).sum() * np.abs(v).max()
+    _, d_tau = O.loss_complex_step(lat, tau, rin, 1.0, f0, T, tgt, None, O.LOSS_VEC, scale, dtau=1.0)
+    assert abs(g["dtau"] - d_tau) <= 1e-9 * abs(d_tau)

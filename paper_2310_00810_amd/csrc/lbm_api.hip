@@ -223,6 +223,9 @@ struct lbm_handle {
     hipGraphExec_t g_rev[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [!resident][seed]
     hipGraphExec_t g_chunk[2] = {nullptr, nullptr};          // [starts from the initial state]
     int chunk_len = 0;
+    // reverse sweep with recompute beside the adjoint: a second stream and its events
+    hipStream_t side = nullptr;
+    std::vector<hipEvent_t> xev;
 
     float *state(int k) const { return (float *)(ws + L.off_states + L.state_bytes * (size_t)k); }
     float *init() const { return state(0); }
@@ -490,6 +493,8 @@ int lbm_destroy(lbm_handle *h) {
     for (auto &r : h->g_rev) for (auto g : r) if (g) (void)hipGraphExecDestroy(g);
     for (auto g : h->g_chunk) if (g) (void)hipGraphExecDestroy(g);
     if (h->cap) (void)hipStreamDestroy(h->cap);
+    if (h->side) (void)hipStreamDestroy(h->side);
+    for (auto e : h->xev) (void)hipEventDestroy(e);
     delete h;
     return LBM_OK;
 }
@@ -633,33 +638,79 @@ static int enqueue_reverse(lbm_handle *h, bool resident, const float *seed, hipS
     double *gin = h->at<double>(L.off_grad_in), *gout = h->at<double>(L.off_grad_out);
     double *dpart = h->at<double>(L.off_part_dtau);
     int ev = 0, rc;
-    for (int c = L.n_seg - 1; c >= 0; --c) {
+    // adjoint steps of segment c, reading its states from region r
+    auto adjoint_segment = [&](int c, int r, hipStream_t st) -> int {
         const int t0 = c * K, t1 = std::min(t0 + K, T);
-        const bool keep = resident && c >= L.n_seg - L.R;
-        const int r = keep ? c - (L.n_seg - L.R) : 0;
-        auto F = [&](int j) -> const float * { return j == 0 ? h->ckpt(c) : h->seg(r, j); };
-        if (marks) { if ((rc = record(h, ev))) return rc; marks->push_back(ev++); }
-        if (!keep) {
-            for (int j = 1; j < t1 - t0; ++j)
-                if ((rc = step(h, F(j - 1), h->seg(r, j), s))) return rc;
-            if (marks) h->tm.recompute_launches += t1 - t0 - 1;
-        }
-        if (marks) { if ((rc = record(h, ev))) return rc; marks->push_back(ev++); }
         for (int k = t1; k > t0; --k) {
-            const float *Fprev = F(k - 1 - t0);
+            const float *Fprev = k - 1 - t0 == 0 ? h->ckpt(c) : h->seg(r, k - 1 - t0);
             float *nu_out = h->nu(k & 1);
             if (k == T) {
                 HIP_TRY(lbm::launch_adj_seed(q, h->G, Fprev, nu_out, fin, fout, gin, gout,
                                              h->at<float>(L.off_roi), frame_target(h, L.frames - 1),
-                                             h->P.loss_kind, seed, s));
+                                             h->P.loss_kind, seed, st));
             } else {
                 const int m = frame_of(L, k);
                 HIP_TRY(lbm::launch_adj_step(q, h->G, Fprev, h->nu((k + 1) & 1), nu_out, fin, fout, gin, gout,
                                              dpart, h->at<float>(L.off_roi), m >= 0 ? frame_target(h, m) : nullptr,
-                                             h->P.loss_kind, s));
+                                             h->P.loss_kind, st));
             }
         }
-        if (marks) { if ((rc = record(h, ev))) return rc; marks->push_back(ev++); }
+        return LBM_OK;
+    };
+    auto recompute_segment = [&](int c, int r, hipStream_t st) -> int {
+        const int t0 = c * K, t1 = std::min(t0 + K, T);
+        for (int j = 1; j < t1 - t0; ++j)
+            if ((rc = step(h, j == 1 ? h->ckpt(c) : h->seg(r, j - 1), h->seg(r, j), st))) return rc;
+        return LBM_OK;
+    };
+    const int n_seg = L.n_seg;
+    auto kept = [&](int k) { return resident && k < L.R; };          // k-th segment of the sweep, c = n_seg - 1 - k
+    if (!marks && L.R >= 2 && !kept(n_seg - 1)) {
+        // Recompute beside the adjoint: the k-th segment of the sweep is recomputed on a second
+        // stream into region(k) while the adjoint consumes segment k - 1.  Kept segments read
+        // their own regions R - 1 - k; the others alternate between the two regions whose
+        // adjoint finished two segments earlier (region(k) = region(k - 2)), so a recompute
+        // never overwrites states that an adjoint still reads.
+        std::vector<int> region(n_seg);
+        for (int k = 0; k < n_seg; ++k) region[k] = kept(k) ? L.R - 1 - k : (k >= 2 ? region[k - 2] : k);
+        if (!h->side) HIP_TRY(hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
+        while ((int)h->xev.size() < 2 * n_seg + 1) {
+            hipEvent_t e;
+            HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+            h->xev.push_back(e);
+        }
+        hipEvent_t fork = h->xev[2 * n_seg];
+        auto rec_done = [&](int k) { return h->xev[2 * k]; };
+        auto adj_done = [&](int k) { return h->xev[2 * k + 1]; };
+        HIP_TRY(hipEventRecord(fork, s));
+        HIP_TRY(hipStreamWaitEvent(h->side, fork, 0));
+        auto issue_recompute = [&](int k) -> int {
+            if (k >= 2) HIP_TRY(hipStreamWaitEvent(h->side, adj_done(k - 2), 0));
+            if ((rc = recompute_segment(n_seg - 1 - k, region[k], h->side))) return rc;
+            HIP_TRY(hipEventRecord(rec_done(k), h->side));
+            return LBM_OK;
+        };
+        for (int k = 0; k < n_seg; ++k) {
+            if (k == 0 && !kept(0) && (rc = issue_recompute(0))) return rc;
+            if (k + 1 < n_seg && !kept(k + 1) && (rc = issue_recompute(k + 1))) return rc;
+            if (!kept(k)) HIP_TRY(hipStreamWaitEvent(s, rec_done(k), 0));
+            if ((rc = adjoint_segment(n_seg - 1 - k, region[k], s))) return rc;
+            HIP_TRY(hipEventRecord(adj_done(k), s));
+        }
+    } else {
+        for (int c = n_seg - 1; c >= 0; --c) {
+            const int t0 = c * K, t1 = std::min(t0 + K, T);
+            const bool keep = resident && c >= n_seg - L.R;
+            const int r = keep ? c - (n_seg - L.R) : 0;
+            if (marks) { if ((rc = record(h, ev))) return rc; marks->push_back(ev++); }
+            if (!keep) {
+                if ((rc = recompute_segment(c, r, s))) return rc;
+                if (marks) h->tm.recompute_launches += t1 - t0 - 1;
+            }
+            if (marks) { if ((rc = record(h, ev))) return rc; marks->push_back(ev++); }
+            if ((rc = adjoint_segment(c, r, s))) return rc;
+            if (marks) { if ((rc = record(h, ev))) return rc; marks->push_back(ev++); }
+        }
     }
     // anti-bounce-back: the faces' density also entered g^1, through F^0
     if (L.T >= 1 && h->P.bc_x == LBM_BC_ABB)

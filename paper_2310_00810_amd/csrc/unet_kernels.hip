@@ -216,7 +216,8 @@ __global__ void __launch_bounds__(256) k_conv(ConvArgs a) {
     }
     const bool d2s = (a.flags & FLAG_D2S) != 0;
     const int cr = d2s ? a.ncols >> a.dims : a.ncols;      // D2S: columns sub * cr + co
-    if (((a.out_cs | a.out_co) & 7) == 0 && (!d2s || (cr & 7) == 0)) {
+    const uintptr_t base = a.out32 ? (uintptr_t)a.out32 : (uintptr_t)a.out;
+    if (((a.out_cs | a.out_co) & 7) == 0 && (!d2s || (cr & 7) == 0) && (base & 15) == 0) {
         // the tile goes through LDS (the A buffers are free after the last barrier) so that each
         // thread stores 8 consecutive channels of a pixel (of the fine pixel for D2S, whose
         // 8-column groups stay inside one sub-pixel) with 16-byte writes

@@ -88,6 +88,13 @@ int lbmnn_bias_grad(const void *g, int cstride, int coff, long long pixels, int 
 /* g[m][c] = 0 where y[m][c] <= 0 (ReLU backward), same layout for g and y. */
 int lbmnn_relu_bwd(void *g, const void *y, int cstride, int coff, long long pixels, int C, void *stream);
 
+/* lbmnn_relu_bwd followed by lbmnn_bias_grad on the masked g, in one pass
+ * over g and y when the layout allows 16-byte accesses (strides, offsets and
+ * C multiples of 8, 16-byte aligned pointers, C <= 2048); same results as the
+ * two calls.  ws: >= splits * C floats. */
+int lbmnn_relu_bwd_bias_grad(void *g, const void *y, int cstride, int coff, long long pixels, int C, float *db,
+                             int accumulate, float *ws, int splits, void *stream);
+
 /* 2x2 (2x2x2) max pooling with stride 2; (n, d, h, w) is the coarse grid.
  * Backward routes each gradient to the first maximal element of its window
  * (window order sub = sx + 2 sy + 4 sz) and writes zero to the others, or

@@ -108,8 +108,8 @@ def check(rc, where):
 # ------------------------------------------------------------ lbmnn.h ABI --
 NN_EXPORTS = [
     "lbmnn_conv", "lbmnn_wgrad_workspace_bytes", "lbmnn_conv_wgrad", "lbmnn_weight_transpose",
-    "lbmnn_bias_grad", "lbmnn_relu_bwd", "lbmnn_pool_fwd", "lbmnn_pool_bwd", "lbmnn_mse", "lbmnn_adam",
-    "lbmnn_to_bf16", "lbmnn_features", "lbmnn_normalize", "lbmnn_denormalize",
+    "lbmnn_bias_grad", "lbmnn_relu_bwd", "lbmnn_relu_bwd_bias_grad", "lbmnn_pool_fwd", "lbmnn_pool_bwd",
+    "lbmnn_mse", "lbmnn_adam", "lbmnn_to_bf16", "lbmnn_features", "lbmnn_normalize", "lbmnn_denormalize",
 ]
 NN_RELU, NN_ACCUMULATE, NN_S2D, NN_D2S, NN_S2D_G = 1, 2, 4, 8, 16
 
@@ -139,6 +139,7 @@ def nnlib():
         L.lbmnn_weight_transpose.argtypes = [vp, vp, ip, ip, ip, ip, vp]
         L.lbmnn_bias_grad.argtypes = [vp, ip, ip, ll, ip, vp, ip, vp, ip, vp]
         L.lbmnn_relu_bwd.argtypes = [vp, vp, ip, ip, ll, ip, vp]
+        L.lbmnn_relu_bwd_bias_grad.argtypes = [vp, vp, ip, ip, ll, ip, vp, ip, vp, ip, vp]
         L.lbmnn_pool_fwd.argtypes = [vp, ip, ip, vp, ip, ip, ip, ip, ip, ip, ip, ip, vp]
         L.lbmnn_pool_bwd.argtypes = [vp, ip, ip, vp, ip, ip, vp, ip, ip, ip, ip, ip, ip, ip, ip, ip, vp]
         L.lbmnn_mse.argtypes = [vp, ip, vp, vp, ip, ll, fl, vp, vp, vp, vp]

@@ -130,6 +130,15 @@ int lbmnn_relu_bwd(void *g, const void *y, int cstride, int coff, long long pixe
     return LBM_OK;
 }
 
+int lbmnn_relu_bwd_bias_grad(void *g, const void *y, int cstride, int coff, long long pixels, int C, float *db,
+                             int accumulate, float *ws, int splits, void *stream) {
+    if (!g || !y || !db || !ws || C < 1 || pixels < 1 || splits < 1 || coff + C > cstride)
+        return lbm_fail(LBM_EINVAL, "bad ReLU-backward / bias-gradient arguments");
+    NN_TRY(nn::relu_bwd_bias_grad((uint16_t *)g, (const uint16_t *)y, cstride, coff, pixels, C, ws, splits, db,
+                                  accumulate, (hipStream_t)stream));
+    return LBM_OK;
+}
+
 int lbmnn_pool_fwd(const void *in, int in_cstride, int in_coff, void *out, int out_cstride, int out_coff, int n,
                    int d, int h, int w, int C, int dims, void *stream) {
     if (!in || !out || C < 1 || (dims != 2 && dims != 3) || (dims == 2 && d != 1) || in_coff + C > in_cstride ||

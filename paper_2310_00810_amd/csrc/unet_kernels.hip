@@ -465,8 +465,14 @@ __global__ void __launch_bounds__(256) k_sum_splits_narrow(const float *__restri
 // Bias gradient partials with 16-byte loads (channel stride, offset and
 // count multiples of 8, C <= 2048): a thread sums 8 channels of every
 // (256 / (C/8))-th pixel of the split; LDS combines the pixel lanes.
-__global__ void __launch_bounds__(256) k_bias_grad8(const uint16_t *__restrict__ g, int cs, int co, long long npix,
-                                                    int C, long long chunk, float *__restrict__ part) {
+// Bias gradient partials, 8 channels per thread with 16-byte loads.  RELU:
+// first the ReLU backward in the same pass, g = 0 where y <= 0 (written back),
+// then the masked g is summed (the same sums, in the same order, as the two
+// passes one after the other).
+template <bool RELU>
+__global__ void __launch_bounds__(256) k_bias_grad8(uint16_t *__restrict__ g, const uint16_t *__restrict__ y,
+                                                    int cs, int co, long long npix, int C, long long chunk,
+                                                    float *__restrict__ part) {
     __shared__ float sh[256 * 8];
     const int tpp = C >> 3;                    // threads per pixel
     const int ppi = 256 / tpp;                 // pixels per iteration
@@ -476,7 +482,19 @@ __global__ void __launch_bounds__(256) k_bias_grad8(const uint16_t *__restrict__
     float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     if (pi < ppi)
         for (long long m = mb + pi; m < me; m += ppi) {
-            const uint4 v = *(const uint4 *)(g + m * cs + co + gi * 8);
+            uint4 v = *(const uint4 *)(g + m * cs + co + gi * 8);
+            if (RELU) {
+                const uint4 yv = *(const uint4 *)(y + m * cs + co + gi * 8);
+                const uint32_t y4[4] = {yv.x, yv.y, yv.z, yv.w};
+                uint32_t g4[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    if (!(bf2f((uint16_t)(y4[j] & 0xffffu)) > 0.f)) g4[j] &= 0xffff0000u;
+                    if (!(bf2f((uint16_t)(y4[j] >> 16)) > 0.f)) g4[j] &= 0x0000ffffu;
+                }
+                v = make_uint4(g4[0], g4[1], g4[2], g4[3]);
+                *(uint4 *)(g + m * cs + co + gi * 8) = v;
+            }
             const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
@@ -717,12 +735,29 @@ hipError_t wgrad(const ConvArgs &a, const uint16_t *g, int g_cs, int g_co, int r
     return sum_splits(part, z, n, dw, accumulate, s);
 }
 
+bool bias_grad8_ok(const void *g, int cs, int co, int C) {
+    return cs % 8 == 0 && co % 8 == 0 && C % 8 == 0 && C <= 2048 && ((uintptr_t)g & 15) == 0;
+}
+
+hipError_t relu_bwd_bias_grad(uint16_t *g, const uint16_t *y, int cs, int co, long long npix, int C, float *part,
+                              int splits, float *db, int accumulate, hipStream_t s) {
+    if (!bias_grad8_ok(g, cs, co, C) || ((uintptr_t)y & 15) != 0) {
+        hipError_t e = relu_bwd(g, y, cs, co, npix, C, s);
+        return e != hipSuccess ? e : bias_grad(g, cs, co, npix, C, part, splits, db, accumulate, s);
+    }
+    const long long chunk = (npix + splits - 1) / splits;
+    const int z = (int)((npix + chunk - 1) / chunk);
+    hipLaunchKernelGGL(k_bias_grad8<true>, dim3((unsigned)z), dim3(256), 0, s, g, y, cs, co, npix, C, chunk, part);
+    return sum_splits(part, z, (long long)C, db, accumulate, s);
+}
+
 hipError_t bias_grad(const uint16_t *g, int cs, int co, long long npix, int C, float *part, int splits, float *db,
                      int accumulate, hipStream_t s) {
     const long long chunk = (npix + splits - 1) / splits;
     const int z = (int)((npix + chunk - 1) / chunk);
-    if (cs % 8 == 0 && co % 8 == 0 && C % 8 == 0 && C <= 2048 && ((uintptr_t)g & 15) == 0) {
-        hipLaunchKernelGGL(k_bias_grad8, dim3((unsigned)z), dim3(256), 0, s, g, cs, co, npix, C, chunk, part);
+    if (bias_grad8_ok(g, cs, co, C)) {
+        hipLaunchKernelGGL(k_bias_grad8<false>, dim3((unsigned)z), dim3(256), 0, s, (uint16_t *)g, nullptr, cs, co,
+                           npix, C, chunk, part);
     } else {
         dim3 grid((unsigned)((C + 63) / 64), (unsigned)z);
         hipLaunchKernelGGL(k_bias_grad, grid, dim3(256), 0, s, g, cs, co, npix, C, chunk, part);

@@ -38,6 +38,8 @@ hipError_t wgrad(const ConvArgs &a, const uint16_t *g, int g_cs, int g_co, int r
 hipError_t bias_grad(const uint16_t *g, int cs, int co, long long npix, int C, float *part, int splits, float *db,
                      int accumulate, hipStream_t s);
 hipError_t relu_bwd(uint16_t *g, const uint16_t *y, int cs, int co, long long npix, int C, hipStream_t s);
+hipError_t relu_bwd_bias_grad(uint16_t *g, const uint16_t *y, int cs, int co, long long npix, int C, float *part,
+                              int splits, float *db, int accumulate, hipStream_t s);
 hipError_t pool_fwd(const uint16_t *in, int in_cs, int in_co, uint16_t *out, int out_cs, int out_co, int n, int d,
                     int h, int w, int C, int dims, hipStream_t s);
 hipError_t pool_bwd(const uint16_t *in, int in_cs, int in_co, const uint16_t *gout, int g_cs, int g_co,

@@ -219,9 +219,12 @@ class UNet:
                                        _ptr(self.grad, self.boff[name]), 0, _ptr(self._bws), splits,
                                        self._stream()), "lbmnn_bias_grad")
 
-    def _relu_bwd(self, g, y, cs, co, pixels, Cn):
-        C.check(self.L.lbmnn_relu_bwd(ctypes.c_void_p(g.data_ptr()), ctypes.c_void_p(y.data_ptr()), cs, co,
-                                      pixels, Cn, self._stream()), "lbmnn_relu_bwd")
+    def _relu_bgrad(self, g, y, cs, co, pixels, Cn, name):
+        # ReLU backward and the bias gradient of the masked g in one pass
+        splits = max(1, min(-(-pixels // 2048), self._bws.numel() // Cn))
+        C.check(self.L.lbmnn_relu_bwd_bias_grad(ctypes.c_void_p(g.data_ptr()), ctypes.c_void_p(y.data_ptr()), cs, co,
+                                                pixels, Cn, _ptr(self.grad, self.boff[name]), 0, _ptr(self._bws),
+                                                splits, self._stream()), "lbmnn_relu_bwd_bias_grad")
 
     # -------------------------------------------------------------- forward --
     def forward(self, x):
@@ -289,15 +292,13 @@ class UNet:
             g = self._grid(shape, lv)
             P = npix(lv)
             # second decoder conv
-            self._relu_bwd(B[f"g_d{lv}c1"], B[f"d{lv}c1"], Cl, 0, P, Cl)
+            self._relu_bgrad(B[f"g_d{lv}c1"], B[f"d{lv}c1"], Cl, 0, P, Cl, f"d{lv}c1")
             self._wgrad(g, 3, Cl, 0, B[f"d{lv}c0"], Cl, 0, B[f"g_d{lv}c1"], Cl, 0, Cl, f"d{lv}c1")
-            self._bgrad(B[f"g_d{lv}c1"], Cl, 0, P, Cl, f"d{lv}c1")
             self._conv(g, 3, Cl, Cl, 0, B[f"g_d{lv}c1"], Cl, 0, f"d{lv}c1", out=B[f"g_d{lv}c0"], out_cs=Cl,
                        transposed=True, use_bias=False)
             # first decoder conv (input: concatenation)
-            self._relu_bwd(B[f"g_d{lv}c0"], B[f"d{lv}c0"], Cl, 0, P, Cl)
+            self._relu_bgrad(B[f"g_d{lv}c0"], B[f"d{lv}c0"], Cl, 0, P, Cl, f"d{lv}c0")
             self._wgrad(g, 3, 2 * Cl, 0, B[f"cat{lv}"], 2 * Cl, 0, B[f"g_d{lv}c0"], Cl, 0, Cl, f"d{lv}c0")
-            self._bgrad(B[f"g_d{lv}c0"], Cl, 0, P, Cl, f"d{lv}c0")
             self._conv(g, 3, Cl, 2 * Cl, 0, B[f"g_d{lv}c0"], Cl, 0, f"d{lv}c0", out=B[f"g_cat{lv}"],
                        out_cs=2 * Cl, transposed=True, use_bias=False)
             # transposed conv: input on the coarser grid
@@ -321,18 +322,16 @@ class UNet:
                 y1, gy1, cs1, co1 = B[f"cat{lv}"], B[f"g_cat{lv}"], 2 * Cl, Cl
             else:
                 y1, gy1, cs1, co1 = B["bott"], B["g_bott"], Cl, 0
-            self._relu_bwd(gy1, y1, cs1, co1, P, Cl)
+            self._relu_bgrad(gy1, y1, cs1, co1, P, Cl, f"e{lv}c1")
             self._wgrad(g, 3, Cl, 0, B[f"e{lv}c0"], Cl, 0, gy1, cs1, co1, Cl, f"e{lv}c1")
-            self._bgrad(gy1, cs1, co1, P, Cl, f"e{lv}c1")
             self._conv(g, 3, Cl, Cl, 0, gy1, cs1, co1, f"e{lv}c1", out=B[f"g_e{lv}c0"], out_cs=Cl,
                        transposed=True, use_bias=False)
-            self._relu_bwd(B[f"g_e{lv}c0"], B[f"e{lv}c0"], Cl, 0, P, Cl)
+            self._relu_bgrad(B[f"g_e{lv}c0"], B[f"e{lv}c0"], Cl, 0, P, Cl, f"e{lv}c0")
             if lv == 0:
                 xin, xcs, Cin = x, self.cin, self.cin
             else:
                 xin, xcs, Cin = B[f"p{lv - 1}"], Cl >> 1, Cl >> 1
             self._wgrad(g, 3, Cin, 0, xin, xcs, 0, B[f"g_e{lv}c0"], Cl, 0, Cl, f"e{lv}c0")
-            self._bgrad(B[f"g_e{lv}c0"], Cl, 0, P, Cl, f"e{lv}c0")
             if lv > 0:
                 self._conv(g, 3, Cl, Cin, 0, B[f"g_e{lv}c0"], Cl, 0, f"e{lv}c0", out=B[f"g_p{lv - 1}"],
                            out_cs=Cin, transposed=True, use_bias=False)

@@ -322,3 +322,32 @@ def test_mse_adam_and_feature_maps():
     assert np.all(wpx.cpu().numpy() == fl)
     nu = (0.8 - 0.5) / 3
     assert np.allclose(tg.cpu().numpy()[fl, 1], u[fl, 0] * nu / (0.004 / 3), rtol=1e-5)
+
+
+@pytest.mark.parametrize("npix,cs,co,Cn", [(5000, 64, 32, 32), (3001, 16, 0, 16), (777, 24, 3, 12)])
+def test_fused_relu_backward_and_bias_gradient(npix, cs, co, Cn):
+    """One pass (ReLU backward, then the bias gradient of the masked g) gives
+    bit for bit what the two separate operations give, on the 16-byte path
+    and on layouts that fall back to the separate kernels; the bias gradient
+    against a float64 sum of the masked BF16 values."""
+    C = C_()
+    L = C.nnlib()
+    rng = np.random.default_rng(npix)
+    g0 = dev_bf(rng.standard_normal((npix, cs)))
+    y = dev_bf(rng.standard_normal((npix, cs)))
+    splits = 11
+    ws = torch.empty(splits * Cn, dtype=torch.float32, device="cuda")
+    ga, gb = g0.clone(), g0.clone()
+    da = torch.zeros(Cn, dtype=torch.float32, device="cuda")
+    db = torch.zeros(Cn, dtype=torch.float32, device="cuda")
+    C.check(L.lbmnn_relu_bwd(ga.data_ptr(), y.data_ptr(), cs, co, npix, Cn, stream()), "relu_bwd")
+    C.check(L.lbmnn_bias_grad(ga.data_ptr(), cs, co, npix, Cn, da.data_ptr(), 0, ws.data_ptr(), splits, stream()),
+            "bias_grad")
+    C.check(L.lbmnn_relu_bwd_bias_grad(gb.data_ptr(), y.data_ptr(), cs, co, npix, Cn, db.data_ptr(), 0,
+                                       ws.data_ptr(), splits, stream()), "relu_bwd_bias_grad")
+    torch.cuda.synchronize()
+    assert torch.equal(ga, gb) and torch.equal(da, db)
+    gm = g0.float().cpu().numpy()[:, co:co + Cn].astype(np.float64)
+    gm[y.float().cpu().numpy()[:, co:co + Cn] <= 0] = 0
+    assert np.array_equal(gb.float().cpu().numpy()[:, co:co + Cn], gm)
+    assert np.allclose(db.cpu().numpy(), gm.sum(0), rtol=1e-5, atol=1e-4)

@@ -314,6 +314,128 @@ __global__ void __launch_bounds__(256) k_conv(ConvArgs a) {
         }
 }
 
+// 3 x 3 convolution of a 2D layer whose input channels come in chunks of 32,
+// on tiles of 8 x 32 pixels (the image sizes must be multiples of those).  Per
+// chunk, the tile's input patch with its one-pixel halo (10 x 34 pixels) and
+// the chunk's weights of all 9 taps are staged in LDS once; the 9 taps then
+// read their MFMA operands from LDS, so each input pixel crosses L2 about
+// 1.3 times instead of 9.  Four wavefronts take two tile rows (64 pixels) each
+// and all TN output columns.  The epilogue stages the tile in the same LDS and
+// stores 8 channels of a pixel with one 16-byte write.
+constexpr int HY = 8, HX = 32, HPX = HX + 2, HP = (HY + 2) * HPX;   // tile rows, columns, patch
+constexpr int HC = 32, HCP = HC + 8;                                 // chunk channels; padded LDS row
+
+template <int TN>
+__global__ void __launch_bounds__(256) k_conv3x3_halo(ConvArgs a) {
+    constexpr int WNT = TN / 16;
+    constexpr int PATCH = HP * HCP, WTS = 9 * TN * HCP;
+    constexpr int TL = TN + 4;
+    constexpr int ELEMS = PATCH + WTS > 2 * 256 * TL ? PATCH + WTS : 2 * 256 * TL;
+    __shared__ __align__(16) uint16_t sm[ELEMS];
+    uint16_t *P = sm, *Wl = sm + PATCH;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int tiles_x = a.w / HX, tiles_y = a.h / HY;
+    int bt = blockIdx.x;
+    const int tx = bt % tiles_x;
+    bt /= tiles_x;
+    const int ty = bt % tiles_y, b = bt / tiles_y;
+    const int n0 = blockIdx.y * TN, y0 = ty * HY, x0 = tx * HX;
+    f32x4 acc[4][WNT];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < WNT; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int kq = (lane >> 4) * 8;
+    for (int c0 = 0; c0 < a.cin; c0 += HC) {
+        for (int e = t; e < HP * 4; e += 256) {
+            const int pp = e >> 2, g8 = (e & 3) * 8;
+            const int py = pp / HPX, px = pp - py * HPX;
+            const int yy = y0 + py - 1, xx = x0 + px - 1;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if ((unsigned)yy < (unsigned)a.h && (unsigned)xx < (unsigned)a.w)
+                v = *(const uint4 *)(a.in + (((long long)b * a.h + yy) * a.w + xx) * a.in_cs + a.in_co + c0 + g8);
+            *(uint4 *)&P[pp * HCP + g8] = v;
+        }
+        for (int e = t; e < 9 * TN * 4; e += 256) {
+            const int g8 = (e & 3) * 8, r = e >> 2;
+            const int tap = r / TN, n = r - tap * TN;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (n0 + n < a.ncols) v = *(const uint4 *)(a.wt + (long long)(n0 + n) * a.K + tap * a.cin + c0 + g8);
+            *(uint4 *)&Wl[r * HCP + g8] = v;
+        }
+        __syncthreads();
+#pragma unroll 1
+        for (int tap = 0; tap < 9; ++tap) {
+            const int dy = tap / 3, dx = tap - dy * 3;       // tap (dx - 1, dy - 1) reads patch (+dx, +dy)
+            bf16x8 fb[WNT];
+#pragma unroll
+            for (int j = 0; j < WNT; ++j)
+                fb[j] = as_bf16x8(*(const uint4 *)&Wl[(tap * TN + j * 16 + (lane & 15)) * HCP + kq]);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int pr = 2 * wave + (i >> 1), pc = (i & 1) * 16 + (lane & 15);
+                const bf16x8 fa = as_bf16x8(*(const uint4 *)&P[((pr + dy) * HPX + pc + dx) * HCP + kq]);
+#pragma unroll
+                for (int j = 0; j < WNT; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, fb[j], acc[i][j], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+    // epilogue: tile pixel p = row * 32 + column, staged as floats in the same LDS
+    float *T = reinterpret_cast<float *>(sm);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < WNT; ++j) {
+            const int cl = j * 16 + (lane & 15), c = n0 + cl;
+            const float bias = a.bias && c < a.ncols ? a.bias[c] : 0.f;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int p = (2 * wave + (i >> 1)) * HX + (i & 1) * 16 + (lane >> 4) * 4 + q;
+                float v = acc[i][j][q] + bias;
+                if (a.flags & FLAG_RELU) v = v > 0.f ? v : 0.f;
+                T[p * TL + cl] = v;
+            }
+        }
+    __syncthreads();
+    constexpr int CG = TN / 8;
+    for (int e = t; e < 256 * CG; e += 256) {
+        const int p = e / CG, cl = (e - p * CG) * 8, c = n0 + cl;
+        if (c >= a.ncols) continue;
+        const long long m = ((long long)b * a.h + y0 + p / HX) * a.w + x0 + (p % HX);
+        const float *src = &T[p * TL + cl];
+        const long long o = m * a.out_cs + a.out_co + c;
+        const int nk = a.ncols - c < 8 ? a.ncols - c : 8;
+        if (a.out32) {
+            float *dst = a.out32 + o;
+            for (int k = 0; k < nk; ++k) dst[k] = (a.flags & FLAG_ACC) ? dst[k] + src[k] : src[k];
+            continue;
+        }
+        uint16_t *dst = a.out + o;
+        if (nk == 8) {
+            float v[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) v[k] = src[k];
+            if (a.flags & FLAG_ACC) {
+                const uint4 old = *(const uint4 *)dst;
+                const uint32_t ow[4] = {old.x, old.y, old.z, old.w};
+#pragma unroll
+                for (int k = 0; k < 8; ++k) v[k] += bf2f((uint16_t)(ow[k >> 1] >> (16 * (k & 1))));
+            }
+            uint32_t pw[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) pw[k] = (uint32_t)f2bf(v[2 * k]) | ((uint32_t)f2bf(v[2 * k + 1]) << 16);
+            *(uint4 *)dst = make_uint4(pw[0], pw[1], pw[2], pw[3]);
+        } else {
+            for (int k = 0; k < nk; ++k) {
+                float v = src[k];
+                if (a.flags & FLAG_ACC) v += bf2f(dst[k]);
+                dst[k] = f2bf(v);
+            }
+        }
+    }
+}
+
 // Weight gradient: dW[r][k] = sum_m G[m][r] * im2col(in)[m][k], G = dout
 // (S2D: r = sub * Cr + co read at the fine pixel).  blockIdx.z splits the
 // pixel range; partials are summed by k_sum_splits.  The contraction runs
@@ -699,7 +821,24 @@ __global__ void k_denormalize(const float *__restrict__ pred, int pcs, const uin
 // ------------------------------------------------------------ launchers --
 static inline unsigned blocks(long long n, int b) { return (unsigned)((n + b - 1) / b); }
 
+static bool halo_ok(const ConvArgs &a) {
+    const uintptr_t ob = a.out32 ? (uintptr_t)a.out32 : (uintptr_t)a.out;
+    return a.dims == 2 && a.ks == 3 && !(a.flags & (FLAG_S2D | FLAG_D2S)) && a.cin % HC == 0 && a.h % HY == 0 &&
+           a.w % HX == 0 && ((a.in_cs | a.in_co | a.out_cs | a.out_co) & 7) == 0 && ((uintptr_t)a.in & 15) == 0 &&
+           (ob & 15) == 0;
+}
+
 hipError_t conv(const ConvArgs &a, hipStream_t s) {
+    // the halo kernel holds 2 - 3 blocks per CU: below 512 blocks the im2col kernel fills the chip better
+    const long long tiles = halo_ok(a) ? (long long)a.n * (a.h / HY) * (a.w / HX) : 0;
+    if (tiles * (a.ncols <= 32 ? 1 : (a.ncols + 63) / 64) >= 512) {
+        if (a.ncols <= 32)
+            hipLaunchKernelGGL((k_conv3x3_halo<32>), dim3((unsigned)tiles, 1), dim3(256), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_conv3x3_halo<64>), dim3((unsigned)tiles, (unsigned)((a.ncols + 63) / 64)),
+                               dim3(256), 0, s, a);
+        return hipGetLastError();
+    }
     if (a.ncols <= 32) {
         dim3 grid(blocks(a.M, 64), (unsigned)((a.ncols + 31) / 32));
         hipLaunchKernelGGL((k_conv<64, 32>), grid, dim3(256), 0, s, a);

@@ -82,8 +82,12 @@ def transpose_call(W, rows, taps, cols, flip):
     return out
 
 
-CASES = [(2, 3, (2, 1, 20, 24), 16, 24), (2, 1, (2, 1, 8, 16), 32, 8), (3, 3, (1, 6, 8, 10), 8, 16),
-         (2, 3, (1, 1, 64, 64), 64, 32)]
+# 2D 3 x 3 layers with input channels in multiples of 32, on multiples of 8 x 32 pixels and with
+# at least 512 tiles, take the halo-tiled kernel: entries 3 (64 columns, two chunks), 6 (40 of 64
+# columns) and 7 (32 columns), and the input gradients of 3 and 7; the others the im2col kernel
+CASES = [(2, 3, (2, 1, 20, 24), 16, 24), (2, 1, (2, 1, 8, 16), 32, 8), (2, 3, (2, 1, 256, 256), 64, 64),
+         (3, 3, (1, 6, 8, 10), 8, 16), (2, 3, (1, 1, 64, 64), 64, 32), (2, 3, (2, 1, 256, 256), 32, 40),
+         (2, 3, (2, 1, 256, 256), 32, 32)]
 
 
 @pytest.mark.parametrize("dims,ks,grid,cin,cout", CASES)
@@ -106,7 +110,9 @@ def test_conv_forward_bf16_relu_and_accumulate(dims, ks, grid, cin, cout):
     y = conv_call(dev_bf(x), dev_bf(W.reshape(cout, -1)), None, ks, dims, cout, flags=C.NN_RELU, out32=False)
     ref = np.maximum(N.conv_fwd(x, W, None, ks, dims), 0)
     got = y.to(torch.float64).cpu().numpy()
-    assert np.all(np.abs(got - ref) <= 2 ** -7 * np.abs(ref) + 1e-30)
+    # BF16 rounding of the output, plus the FP32 accumulation error before it, which dominates
+    # for outputs near zero (about 1e-6 over K = 576 for unit-variance outputs)
+    assert np.all(np.abs(got - ref) <= 2 ** -7 * np.abs(ref) + 1e-5)
     # accumulate into an existing BF16 tensor, writing a channel slice of a wider buffer
     base = bf(rng.standard_normal(grid + (2 * cout,)))
     buf = dev_bf(base)
@@ -115,7 +121,7 @@ def test_conv_forward_bf16_relu_and_accumulate(dims, ks, grid, cin, cout):
     got = buf.to(torch.float64).cpu().numpy()
     assert np.array_equal(got[..., :cout], base[..., :cout])
     exp = base[..., cout:] + N.conv_fwd(x, W, None, ks, dims)
-    assert np.all(np.abs(got[..., cout:] - exp) <= 2 ** -7 * np.abs(exp) + 1e-6)
+    assert np.all(np.abs(got[..., cout:] - exp) <= 2 ** -7 * np.abs(exp) + 1e-5)
 
 
 @pytest.mark.parametrize("dims,ks,grid,cin,cout", CASES)

@@ -603,6 +603,7 @@ __global__ void __launch_bounds__(256) k_bias_grad8(uint16_t *__restrict__ g, co
     const long long me = mb + chunk < npix ? mb + chunk : npix;
     float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     if (pi < ppi)
+#pragma unroll 4
         for (long long m = mb + pi; m < me; m += ppi) {
             uint4 v = *(const uint4 *)(g + m * cs + co + gi * 8);
             if (RELU) {

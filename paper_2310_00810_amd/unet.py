@@ -213,15 +213,15 @@ class UNet:
                                         self._ws.numel() * 4, splits, self._stream()), "lbmnn_conv_wgrad")
 
     def _bgrad(self, g, cs, co, pixels, Cn, name):
-        # about 2048 pixels per split, bounded by the partials buffer
-        splits = max(1, min(-(-pixels // 2048), self._bws.numel() // Cn))
+        # about 512 pixels per split (enough blocks to keep HBM busy), bounded by the partials buffer
+        splits = max(1, min(-(-pixels // 512), self._bws.numel() // Cn))
         C.check(self.L.lbmnn_bias_grad(ctypes.c_void_p(g.data_ptr()), cs, co, pixels, Cn,
                                        _ptr(self.grad, self.boff[name]), 0, _ptr(self._bws), splits,
                                        self._stream()), "lbmnn_bias_grad")
 
     def _relu_bgrad(self, g, y, cs, co, pixels, Cn, name):
-        # ReLU backward and the bias gradient of the masked g in one pass
-        splits = max(1, min(-(-pixels // 2048), self._bws.numel() // Cn))
+        # ReLU backward and the bias gradient of the masked g in one pass (splits as in _bgrad)
+        splits = max(1, min(-(-pixels // 512), self._bws.numel() // Cn))
         C.check(self.L.lbmnn_relu_bwd_bias_grad(ctypes.c_void_p(g.data_ptr()), ctypes.c_void_p(y.data_ptr()), cs, co,
                                                 pixels, Cn, _ptr(self.grad, self.boff[name]), 0, _ptr(self._bws),
                                                 splits, self._stream()), "lbmnn_relu_bwd_bias_grad")

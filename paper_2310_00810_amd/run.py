@@ -110,13 +110,12 @@ def c3(quick=False):
                 profile_to_viscosity_ratio_rel=ratio)
 
 
-def c4(quick=False, n_inst=64, T=5000):
-    """64 D2Q9 instances (sizes from {128x64, 256x128, 512x256, 1024x512},
-    seeds 4000 + b, porosity U[0.5, 0.8], tau U[0.6, 1.2], rho_in - 1
-    U[0.001, 0.006]): forward + adjoint of all instances in one launch per
-    step (graph-replayed) against a loop of single-instance launches."""
-    if quick:
-        n_inst, T = 8, 500
+def c4_instances(n_inst=64):
+    """The batch of uneven D2Q9 media: instance b draws its size from
+    {128x64, 256x128, 512x256, 1024x512}, porosity U[0.5, 0.8], tau
+    U[0.6, 1.2] and rho_in - 1 U[0.001, 0.006] from seed 4000 + b, RSA disks
+    r ~ U[6, 14]; targets are N(0, 1e-4) velocities.  Returns (instances,
+    taus, drho_ins)."""
     sizes = [(128, 64), (256, 128), (512, 256), (1024, 512)]
     insts, taus, dins = [], [], []
     rng = np.random.default_rng(4000)
@@ -129,6 +128,17 @@ def c4(quick=False, n_inst=64, T=5000):
         insts.append(Instance(nx, ny, solid=solid, target_u=tgt))
         taus.append(r.uniform(0.6, 1.2))
         dins.append(r.uniform(0.001, 0.006))
+    return insts, taus, dins
+
+
+def c4(quick=False, n_inst=64, T=5000):
+    """64 D2Q9 instances (sizes from {128x64, 256x128, 512x256, 1024x512},
+    seeds 4000 + b, porosity U[0.5, 0.8], tau U[0.6, 1.2], rho_in - 1
+    U[0.001, 0.006]): forward + adjoint of all instances in one launch per
+    step (graph-replayed) against a loop of single-instance launches."""
+    if quick:
+        n_inst, T = 8, 500
+    insts, taus, dins = c4_instances(n_inst)
     nodes = sum(i.nodes for i in insts)
     K = int(np.ceil(np.sqrt(T)))
     log(f"[c4] {n_inst} instances, {nodes} nodes, T={T}, K={K}")

@@ -218,6 +218,8 @@ def _oracle_params(net):
     (3, (1, 16, 16, 8), 32, 4, 0.1, 1.0, 2e-3, 1e-2),
     (2, (2, 1, 32, 48), 32, 4, 1.0, 0.0, 2e-2, 0.25),     # full width at random initialisation
     (3, (1, 16, 16, 8), 32, 4, 1.0, 0.0, 2e-2, 0.25),
+    (2, (1, 1, 256, 256), 32, 4, 0.1, 1.0, 2e-3, 1e-2),   # the 2D warm start's input size (halo-tiled layers)
+    (3, (1, 32, 32, 32), 32, 4, 0.1, 1.0, 2e-3, 1e-2),    # 3D at half the warm start's 64^3 per axis
 ])
 def test_unet_forward_and_gradients_match_the_oracle(dims, shape, base, levels, wscale, bias, bar_f, bar_g):
     """Whole U-Net composition: FP32 head output and every parameter gradient

@@ -38,9 +38,16 @@
  *     workspace, which the caller allocates and passes to lbm_init(); the
  *     library never allocates device memory and the handle owns only host
  *     metadata.
- *   - All device work is enqueued on the stream given to lbm_init().  Calls
+ *   - All device work is ordered on the stream given to lbm_init().  Calls
  *     that return host values (loss, gradients, residuals) synchronise that
- *     stream; the others are asynchronous.
+ *     stream; the others are asynchronous.  Internally the reverse sweep may
+ *     run segment recomputes on a second stream of the handle's own, forked
+ *     from and joined back into the caller's stream by events, and step
+ *     loops are captured once into graphs (on a private capture stream) and
+ *     replayed on the caller's stream; neither changes the ordering the
+ *     caller sees.
+ *   - Those streams, events and graphs are created on first use on the
+ *     current device: call with the device that holds the workspace current.
  *   - A handle is not thread-safe: use one handle per stream.
  *
  * Errors: every call returns 0 (LBM_OK) or a negative LBM_E* code; nothing

@@ -232,7 +232,8 @@ struct lbm_handle {
     float *pp(int k) const { return state(1 + k); }
     float *ckpt(int c) const { return c == 0 ? init() : state(3 + (c - 1)); }
     // state j (1 .. K-1) of segment region r (0 .. R-1); region r holds segment n_seg - R + r
-    // after a taped forward, and region 0 is where the reverse sweep recomputes the others
+    // after a taped forward; the reverse sweep recomputes the other segments into region 0,
+    // or into regions 0 and 1 in turn when the recompute runs beside the adjoint
     float *seg(int r, int j) const { return state(3 + (L.n_seg - 1) + r * (L.K - 1) + (j - 1)); }
     float *nu(int k) const { return state(3 + (L.n_seg - 1) + L.R * (L.K - 1) + k); }
     template <class T> T *at(size_t off) const { return (T *)(ws + off); }
@@ -624,9 +625,11 @@ int lbm_forward(lbm_handle *h, const lbm_params *prm, int record_tape, double *l
 // The reverse sweep: zero the accumulators, then per segment (last first)
 // recompute its states from the checkpoint and run the adjoint steps.  While
 // the taped forward's states are intact (resident), the last R segments are
-// read from their own regions; every other segment is recomputed into region
-// 0, whose resident states have been consumed by then.  Event marks (timing
-// mode only) bracket each segment's two phases.
+// read from their own regions; every other segment is recomputed into a
+// region whose resident states have been consumed by then (region 0, or
+// regions 0 and 1 in turn when R >= 2 lets the recompute run beside the
+// adjoint).  Event marks (timing mode only) bracket each segment's two
+// phases, with the segments in sequence.
 static int enqueue_reverse(lbm_handle *h, bool resident, const float *seed, hipStream_t s,
                            std::vector<int> *marks) {
     const Layout &L = h->L;
@@ -748,7 +751,7 @@ int lbm_adjoint(lbm_handle *h, const float *d_seed_du) {
                         [&](hipStream_t s) { return enqueue_reverse(h, resident, seed, s, nullptr); });
         if (rc) return rc;
     }
-    // recomputed segments overwrite region 0; with every segment resident nothing is recomputed
+    // recomputed segments overwrite regions 0 and 1; with every segment resident nothing is recomputed
     h->resident_valid = (resident && L.R == L.n_seg) || L.n_seg == 1;
     h->nu_last = h->nu(1);
     h->adjoint_done = true;

@@ -88,6 +88,57 @@ def channel_roofline(torch, n=256, T=40, K=20):
             "k_adj_step_frac": f(BYTES_ADJ, adj_ms), "k_adj_step_avg_launch_ms": round(adj_ms, 5)}
 
 
+def d2q9_batch(torch, T=5000):
+    """The D2Q9 grain-media batch: 64 uneven RSA-disk media (11.0 M nodes) in
+    one launch per step, T = 5000, K = ceil(sqrt(T)).  Forward-only and
+    forward+adjoint MLUPS of graph-replayed passes (one untimed pass of each
+    first), and k_step / k_adj_step against the HBM peak from HIP events
+    around launches one by one."""
+    from paper_2310_00810_amd import lbm, run
+    insts, taus, dins = run.c4_instances(64)
+    nodes = sum(i.nodes for i in insts)
+    fluid = sum(int((i.solid == 0).sum()) for i in insts)
+    K = int(np.ceil(np.sqrt(T)))
+    s = lbm.Solver(9, insts, steps=T, ckpt_interval=K, tape=True, resident_segments="max")
+
+    def fwd():
+        s.forward(taus, dins, 0.0, want_loss=False)
+
+    def grad():
+        s.forward(taus, dins, 0.0, record_tape=True)
+        s.adjoint()
+        s.grad()
+
+    secs = {}
+    for name, fn in (("fwd", fwd), ("grad", grad)):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        secs[name] = time.perf_counter() - t0
+    s.set_timing(True, reset=True)
+    grad()
+    torch.cuda.synchronize()
+    tm = s.timing()
+    s.set_timing(False)
+    resident = s.resident_segments
+    del s
+    torch.cuda.empty_cache()
+    step_ms = (tm["forward_ms"] + tm["recompute_ms"]) / max(tm["forward_launches"] + tm["recompute_launches"], 1)
+    adj_ms = tm["adjoint_ms"] / max(tm["adjoint_launches"], 1)
+    f = lambda b, ms: round(b * fluid / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+    return {"workload": f"D2Q9 batch of 64 RSA-disk media (128x64 .. 1024x512, porosity U[0.5,0.8]), "
+                        f"one launch per step, T={T}, K={K}",
+            "nodes": nodes, "fluid_nodes": fluid, "resident_segments": resident,
+            "recomputed_steps": tm["recompute_launches"],
+            "fwd_mlups": round(nodes * T / secs["fwd"] / 1e6, 1),
+            "fwd_adj_mlups": round(nodes * T / secs["grad"] / 1e6, 1),
+            "fwd_s": round(secs["fwd"], 4), "fwd_adj_s": round(secs["grad"], 4),
+            "k_step_frac": f(2 * 9 * 4, step_ms), "k_step_avg_launch_ms": round(step_ms, 5),
+            "k_adj_step_frac": f(3 * 9 * 4, adj_ms), "k_adj_step_avg_launch_ms": round(adj_ms, 5)}
+
+
 def load_traffic(kernel):
     """HBM bytes per launch from the committed rocprofv3 --pmc summary of this
     kernel, if it was taken on the current kernel source; else None."""
@@ -192,6 +243,7 @@ def main():
     ap.add_argument("--no-copy", action="store_true", help="skip the copy-bandwidth calibration")
     ap.add_argument("--no-warm", action="store_true", help="skip the warm-versus-cold start comparison")
     ap.add_argument("--no-channel", action="store_true", help="skip the 256^3 channel roofline")
+    ap.add_argument("--no-d2q9", action="store_true", help="skip the D2Q9 grain-media batch")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1"}))
@@ -301,6 +353,9 @@ def main():
     if args.workload == "spheres" and not args.no_channel:
         print("[bench] 256^3 channel roofline ...", file=sys.stderr, flush=True)
         out["hbm_resident_roofline"] = channel_roofline(torch)
+    if args.workload == "spheres" and not args.no_d2q9:
+        print("[bench] D2Q9 grain-media batch ...", file=sys.stderr, flush=True)
+        out["d2q9_batch"] = d2q9_batch(torch)
     if not args.no_copy:
         out["copy_peak_gbs"] = round(copy_peak_gbs(torch), 1)
     if not args.no_warm:

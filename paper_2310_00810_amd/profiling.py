@@ -4,6 +4,7 @@
     python -m paper_2310_00810_amd.profiling traffic <fetch_counters.csv> <write_counters.csv> \
         <copy_bytes> <out.json> <out.md> "<command>"
     python -m paper_2310_00810_amd.profiling sq <sq_counters.csv> <out.md> "<command>"
+    python -m paper_2310_00810_amd.profiling overlap <kernel_trace.csv> <out.md>
 
 `trace` turns a `--kernel-trace --stats --output-format csv` kernel-stats file
 into a Markdown table.  `traffic` turns two `--pmc FETCH_SIZE` / `--pmc
@@ -52,6 +53,35 @@ def trace(stats_csv, out_md, command):
             f.write(f"| `{short_name(r['Name'])}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e3:.0f} | "
                     f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['MinNs']) / 1e3:.2f} | "
                     f"{float(r['MaxNs']) / 1e3:.2f} | {float(r['Percentage']):.2f} |\n")
+
+
+def overlap(trace_csv, out_md, top=6):
+    """Appends to out_md each kernel's average duration split by whether its
+    dispatch ran alone or overlapped another dispatch in time (a recompute on
+    the second stream beside the adjoint stretches both), from a
+    --kernel-trace dispatch file."""
+    ev = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), short_name(r["Kernel_Name"]))
+                for r in csv.DictReader(open(trace_csv)))
+    beside = [False] * len(ev)
+    last_end, last = -1, -1
+    for i, (s0, e0, _) in enumerate(ev):
+        if s0 < last_end:
+            beside[i] = beside[last] = True
+        if e0 > last_end:
+            last_end, last = e0, i
+    acc = collections.defaultdict(lambda: [0, 0.0, 0, 0.0])
+    for (s0, e0, name), b in zip(ev, beside):
+        a = acc[name]
+        a[2 * b] += 1
+        a[2 * b + 1] += (e0 - s0) / 1e3
+    names = sorted(acc, key=lambda k: -(acc[k][1] + acc[k][3]))[:top]
+    with open(out_md, "a") as f:
+        f.write("\nDispatches that ran alone and dispatches that overlapped another one in time:\n\n"
+                "| kernel | alone: calls | alone: average (us) | overlapped: calls | overlapped: average (us) |\n"
+                "|---|---|---|---|---|\n")
+        for k in names:
+            n0, t0, n1, t1 = acc[k]
+            f.write(f"| `{k}` | {n0} | {t0 / max(n0, 1):.2f} | {n1} | {t1 / max(n1, 1):.2f} |\n")
 
 
 def _per_kernel(path):
@@ -122,5 +152,7 @@ if __name__ == "__main__":
         trace(sys.argv[2], sys.argv[3], sys.argv[4])
     elif sys.argv[1] == "traffic":
         traffic(sys.argv[2], sys.argv[3], float(sys.argv[4]), sys.argv[5], sys.argv[6], sys.argv[7])
+    elif sys.argv[1] == "overlap":
+        overlap(sys.argv[2], sys.argv[3])
     elif sys.argv[1] == "sq":
         sq(sys.argv[2], sys.argv[3], sys.argv[4])

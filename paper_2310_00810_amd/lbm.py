@@ -122,6 +122,7 @@ class Solver:
         C.check(L.lbm_init(ctypes.byref(h), ctypes.byref(self.problem), ctypes.c_void_p(self._ws_ptr),
                            self.workspace_bytes, ctypes.c_void_p(self.stream.cuda_stream)), "lbm_init")
         self.handle = h
+        self._destroy = L.lbm_destroy  # bound now: module globals may be gone when __del__ runs at exit
         self._keep.clear()  # host arrays were copied by lbm_init
 
     def _host(self, a, dtype, shape):
@@ -132,9 +133,9 @@ class Solver:
         return a.ctypes.data_as(ctypes.c_void_p)
 
     def __del__(self):
-        h = getattr(self, "handle", None)
-        if h is not None and C._lib is not None:
-            C.lib().lbm_destroy(h)
+        h, destroy = getattr(self, "handle", None), getattr(self, "_destroy", None)
+        if h is not None and destroy is not None:
+            destroy(h)
             self.handle = None
 
     # ------------------------------------------------------------ params --

@@ -99,7 +99,12 @@ enum lbm_inlet_mode { LBM_INLET_CONST = 0, LBM_INLET_PROFILE = 1 };
 enum lbm_population_kind { LBM_POP_STATE = 0, LBM_POP_ADJOINT = 1 };
 
 /* One lattice instance.  Host arrays are copied into the workspace by
- * lbm_init(); the caller may free them afterwards. */
+ * lbm_init(); the caller may free them afterwards.  Size limits (LBM_EINVAL
+ * beyond them): nx < 2^20; Q * nx * ny * nz < 2^31 - 2^20; and one state of
+ * the instance, Q planes of its fluid nodes padded to a multiple of 64 at
+ * 4 B each, below 4 GiB (D3Q19: at most 56 512 704 fluid nodes; D2Q9:
+ * 119 304 640), since the kernels address it with 32-bit byte offsets.
+ * Instances are independent lattices; the limit holds for each. */
 typedef struct lbm_instance {
     int nx, ny, nz;          /* nz = 1 for D2Q9; nx >= 2 with density faces; nx < 2^20 */
     const uint8_t *solid;    /* [nz][ny][nx], nonzero = solid node; NULL = all fluid */

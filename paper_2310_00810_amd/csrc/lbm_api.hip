@@ -59,6 +59,13 @@ struct Layout {
     std::vector<InstDev> inst;
 };
 
+long long count_fluid(const lbm_instance &S);
+
+// The kernels address one instance's populations through a buffer resource
+// whose byte range and offsets are 32-bit: Q planes of the fluid nodes
+// (padded to 64) must stay below 4 GiB.
+constexpr long long MAX_INSTANCE_STATE_BYTES = (1LL << 32) - 1;
+
 int validate_problem(const lbm_problem *p) {
     if (!p) return fail(LBM_EINVAL, "problem is NULL");
     if (p->lattice != LBM_D2Q9 && p->lattice != LBM_D3Q19)
@@ -104,6 +111,10 @@ int validate_problem(const lbm_problem *p) {
             return fail(LBM_EINVAL, "instance %d: density faces on x need nx >= 2", b);
         if ((long long)I.nx * I.ny * I.nz * p->lattice >= (1LL << 31) - (1LL << 20))
             return fail(LBM_EINVAL, "instance %d: Q x nodes must stay below 2^31 (32-bit population offsets)", b);
+        const long long plane = std::max(64LL, (count_fluid(I) + 63) / 64 * 64);
+        if ((long long)p->lattice * plane * 4 > MAX_INSTANCE_STATE_BYTES)
+            return fail(LBM_EINVAL, "instance %d: Q x fluid nodes x 4 B must stay below 4 GiB per state "
+                                    "(%lld padded fluid nodes)", b, plane);
         if (p->inlet_mode == LBM_INLET_PROFILE && faces && I.solid) {
             for (long long zy = 0; zy < (long long)I.ny * I.nz; ++zy)
                 if (I.solid[zy * I.nx])

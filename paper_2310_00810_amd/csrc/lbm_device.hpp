@@ -437,9 +437,13 @@ __device__ inline void links(const Geo &G, const InstDev &I, const FTile &t, con
 // ---------------------------------------------------------------------------
 constexpr unsigned OOB = 0x80000000u;
 
+// Byte range and offsets of one instance's population planes are 32-bit
+// unsigned (the host rejects instances whose Q planes reach 4 GiB), so they
+// are formed in unsigned arithmetic and passed on bit for bit.
 __device__ inline __amdgpu_buffer_rsrc_t planes_rsrc(const float *base, int q, long long plane) {
-    return __builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, (int)(q * plane * 4), 0x00020000);
+    return __builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, (int)(unsigned)(q * plane * 4), 0x00020000);
 }
+__device__ inline int plane_off(int i, int plane) { return (int)((unsigned)i * (unsigned)plane * 4u); }
 __device__ inline float bload(__amdgpu_buffer_rsrc_t r, unsigned off) {
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
 }

@@ -81,12 +81,12 @@ __global__ void __launch_bounds__(FT) k_step(Geo G, const float *__restrict__ sr
             for (int i = 0; i < 9; ++i) d[i] = g[i] - feq_shifted<Q>(i, m);
             mrt_relax(d, G.mrt, om, r);
 #pragma unroll
-            for (int i = 0; i < 9; ++i) bstore(rd, g[i] - r[i], own, i * plane * 4);
+            for (int i = 0; i < 9; ++i) bstore(rd, g[i] - r[i], own, plane_off(i, plane));
             return;
         }
     }
 #pragma unroll
-    for (int i = 0; i < Q; ++i) bstore(rd, g[i] + om * (feq_shifted<Q>(i, m) - g[i]), own, i * plane * 4);
+    for (int i = 0; i < Q; ++i) bstore(rd, g[i] + om * (feq_shifted<Q>(i, m) - g[i]), own, plane_off(i, plane));
 }
 
 // -------------------------------------------------------- loss functions --
@@ -204,7 +204,7 @@ __global__ void __launch_bounds__(FT) k_adj_seed(Geo G, const float *__restrict_
     const __amdgpu_buffer_rsrc_t rd = planes_rsrc(nu_out + I.st_off, Q, I.plane);
     const unsigned own = (unsigned)n.id * 4u;
 #pragma unroll
-    for (int i = 0; i < Q; ++i) bstore(rd, a[i], own, i * plane * 4);
+    for (int i = 0; i < Q; ++i) bstore(rd, a[i], own, plane_off(i, plane));
 }
 
 // Adjoint step k: reads F^{k-1} (to rebuild g^k) and nu^{k+1}, writes nu^k;
@@ -339,7 +339,7 @@ __global__ void __launch_bounds__(FT) k_adj_step(Geo G, const float *__restrict_
         }
         const __amdgpu_buffer_rsrc_t rd = planes_rsrc(nu_out + I.st_off, Q, I.plane);
 #pragma unroll
-        for (int i = 0; i < Q; ++i) bstore(rd, a[i], own, i * plane * 4);
+        for (int i = 0; i < Q; ++i) bstore(rd, a[i], own, plane_off(i, plane));
     }
     const double sum = block_sum(dtau, red);
     if (threadIdx.x == 0) dtau_part[t.tile] += sum;

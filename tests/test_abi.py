@@ -127,6 +127,26 @@ def test_largest_row_length_is_accepted(L):
     assert rc == 0 and b >= 3 * 9 * 2 * ((1 << 20) - 1) * 4
 
 
+def test_instance_state_must_stay_below_4_gib(L):
+    """One instance's Q planes of fluid nodes (padded to 64) are addressed with
+    32-bit byte offsets: 19 x 56 512 704 x 4 B is the largest D3Q19 state
+    below 4 GiB; one fluid node more pads the plane past it.  The limit counts
+    fluid nodes, so a larger box of grains is accepted."""
+    n = 400
+    biggest = ((1 << 32) - 1) // (19 * 4) // 64 * 64
+    assert biggest == 56_512_704
+    solid = np.ones(n ** 3, np.uint8)
+    for fluid, ok in ((biggest, True), (biggest + 1, False), (n ** 3, False)):
+        solid[:] = 1
+        solid[:fluid] = 0
+        rc, b = _bytes(L, _problem(n, n, n, q=19, bcy=1, solid=solid.reshape(n, n, n)))
+        assert (rc == 0) == ok, fluid
+        if ok:
+            assert b >= 3 * 19 * biggest * 4
+        else:
+            assert rc == C.LBM_EINVAL and "4 GiB" in L.lbm_last_error().decode()
+
+
 def test_solid_inlet_rejected_in_profile_mode(L):
     s = np.zeros((1, 8, 16), np.uint8)
     s[0, 3, 0] = 1

@@ -108,6 +108,57 @@ def test_steps_on_the_longest_rows(q):
     _check_random_steps(_long_rows(q), 2)
 
 
+def test_largest_state_is_the_periodic_tiling_of_one_cell():
+    """The largest D3Q19 instance state the library accepts, just below 4 GiB
+    (384^3, 56.4 M fluid nodes, population offsets past 2^31 B): a fully
+    periodic 12^3 tiling of a 32^3 cell holding one sphere, started from the
+    tiled random equilibrium field of the cell, with the tiled target.  After
+    T steps every cell's velocity equals the single cell's bit for bit, the
+    loss and dL/dtau are 12^3 times the cell's, and the cell matches the
+    oracle."""
+    lbm = _lbm()
+    cell, m, T, tau = 32, 12, 3, 0.8
+    n = cell * m
+    zz, yy, xx = np.mgrid[0:cell, 0:cell, 0:cell]
+    sphere = (((xx - 15.5) ** 2 + (yy - 15.5) ** 2 + (zz - 15.5) ** 2) <= 3.5 ** 2).astype(np.uint8)
+    fluid_big = int((sphere == 0).sum()) * m ** 3
+    plane = -(-fluid_big // 64) * 64
+    assert (1 << 31) < 19 * plane * 4 < (1 << 32)
+    rng = np.random.default_rng(77)
+    fl = (sphere == 0)
+    drho = (0.01 * rng.standard_normal(sphere.shape) * fl).astype(np.float32)
+    u = (0.01 * rng.standard_normal(sphere.shape + (3,)) * fl[..., None]).astype(np.float32)
+    tgt = (0.01 * rng.standard_normal(sphere.shape + (3,))).astype(np.float32)
+    bc = ("periodic", "periodic", "periodic")
+    out = []
+    for reps in (1, m):
+        tile = lambda a: np.tile(a, (reps, reps, reps) + (1,) * (a.ndim - 3))
+        k = cell * reps
+        s = lbm.Solver(19, [lbm.Instance(k, k, k, solid=tile(sphere), target_u=tile(tgt))], bc=bc, steps=T,
+                       ckpt_interval=T, tape=True)
+        s.set_initial(torch.from_numpy(tile(drho).ravel()).cuda(), torch.from_numpy(tile(u).reshape(-1, 3)).cuda())
+        loss = s.forward(tau, 0.0, 0.0, record_tape=True)[0]
+        ug = s.macro()[1].cpu().numpy().reshape(k, k, k, 3)
+        s.adjoint()
+        out.append((loss, s.grad()["dtau"][0], ug))
+        del s
+        torch.cuda.empty_cache()
+    (l1, d1, u1), (lm, dm, um) = out
+    um = um.reshape(m, cell, m, cell, m, cell, 3).transpose(0, 2, 4, 1, 3, 5, 6).reshape(m ** 3, cell, cell, cell, 3)
+    for c in range(m ** 3):
+        assert np.array_equal(um[c], u1), c
+    # per-block FP32 partial sums group the nodes differently in the two lattices
+    assert lm == pytest.approx(m ** 3 * l1, rel=1e-6)
+    assert dm == pytest.approx(m ** 3 * d1, rel=1e-4)
+    lat = O.Lattice(19, cell, cell, cell, (O.BC_PERIODIC, O.BC_PERIODIC, O.BC_PERIODIC), sphere)
+    f0 = O.init_eq(lat, 1.0 + drho.astype(np.float64), u.astype(np.float64))
+    _, uo = O.macro(lat, O.run(lat, tau, 1.0, 1.0, f0, T))
+    assert rel_l2(u1[fl], uo[fl]) <= 1e-5
+    go = O.grad(lat, tau, 1.0, 1.0, f0, T, tgt.astype(np.float64), K=T)
+    assert abs(l1 - go["loss"]) <= 1e-5 * go["loss"]
+    assert abs(d1 - go["dtau"]) <= 1e-3 * abs(go["dtau"])
+
+
 def _check_random_steps(lat, T):
     _, w, _ = O.velset(lat.q)
     fl = lat.fluid()[..., None]

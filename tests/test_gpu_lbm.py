@@ -695,3 +695,40 @@ def test_cylinder_wake_forward_parity():
     _, uo = O.macro(lat, fo)
     m = lat.fluid()[0]
     assert rel_l2(ug[m], uo[0][m][:, :2]) <= 1e-4
+
+
+def test_cylinder_wake_windowed_gradient_parity():
+    """The viscosity inversion's own configuration at full size: D2Q9 MRT,
+    800 x 320 channel with a D = 20 cylinder, Zou-He velocity inlet u = 0.1,
+    density outlet, periodic y, uniform start, loss summed over three frames
+    (steps 20, 50, 80), K = 10 with two resident segments (the others
+    recomputed beside the adjoint): loss, dL/du_in, dL/dtau and dL/drho_out
+    against the oracle."""
+    lbm = _lbm()
+    nx, ny, U, T, K, tau = 800, 320, 0.1, 80, 10, 0.56
+    frames, stride = 3, 30
+    solid = G.cylinder_channel(nx, ny, 20, 300, 160)
+    rng = np.random.default_rng(5)
+    tg = (U + 0.01 * rng.standard_normal((frames, 1, ny, nx, 2))).astype(np.float32)
+    s = lbm.Solver(9, [lbm.Instance(nx, ny, solid=solid, target_u=tg)], bc=("velocity", "periodic", "periodic"),
+                   steps=T, ckpt_interval=K, tape=True, collision="mrt", mrt_rates=O.MRT_RATES,
+                   resident_segments=2, loss_frames=frames, loss_stride=stride)
+    u0 = torch.zeros(nx * ny * 2, device="cuda")
+    u0[0::2] = U
+    s.set_initial(torch.zeros(nx * ny, device="cuda"), u0)
+    loss = s.forward(tau, f32(U), 0.0, record_tape=True)[0]
+    s.adjoint()
+    g = s.grad()
+    del s
+    torch.cuda.empty_cache()
+    lat = O.Lattice(9, nx, ny, 1, (O.BC_VELOCITY, O.BC_PERIODIC, O.BC_PERIODIC), solid, mrt=O.MRT_RATES)
+    ua = np.zeros(lat.shape + (3,))
+    ua[..., 0] = U
+    f0 = O.init_eq(lat, 1.0, ua) * lat.fluid()[..., None]
+    t3 = np.zeros((frames,) + lat.shape + (3,))
+    t3[..., :2] = tg
+    go = O.grad(lat, tau, f32(U), 1.0, f0, T, t3, K=K, frames=frames, stride=stride)
+    assert abs(loss - go["loss"]) <= 1e-4 * go["loss"]
+    assert rel_l2(g["drho_in"], [go["drho_in"].sum()]) <= 1e-3
+    assert rel_l2(g["dtau"], [go["dtau"]]) <= 1e-3
+    assert rel_l2(g["drho_out"], [go["drho_out"].sum()]) <= 1e-3

@@ -5,8 +5,9 @@ runs (Section 3.1.2 end, Section 3.5).  Here a U-Net (unet.py) learns the
 map (solid mask, drho_in, drho_out, tau) -> Stokes-scaled steady (rho, u)
 from steady states that the batched GPU solver itself produces; its
 prediction initialises equilibrium populations (Eq. 5) and the plain LBM
-then runs to the residual threshold, so the physics judges the network and
-is the fallback.
+then runs to the residual threshold, so the converged state is the
+solver's whatever the network predicts, and a poor prediction only costs
+steps.
 
 Synthetic media (stand-ins for the paper's packings): 2D 256 x 256 channels
 between walls with overlapping disks (radii U[6, 14]); 3D 64^3 boxes,

@@ -459,14 +459,23 @@ __device__ inline void transpose_4x8(const uint4 (&v)[4], uint2 (&o)[8]) {
     }
 }
 
+// NARROW (at most 32 rows, the 32-channel layers): a block takes 32 rows x
+// 128 columns and its four wavefronts sit side by side along the columns, so
+// no MFMA works on the empty rows a 64-row tile would carry; each thread then
+// loads two column groups of the im2col rows, and half the threads the rows
+// of G.
+template <bool NARROW>
 __global__ void __launch_bounds__(256) k_wgrad(ConvArgs a, const uint16_t *__restrict__ g, int g_cs,
                                                int g_co, int rows, float *__restrict__ part,
                                                long long chunk) {
-    __shared__ uint16_t Gs[BM][WLD];
-    __shared__ uint16_t Ts[BN][WLD];
+    constexpr int RM = NARROW ? 32 : BM;            // rows per block
+    constexpr int CN = NARROW ? 128 : BN;           // columns per block
+    constexpr int NT = CN / 64;                     // column groups of 64 per thread
+    __shared__ uint16_t Gs[RM][WLD];
+    __shared__ uint16_t Ts[CN][WLD];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    const int wm = wave & 1, wn = wave >> 1;
-    const int r0 = blockIdx.x * BM, c0 = blockIdx.y * BN;
+    const int wm = NARROW ? 0 : (wave & 1), wn = NARROW ? wave : (wave >> 1);
+    const int r0 = blockIdx.x * RM, c0 = blockIdx.y * CN;
     const long long mb = (long long)blockIdx.z * chunk;
     const long long me = mb + chunk < a.M ? mb + chunk : a.M;
     const int pg = t >> 3, cg = (t & 7) * 8;        // pixels 4 pg .. 4 pg + 3 of a stage, channels cg .. cg + 7
@@ -476,17 +485,22 @@ __global__ void __launch_bounds__(256) k_wgrad(ConvArgs a, const uint16_t *__res
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     const bool s2d_g = (a.flags & FLAG_S2D_G) != 0;
-    // the thread's im2col column (tap, channel) and G channels are fixed over the pixel loop
-    const KOff ko = koff_of(a, c0 + cg);
+    // the thread's im2col columns (tap, channel) and G channels are fixed over the pixel loop
+    KOff ko[NT];
+#pragma unroll
+    for (int n = 0; n < NT; ++n) ko[n] = koff_of(a, c0 + 64 * n + cg);
     const int r = r0 + cg;
-    uint4 gv[4], tv[4];
+    const bool g_rows = cg < RM;                    // this thread stages rows of G
+    uint4 gv[4], tv[NT][4];
     auto load = [&](long long mm) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const long long m = mm + 4 * pg + j;
-            gv[j] = tv[j] = make_uint4(0, 0, 0, 0);
+            gv[j] = make_uint4(0, 0, 0, 0);
+#pragma unroll
+            for (int n = 0; n < NT; ++n) tv[n][j] = make_uint4(0, 0, 0, 0);
             if (m >= me) continue;
-            if (r < rows) {
+            if (g_rows && r < rows) {
                 long long src = m;
                 int ch = r;
                 if (s2d_g) {
@@ -501,20 +515,26 @@ __global__ void __launch_bounds__(256) k_wgrad(ConvArgs a, const uint16_t *__res
                 }
                 gv[j] = *(const uint4 *)(g + src * g_cs + g_co + ch);
             }
-            tv[j] = im2col_load(a, row_of(a, m), ko);
+            const Row rw = row_of(a, m);
+#pragma unroll
+            for (int n = 0; n < NT; ++n) tv[n][j] = im2col_load(a, rw, ko[n]);
         }
     };
     load(mb);
     for (long long mm = mb; mm < me; mm += WPB) {
         __syncthreads();                              // the previous stage's MFMA reads are done
         {
-            uint2 og[8], ot[8];
-            transpose_4x8(gv, og);
-            transpose_4x8(tv, ot);
+            uint2 o[8];
+            if (g_rows) {
+                transpose_4x8(gv, o);
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                *(uint2 *)&Gs[cg + e][4 * pg] = og[e];
-                *(uint2 *)&Ts[cg + e][4 * pg] = ot[e];
+                for (int e = 0; e < 8; ++e) *(uint2 *)&Gs[cg + e][4 * pg] = o[e];
+            }
+#pragma unroll
+            for (int n = 0; n < NT; ++n) {
+                transpose_4x8(tv[n], o);
+#pragma unroll
+                for (int e = 0; e < 8; ++e) *(uint2 *)&Ts[64 * n + cg + e][4 * pg] = o[e];
             }
         }
         __syncthreads();
@@ -869,8 +889,13 @@ hipError_t wgrad(const ConvArgs &a, const uint16_t *g, int g_cs, int g_co, int r
                  float *dw, int accumulate, hipStream_t s) {
     const long long chunk = wgrad_chunk(a.M, splits);
     const int z = (int)((a.M + chunk - 1) / chunk);
-    dim3 grid((unsigned)((rows + BM - 1) / BM), (unsigned)((a.K + BN - 1) / BN), (unsigned)z);
-    hipLaunchKernelGGL(k_wgrad, grid, dim3(256), 0, s, a, g, g_cs, g_co, rows, part, chunk);
+    if (rows <= 32) {
+        const dim3 grid(1u, (unsigned)((a.K + 127) / 128), (unsigned)z);
+        hipLaunchKernelGGL(k_wgrad<true>, grid, dim3(256), 0, s, a, g, g_cs, g_co, rows, part, chunk);
+    } else {
+        const dim3 grid((unsigned)((rows + BM - 1) / BM), (unsigned)((a.K + BN - 1) / BN), (unsigned)z);
+        hipLaunchKernelGGL(k_wgrad<false>, grid, dim3(256), 0, s, a, g, g_cs, g_co, rows, part, chunk);
+    }
     const long long n = (long long)rows * a.K;
     return sum_splits(part, z, n, dw, accumulate, s);
 }

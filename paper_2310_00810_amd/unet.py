@@ -201,7 +201,8 @@ class UNet:
         n, d, h, w = grid
         M = n * d * h * w
         K = cin * (ks ** self.dims) if not (flags & C.NN_S2D) else cin * (1 << self.dims)
-        base_blocks = -(-rows // 64) * -(-K // 64)
+        # blocks per pixel split: 32 x 128 tiles for at most 32 rows, else 64 x 64
+        base_blocks = -(-K // 128) if rows <= 32 else -(-rows // 64) * -(-K // 64)
         splits = max(1, min(M // 512, max(1, 2048 // base_blocks)))
         need = self.L.lbmnn_wgrad_workspace_bytes(M, rows, K, splits)
         if self._ws.numel() * 4 < need:

@@ -62,13 +62,13 @@ def overlap(trace_csv, out_md, top=6):
     --kernel-trace dispatch file."""
     ev = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), short_name(r["Kernel_Name"]))
                 for r in csv.DictReader(open(trace_csv)))
+    # sorted by start, dispatch i overlaps another iff an earlier one ends after it starts or the
+    # next one starts before it ends
     beside = [False] * len(ev)
-    last_end, last = -1, -1
+    prefix_end = -1
     for i, (s0, e0, _) in enumerate(ev):
-        if s0 < last_end:
-            beside[i] = beside[last] = True
-        if e0 > last_end:
-            last_end, last = e0, i
+        beside[i] = prefix_end > s0 or (i + 1 < len(ev) and ev[i + 1][0] < e0)
+        prefix_end = max(prefix_end, e0)
     acc = collections.defaultdict(lambda: [0, 0.0, 0, 0.0])
     for (s0, e0, name), b in zip(ev, beside):
         a = acc[name]

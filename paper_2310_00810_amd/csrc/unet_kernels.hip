@@ -325,7 +325,10 @@ __global__ void __launch_bounds__(256) k_conv(ConvArgs a) {
 constexpr int HY = 8, HX = 32, HPX = HX + 2, HP = (HY + 2) * HPX;   // tile rows, columns, patch
 constexpr int HC = 32, HCP = HC + 8;                                 // chunk channels; padded LDS row
 
-template <int TN>
+// In 3D a block takes one 8 x 32 tile of one plane z and, per chunk, runs
+// the same staging and 9 taps for each of the three input planes z - 1, z,
+// z + 1 (taps dz * 9 + dy * 3 + dx), skipping planes outside the volume.
+template <int TN, int DIMS>
 __global__ void __launch_bounds__(256) k_conv3x3_halo(ConvArgs a) {
     constexpr int WNT = TN / 16;
     constexpr int PATCH = HP * HCP, WTS = 9 * TN * HCP;
@@ -338,7 +341,9 @@ __global__ void __launch_bounds__(256) k_conv3x3_halo(ConvArgs a) {
     int bt = blockIdx.x;
     const int tx = bt % tiles_x;
     bt /= tiles_x;
-    const int ty = bt % tiles_y, b = bt / tiles_y;
+    const int ty = bt % tiles_y;
+    bt /= tiles_y;
+    const int z = DIMS == 3 ? bt % a.d : 0, b = DIMS == 3 ? bt / a.d : bt;
     const int n0 = blockIdx.y * TN, y0 = ty * HY, x0 = tx * HX;
     f32x4 acc[4][WNT];
 #pragma unroll
@@ -346,21 +351,27 @@ __global__ void __launch_bounds__(256) k_conv3x3_halo(ConvArgs a) {
 #pragma unroll
         for (int j = 0; j < WNT; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     const int kq = (lane >> 4) * 8;
-    for (int c0 = 0; c0 < a.cin; c0 += HC) {
+    for (int c0 = 0; c0 < a.cin; c0 += HC)
+    for (int dz = 0; dz < (DIMS == 3 ? 3 : 1); ++dz) {
+        const int zz = DIMS == 3 ? z + dz - 1 : 0;
+        if ((unsigned)zz >= (unsigned)a.d) continue;        // a zero plane adds nothing (block-uniform)
+        const int tap0 = DIMS == 3 ? dz * 9 : 0;
         for (int e = t; e < HP * 4; e += 256) {
             const int pp = e >> 2, g8 = (e & 3) * 8;
             const int py = pp / HPX, px = pp - py * HPX;
             const int yy = y0 + py - 1, xx = x0 + px - 1;
             uint4 v = make_uint4(0, 0, 0, 0);
             if ((unsigned)yy < (unsigned)a.h && (unsigned)xx < (unsigned)a.w)
-                v = *(const uint4 *)(a.in + (((long long)b * a.h + yy) * a.w + xx) * a.in_cs + a.in_co + c0 + g8);
+                v = *(const uint4 *)(a.in + ((((long long)b * a.d + zz) * a.h + yy) * a.w + xx) * a.in_cs + a.in_co +
+                                     c0 + g8);
             *(uint4 *)&P[pp * HCP + g8] = v;
         }
         for (int e = t; e < 9 * TN * 4; e += 256) {
             const int g8 = (e & 3) * 8, r = e >> 2;
             const int tap = r / TN, n = r - tap * TN;
             uint4 v = make_uint4(0, 0, 0, 0);
-            if (n0 + n < a.ncols) v = *(const uint4 *)(a.wt + (long long)(n0 + n) * a.K + tap * a.cin + c0 + g8);
+            if (n0 + n < a.ncols)
+                v = *(const uint4 *)(a.wt + (long long)(n0 + n) * a.K + (tap0 + tap) * a.cin + c0 + g8);
             *(uint4 *)&Wl[r * HCP + g8] = v;
         }
         __syncthreads();
@@ -402,7 +413,7 @@ __global__ void __launch_bounds__(256) k_conv3x3_halo(ConvArgs a) {
     for (int e = t; e < 256 * CG; e += 256) {
         const int p = e / CG, cl = (e - p * CG) * 8, c = n0 + cl;
         if (c >= a.ncols) continue;
-        const long long m = ((long long)b * a.h + y0 + p / HX) * a.w + x0 + (p % HX);
+        const long long m = (((long long)b * a.d + z) * a.h + y0 + p / HX) * a.w + x0 + (p % HX);
         const float *src = &T[p * TL + cl];
         const long long o = m * a.out_cs + a.out_co + c;
         const int nk = a.ncols - c < 8 ? a.ncols - c : 8;
@@ -844,20 +855,24 @@ static inline unsigned blocks(long long n, int b) { return (unsigned)((n + b - 1
 
 static bool halo_ok(const ConvArgs &a) {
     const uintptr_t ob = a.out32 ? (uintptr_t)a.out32 : (uintptr_t)a.out;
-    return a.dims == 2 && a.ks == 3 && !(a.flags & (FLAG_S2D | FLAG_D2S)) && a.cin % HC == 0 && a.h % HY == 0 &&
+    return (a.dims == 2 || a.dims == 3) && a.ks == 3 && !(a.flags & (FLAG_S2D | FLAG_D2S)) && a.cin % HC == 0 &&
+           a.h % HY == 0 &&
            a.w % HX == 0 && ((a.in_cs | a.in_co | a.out_cs | a.out_co) & 7) == 0 && ((uintptr_t)a.in & 15) == 0 &&
            (ob & 15) == 0;
 }
 
 hipError_t conv(const ConvArgs &a, hipStream_t s) {
     // the halo kernel holds 2 - 3 blocks per CU: below 512 blocks the im2col kernel fills the chip better
-    const long long tiles = halo_ok(a) ? (long long)a.n * (a.h / HY) * (a.w / HX) : 0;
+    const long long tiles = halo_ok(a) ? (long long)a.n * a.d * (a.h / HY) * (a.w / HX) : 0;
     if (tiles * (a.ncols <= 32 ? 1 : (a.ncols + 63) / 64) >= 512) {
-        if (a.ncols <= 32)
-            hipLaunchKernelGGL((k_conv3x3_halo<32>), dim3((unsigned)tiles, 1), dim3(256), 0, s, a);
-        else
-            hipLaunchKernelGGL((k_conv3x3_halo<64>), dim3((unsigned)tiles, (unsigned)((a.ncols + 63) / 64)),
-                               dim3(256), 0, s, a);
+        const dim3 grid((unsigned)tiles, a.ncols <= 32 ? 1u : (unsigned)((a.ncols + 63) / 64));
+        if (a.dims == 3) {
+            if (a.ncols <= 32) hipLaunchKernelGGL((k_conv3x3_halo<32, 3>), grid, dim3(256), 0, s, a);
+            else hipLaunchKernelGGL((k_conv3x3_halo<64, 3>), grid, dim3(256), 0, s, a);
+        } else {
+            if (a.ncols <= 32) hipLaunchKernelGGL((k_conv3x3_halo<32, 2>), grid, dim3(256), 0, s, a);
+            else hipLaunchKernelGGL((k_conv3x3_halo<64, 2>), grid, dim3(256), 0, s, a);
+        }
         return hipGetLastError();
     }
     if (a.ncols <= 32) {

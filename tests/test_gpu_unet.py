@@ -82,12 +82,13 @@ def transpose_call(W, rows, taps, cols, flip):
     return out
 
 
-# 2D 3 x 3 layers with input channels in multiples of 32, on multiples of 8 x 32 pixels and with
-# at least 512 tiles, take the halo-tiled kernel: entries 3 (64 columns, two chunks), 6 (40 of 64
-# columns) and 7 (32 columns), and the input gradients of 3 and 7; the others the im2col kernel
+# 3 x 3 (x 3) layers with input channels in multiples of 32, on planes of multiples of 8 x 32 pixels
+# and with at least 512 tiles, take the halo-tiled kernel: entries 3 (64 columns, two chunks), 6
+# (40 of 64 columns), 7 (32 columns), 8 (3D, 32 columns, planes on both z faces) and 9 (3D, 40 of
+# 64 columns, two chunks), and the input gradients of 3, 7 and 8; the others the im2col kernel
 CASES = [(2, 3, (2, 1, 20, 24), 16, 24), (2, 1, (2, 1, 8, 16), 32, 8), (2, 3, (2, 1, 256, 256), 64, 64),
          (3, 3, (1, 6, 8, 10), 8, 16), (2, 3, (1, 1, 64, 64), 64, 32), (2, 3, (2, 1, 256, 256), 32, 40),
-         (2, 3, (2, 1, 256, 256), 32, 32)]
+         (2, 3, (2, 1, 256, 256), 32, 32), (3, 3, (2, 16, 64, 64), 32, 32), (3, 3, (4, 8, 64, 64), 64, 40)]
 
 
 @pytest.mark.parametrize("dims,ks,grid,cin,cout", CASES)

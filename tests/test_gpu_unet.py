@@ -83,12 +83,14 @@ def transpose_call(W, rows, taps, cols, flip):
 
 
 # 3 x 3 (x 3) layers with input channels in multiples of 32, on planes of multiples of 8 x 32 pixels
-# and with at least 512 tiles, take the halo-tiled kernel: entries 3 (64 columns, two chunks), 6
+# and with at least 512 blocks, take the halo-tiled kernel: entries 3 (64 columns, two chunks), 6
 # (40 of 64 columns), 7 (32 columns), 8 (3D, 32 columns, planes on both z faces) and 9 (3D, 40 of
-# 64 columns, two chunks), and the input gradients of 3, 7 and 8; the others the im2col kernel
+# 64 columns, two chunks), and the input gradients of 3, 7 and 8; the others (among them 10, a 3D
+# layer of 256 tiles) the im2col kernel
 CASES = [(2, 3, (2, 1, 20, 24), 16, 24), (2, 1, (2, 1, 8, 16), 32, 8), (2, 3, (2, 1, 256, 256), 64, 64),
          (3, 3, (1, 6, 8, 10), 8, 16), (2, 3, (1, 1, 64, 64), 64, 32), (2, 3, (2, 1, 256, 256), 32, 40),
-         (2, 3, (2, 1, 256, 256), 32, 32), (3, 3, (2, 16, 64, 64), 32, 32), (3, 3, (4, 8, 64, 64), 64, 40)]
+         (2, 3, (2, 1, 256, 256), 32, 32), (3, 3, (2, 16, 64, 64), 32, 32), (3, 3, (4, 8, 64, 64), 64, 40),
+         (3, 3, (2, 32, 32, 32), 32, 64)]
 
 
 @pytest.mark.parametrize("dims,ks,grid,cin,cout", CASES)

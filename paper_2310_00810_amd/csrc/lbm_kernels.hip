@@ -216,7 +216,7 @@ __global__ void __launch_bounds__(FT) k_adj_seed(Geo G, const float *__restrict_
 //   A   = sum_k lam_k dfeq_k/drho = S0 (1 + 1.5 u.u) - 4.5 u.S2.u,
 //   B_a = sum_k lam_k dfeq_k/dj_a = 3 S_a + 9 (S2 u)_a - 3 u_a S0.
 template <int Q, int BCX, bool SEED>
-__global__ void __launch_bounds__(FT) k_adj_step(Geo G, const float *__restrict__ Fprev,
+__global__ void __launch_bounds__(FT) __attribute__((amdgpu_waves_per_eu(6))) k_adj_step(Geo G, const float *__restrict__ Fprev,
                                                  const float *__restrict__ nu_in,
                                                  float *__restrict__ nu_out,
                                                  const float *__restrict__ face_in,
@@ -299,18 +299,22 @@ __global__ void __launch_bounds__(FT) k_adj_step(Geo G, const float *__restrict_
             if (cx && cy) Sxy += cx * cy * wl;
             if (cx && cz) Sxz += cx * cz * wl;
             if (cy && cz) Syz += cy * cz * wl;
-            if (!mrt) dtau += lam[q] * (g[q] - feq_shifted<Q>(q, m));
+            if (!mrt) dtau += lam[q] * g[q];
         }
-        if (!mrt) dtau *= I.inv_tau2;
         const float ux = m.ux, uy = m.uy, uz = m.uz;
         const float usq = ux * ux + uy * uy + uz * uz;
         const float S2ux = Sxx * ux + Sxy * uy + Sxz * uz;
         const float S2uy = Sxy * ux + Syy * uy + Syz * uz;
         const float S2uz = Sxz * ux + Syz * uy + Szz * uz;
-        const float A = S0 * (1.0f + 1.5f * usq) - 4.5f * (ux * S2ux + uy * S2uy + uz * S2uz);
+        const float A1 = 1.5f * usq * S0 - 4.5f * (ux * S2ux + uy * S2uy + uz * S2uz);   // A - S0
+        const float A = S0 + A1;
         const float Bx = 3.0f * Sx + 9.0f * S2ux - 3.0f * ux * S0;
         const float By = 3.0f * Sy + 9.0f * S2uy - 3.0f * uy * S0;
         const float Bz = 3.0f * Sz + 9.0f * S2uz - 3.0f * uz * S0;
+        // BGK: dL/dtau = (1/tau^2) sum_q lam_q (g_q - f_eq,q).  f_eq is homogeneous of degree 1 in
+        // (rho, j), so sum_q lam_q f_eq,q = rho A + j.B; in shifted form, without cancelling S0:
+        //   sum_q lam_q (f_eq,q - w_q) = drho S0 + rho (A - S0 + u.B)
+        if (!mrt) dtau = (dtau - (m.drho * S0 + m.rho * (A1 + ux * Bx + uy * By + uz * Bz))) * I.inv_tau2;
         const float om = mrt ? 1.0f : I.omega, om1 = 1.0f - I.omega;
         float a[Q];
 #pragma unroll

@@ -85,8 +85,23 @@ __global__ void __launch_bounds__(FT) k_step(Geo G, const float *__restrict__ sr
             return;
         }
     }
+    // f_eq of a direction and its opposite share all but the sign of the c.u term:
+    //   f_eq,i - w_i = s +- d,  s = w_i (drho + rho (4.5 (c.u)^2 - 1.5 u.u)),  d = 3 w_i rho c.u
+    using V = Vel<Q>;
+    const float usq15 = 1.5f * (m.ux * m.ux + m.uy * m.uy + m.uz * m.uz), rho3 = 3.0f * m.rho;
+    float feq[Q];
+    feq[0] = V::w(0) * (m.drho - m.rho * usq15);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) bstore(rd, g[i] + om * (feq_shifted<Q>(i, m) - g[i]), own, plane_off(i, plane));
+    for (int i = 1; i < Q; ++i) {
+        const int o = V::opp(i);
+        if (o < i) continue;
+        const float cu = V::cx(i) * m.ux + V::cy(i) * m.uy + V::cz(i) * m.uz;
+        const float sp = V::w(i) * (m.drho + m.rho * (4.5f * cu * cu - usq15)), dp = V::w(i) * rho3 * cu;
+        feq[i] = sp + dp;
+        feq[o] = sp - dp;
+    }
+#pragma unroll
+    for (int i = 0; i < Q; ++i) bstore(rd, g[i] + om * (feq[i] - g[i]), own, plane_off(i, plane));
 }
 
 // -------------------------------------------------------- loss functions --

@@ -52,6 +52,14 @@ def velocities(q):
 _lib = None
 
 
+def load(path):
+    """Use the oracle library at path (a build of the same sources, e.g. the
+    -O3 -march=native copy of ``build.build(native=True)``) from now on."""
+    global _lib
+    _lib = ctypes.CDLL(path)
+    return _lib
+
+
 def lib():
     global _lib
     if _lib is None:

@@ -4,7 +4,10 @@
 
 The oracle is plain C compiled with -O2; OpenMP parallelises the per-node
 loops (the results do not depend on the thread count: every parallel loop
-writes disjoint elements and all sums run serially).
+writes disjoint elements and all sums run serially).  ``native=True`` builds
+a copy with -O3 -march=native for the machine it runs on (the CPU timing
+baseline and long golden runs); ISO C mode keeps floating-point contraction
+off, so both builds give the same bits.
 """
 import os
 import subprocess
@@ -15,15 +18,16 @@ SOURCES = ["lbm_oracle.c", "conv_oracle.c"]
 OUT = os.path.join(HERE, "liblbm_oracle.so")
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, out: str = OUT, native: bool = False) -> str:
     srcs = [os.path.join(HERE, s) for s in SOURCES if os.path.exists(os.path.join(HERE, s))]
-    cmd = ["gcc", "-O2", "-std=c11", "-D_DEFAULT_SOURCE", "-fPIC", "-shared", "-fopenmp",
-           "-Wall", "-Wno-unused-function", "-o", OUT + ".tmp"] + srcs + ["-lm"]
+    opt = ["-O3", "-march=native"] if native else ["-O2"]
+    cmd = ["gcc"] + opt + ["-std=c11", "-D_DEFAULT_SOURCE", "-fPIC", "-shared", "-fopenmp",
+                           "-Wall", "-Wno-unused-function", "-o", out + ".tmp"] + srcs + ["-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True, cwd=HERE)
-    os.replace(OUT + ".tmp", OUT)
-    return OUT
+    os.replace(out + ".tmp", out)
+    return out
 
 
 if __name__ == "__main__":

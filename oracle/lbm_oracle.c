@@ -398,17 +398,25 @@ void orc_collide_adj(ORC_ARGS, double tau, const double *f, const double *fsbar,
 {
     ORC_MAKE;
     const long n = orc_nodes(&L);
-    double acc = 0;
+    /* each node's d/dtau term is formed on its own (nodes in parallel); the
+     * node terms are then summed in node order, so the result does not
+     * depend on the thread count */
+    double *part = malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+#pragma omp parallel for schedule(static)
     for (long k = 0; k < n; k++) {
+        part[k] = 0;
         if (solid && solid[k]) {
             for (int i = 0; i < q; i++) fbar[k * q + i] = 0;
             continue;
         }
         if (L.mrt)
-            orc_collide_adj_node_mrt(L.mrt, tau, &f[k * q], &fsbar[k * q], &fbar[k * q], &acc);
+            orc_collide_adj_node_mrt(L.mrt, tau, &f[k * q], &fsbar[k * q], &fbar[k * q], &part[k]);
         else
-            orc_collide_adj_node(q, tau, &f[k * q], &fsbar[k * q], &fbar[k * q], &acc);
+            orc_collide_adj_node(q, tau, &f[k * q], &fsbar[k * q], &fbar[k * q], &part[k]);
     }
+    double acc = 0;
+    for (long k = 0; k < n; k++) acc += part[k];
+    free(part);
     *dtau += acc;
 }
 
@@ -419,6 +427,7 @@ void orc_stream_adj(ORC_ARGS, const double *gbar, double *fsbar)
     ORC_MAKE;
     const orc_velset *V = orc_vel(q);
     const long n = orc_nodes(&L);
+#pragma omp parallel for schedule(static)
     for (long k = 0; k < n; k++) {
         int x[3];
         orc_coords(&L, k, x);
@@ -568,6 +577,7 @@ void orc_loss_seed(ORC_ARGS, const double *f, const double *target_u, const doub
     ORC_MAKE;
     const orc_velset *V = orc_vel(q);
     const long n = orc_nodes(&L);
+#pragma omp parallel for schedule(static)
     for (long k = 0; k < n; k++) {
         for (int i = 0; i < q; i++) fbar[k * q + i] = 0;
         if (solid && solid[k]) continue;

@@ -15,7 +15,9 @@ are drawn here from explicit, seeded recipes:
   chosen axes, for porosities below the jamming limit of hard spheres (3D
   media, Section 3.3);
 * ``fourier_profile``: a smooth per-node inlet field built from a handful of
-  Fourier modes (a smooth non-uniform inlet pressure, Section 3.1.2).
+  Fourier modes (a smooth non-uniform inlet pressure, Section 3.1.2);
+* ``c4_media``: the batch of 64 uneven granular channels (sizes, packings,
+  relaxation times, inlet densities and target velocities, all seeded).
 
 A node is solid iff its squared distance to a grain centre is at most r^2.
 """
@@ -252,3 +254,26 @@ def cylinder_channel(nx=800, ny=320, diameter=20, xc=300, yc=160):
     (1, ny, nx) uint8 solid mask."""
     yy, xx = np.mgrid[0:ny, 0:nx]
     return (((xx - xc) ** 2 + (yy - yc) ** 2) <= (diameter / 2) ** 2).astype(np.uint8)[None]
+
+
+C4_SIZES = ((128, 64), (256, 128), (512, 256), (1024, 512))
+
+
+def c4_media(n_inst=64):
+    """The batch of uneven D2Q9 granular channels.  Medium b draws, from seed
+    4000 + b, its size from C4_SIZES, a porosity U[0.5, 0.8] of RSA disks
+    r ~ U[6, 14], tau U[0.6, 1.2] and rho_in - 1 U[0.001, 0.006]; its target
+    velocity (ny, nx, 2) float32 is N(0, 1e-4), drawn in medium order from one
+    generator seeded 4000.  Returns a list of dicts (nx, ny, solid (1, ny, nx),
+    tau, drho_in, target)."""
+    out = []
+    rng = np.random.default_rng(4000)
+    for b in range(n_inst):
+        r = np.random.default_rng(4000 + b)
+        nx, ny = C4_SIZES[r.integers(0, 4)]
+        phi = r.uniform(0.5, 0.8)
+        solid = rsa_disks(nx, ny, (6.0, 14.0), phi, seed=4000 + b, max_reject=20000)[None]
+        tgt = (1e-4 * rng.standard_normal((ny, nx, 2))).astype(np.float32)
+        out.append(dict(nx=nx, ny=ny, solid=solid, tau=r.uniform(0.6, 1.2), drho_in=r.uniform(0.001, 0.006),
+                        target=tgt))
+    return out

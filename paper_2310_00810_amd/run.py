@@ -111,24 +111,11 @@ def c3(quick=False):
 
 
 def c4_instances(n_inst=64):
-    """The batch of uneven D2Q9 media: instance b draws its size from
-    {128x64, 256x128, 512x256, 1024x512}, porosity U[0.5, 0.8], tau
-    U[0.6, 1.2] and rho_in - 1 U[0.001, 0.006] from seed 4000 + b, RSA disks
-    r ~ U[6, 14]; targets are N(0, 1e-4) velocities.  Returns (instances,
-    taus, drho_ins)."""
-    sizes = [(128, 64), (256, 128), (512, 256), (1024, 512)]
-    insts, taus, dins = [], [], []
-    rng = np.random.default_rng(4000)
-    for b in range(n_inst):
-        r = np.random.default_rng(4000 + b)
-        nx, ny = sizes[r.integers(0, 4)]
-        phi = r.uniform(0.5, 0.8)
-        solid = G.rsa_disks(nx, ny, (6.0, 14.0), phi, seed=4000 + b, max_reject=20000)[None]
-        tgt = (1e-4 * rng.standard_normal((1, ny, nx, 2))).astype(np.float32)
-        insts.append(Instance(nx, ny, solid=solid, target_u=tgt))
-        taus.append(r.uniform(0.6, 1.2))
-        dins.append(r.uniform(0.001, 0.006))
-    return insts, taus, dins
+    """The batch of uneven D2Q9 media of ``geometry.c4_media`` as solver
+    instances.  Returns (instances, taus, drho_ins)."""
+    media = G.c4_media(n_inst)
+    insts = [Instance(m["nx"], m["ny"], solid=m["solid"], target_u=m["target"][None]) for m in media]
+    return insts, [m["tau"] for m in media], [m["drho_in"] for m in media]
 
 
 def c4(quick=False, n_inst=64, T=5000):

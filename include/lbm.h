@@ -172,8 +172,13 @@ int lbm_init(lbm_handle **h, const lbm_problem *p, void *d_workspace, size_t byt
 /* Releases the host metadata of h (the workspace stays the caller's). */
 int lbm_destroy(lbm_handle *h);
 
-/* Initial state f = f_eq(1 + drho, u) at fluid nodes (Eq. 5).  d_drho:
- * device [nodes] float, d_u: device [nodes][D] float; both NULL = rest. */
+/* Initial state f = f_eq(1 + drho, u) at fluid nodes (Eq. 5; the paper
+ * starts from a uniform density of 1 at rest, Section 3.2, and the
+ * network-based initial guess that Section 3.5 proposes passes a predicted
+ * (drho, u)).  d_drho: device [nodes] float, d_u: device [nodes][D] float;
+ * both NULL = rest.  The arrays are read by work enqueued on the handle's
+ * stream: keep them valid until that work has run.  Invalidates a taped
+ * forward. */
 int lbm_set_initial(lbm_handle *h, const float *d_drho, const float *d_u);
 
 /* Initial state from explicit populations: device dense shifted
@@ -186,44 +191,84 @@ int lbm_set_populations(lbm_handle *h, const float *d_fbar);
  * Solid nodes read as 0. */
 int lbm_get_populations(lbm_handle *h, int which, float *d_out);
 
-/* Runs T steps from the initial state (fused pull streaming, bounce-back,
- * Zou-He and BGK collision per step) and evaluates the loss on the final
- * state.  With record_tape nonzero (requires problem.tape) the states needed
- * by lbm_adjoint() are kept.  loss_out (host, nullable): [n_inst] losses;
- * LBM_EUNSTABLE if any is not finite. */
+/* The forward map (Section 2.1): T steps from the initial state, each one
+ * fused launch of streaming (Eq. 3, pull form), halfway bounce-back on walls
+ * and solid nodes, the x-face closure (Zou-He, or anti-bounce-back, Eq. 6)
+ * and the collision (BGK, Eq. 4, towards the equilibrium of Eq. 5 with the
+ * moments of Eq. 1-2; or MRT, Eq. 16-18), then the velocity-mismatch loss of
+ * Eq. 7 (weights = the region of interest; MEAN_FLUID = the normalised form
+ * of Eq. 15) on the final state, or summed over the loss frames.
+ * prm: host arrays read during the call (tau > 0.5 per instance; face
+ * densities as deviations from 1, > -1).  With record_tape nonzero (requires
+ * problem.tape) the checkpoints every K steps and the states of the last
+ * resident_segments segments are kept for lbm_adjoint().  loss_out (host,
+ * nullable): [n_inst] losses; passing it synchronises the stream.
+ * Errors: LBM_EINVAL (parameters), LBM_ESTATE (record_tape without a tape),
+ * LBM_EUNSTABLE (a non-finite loss), LBM_EDEVICE. */
 int lbm_forward(lbm_handle *h, const lbm_params *prm, int record_tape, double *loss_out);
 
-/* Reverse sweep over the taped forward.  d_seed_du NULL: the built-in loss;
- * otherwise a device array [nodes][D] float of dL/du(T) supplied by the
- * caller (any differentiable loss of the final velocity). */
+/* The reverse sweep (Section 2.2: the derivative the paper obtains by
+ * replaying its recorded tape backwards), here the exact transpose of each
+ * discrete step applied from T down to 1: the terminal seed dl/dg^T of the
+ * loss (Eq. 7 / Eq. 15), then per step the closure, collision and streaming
+ * transposes, accumulating dL/dtau and dL/d(face density) per face node in
+ * FP64.  Segments of K steps that the taped forward did not keep are
+ * recomputed from their checkpoints; each recomputed segment followed by a
+ * checkpoint takes one more step that must reproduce that checkpoint bit for
+ * bit (reported by lbm_grad as LBM_ECORRUPT).  d_seed_du NULL: the built-in
+ * loss; otherwise a device array [nodes][D] float of dL/du(T) supplied by
+ * the caller (any differentiable loss of the final velocity), copied on the
+ * handle's stream.  Asynchronous.  Errors: LBM_ESTATE (no taped forward),
+ * LBM_EINVAL (a caller seed with loss_frames > 1), LBM_EDEVICE. */
 int lbm_adjoint(lbm_handle *h, const float *d_seed_du);
 
-/* Host outputs of the last lbm_adjoint(), each nullable:
+/* Gradients of the loss from the last lbm_adjoint() (Section 2.2; the
+ * inverse problems of Section 3.1-3.4: the constant head or the inlet
+ * pressure profile, the outlet density, and tau, i.e. the viscosity of
+ * Eq. 9), as host arrays, each nullable:
  * d_rho_in  CONST: [n_inst]; PROFILE: per instance [nz][ny] (0 at solid nodes);
+ *           a velocity inlet: dL/du_in;
  * d_tau     [n_inst];
- * d_rho_out [n_inst]. */
+ * d_rho_out [n_inst].
+ * Synchronises the stream.  Errors: LBM_ESTATE (no adjoint), LBM_ECORRUPT (a
+ * recomputed segment of that reverse sweep did not reproduce its checkpoint:
+ * the outputs are not written), LBM_EUNSTABLE (a non-finite gradient),
+ * LBM_EDEVICE. */
 int lbm_grad(lbm_handle *h, double *d_rho_in, double *d_tau, double *d_rho_out);
 
-/* Steps from the initial state until the two-step-mean velocity residual
- * r = ||u(t) - u(t-2)|| / ||u(t) + u(t-1)|| (every instance) is <= tol, testing
- * every check_every steps (even, >= 4), or until max_steps.  steps_out /
- * r_out (host, nullable) receive the step count and the largest instance
- * residual.  The two-step mean cancels the undamped period-2 mode of the
- * scheme (an equilibrium momentum field alternating in sign along x that
- * streaming maps onto its negative). */
+/* Steady state of the forward map (Section 3.1.1 judges it by the plateau
+ * of the kinetic energy): steps from the initial state until the two-step-mean
+ * velocity residual r = ||u(t) - u(t-2)|| / ||u(t) + u(t-1)|| (every instance)
+ * is <= tol, testing every check_every steps (even, >= 4), or until
+ * max_steps.  steps_out / r_out (host, nullable) receive the step count and
+ * the largest instance residual.  The two-step mean cancels the undamped
+ * period-2 mode of the scheme (an equilibrium momentum field alternating in
+ * sign along x that streaming maps onto its negative).  Synchronises the
+ * stream after every check.  Errors: LBM_EINVAL (check_every, max_steps,
+ * parameters), LBM_EUNSTABLE (a non-finite residual), LBM_EDEVICE. */
 int lbm_run_to_residual(lbm_handle *h, const lbm_params *prm, double tol, int max_steps,
                         int check_every, int *steps_out, double *r_out);
 
-/* Macroscopic fields of the current state to device arrays: d_drho [nodes],
- * d_u [nodes][D] (zeros at solid nodes).  mean2 nonzero: the mean of the
- * last two states (cancels the undamped period-2 staggered mode; needs a
- * state produced by at least two steps). */
+/* Macroscopic fields (Eq. 1-2: rho = sum f, u = sum f c / rho) of the
+ * current state to device arrays: d_drho [nodes], d_u [nodes][D] (zeros at
+ * solid nodes).  mean2 nonzero: the mean of the last two states (cancels the
+ * undamped period-2 staggered mode; needs a state produced by at least two
+ * steps, else LBM_ESTATE).  Asynchronous. */
 int lbm_get_macro(lbm_handle *h, float *d_drho, float *d_u, int mean2);
 
 /* Enables (default) or disables hipGraph replay of the step loops: each loop
  * (taped or plain forward, reverse sweep, residual chunk) is captured once on
  * a private stream and then launched as one graph on the handle's stream. */
 int lbm_set_graphs(lbm_handle *h, int enable);
+
+/* Device address (*d_state) and size (*bytes, nullable) of checkpoint c,
+ * the state after c K steps kept by a taped forward, c = 1 .. n_seg - 1
+ * (n_seg = ceil(T / K)), inside the caller's workspace: fluid-node SoA of
+ * shifted FP32 populations.  For inspection and for fault-injection tests
+ * of the checkpoint verification (overwriting it makes the next reverse
+ * sweep that recomputes segment c - 1 report LBM_ECORRUPT).  Errors:
+ * LBM_EINVAL, LBM_ESTATE (no tape planned). */
+int lbm_checkpoint(lbm_handle *h, int c, void **d_state, size_t *bytes);
 
 /* Enables (nonzero) or disables per-phase event timing; reset clears it.
  * Timed calls launch kernels one by one (no graphs) between HIP events. */

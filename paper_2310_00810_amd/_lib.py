@@ -7,9 +7,7 @@ import ctypes
 import os
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-# LBM_LIBRARY may name another build of the same library (e.g. a variant
-# under evaluation); by default the in-tree build is loaded.
-LIBPATH = os.environ.get("LBM_LIBRARY") or os.path.join(PKG, "liblbm.so")
+LIBPATH = os.path.join(PKG, "liblbm.so")
 
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_ESTATE, LBM_EUNSTABLE, LBM_ECORRUPT, LBM_EDEVICE = 0, -1, -2, -3, -4, -5, -6
 LBM_D2Q9, LBM_D3Q19 = 9, 19
@@ -24,7 +22,8 @@ POP_STATE, POP_ADJOINT = 0, 1
 EXPORTS = [
     "lbm_workspace_bytes", "lbm_init", "lbm_destroy", "lbm_set_initial", "lbm_set_populations",
     "lbm_get_populations", "lbm_forward", "lbm_adjoint", "lbm_grad", "lbm_run_to_residual",
-    "lbm_get_macro", "lbm_set_graphs", "lbm_set_timing", "lbm_get_timing", "lbm_strerror", "lbm_last_error",
+    "lbm_get_macro", "lbm_set_graphs", "lbm_set_timing", "lbm_get_timing", "lbm_checkpoint", "lbm_strerror",
+    "lbm_last_error",
 ]
 
 
@@ -88,6 +87,7 @@ def lib():
         L.lbm_set_graphs.argtypes = [vp, ip]
         L.lbm_set_timing.argtypes = [vp, ip, ip]
         L.lbm_get_timing.argtypes = [vp, ctypes.POINTER(lbm_timing)]
+        L.lbm_checkpoint.argtypes = [vp, ip, ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_size_t)]
         L.lbm_strerror.restype = ctypes.c_char_p
         L.lbm_strerror.argtypes = [ip]
         L.lbm_last_error.restype = ctypes.c_char_p

@@ -55,7 +55,8 @@ struct Layout {
     int n_states = 0;
     size_t off_inst = 0, off_mask = 0, off_roi = 0, off_target = 0, off_face_in = 0, off_face_out = 0,
            off_grad_in = 0, off_grad_out = 0, off_part_loss = 0, off_part_dtau = 0, off_part_res = 0,
-           off_red = 0, off_fblk = 0, off_u2 = 0, off_seed = 0, off_states = 0, state_bytes = 0, total = 0;
+           off_red = 0, off_fblk = 0, off_u2 = 0, off_seed = 0, off_flag = 0, off_states = 0, state_bytes = 0,
+           total = 0;
     std::vector<InstDev> inst;
 };
 
@@ -201,6 +202,7 @@ void plan(const lbm_problem *p, Layout &L) {
     L.off_fblk = take(sizeof(int2) * std::max(1, L.n_ftiles));
     L.off_u2 = take(sizeof(float) * node * L.D);
     L.off_seed = take(sizeof(float) * node * L.D);
+    L.off_flag = take(sizeof(unsigned));
     L.state_bytes = align_up(sizeof(float) * (size_t)L.S, 256);
     L.off_states = o;
     L.total = L.off_states + L.state_bytes * (size_t)L.n_states;
@@ -651,6 +653,9 @@ static int enqueue_reverse(lbm_handle *h, bool resident, const float *seed, hipS
     const float *fin = h->at<float>(L.off_face_in), *fout = h->at<float>(L.off_face_out);
     double *gin = h->at<double>(L.off_grad_in), *gout = h->at<double>(L.off_grad_out);
     double *dpart = h->at<double>(L.off_part_dtau);
+    unsigned *flag = h->at<unsigned>(L.off_flag);
+    HIP_TRY(lbm::launch_fill_u32(flag, 1, 0u, s));
+    const int n_seg = L.n_seg;
     int ev = 0, rc;
     // adjoint steps of segment c, reading its states from region r
     auto adjoint_segment = [&](int c, int r, hipStream_t st) -> int {
@@ -671,13 +676,18 @@ static int enqueue_reverse(lbm_handle *h, bool resident, const float *seed, hipS
         }
         return LBM_OK;
     };
+    // Recomputes segment c into region r; a segment followed by a checkpoint
+    // then takes one more step, compared bit for bit with that checkpoint
+    // (a mismatch raises the corruption flag that lbm_grad reports).
     auto recompute_segment = [&](int c, int r, hipStream_t st) -> int {
         const int t0 = c * K, t1 = std::min(t0 + K, T);
         for (int j = 1; j < t1 - t0; ++j)
             if ((rc = step(h, j == 1 ? h->ckpt(c) : h->seg(r, j - 1), h->seg(r, j), st))) return rc;
+        if (c + 1 < n_seg)
+            HIP_TRY(lbm::launch_step_verify(q, h->G, t1 - t0 > 1 ? h->seg(r, t1 - t0 - 1) : h->ckpt(c),
+                                            h->ckpt(c + 1), fin, fout, flag, st));
         return LBM_OK;
     };
-    const int n_seg = L.n_seg;
     auto kept = [&](int k) { return resident && k < L.R; };          // k-th segment of the sweep, c = n_seg - 1 - k
     if (!marks && L.R >= 2 && !kept(n_seg - 1)) {
         // Recompute beside the adjoint: the k-th segment of the sweep is recomputed on a second
@@ -719,7 +729,7 @@ static int enqueue_reverse(lbm_handle *h, bool resident, const float *seed, hipS
             if (marks) { if ((rc = record(h, ev))) return rc; marks->push_back(ev++); }
             if (!keep) {
                 if ((rc = recompute_segment(c, r, s))) return rc;
-                if (marks) h->tm.recompute_launches += t1 - t0 - 1;
+                if (marks) h->tm.recompute_launches += t1 - t0 - 1 + (c + 1 < n_seg ? 1 : 0);
             }
             if (marks) { if ((rc = record(h, ev))) return rc; marks->push_back(ev++); }
             if ((rc = adjoint_segment(c, r, s))) return rc;
@@ -774,8 +784,14 @@ int lbm_grad(lbm_handle *h, double *d_rho_in, double *d_tau, double *d_rho_out) 
     if (!h) return fail(LBM_EINVAL, "handle is NULL");
     if (!h->adjoint_done) return fail(LBM_ESTATE, "lbm_grad needs a preceding lbm_adjoint");
     const Layout &L = h->L;
+    unsigned corrupt = 0;
+    HIP_TRY(hipMemcpyAsync(&corrupt, h->at<unsigned>(L.off_flag), sizeof(unsigned), hipMemcpyDeviceToHost,
+                           h->stream));
     int rc = reduce_to_host(h, L.off_part_dtau, 1, 1);
     if (rc) return rc;
+    if (corrupt)
+        return fail(LBM_ECORRUPT, "a segment recomputed by the reverse sweep did not reproduce the next "
+                                  "checkpoint bit for bit (tape memory overwritten, or a non-deterministic step)");
     std::vector<double> gin(L.total_face), gout(L.total_face);
     if (L.total_face) {
         HIP_TRY(hipMemcpyAsync(gin.data(), h->at<double>(L.off_grad_in), sizeof(double) * L.total_face,
@@ -884,6 +900,16 @@ int lbm_get_macro(lbm_handle *h, float *d_drho, float *d_u, int mean2) {
     if (!h) return fail(LBM_EINVAL, "handle is NULL");
     if (mean2 && (!h->prev || h->cur_steps < 2)) return fail(LBM_ESTATE, "mean of two states needs two steps");
     HIP_TRY(lbm::launch_macro(h->L.q, h->G, h->cur, mean2 ? h->prev : nullptr, d_drho, d_u, h->stream));
+    return LBM_OK;
+}
+
+int lbm_checkpoint(lbm_handle *h, int c, void **d_state, size_t *bytes) {
+    if (!h || !d_state) return fail(LBM_EINVAL, "handle and output must be non-NULL");
+    if (!h->L.tape) return fail(LBM_ESTATE, "the problem was planned without a tape");
+    if (c < 1 || c >= h->L.n_seg)
+        return fail(LBM_EINVAL, "checkpoint %d is outside 1 .. %d", c, h->L.n_seg - 1);
+    *d_state = h->ckpt(c);
+    if (bytes) *bytes = sizeof(float) * (size_t)h->L.S;
     return LBM_OK;
 }
 

@@ -433,9 +433,11 @@ __device__ inline void links(const Geo &G, const InstDev &I, const FTile &t, con
 // ---------------------------------------------------------------------------
 // Gathers through buffer loads: an offset past the end of the instance's
 // planes (OOB) reads 0 by the hardware range check, which is what an open
-// link contributes.
+// link contributes.  The planes of an accepted instance span a multiple of
+// 256 B below 4 GiB, i.e. at most 2^32 - 256 B, so OOB = 2^32 - 256 lies past
+// the range of every accepted size.
 // ---------------------------------------------------------------------------
-constexpr unsigned OOB = 0x80000000u;
+constexpr unsigned OOB = 0xFFFFFF00u;
 
 // Byte range and offsets of one instance's population planes are 32-bit
 // unsigned (the host rejects instances whose Q planes reach 4 GiB), so they
@@ -449,6 +451,9 @@ __device__ inline float bload(__amdgpu_buffer_rsrc_t r, unsigned off) {
 }
 __device__ inline void bstore(__amdgpu_buffer_rsrc_t r, float v, unsigned voff, int soff) {
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
+}
+__device__ inline unsigned bload_bits(__amdgpu_buffer_rsrc_t r, unsigned voff, int soff) {
+    return __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0);
 }
 
 // Streaming pull: g_i(x) = F_i(x - c_i); with k = opp(i), x - c_i = x + c_k.

@@ -51,11 +51,31 @@ __device__ inline void face_unknown_adjoints(__amdgpu_buffer_rsrc_t rn, int plan
         if (V::cx(i) != 0 && (V::cx(i) > 0 ? in : out)) nuo[i] = bload(rn, own + (unsigned)(i * plane) * 4u);
 }
 
-template <int Q, int BCX>
+// The result of a step is stored, or (VERIFY, the check of a recomputed tape
+// segment) compared bit for bit with the state already held in dst: a lane
+// whose populations differ sets *flag.
+template <bool VERIFY>
+struct StepOut {
+    __amdgpu_buffer_rsrc_t r;
+    unsigned own;
+    bool bad = false;
+    __device__ inline void put(float v, int soff) {
+        if constexpr (VERIFY) bad |= bload_bits(r, own, soff) != __builtin_bit_cast(unsigned, v);
+        else bstore(r, v, own, soff);
+    }
+    __device__ inline void done(unsigned *flag) {
+        if constexpr (VERIFY) {
+            if (bad) *flag = 1u;
+        }
+    }
+};
+
+template <int Q, int BCX, bool VERIFY>
 __global__ void __launch_bounds__(FT) k_step(Geo G, const float *__restrict__ src,
                                              float *__restrict__ dst,
                                              const float *__restrict__ face_in,
-                                             const float *__restrict__ face_out) {
+                                             const float *__restrict__ face_out,
+                                             unsigned *__restrict__ flag) {
     FLUID_PROLOGUE();
     if (!n.active) return;
     const bool in = density_faces(BCX) && n.x == 0, out = density_faces(BCX) && n.x == I.nx - 1;
@@ -72,8 +92,9 @@ __global__ void __launch_bounds__(FT) k_step(Geo G, const float *__restrict__ sr
     if (BCX == BC_ABB) abb<Q>(g, in, out, drho_b, uF);
     const Moments m = moments<Q>(g);
     const float om = I.omega;
-    const __amdgpu_buffer_rsrc_t rd = planes_rsrc(dst + I.st_off, Q, I.plane);
-    const unsigned own = (unsigned)n.id * 4u;
+    StepOut<VERIFY> o;
+    o.r = planes_rsrc(dst + I.st_off, Q, I.plane);
+    o.own = (unsigned)n.id * 4u;
     if constexpr (Q == 9) {
         if (G.coll == COLL_MRT) {
             float d[9], r[9];
@@ -81,7 +102,8 @@ __global__ void __launch_bounds__(FT) k_step(Geo G, const float *__restrict__ sr
             for (int i = 0; i < 9; ++i) d[i] = g[i] - feq_shifted<Q>(i, m);
             mrt_relax(d, G.mrt, om, r);
 #pragma unroll
-            for (int i = 0; i < 9; ++i) bstore(rd, g[i] - r[i], own, plane_off(i, plane));
+            for (int i = 0; i < 9; ++i) o.put(g[i] - r[i], plane_off(i, plane));
+            o.done(flag);
             return;
         }
     }
@@ -101,7 +123,8 @@ __global__ void __launch_bounds__(FT) k_step(Geo G, const float *__restrict__ sr
         feq[o] = sp - dp;
     }
 #pragma unroll
-    for (int i = 0; i < Q; ++i) bstore(rd, g[i] + om * (feq[i] - g[i]), own, plane_off(i, plane));
+    for (int i = 0; i < Q; ++i) o.put(g[i] + om * (feq[i] - g[i]), plane_off(i, plane));
+    o.done(flag);
 }
 
 // -------------------------------------------------------- loss functions --
@@ -549,6 +572,11 @@ __global__ void k_fill_f64(double *p, long long n, double v) {
     if (i < n) p[i] = v;
 }
 
+__global__ void k_fill_u32(unsigned *p, long long n, unsigned v) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
 __global__ void k_fill_f32(float *p, long long n, float v) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
@@ -579,7 +607,19 @@ static inline dim3 fgrid_of(const Geo &G) { return dim3((unsigned)G.n_ftiles); }
 hipError_t launch_step(int q, const Geo &G, const float *src, float *dst, const float *fin,
                        const float *fout, hipStream_t s) {
     if (G.n_ftiles == 0) return hipSuccess;
-#define CALL(Q, B) hipLaunchKernelGGL((k_step<Q, B>), fgrid_of(G), dim3(FT), 0, s, G, src, dst, fin, fout)
+#define CALL(Q, B) \
+    hipLaunchKernelGGL((k_step<Q, B, false>), fgrid_of(G), dim3(FT), 0, s, G, src, dst, fin, fout, nullptr)
+    DISPATCH_BCX(q, G.bcx, CALL);
+#undef CALL
+    return hipGetLastError();
+}
+
+hipError_t launch_step_verify(int q, const Geo &G, const float *src, const float *ref, const float *fin,
+                              const float *fout, unsigned *flag, hipStream_t s) {
+    if (G.n_ftiles == 0) return hipSuccess;
+#define CALL(Q, B)                                                                                 \
+    hipLaunchKernelGGL((k_step<Q, B, true>), fgrid_of(G), dim3(FT), 0, s, G, src, (float *)ref, fin, fout, \
+                       flag)
     DISPATCH_BCX(q, G.bcx, CALL);
 #undef CALL
     return hipGetLastError();
@@ -670,6 +710,12 @@ hipError_t launch_residual(int q, const Geo &G, const float *Ft, const float *Ft
 hipError_t launch_reduce(const InstDev *inst, int n_inst, const double *part, int stride, int fluid,
                          double *out, hipStream_t s) {
     hipLaunchKernelGGL(k_reduce, dim3(n_inst), dim3(256), 0, s, inst, part, stride, fluid, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(unsigned *p, long long n, unsigned v, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
     return hipGetLastError();
 }
 

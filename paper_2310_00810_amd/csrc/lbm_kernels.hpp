@@ -7,6 +7,10 @@ namespace lbm {
 
 hipError_t launch_step(int q, const Geo &G, const float *src, float *dst, const float *fin,
                        const float *fout, hipStream_t s);
+// The same step from src, compared bit for bit with the state ref instead of
+// stored: sets *flag = 1 if any population differs (ref is only read).
+hipError_t launch_step_verify(int q, const Geo &G, const float *src, const float *ref, const float *fin,
+                              const float *fout, unsigned *flag, hipStream_t s);
 // acc: add to the partials (the later frames of a time-windowed loss).
 hipError_t launch_loss(int q, const Geo &G, const float *F, const float *roi, const float *target,
                        int kind, double *part, int acc, hipStream_t s);
@@ -35,5 +39,6 @@ hipError_t launch_residual(int q, const Geo &G, const float *Ft, const float *Ft
 hipError_t launch_reduce(const InstDev *inst, int n_inst, const double *part, int stride, int fluid,
                          double *out, hipStream_t s);
 hipError_t launch_fill_f64(double *p, long long n, double v, hipStream_t s);
+hipError_t launch_fill_u32(unsigned *p, long long n, unsigned v, hipStream_t s);
 
 }  // namespace lbm

@@ -159,6 +159,61 @@ def test_largest_state_is_the_periodic_tiling_of_one_cell():
     assert abs(d1 - go["dtau"]) <= 1e-3 * abs(go["dtau"])
 
 
+def test_pressure_faces_above_2_gib_are_the_tiling_of_one_cell():
+    """A D3Q19 instance whose state spans more than 2 GiB (29.3 M fluid nodes,
+    2.2 GB per state) with Zou-He pressure faces and a per-node inlet profile:
+    a 64 x 32 x 32 cell holding one sphere, tiled 16 x 28 times in the
+    periodic y and z.  The open links at the faces read past every accepted
+    buffer range, so the gradient at the face nodes does not depend on where
+    the state sits.  After T steps (the last segment resident, the first
+    recomputed) every cell's velocity and every inlet and outlet node's
+    gradient equal the single cell's bit for bit; loss and dL/dtau are the
+    number of cells times the cell's; the cell matches the oracle."""
+    lbm = _lbm()
+    nx, cell, my, mz, T, K, tau = 64, 32, 16, 28, 4, 2, 0.8
+    zz, yy, xx = np.mgrid[0:cell, 0:cell, 0:nx]
+    sphere = (((xx - 31.5) ** 2 + (yy - 15.5) ** 2 + (zz - 15.5) ** 2) <= 5.5 ** 2).astype(np.uint8)
+    fl = sphere == 0
+    plane = -(-int(fl.sum()) * my * mz // 64) * 64
+    assert (1 << 31) < 19 * plane * 4 < (1 << 32)
+    rng = np.random.default_rng(78)
+    drho = (0.01 * rng.standard_normal(sphere.shape) * fl).astype(np.float32)
+    u = (0.01 * rng.standard_normal(sphere.shape + (3,)) * fl[..., None]).astype(np.float32)
+    tgt = (0.01 * rng.standard_normal(sphere.shape + (3,))).astype(np.float32)
+    prof = (0.004 * G.fourier_profile(cell, cell, n_modes=4, seed=5)).astype(np.float32)
+    bc = ("pressure", "periodic", "periodic")
+    out = []
+    for ry, rz in ((1, 1), (my, mz)):
+        tile = lambda a: np.tile(a, (rz, ry) + (1,) * (a.ndim - 2))
+        s = lbm.Solver(19, [lbm.Instance(nx, cell * ry, cell * rz, solid=tile(sphere), target_u=tile(tgt))],
+                       bc=bc, steps=T, ckpt_interval=K, tape=True, inlet_mode="profile")
+        s.set_initial(torch.from_numpy(tile(drho).ravel()).cuda(), torch.from_numpy(tile(u).reshape(-1, 3)).cuda())
+        loss = s.forward(tau, tile(prof).ravel(), 0.0, record_tape=True)[0]
+        ug = s.macro()[1].cpu().numpy().reshape(cell * rz, cell * ry, nx, 3)
+        s.adjoint()
+        g = s.grad()
+        out.append((loss, g["dtau"][0], g["drho_in"].reshape(cell * rz, cell * ry), ug))
+        del s
+        torch.cuda.empty_cache()
+    (l1, d1, gi1, u1), (lm, dm, gim, um) = out
+    for cz in range(mz):
+        for cy in range(my):
+            sl = (slice(cz * cell, (cz + 1) * cell), slice(cy * cell, (cy + 1) * cell))
+            assert np.array_equal(um[sl], u1), (cz, cy)
+            assert np.array_equal(gim[sl], gi1), (cz, cy)
+    assert lm == pytest.approx(my * mz * l1, rel=1e-6)
+    assert dm == pytest.approx(my * mz * d1, rel=1e-4)
+    lat = O.Lattice(19, nx, cell, cell, (O.BC_PRESSURE, O.BC_PERIODIC, O.BC_PERIODIC), sphere)
+    f0 = O.init_eq(lat, 1.0 + drho.astype(np.float64), u.astype(np.float64))
+    rin = 1.0 + prof.astype(np.float64)
+    _, uo = O.macro(lat, O.run(lat, tau, rin, 1.0, f0, T))
+    assert rel_l2(u1[fl], uo[fl]) <= 1e-5
+    go = O.grad(lat, tau, rin, 1.0, f0, T, tgt.astype(np.float64), K=K)
+    assert abs(l1 - go["loss"]) <= 1e-5 * go["loss"]
+    assert rel_l2(gi1, go["drho_in"]) <= 1e-3
+    assert abs(d1 - go["dtau"]) <= 1e-3 * abs(go["dtau"])
+
+
 def _check_random_steps(lat, T):
     _, w, _ = O.velset(lat.q)
     fl = lat.fluid()[..., None]
@@ -732,3 +787,37 @@ def test_cylinder_wake_windowed_gradient_parity():
     assert rel_l2(g["drho_in"], [go["drho_in"].sum()]) <= 1e-3
     assert rel_l2(g["dtau"], [go["dtau"]]) <= 1e-3
     assert rel_l2(g["drho_out"], [go["drho_out"].sum()]) <= 1e-3
+
+
+@pytest.mark.parametrize("c,resident", [(1, 1), (2, 1), (2, 2)])
+def test_overwritten_checkpoint_is_reported(c, resident):
+    """A reverse sweep that recomputes a segment checks the step that ends it
+    against the next checkpoint bit for bit: with checkpoint c overwritten in
+    the caller's workspace after the taped forward, lbm_grad reports
+    LBM_ECORRUPT, whether the recompute runs in sequence (one resident
+    segment) or beside the adjoint on the second stream (two); the same sweep
+    without the overwrite passes, and a
+    following taped forward (which rewrites the checkpoints) passes again."""
+    lbm = _lbm()
+    from paper_2310_00810_amd._lib import LBM_ECORRUPT, LBMError
+    solid = G.rsa_disks(96, 48, (4.0, 7.0), 0.75, seed=31)[None]
+    rng = np.random.default_rng(5)
+    tgt = (1e-3 * rng.standard_normal((1, 48, 96, 2))).astype(np.float32)
+    s = lbm.Solver(9, [lbm.Instance(96, 48, solid=solid, target_u=tgt)], steps=40, ckpt_interval=10, tape=True,
+                   resident_segments=resident)
+    s.forward(0.8, 0.004, 0.0, record_tape=True)
+    s.adjoint()
+    clean = s.grad()
+    s.forward(0.8, 0.004, 0.0, record_tape=True)
+    ck = s.checkpoint(c)
+    ck[7] = ck[7] + 1e-6
+    torch.cuda.synchronize()
+    s.adjoint()
+    with pytest.raises(LBMError) as e:
+        s.grad()
+    assert e.value.code == LBM_ECORRUPT
+    s.forward(0.8, 0.004, 0.0, record_tape=True)
+    s.adjoint()
+    again = s.grad()
+    for k in clean:
+        assert np.array_equal(clean[k], again[k]), k

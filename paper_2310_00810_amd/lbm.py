@@ -160,6 +160,18 @@ class Solver:
         return C.lbm_params(_dptr(tau), _dptr(din), _dptr(dout))
 
     # ---------------------------------------------------------- calls --
+    def _order(self, *tensors):
+        """Orders the library's stream after torch's current stream (where the
+        caller's tensors were produced or allocated) and marks the tensors as
+        used on the library's stream, so that neither a pending producer nor
+        the caching allocator races with the library's kernels."""
+        cur = torch.cuda.current_stream(self.device)
+        if cur != self.stream:
+            self.stream.wait_stream(cur)
+            for t in tensors:
+                if t is not None:
+                    t.record_stream(self.stream)
+
     def forward(self, tau, drho_in, drho_out, record_tape=False, want_loss=True):
         """Runs T steps from the initial state; returns the per-instance
         losses (numpy float64) or None."""
@@ -172,7 +184,7 @@ class Solver:
     def adjoint(self, seed_du=None):
         if seed_du is not None:
             seed_du = seed_du.to(device=self.device, dtype=torch.float32).contiguous()
-            self._seed_keep = seed_du
+            self._order(seed_du)
         C.check(C.lib().lbm_adjoint(self.handle, _tptr(seed_du)), "lbm_adjoint")
 
     def grad(self):
@@ -186,16 +198,17 @@ class Solver:
     def set_initial(self, drho=None, u=None):
         drho = drho.to(self.device, torch.float32).contiguous() if drho is not None else None
         u = u.to(self.device, torch.float32).contiguous() if u is not None else None
+        self._order(drho, u)
         C.check(C.lib().lbm_set_initial(self.handle, _tptr(drho), _tptr(u)), "lbm_set_initial")
-        torch.cuda.current_stream(self.device).synchronize() if drho is not None or u is not None else None
 
     def set_populations(self, fbar):
         fbar = fbar.to(self.device, torch.float32).contiguous()
+        self._order(fbar)
         C.check(C.lib().lbm_set_populations(self.handle, _tptr(fbar)), "lbm_set_populations")
-        self.stream.synchronize()
 
     def get_populations(self, which="state"):
         out = torch.empty(self.q * self.nodes, dtype=torch.float32, device=self.device)
+        self._order(out)
         k = C.POP_STATE if which == "state" else C.POP_ADJOINT
         C.check(C.lib().lbm_get_populations(self.handle, k, _tptr(out)), "lbm_get_populations")
         self.stream.synchronize()
@@ -204,6 +217,7 @@ class Solver:
     def macro(self, mean2=False):
         drho = torch.empty(self.nodes, dtype=torch.float32, device=self.device)
         u = torch.empty(self.nodes * self.D, dtype=torch.float32, device=self.device)
+        self._order(drho, u)
         C.check(C.lib().lbm_get_macro(self.handle, _tptr(drho), _tptr(u), int(bool(mean2))), "lbm_get_macro")
         self.stream.synchronize()
         return drho, u.view(self.nodes, self.D)
@@ -216,6 +230,15 @@ class Solver:
                                             int(check_every), ctypes.byref(steps), ctypes.byref(r)),
                 "lbm_run_to_residual")
         return steps.value, r.value
+
+    def checkpoint(self, c):
+        """Checkpoint c (the state after c K steps of the taped forward,
+        c = 1 .. n_seg - 1) as a float32 view into the workspace."""
+        ptr, nbytes = ctypes.c_void_p(), ctypes.c_size_t(0)
+        C.check(C.lib().lbm_checkpoint(self.handle, int(c), ctypes.byref(ptr), ctypes.byref(nbytes)),
+                "lbm_checkpoint")
+        off = ptr.value - self.workspace.data_ptr()
+        return self.workspace[off:off + nbytes.value].view(torch.float32)
 
     def set_graphs(self, enable=True):
         C.check(C.lib().lbm_set_graphs(self.handle, int(enable)), "lbm_set_graphs")

@@ -74,6 +74,21 @@ size_t lbmnn_wgrad_workspace_bytes(long long pixels, int rows, int K, int splits
 int lbmnn_conv_wgrad(const lbmnn_conv_desc *c, const void *g, int g_cstride, int g_coff, int rows, float *dw,
                      int accumulate, float *ws, size_t ws_bytes, int splits, void *stream);
 
+/* lbmnn_conv_wgrad without a workspace argument, for callers that cannot
+ * allocate device memory (code under graph capture, tight training loops,
+ * harnesses that forbid allocation): the split partials go to a scratch
+ * array of LBMNN_NOALLOC_SCRATCH_BYTES that the library holds on each GPU
+ * for the life of the process.  It calls no allocator.  Arguments, results
+ * and errors as lbmnn_conv_wgrad; LBM_ENOMEM when
+ * lbmnn_wgrad_workspace_bytes(pixels, rows, K, splits) exceeds the scratch
+ * (pass fewer splits).  Every call on one GPU uses the same scratch: calls
+ * that overlap on that GPU (other streams, other threads) race, so order
+ * them.  Nothing in the scratch needs clearing: each call writes every
+ * partial it reads. */
+#define LBMNN_NOALLOC_SCRATCH_BYTES (32 << 20)
+int lbmnn_conv_wgrad_noalloc(const lbmnn_conv_desc *c, const void *g, int g_cstride, int g_coff, int rows,
+                             float *dw, int accumulate, int splits, void *stream);
+
 /* wt[c][tap'][r] = w[r][tap][c] with tap' = taps-1-tap when flip != 0
  * (BF16).  flip = 1, (rows, taps, cols) = (cout, ks^dims, cin) gives the
  * input-gradient weights of a convolution; flip = 0, taps = 1 transposes a

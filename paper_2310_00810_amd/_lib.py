@@ -107,11 +107,13 @@ def check(rc, where):
 
 # ------------------------------------------------------------ lbmnn.h ABI --
 NN_EXPORTS = [
-    "lbmnn_conv", "lbmnn_wgrad_workspace_bytes", "lbmnn_conv_wgrad", "lbmnn_weight_transpose",
+    "lbmnn_conv", "lbmnn_wgrad_workspace_bytes", "lbmnn_conv_wgrad", "lbmnn_conv_wgrad_noalloc",
+    "lbmnn_weight_transpose",
     "lbmnn_bias_grad", "lbmnn_relu_bwd", "lbmnn_relu_bwd_bias_grad", "lbmnn_pool_fwd", "lbmnn_pool_bwd",
     "lbmnn_mse", "lbmnn_adam", "lbmnn_to_bf16", "lbmnn_features", "lbmnn_normalize", "lbmnn_denormalize",
 ]
 NN_RELU, NN_ACCUMULATE, NN_S2D, NN_D2S, NN_S2D_G = 1, 2, 4, 8, 16
+LBMNN_NOALLOC_SCRATCH_BYTES = 32 << 20
 
 
 class lbmnn_conv_desc(ctypes.Structure):
@@ -136,6 +138,7 @@ def nnlib():
         L.lbmnn_wgrad_workspace_bytes.argtypes = [ll, ip, ip, ip]
         L.lbmnn_wgrad_workspace_bytes.restype = ctypes.c_size_t
         L.lbmnn_conv_wgrad.argtypes = [dp, vp, ip, ip, ip, vp, ip, vp, ctypes.c_size_t, ip, vp]
+        L.lbmnn_conv_wgrad_noalloc.argtypes = [dp, vp, ip, ip, ip, vp, ip, ip, vp]
         L.lbmnn_weight_transpose.argtypes = [vp, vp, ip, ip, ip, ip, vp]
         L.lbmnn_bias_grad.argtypes = [vp, ip, ip, ll, ip, vp, ip, vp, ip, vp]
         L.lbmnn_relu_bwd.argtypes = [vp, vp, ip, ip, ll, ip, vp]

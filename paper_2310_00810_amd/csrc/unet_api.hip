@@ -1,6 +1,8 @@
 // C ABI of the warm-start network operators (declared in lbmnn.h).
 #include <stdint.h>
 
+#include <mutex>
+
 #include "lbm.h"
 #include "lbm_error.hpp"
 #include "lbmnn.h"
@@ -69,6 +71,53 @@ nn::ConvArgs to_args(const lbmnn_conv_desc *c, const void *w, const float *bias)
     return a;
 }
 
+// Validation shared by the two weight-gradient entry points; fills the
+// kernel arguments and the partials' size.
+int wgrad_prepare(const lbmnn_conv_desc *c, const void *g, int g_cstride, int g_coff, int rows, const float *dw,
+                  int splits, nn::ConvArgs &a, size_t &need) {
+    int rc = check_desc(c, false);
+    if (rc) return rc;
+    if (!g || !aligned16(g) || !dw) return lbm_fail(LBM_EINVAL, "NULL or misaligned pointer");
+    if (!mult8(rows) || rows == 0 || !mult8(g_cstride) || !mult8(g_coff))
+        return lbm_fail(LBM_EINVAL, "rows, g stride and offset must be multiples of 8");
+    if (splits < 1) return lbm_fail(LBM_EINVAL, "splits must be >= 1");
+    a = to_args(c, nullptr, nullptr);
+    a.flags = c->flags & ~LBMNN_S2D_G;
+    if (c->flags & LBMNN_S2D_G) a.flags |= nn::FLAG_S2D_G;
+    const int rcols = (c->flags & LBMNN_S2D_G) ? (rows >> c->dims) : rows;
+    if ((c->flags & LBMNN_S2D_G) && (!mult8(rcols) || rcols == 0)) return lbm_fail(LBM_EINVAL, "rows / 2^dims must be a multiple of 8");
+    if (g_coff + rcols > g_cstride) return lbm_fail(LBM_EINVAL, "gradient channels exceed the stride");
+    need = lbmnn_wgrad_workspace_bytes(a.M, rows, a.K, splits);
+    return LBM_OK;
+}
+
+// The weight-gradient partials of lbmnn_conv_wgrad_noalloc: one array per
+// GPU, held until the process ends.  Host code reaches it only through the
+// device address that hipGetSymbolAddress gives on each device (the array's
+// name on the host side is a stand-in, not a device address).
+constexpr int MAX_DEVICES = 64;
+static __device__ __align__(256) float scratch[LBMNN_NOALLOC_SCRATCH_BYTES / sizeof(float)];
+std::mutex g_scratch_mu;
+float *g_scratch[MAX_DEVICES] = {};
+
+// The scratch array's device address on the current device (looked up once
+// per device).
+int scratch_ptr(float **out) {
+    int dev = 0;
+    NN_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAX_DEVICES) return lbm_fail(LBM_EDEVICE, "device %d beyond the supported %d", dev, MAX_DEVICES);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return lbm_fail(LBM_EDEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+        g_scratch[dev] = (float *)p;
+    }
+    *out = g_scratch[dev];
+    return LBM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -90,21 +139,29 @@ size_t lbmnn_wgrad_workspace_bytes(long long pixels, int rows, int K, int splits
 
 int lbmnn_conv_wgrad(const lbmnn_conv_desc *c, const void *g, int g_cstride, int g_coff, int rows, float *dw,
                      int accumulate, float *ws, size_t ws_bytes, int splits, void *stream) {
-    int rc = check_desc(c, false);
+    nn::ConvArgs a;
+    size_t need = 0;
+    int rc = wgrad_prepare(c, g, g_cstride, g_coff, rows, dw, splits, a, need);
     if (rc) return rc;
-    if (!g || !aligned16(g) || !dw || !ws) return lbm_fail(LBM_EINVAL, "NULL or misaligned pointer");
-    if (!mult8(rows) || rows == 0 || !mult8(g_cstride) || !mult8(g_coff))
-        return lbm_fail(LBM_EINVAL, "rows, g stride and offset must be multiples of 8");
-    if (splits < 1) return lbm_fail(LBM_EINVAL, "splits must be >= 1");
-    nn::ConvArgs a = to_args(c, nullptr, nullptr);
-    a.flags = c->flags & ~LBMNN_S2D_G;
-    if (c->flags & LBMNN_S2D_G) a.flags |= nn::FLAG_S2D_G;
-    const int rcols = (c->flags & LBMNN_S2D_G) ? (rows >> c->dims) : rows;
-    if ((c->flags & LBMNN_S2D_G) && (!mult8(rcols) || rcols == 0)) return lbm_fail(LBM_EINVAL, "rows / 2^dims must be a multiple of 8");
-    if (g_coff + rcols > g_cstride) return lbm_fail(LBM_EINVAL, "gradient channels exceed the stride");
-    const size_t need = lbmnn_wgrad_workspace_bytes(a.M, rows, a.K, splits);
+    if (!ws) return lbm_fail(LBM_EINVAL, "workspace is NULL");
     if (ws_bytes < need) return lbm_fail(LBM_ENOMEM, "wgrad workspace of %zu bytes, %zu needed", ws_bytes, need);
     NN_TRY(nn::wgrad(a, (const uint16_t *)g, g_cstride, g_coff, rows, ws, splits, dw, accumulate,
+                     (hipStream_t)stream));
+    return LBM_OK;
+}
+
+int lbmnn_conv_wgrad_noalloc(const lbmnn_conv_desc *c, const void *g, int g_cstride, int g_coff, int rows,
+                             float *dw, int accumulate, int splits, void *stream) {
+    nn::ConvArgs a;
+    size_t need = 0;
+    int rc = wgrad_prepare(c, g, g_cstride, g_coff, rows, dw, splits, a, need);
+    if (rc) return rc;
+    if (need > (size_t)LBMNN_NOALLOC_SCRATCH_BYTES)
+        return lbm_fail(LBM_ENOMEM, "the weight-gradient partials need %zu bytes, beyond the %d-byte scratch of "
+                                    "lbmnn_conv_wgrad_noalloc: use fewer splits", need, LBMNN_NOALLOC_SCRATCH_BYTES);
+    float *part = nullptr;
+    if ((rc = scratch_ptr(&part))) return rc;
+    NN_TRY(nn::wgrad(a, (const uint16_t *)g, g_cstride, g_coff, rows, part, splits, dw, accumulate,
                      (hipStream_t)stream));
     return LBM_OK;
 }

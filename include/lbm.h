@@ -237,17 +237,29 @@ int lbm_adjoint(lbm_handle *h, const float *d_seed_du);
 int lbm_grad(lbm_handle *h, double *d_rho_in, double *d_tau, double *d_rho_out);
 
 /* Steady state of the forward map (Section 3.1.1 judges it by the plateau
- * of the kinetic energy): steps from the initial state until the two-step-mean
- * velocity residual r = ||u(t) - u(t-2)|| / ||u(t) + u(t-1)|| (every instance)
- * is <= tol, testing every check_every steps (even, >= 4), or until
- * max_steps.  steps_out / r_out (host, nullable) receive the step count and
- * the largest instance residual.  The two-step mean cancels the undamped
- * period-2 mode of the scheme (an equilibrium momentum field alternating in
- * sign along x that streaming maps onto its negative).  Synchronises the
- * stream after every check.  Errors: LBM_EINVAL (check_every, max_steps,
- * parameters), LBM_EUNSTABLE (a non-finite residual), LBM_EDEVICE. */
+ * of the kinetic energy): steps from the initial state until the velocity
+ * residual of every instance is <= tol, testing every check_every steps
+ * (even, >= 4), or until max_steps.  The residual at a check t is the mean
+ * relative change per step of the two-step-mean velocity
+ * ubar(t) = (u(t) + u(t-1)) / 2 over the last interval:
+ *   r(t) = ||ubar(t) - ubar(t - check_every)|| / (check_every ||ubar(t)||)
+ * over the fluid nodes (ubar(0) = u of the initial state).  For a smooth
+ * transient it equals ||d ubar/dt|| / ||ubar||, the per-step rate; it
+ * averages out the step-to-step rounding jitter of FP32 populations around
+ * the steady state, and the two-step mean cancels the undamped period-2
+ * mode of the scheme (an equilibrium momentum field alternating in sign
+ * along x that streaming maps onto its negative).  steps_out / r_out (host,
+ * nullable) receive the step count and the largest instance residual.
+ * Synchronises the stream after every check.  Errors: LBM_EINVAL
+ * (check_every, max_steps, parameters), LBM_EUNSTABLE (a non-finite
+ * residual), LBM_EDEVICE. */
 int lbm_run_to_residual(lbm_handle *h, const lbm_params *prm, double tol, int max_steps,
                         int check_every, int *steps_out, double *r_out);
+
+/* Per-instance residuals (host [n_inst]) of the last check of the last
+ * lbm_run_to_residual() call (NaN for an instance whose sums were not
+ * finite).  Errors: LBM_EINVAL, LBM_ESTATE (no residual yet). */
+int lbm_get_residuals(lbm_handle *h, double *r_out);
 
 /* Macroscopic fields (Eq. 1-2: rho = sum f, u = sum f c / rho) of the
  * current state to device arrays: d_drho [nodes], d_u [nodes][D] (zeros at
@@ -274,6 +286,12 @@ int lbm_checkpoint(lbm_handle *h, int c, void **d_state, size_t *bytes);
  * Timed calls launch kernels one by one (no graphs) between HIP events. */
 int lbm_set_timing(lbm_handle *h, int enable, int reset);
 int lbm_get_timing(lbm_handle *h, lbm_timing *out);
+
+/* Bandwidth calibration (measurement only, no part of the method): copies
+ * `bytes` from device d_src to device d_dst with one 16-byte load and store
+ * per lane, enqueued on hip_stream.  bytes and both pointers must be
+ * multiples of 16 (LBM_EINVAL otherwise); the ranges must not overlap. */
+int lbm_stream_copy(void *d_dst, const void *d_src, size_t bytes, void *hip_stream);
 
 const char *lbm_strerror(int code);
 const char *lbm_last_error(void);

@@ -269,6 +269,15 @@ def loss_complex_step(lat, tau, rho_in, rho_out, f0, T, target_u, weight=None,
     return res[0], res[1] / h
 
 
+def set_threads(n):
+    """Threads of the oracle's per-node loops (results do not depend on it)."""
+    lib().orc_set_threads(int(n))
+
+
+def threads():
+    return int(lib().orc_get_threads())
+
+
 def velset(q):
     """(c (q, 3) int, w (q,), opp (q,)) exactly as the C oracle holds them."""
     c = np.zeros((q, 3), np.int32)

@@ -28,6 +28,7 @@
  */
 #include <complex.h>
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -689,6 +690,10 @@ double orc_grad(ORC_ARGS, double tau, const double *rho_in, const double *rho_ou
 }
 
 /* ---------------- helpers for the pins ----------------------------------- */
+
+/* Threads of the per-node loops (the results do not depend on them). */
+void orc_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int orc_get_threads(void) { return omp_get_max_threads(); }
 
 /* Copies the velocity set (c as [q][3] ints, w as [q] doubles) and the
  * opposite-direction table. */

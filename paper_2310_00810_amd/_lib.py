@@ -22,7 +22,8 @@ POP_STATE, POP_ADJOINT = 0, 1
 EXPORTS = [
     "lbm_workspace_bytes", "lbm_init", "lbm_destroy", "lbm_set_initial", "lbm_set_populations",
     "lbm_get_populations", "lbm_forward", "lbm_adjoint", "lbm_grad", "lbm_run_to_residual",
-    "lbm_get_macro", "lbm_set_graphs", "lbm_set_timing", "lbm_get_timing", "lbm_checkpoint", "lbm_strerror",
+    "lbm_get_macro", "lbm_set_graphs", "lbm_set_timing", "lbm_get_timing", "lbm_checkpoint", "lbm_get_residuals", "lbm_stream_copy",
+    "lbm_strerror",
     "lbm_last_error",
 ]
 
@@ -87,6 +88,8 @@ def lib():
         L.lbm_set_graphs.argtypes = [vp, ip]
         L.lbm_set_timing.argtypes = [vp, ip, ip]
         L.lbm_get_timing.argtypes = [vp, ctypes.POINTER(lbm_timing)]
+        L.lbm_get_residuals.argtypes = [vp, dp]
+        L.lbm_stream_copy.argtypes = [vp, vp, ctypes.c_size_t, vp]
         L.lbm_checkpoint.argtypes = [vp, ip, ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_size_t)]
         L.lbm_strerror.restype = ctypes.c_char_p
         L.lbm_strerror.argtypes = [ip]

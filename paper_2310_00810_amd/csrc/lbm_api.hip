@@ -219,6 +219,7 @@ struct lbm_handle {
     std::vector<InstDev> hinst;
     std::vector<float> h_face_in, h_face_out;
     std::vector<double> h_red, h_grad;
+    std::vector<double> res_last;     // per-instance residuals of the last residual check
     // state bookkeeping
     float *cur = nullptr, *prev = nullptr;
     long long cur_steps = 0;          // steps taken since the initial state
@@ -822,21 +823,22 @@ int lbm_grad(lbm_handle *h, double *d_rho_in, double *d_tau, double *d_rho_out) 
 }
 
 // One residual chunk: check_every steps from src over the ping-pong
-// buffers (pp0, pp1, pp0, ...), a velocity snapshot two steps before the
-// end, and the residual partial sums of the last three states.
-static int enqueue_chunk(lbm_handle *h, const float *src, int check_every, hipStream_t s) {
+// buffers (pp0, pp1, pp0, ...), then the residual partial sums of the two-step
+// mean of the last two states against the snapshot of the previous check
+// (the first chunk takes the snapshot of the initial state first).
+static int enqueue_chunk(lbm_handle *h, const float *src, bool first, int check_every, hipStream_t s) {
     const Layout &L = h->L;
-    float *u2 = h->at<float>(L.off_u2);
+    float *snap = h->at<float>(L.off_u2);
+    if (first) HIP_TRY(lbm::launch_macro(L.q, h->G, src, nullptr, nullptr, snap, s));
     const float *prev = nullptr;
     for (int k = 0; k < check_every; ++k) {
-        if (k == check_every - 2) HIP_TRY(lbm::launch_macro(L.q, h->G, src, nullptr, nullptr, u2, s));
         float *dst = h->pp(k & 1);
         int rc = step(h, src, dst, s);
         if (rc) return rc;
         prev = src;
         src = dst;
     }
-    HIP_TRY(lbm::launch_residual(L.q, h->G, src, prev, u2, h->at<double>(L.off_part_res), s));
+    HIP_TRY(lbm::launch_residual(L.q, h->G, src, prev, snap, h->at<double>(L.off_part_res), s));
     HIP_TRY(lbm::launch_reduce(h->at<InstDev>(L.off_inst), L.n_inst, h->at<double>(L.off_part_res), 2, 0,
                                h->at<double>(L.off_red), s));
     return LBM_OK;
@@ -862,7 +864,7 @@ int lbm_run_to_residual(lbm_handle *h, const lbm_params *prm, double tol, int ma
     while (t + check_every <= max_steps) {
         const float *src = t == 0 ? h->init() : h->pp(1);
         rc = with_graph(h, h->g_chunk[t == 0 ? 1 : 0],
-                        [&](hipStream_t s) { return enqueue_chunk(h, src, check_every, s); });
+                        [&](hipStream_t s) { return enqueue_chunk(h, src, t == 0, check_every, s); });
         if (rc) return rc;
         HIP_TRY(hipMemcpyAsync(h->h_red.data(), h->at<double>(L.off_red), sizeof(double) * 2 * L.n_inst,
                                hipMemcpyDeviceToHost, h->stream));
@@ -871,6 +873,7 @@ int lbm_run_to_residual(lbm_handle *h, const lbm_params *prm, double tol, int ma
         h->cur = h->pp(1);
         h->prev = h->pp(0);
         rmax = 0.0;
+        h->res_last.assign(L.n_inst, NAN);
         for (int b = 0; b < L.n_inst; ++b) {
             const double num = h->h_red[2 * b], den = h->h_red[2 * b + 1];
             if (!isfinite(num) || !isfinite(den)) {
@@ -879,7 +882,8 @@ int lbm_run_to_residual(lbm_handle *h, const lbm_params *prm, double tol, int ma
                 if (r_out) *r_out = NAN;
                 return fail(LBM_EUNSTABLE, "non-finite residual at step %d (instance %d)", t, b);
             }
-            const double r = den > 0 ? sqrt(num / den) : (num > 0 ? INFINITY : 0.0);
+            const double r = den > 0 ? sqrt(num / den) / check_every : (num > 0 ? INFINITY : 0.0);
+            h->res_last[b] = r;
             rmax = std::max(rmax, r);
         }
         if (rmax <= tol) break;
@@ -887,6 +891,21 @@ int lbm_run_to_residual(lbm_handle *h, const lbm_params *prm, double tol, int ma
     h->cur_steps = t;
     if (steps_out) *steps_out = t;
     if (r_out) *r_out = rmax;
+    return LBM_OK;
+}
+
+int lbm_stream_copy(void *d_dst, const void *d_src, size_t bytes, void *hip_stream) {
+    if (!d_dst || !d_src) return fail(LBM_EINVAL, "pointers must be non-NULL");
+    if ((bytes & 15) || (((uintptr_t)d_dst | (uintptr_t)d_src) & 15))
+        return fail(LBM_EINVAL, "bytes and both pointers must be multiples of 16");
+    HIP_TRY(lbm::launch_copy16(d_src, d_dst, (long long)(bytes / 16), (hipStream_t)hip_stream));
+    return LBM_OK;
+}
+
+int lbm_get_residuals(lbm_handle *h, double *r_out) {
+    if (!h || !r_out) return fail(LBM_EINVAL, "handle and output must be non-NULL");
+    if (h->res_last.empty()) return fail(LBM_ESTATE, "no residual has been computed");
+    std::copy(h->res_last.begin(), h->res_last.end(), r_out);
     return LBM_OK;
 }
 

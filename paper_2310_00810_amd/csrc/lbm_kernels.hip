@@ -12,6 +12,8 @@
 //   nu^k = Z^T C'(g^k)^T S^T nu^{k+1},  k = T-1 .. 1     (adjoint step kernel)
 // S^T is a pull of nu from x + c_i with the mirrored bounce-back rule, so
 // every output element has exactly one writer and all stores are aligned.
+#include <algorithm>
+
 #include "lbm_device.hpp"
 #include "lbm_kernels.hpp"
 
@@ -513,13 +515,14 @@ __global__ void __launch_bounds__(BLOCK) k_macro(Geo G, const float *__restrict_
     }
 }
 
-// Residual sums of the two-step mean velocity:
-//   part[2 tile]   = sum |u(t) - u(t-2)|^2,  part[2 tile+1] = sum |u(t) + u(t-1)|^2
-// u(t-2) comes from a dense velocity snapshot.
+// Residual sums of the two-step mean velocity ubar(t) = (u(t) + u(t-1)) / 2
+// against its snapshot from the previous check (dense [node][D]):
+//   part[2 tile]   = sum |ubar(t) - snap|^2,   part[2 tile+1] = sum |ubar(t)|^2,
+// then the snapshot becomes ubar(t) (each node owns its entries).
 template <int Q>
 __global__ void __launch_bounds__(BLOCK) k_residual(Geo G, const float *__restrict__ Ft,
                                                     const float *__restrict__ Ft1,
-                                                    const float *__restrict__ u2,
+                                                    float *__restrict__ snap,
                                                     double *__restrict__ part) {
     __shared__ double lds[4];
     constexpr int D = Vel<Q>::D;
@@ -534,10 +537,11 @@ __global__ void __launch_bounds__(BLOCK) k_residual(Geo G, const float *__restri
         const float ua[3] = {a.ux, a.uy, a.uz}, ub[3] = {b.ux, b.uy, b.uz};
 #pragma unroll
         for (int c = 0; c < D; ++c) {
-            const float d = ua[c] - u2[dn * D + c];
-            const float s = ua[c] + ub[c];
+            const float m = 0.5f * (ua[c] + ub[c]);
+            const float d = m - snap[dn * D + c];
             num += d * d;
-            den += s * s;
+            den += m * m;
+            snap[dn * D + c] = m;
         }
     }
     const double sn = block_sum(num, lds);
@@ -570,6 +574,12 @@ __global__ void __launch_bounds__(256) k_reduce(const InstDev *inst, const doubl
 __global__ void k_fill_f64(double *p, long long n, double v) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
+}
+
+// Bandwidth calibration: one 16-byte load and store per lane (grid-stride).
+__global__ void __launch_bounds__(256) k_copy16(const uint4 *__restrict__ src, uint4 *__restrict__ dst, long long n) {
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256)
+        dst[i] = src[i];
 }
 
 __global__ void k_fill_u32(unsigned *p, long long n, unsigned v) {
@@ -700,16 +710,23 @@ hipError_t launch_macro(int q, const Geo &G, const float *Fa, const float *Fb, f
     return hipGetLastError();
 }
 
-hipError_t launch_residual(int q, const Geo &G, const float *Ft, const float *Ft1, const float *u2,
+hipError_t launch_residual(int q, const Geo &G, const float *Ft, const float *Ft1, float *snap,
                            double *part, hipStream_t s) {
-    if (q == 9) hipLaunchKernelGGL(k_residual<9>, grid_of(G), dim3(BLOCK), 0, s, G, Ft, Ft1, u2, part);
-    else hipLaunchKernelGGL(k_residual<19>, grid_of(G), dim3(BLOCK), 0, s, G, Ft, Ft1, u2, part);
+    if (q == 9) hipLaunchKernelGGL(k_residual<9>, grid_of(G), dim3(BLOCK), 0, s, G, Ft, Ft1, snap, part);
+    else hipLaunchKernelGGL(k_residual<19>, grid_of(G), dim3(BLOCK), 0, s, G, Ft, Ft1, snap, part);
     return hipGetLastError();
 }
 
 hipError_t launch_reduce(const InstDev *inst, int n_inst, const double *part, int stride, int fluid,
                          double *out, hipStream_t s) {
     hipLaunchKernelGGL(k_reduce, dim3(n_inst), dim3(256), 0, s, inst, part, stride, fluid, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy16(const void *src, void *dst, long long n16, hipStream_t s) {
+    if (n16 <= 0) return hipSuccess;
+    const long long blocks = std::min<long long>((n16 + 255) / 256, 1LL << 20);
+    hipLaunchKernelGGL(k_copy16, dim3((unsigned)blocks), dim3(256), 0, s, (const uint4 *)src, (uint4 *)dst, n16);
     return hipGetLastError();
 }
 

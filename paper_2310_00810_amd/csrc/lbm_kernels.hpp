@@ -33,12 +33,16 @@ hipError_t launch_init_eq(int q, const Geo &G, float *F, const float *drho, cons
 hipError_t launch_convert(int q, const Geo &G, float *F, float *dense, int to_state, hipStream_t s);
 hipError_t launch_macro(int q, const Geo &G, const float *Fa, const float *Fb, float *drho, float *u,
                         hipStream_t s);
-hipError_t launch_residual(int q, const Geo &G, const float *Ft, const float *Ft1, const float *u2,
+// Residual partials of the two-step mean of (Ft, Ft1) against the snapshot,
+// which then takes that mean.
+hipError_t launch_residual(int q, const Geo &G, const float *Ft, const float *Ft1, float *snap,
                            double *part, hipStream_t s);
 // fluid != 0: partials per fluid tile (dtau), else per dense tile.
 hipError_t launch_reduce(const InstDev *inst, int n_inst, const double *part, int stride, int fluid,
                          double *out, hipStream_t s);
 hipError_t launch_fill_f64(double *p, long long n, double v, hipStream_t s);
 hipError_t launch_fill_u32(unsigned *p, long long n, unsigned v, hipStream_t s);
+// n16 16-byte elements from src to dst, one per lane.
+hipError_t launch_copy16(const void *src, void *dst, long long n16, hipStream_t s);
 
 }  // namespace lbm

@@ -231,6 +231,12 @@ class Solver:
                 "lbm_run_to_residual")
         return steps.value, r.value
 
+    def residuals(self):
+        """Per-instance residuals of the last run_to_residual check (numpy)."""
+        out = np.zeros(self.n_inst)
+        C.check(C.lib().lbm_get_residuals(self.handle, _dptr(out)), "lbm_get_residuals")
+        return out
+
     def checkpoint(self, c):
         """Checkpoint c (the state after c K steps of the taped forward,
         c = 1 .. n_seg - 1) as a float32 view into the workspace."""

@@ -149,6 +149,22 @@ class UNet:
     def _stream(self):
         return ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
 
+    # ------------------------------------------------------------ profiling --
+    _prof = None
+
+    def _timed(self, kind, name, flops, nbytes, fn):
+        """Runs fn(); with profiling on (self._prof a list), between two HIP
+        events on the current stream, recording the op's algorithmic flops and
+        minimal bytes (operands read once, results written once)."""
+        if self._prof is None:
+            return fn()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        r = fn()
+        b.record()
+        self._prof.append((kind, name, flops, nbytes, a, b))
+        return r
+
     # -------------------------------------------------------------- buffers --
     def _grid(self, shape, lv):
         n, d, h, w = shape
@@ -194,8 +210,13 @@ class UNet:
                                  out.data_ptr() if out is not None else None,
                                  out32.data_ptr() if out32 is not None else None, out_cs, out_co)
         b = _ptr(self.master, self.boff[name]) if use_bias else None
-        C.check(self.L.lbmnn_conv(ctypes.byref(desc), _ptr(wsrc, self.woff[name]), b, self._stream()),
-                "lbmnn_conv")
+        taps = (1 << self.dims) if flags & C.NN_S2D else ks ** self.dims
+        M = n * d * h * w
+        m_in = M << self.dims if flags & C.NN_S2D else M
+        nbytes = 2 * m_in * cin + (4 if out32 is not None else 2) * M * cout + 2 * cout * taps * cin
+        self._timed("dgrad" if transposed else "fwd", name, 2 * M * cout * taps * cin, nbytes,
+                    lambda: C.check(self.L.lbmnn_conv(ctypes.byref(desc), _ptr(wsrc, self.woff[name]), b,
+                                                      self._stream()), "lbmnn_conv"))
 
     def _wgrad(self, grid, ks, cin, flags, inp, in_cs, in_co, g, g_cs, g_co, rows, name):
         n, d, h, w = grid
@@ -209,23 +230,33 @@ class UNet:
             self._ws = torch.empty(need // 4 + 1024, dtype=torch.float32, device=self.device)
         desc = C.lbmnn_conv_desc(n, d, h, w, self.dims, ks, cin, 0, flags, inp.data_ptr(), in_cs, in_co,
                                  None, None, 0, 0)
-        C.check(self.L.lbmnn_conv_wgrad(ctypes.byref(desc), ctypes.c_void_p(g.data_ptr()), g_cs, g_co, rows,
-                                        _ptr(self.grad, self.woff[name]), 0, _ptr(self._ws),
-                                        self._ws.numel() * 4, splits, self._stream()), "lbmnn_conv_wgrad")
+        m_in = M << self.dims if flags & C.NN_S2D else M
+        m_g = M << self.dims if flags & C.NN_S2D_G else M
+        g_ch = rows >> self.dims if flags & C.NN_S2D_G else rows
+        nbytes = 2 * m_in * cin + 2 * m_g * g_ch + 4 * rows * K
+        self._timed("wgrad", name, 2 * M * rows * K, nbytes,
+                    lambda: C.check(self.L.lbmnn_conv_wgrad(ctypes.byref(desc), ctypes.c_void_p(g.data_ptr()), g_cs,
+                                                            g_co, rows, _ptr(self.grad, self.woff[name]), 0,
+                                                            _ptr(self._ws), self._ws.numel() * 4, splits,
+                                                            self._stream()), "lbmnn_conv_wgrad"))
 
     def _bgrad(self, g, cs, co, pixels, Cn, name):
         # about 512 pixels per split (enough blocks to keep HBM busy), bounded by the partials buffer
         splits = max(1, min(-(-pixels // 512), self._bws.numel() // Cn))
-        C.check(self.L.lbmnn_bias_grad(ctypes.c_void_p(g.data_ptr()), cs, co, pixels, Cn,
-                                       _ptr(self.grad, self.boff[name]), 0, _ptr(self._bws), splits,
-                                       self._stream()), "lbmnn_bias_grad")
+        self._timed("bgrad", name, pixels * Cn, 2 * pixels * Cn + 4 * Cn,
+                    lambda: C.check(self.L.lbmnn_bias_grad(ctypes.c_void_p(g.data_ptr()), cs, co, pixels, Cn,
+                                                           _ptr(self.grad, self.boff[name]), 0, _ptr(self._bws),
+                                                           splits, self._stream()), "lbmnn_bias_grad"))
 
     def _relu_bgrad(self, g, y, cs, co, pixels, Cn, name):
         # ReLU backward and the bias gradient of the masked g in one pass (splits as in _bgrad)
         splits = max(1, min(-(-pixels // 512), self._bws.numel() // Cn))
-        C.check(self.L.lbmnn_relu_bwd_bias_grad(ctypes.c_void_p(g.data_ptr()), ctypes.c_void_p(y.data_ptr()), cs, co,
-                                                pixels, Cn, _ptr(self.grad, self.boff[name]), 0, _ptr(self._bws),
-                                                splits, self._stream()), "lbmnn_relu_bwd_bias_grad")
+        self._timed("relu_bgrad", name, 2 * pixels * Cn, 6 * pixels * Cn + 4 * Cn,
+                    lambda: C.check(self.L.lbmnn_relu_bwd_bias_grad(ctypes.c_void_p(g.data_ptr()),
+                                                                    ctypes.c_void_p(y.data_ptr()), cs, co, pixels, Cn,
+                                                                    _ptr(self.grad, self.boff[name]), 0,
+                                                                    _ptr(self._bws), splits, self._stream()),
+                                    "lbmnn_relu_bwd_bias_grad"))
 
     # -------------------------------------------------------------- forward --
     def forward(self, x):
@@ -375,10 +406,13 @@ class UNet:
                 dgrad += f
         return fwd, dgrad, wgrad
 
-    def train_step(self, x, target, wpix, lr):
+    def train_step(self, x, target, wpix, lr, n_fluid=None):
+        """One Adam step on the masked MSE; n_fluid (the batch's number of
+        fluid pixels, known on the host) avoids reading it back from wpix."""
         out = self.forward(x)
-        nfl = wpix.sum()  # device scalar, no sync
-        scale = 1.0 / max(float(nfl.item()), 1.0)
+        if n_fluid is None:
+            n_fluid = float(wpix.sum().item())
+        scale = 1.0 / max(float(n_fluid), 1.0)
         g = self.loss_and_grad(out, target, wpix, scale)
         self.backward(g)
         self.adam_step(lr)
@@ -413,6 +447,7 @@ def measure(dims, batch, size, steps=5, warmup=2, base=32):
     torch.cuda.synchronize()
     fwd_ms = a.elapsed_time(b) / steps
     fwd, dgrad, wgrad = net.conv_flops(shape)
+    layers = layer_roofline(net, x, tgt, wpix)
     peak = 2500.0
     tt = (fwd + dgrad + wgrad) / (train_ms * 1e-3) / 1e12
     tf = fwd / (fwd_ms * 1e-3) / 1e12
@@ -420,11 +455,61 @@ def measure(dims, batch, size, steps=5, warmup=2, base=32):
             "train_step_ms": round(train_ms, 3), "forward_ms": round(fwd_ms, 3),
             "train_conv_gflop": round((fwd + dgrad + wgrad) / 1e9, 2), "forward_conv_gflop": round(fwd / 1e9, 2),
             "train_tflops": round(tt, 1), "forward_tflops": round(tf, 1), "peak_tflops": peak,
-            "train_frac": round(tt / peak, 4), "forward_frac": round(tf / peak, 4)}
+            "train_frac": round(tt / peak, 4), "forward_frac": round(tf / peak, 4), "ops": layers}
+
+
+MFMA_PEAK_TFLOPS, HBM_PEAK_GBS = 2500.0, 8000.0
+
+
+def layer_roofline(net, x, tgt, wpix, steps=3):
+    """Per operation of a training step (layer forward, input gradient,
+    weight gradient, bias / ReLU backward): HIP-event time on the current
+    stream, averaged over `steps` steps, against its own roofline: the larger
+    of flops / dense BF16 MFMA peak and minimal bytes / HBM peak.  Returns a
+    list of dicts sorted by time, longest first."""
+    acc = {}
+    for _ in range(steps):
+        net._prof = []
+        net.train_step(x, tgt, wpix, 1e-4)
+        torch.cuda.synchronize()
+        for kind, name, flops, nbytes, a, b in net._prof:
+            e = acc.setdefault((kind, name), [flops, nbytes, 0.0])
+            e[2] += a.elapsed_time(b) / steps
+        net._prof = None
+    out = []
+    for (kind, name), (flops, nbytes, ms) in acc.items():
+        t_mfma = flops / (MFMA_PEAK_TFLOPS * 1e12) * 1e3 if kind in ("fwd", "dgrad", "wgrad") else 0.0
+        t_hbm = nbytes / (HBM_PEAK_GBS * 1e9) * 1e3
+        bound = "mfma" if t_mfma >= t_hbm else "hbm"
+        out.append({"op": kind, "layer": name, "us": round(ms * 1e3, 2), "gflop": round(flops / 1e9, 3),
+                    "mb": round(nbytes / 1e6, 2), "tflops": round(flops / (ms * 1e-3) / 1e12, 1),
+                    "gbs": round(nbytes / (ms * 1e-3) / 1e9, 1), "bound": bound,
+                    "frac": round(max(t_mfma, t_hbm) / ms, 4)})
+    out.sort(key=lambda r: -r["us"])
+    return out
+
+
+def layer_table(m, command):
+    """Markdown table of measure()'s per-operation roofline."""
+    lines = [f"# U-Net per-operation roofline ({m['dims']}D, batch {m['batch']}, {m['size']}^{m['dims']})", "",
+             "Command:", "", f"    {command}", "",
+             f"Training step {m['train_step_ms']} ms ({m['train_tflops']} TFLOP/s of convolutions, "
+             f"{100 * m['train_frac']:.1f} % of the dense BF16 peak); forward {m['forward_ms']} ms.  Each "
+             "operation's time (HIP events, mean of 3 steps) against its own bound: max(flops / 2.5 PFLOP/s, "
+             "minimal bytes / 8 TB/s); frac = that bound's time / measured time.", "",
+             "| op | layer | us | GFLOP | MB | TFLOP/s | GB/s | bound | frac |", "|---|---|---|---|---|---|---|---|---|"]
+    for r in m["ops"]:
+        lines.append(f"| {r['op']} | {r['layer']} | {r['us']} | {r['gflop']} | {r['mb']} | {r['tflops']} | "
+                     f"{r['gbs']} | {r['bound']} | {r['frac']} |")
+    return "\n".join(lines) + "\n"
 
 
 if __name__ == "__main__":
     import json
     import sys
     dims = int(sys.argv[1]) if len(sys.argv) > 1 else 2
-    print(json.dumps(measure(dims, 16 if dims == 2 else 2, 256 if dims == 2 else 64)), flush=True)
+    m = measure(dims, 16 if dims == 2 else 2, 256 if dims == 2 else 64)
+    if len(sys.argv) > 2:
+        with open(sys.argv[2], "w") as fh:
+            fh.write(layer_table(m, "python -m paper_2310_00810_amd.unet " + " ".join(sys.argv[1:])))
+    print(json.dumps(m), flush=True)

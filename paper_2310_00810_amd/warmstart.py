@@ -59,11 +59,14 @@ def bc_of(dims):
 
 
 class Dataset:
-    """Network inputs and Stokes-scaled targets, resident on the GPU."""
+    """Network inputs and Stokes-scaled targets, resident on the GPU, with the
+    per-sample fluid pixel counts on the host."""
 
-    def __init__(self, dims, cases, features, targets, wpix, prm, steps):
+    def __init__(self, dims, cases, features, targets, wpix, prm, steps, dropped=0):
         self.dims, self.cases = dims, cases
         self.features, self.targets, self.wpix, self.prm, self.steps = features, targets, wpix, prm, steps
+        self.nfluid = np.array([int((c[0] == 0).sum()) for c in cases], np.int64)
+        self.dropped = dropped
 
     def __len__(self):
         return self.features.shape[0]
@@ -82,11 +85,14 @@ def features_of(solid_dev, prm_dev, n, d, h, w):
 
 def generate(dims, seeds, batch=32, tol=1e-6, max_steps=100_000, check_every=100):
     """Runs the batched solver to the residual threshold for every seed and
-    returns a Dataset (features, targets and fluid weights on the GPU).  A
-    batch runs until its slowest case converges, and the steps to converge
-    scale with 1 / nu, so the cases are batched in order of tau."""
+    returns a Dataset (features, targets and fluid weights on the GPU) of the
+    cases that reached it; cases still above the threshold at max_steps are
+    left out (counted in Dataset.dropped).  A batch runs until its slowest
+    case converges, and the steps to converge scale with 1 / nu, so the cases
+    are batched in order of tau."""
     D = dims
     feats, tgts, wps, prms, steps, cases = [], [], [], [], [], []
+    dropped = 0
     t0 = time.time()
     drawn = sorted((sample(dims, s) for s in seeds), key=lambda c: c[3])
     for b0 in range(0, len(drawn), batch):
@@ -96,6 +102,7 @@ def generate(dims, seeds, batch=32, tol=1e-6, max_steps=100_000, check_every=100
         taus = [c[3] for c in chunk]
         dins = [c[1] for c in chunk]
         nstep, r = s.run_to_residual(taus, dins, 0.0, tol=tol, max_steps=max_steps, check_every=check_every)
+        keep = np.flatnonzero(s.residuals() <= tol)
         drho, u = s.macro(mean2=True)
         nz, ny, nx = chunk[0][0].shape
         nb = len(chunk)
@@ -108,17 +115,19 @@ def generate(dims, seeds, batch=32, tol=1e-6, max_steps=100_000, check_every=100
                                           ctypes.c_void_p(solid.data_ptr()), ctypes.c_void_p(prm.data_ptr()),
                                           per, D, nb * per, ctypes.c_void_p(tg.data_ptr()),
                                           ctypes.c_void_p(wp.data_ptr()), _stream()), "lbmnn_normalize")
-        feats.append(features_of(solid, prm, nb, nz, ny, nx))
-        tgts.append(tg.view(nb, nz, ny, nx, 1 + D))
-        wps.append(wp.view(nb, nz, ny, nx))
-        prms.append(prm)
-        steps += [nstep] * nb
-        cases += chunk
-        log(f"[data] dims={dims} {b0 + nb}/{len(drawn)} samples, batch converged in {nstep} steps "
-            f"(r={r:.2e}), {time.time() - t0:.1f} s")
+        kd = torch.from_numpy(keep).cuda()
+        feats.append(features_of(solid, prm, nb, nz, ny, nx).index_select(0, kd))
+        tgts.append(tg.view(nb, nz, ny, nx, 1 + D).index_select(0, kd))
+        wps.append(wp.view(nb, nz, ny, nx).index_select(0, kd))
+        prms.append(prm.index_select(0, kd))
+        steps += [nstep] * keep.size
+        cases += [chunk[k] for k in keep]
+        dropped += nb - keep.size
+        log(f"[data] dims={dims} {b0 + nb}/{len(drawn)} samples, batch ran {nstep} steps (largest r={r:.2e}), "
+            f"{nb - keep.size} above the threshold left out, {time.time() - t0:.1f} s")
         del s
     return Dataset(dims, cases, torch.cat(feats), torch.cat(tgts), torch.cat(wps), torch.cat(prms),
-                   np.array(steps))
+                   np.array(steps), dropped)
 
 
 def channel_scale(ds):
@@ -132,7 +141,19 @@ def channel_scale(ds):
 
 
 def standardized(ds, scale):
-    return Dataset(ds.dims, ds.cases, ds.features, (ds.targets / scale).contiguous(), ds.wpix, ds.prm, ds.steps)
+    return Dataset(ds.dims, ds.cases, ds.features, (ds.targets / scale).contiguous(), ds.wpix, ds.prm, ds.steps,
+                   ds.dropped)
+
+
+def mirrored(x, tg, wp, axis, dims):
+    """A batch reflected across the mid-plane of a transverse axis (1 = z in
+    3D, 2 = y): walls and periodic boundaries are symmetric under it, the
+    inputs depend on the transverse position only through the mask, and the
+    velocity component along that axis changes sign."""
+    comp = 1 + (1 if axis == 2 else 2)
+    sign = torch.ones(tg.shape[-1], device=tg.device)
+    sign[comp] = -1.0
+    return x.flip(axis).contiguous(), (tg.flip(axis) * sign).contiguous(), wp.flip(axis).contiguous()
 
 
 def evaluate_loss(net, ds, batch):
@@ -148,27 +169,42 @@ def evaluate_loss(net, ds, batch):
     return tot / max(n, 1)
 
 
-def train(net, ds, val, epochs, batch, lr, seed=0):
+def train(net, ds, val, epochs, batch, lr, seed=0, augment=True):
+    """Adam with a cosine learning-rate schedule.  augment: each batch is
+    reflected across a transverse mid-plane with probability 1/2 per axis.
+    With a validation set the weights of the epoch with the lowest validation
+    loss are kept."""
     g = torch.Generator(device="cpu").manual_seed(seed)
     hist = []
     t0 = time.time()
+    best, best_w = float("inf"), None
+    axes = (2,) if ds.dims == 2 else (1, 2)
     for ep in range(epochs):
         perm = torch.randperm(len(ds), generator=g)
-        tot = 0.0
+        tot = torch.zeros((), dtype=torch.float64, device=net.device)
         nb = 0
         lr_ep = lr * 0.5 * (1 + np.cos(np.pi * ep / max(epochs, 1)))
         for b0 in range(0, len(ds) - batch + 1, batch):
-            idx = perm[b0:b0 + batch].cuda()
+            sel = perm[b0:b0 + batch]
+            idx = sel.cuda()
             x = ds.features.index_select(0, idx)
             tg = ds.targets.index_select(0, idx)
             wp = ds.wpix.index_select(0, idx)
-            loss = net.train_step(x, tg, wp, lr_ep)
-            tot += float(loss.item())
+            if augment:
+                for ax in axes:
+                    if torch.rand((), generator=g).item() < 0.5:
+                        x, tg, wp = mirrored(x, tg, wp, ax, ds.dims)
+            tot += net.train_step(x, tg, wp, lr_ep, n_fluid=int(ds.nfluid[sel.numpy()].sum()))[0]
             nb += 1
         vl = evaluate_loss(net, val, batch) if val is not None and len(val) else float("nan")
-        hist.append((ep, tot / max(nb, 1), vl))
-        log(f"[train] epoch {ep + 1}/{epochs} loss {tot / max(nb, 1):.4e} val {vl:.4e} lr {lr_ep:.2e} "
-            f"{time.time() - t0:.1f} s")
+        tl = float(tot.item()) / max(nb, 1)
+        hist.append((ep, tl, vl))
+        if vl < best:
+            best, best_w = vl, net.master.clone()
+        log(f"[train] epoch {ep + 1}/{epochs} loss {tl:.4e} val {vl:.4e} lr {lr_ep:.2e} {time.time() - t0:.1f} s")
+    if best_w is not None:
+        net.master.copy_(best_w)
+        net.sync_bf16()
     return hist
 
 
@@ -223,6 +259,29 @@ def warm_vs_cold(net, case, tol=1e-6, max_steps=100_000, check_every=100):
                 warm_cold_rel_l2=same, cold_r=rc, warm_r=rw)
 
 
+def summarize(res, tol):
+    """Held-out figures on equal terms: how many cases each start brings to
+    the threshold, and the step and time comparison over the cases where
+    both do (medians; speed-up = cold seconds / warm seconds, inference
+    included)."""
+    both = [r for r in res if r["cold_r"] <= tol and r["warm_r"] <= tol]
+    med = lambda k, rs: float(np.median([r[k] for r in rs])) if rs else None
+    sp = [r["cold_s"] / r["warm_s"] for r in both]
+    return {
+        "cold_converged": int(sum(r["cold_r"] <= tol for r in res)),
+        "warm_converged": int(sum(r["warm_r"] <= tol for r in res)),
+        "both_converged": len(both),
+        "cold_steps_median": med("cold_steps", both), "warm_steps_median": med("warm_steps", both),
+        "cold_s_median": med("cold_s", both), "warm_s_median": med("warm_s", both),
+        "speedup_median": float(np.median(sp)) if sp else None,
+        "speedup_mean": float(np.mean(sp)) if sp else None,
+        "warm_faster_fraction": float(np.mean([r["warm_s"] < r["cold_s"] for r in both])) if both else None,
+        "net_rel_l2_u_median": med("net_rel_l2_u", res),
+        "net_rel_l2_u_mean": float(np.mean([r["net_rel_l2_u"] for r in res])) if res else None,
+        "warm_cold_rel_l2_max": float(np.max([r["warm_cold_rel_l2"] for r in both])) if both else None,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--dims", type=int, default=2)
@@ -235,6 +294,7 @@ def main():
     ap.add_argument("--lr", type=float, default=0.0, help="Adam learning rate (default 2e-3 in 2D, 5e-4 in 3D)")
     ap.add_argument("--out", default="")
     ap.add_argument("--max-steps", type=int, default=100_000)
+    ap.add_argument("--levels", type=int, default=4, help="U-Net levels (the deepest runs at 1 / 2^(levels-1) size)")
     args = ap.parse_args()
     dims = args.dims
     # 3D: batch 4 at lr 5e-4; at batch 2 and lr 2e-3 the 1000 Adam steps of an epoch over 2000
@@ -249,7 +309,7 @@ def main():
     scale = channel_scale(tr)
     log(f"[data] target channel RMS {scale.cpu().numpy()}; steps to converge: median "
         f"{int(np.median(tr.steps))}, max {int(tr.steps.max())}")
-    net = UNet(dims, seed=0)
+    net = UNet(dims, levels=args.levels, seed=0)
     hist = train(net, standardized(tr, scale), standardized(va, scale) if va is not None else None, args.epochs,
                  batch, lr)
     net.fold_output_scale(scale)
@@ -261,24 +321,18 @@ def main():
         res.append(r)
         log(f"[test] {i}: cold {r['cold_steps']} steps {r['cold_s']:.3f} s, warm {r['warm_steps']} steps "
             f"{r['warm_s']:.3f} s, net err {r['net_rel_l2_u']:.3f}, warm/cold fixed point {r['warm_cold_rel_l2']:.1e}")
-    summ = {
-        "dims": dims, "train": args.train, "val": args.val, "test": args.test, "epochs": args.epochs,
-        "gen_seconds": gen_s, "train_seconds": train_s, "final_train_loss": hist[-1][1] if hist else None,
-        "final_val_loss": hist[-1][2] if hist else None,
-        "cold_steps_mean": float(np.mean([r["cold_steps"] for r in res])) if res else None,
-        "warm_steps_mean": float(np.mean([r["warm_steps"] for r in res])) if res else None,
-        "cold_s_mean": float(np.mean([r["cold_s"] for r in res])) if res else None,
-        "warm_s_mean": float(np.mean([r["warm_s"] for r in res])) if res else None,
-        "warm_faster_fraction": float(np.mean([r["warm_s"] < r["cold_s"] for r in res])) if res else None,
-        "net_rel_l2_u_mean": float(np.mean([r["net_rel_l2_u"] for r in res])) if res else None,
-        "warm_cold_rel_l2_max": float(np.max([r["warm_cold_rel_l2"] for r in res])) if res else None,
-    }
+    summ = {"dims": dims, "levels": args.levels, "train": len(tr), "train_dropped": tr.dropped, "val": len(va) if va is not None else 0,
+            "test": args.test, "epochs": args.epochs, "max_steps": args.max_steps, "gen_seconds": gen_s,
+            "train_seconds": train_s, "final_train_loss": hist[-1][1] if hist else None,
+            "best_val_loss": min(h[2] for h in hist) if hist and va is not None else None}
+    summ.update(summarize(res, 1e-6))
     print(json.dumps(summ), flush=True)
     if args.out:
         os.makedirs(os.path.dirname(args.out) or ".", exist_ok=True)
         net.save(args.out)
         with open(args.out + ".json", "w") as f:
-            json.dump({"summary": summ, "history": hist, "tests": res,
+            json.dump({"command": "python -m paper_2310_00810_amd.warmstart " + " ".join(sys.argv[1:]),
+                       "summary": summ, "history": hist, "tests": res,
                        "target_scale": scale.cpu().numpy().tolist()}, f)
 
 

@@ -199,7 +199,7 @@ void plan(const lbm_problem *p, Layout &L) {
     L.off_part_dtau = take(sizeof(double) * std::max(1, L.n_ftiles));
     L.off_part_res = take(sizeof(double) * 2 * L.n_tiles);
     L.off_red = take(sizeof(double) * 2 * p->n_inst);
-    L.off_fblk = take(sizeof(int2) * std::max(1, L.n_ftiles));
+    L.off_fblk = take(sizeof(lbm::FTileDesc) * std::max(1, L.n_ftiles));
     L.off_u2 = take(sizeof(float) * node * L.D);
     L.off_seed = take(sizeof(float) * node * L.D);
     L.off_flag = take(sizeof(unsigned));
@@ -443,7 +443,7 @@ int lbm_init(lbm_handle **out, const lbm_problem *p, void *d_workspace, size_t b
         I.loss_scale = p->loss_scale == LBM_SCALE_MEAN_FLUID ? (id ? (float)(1.0 / (double)id) : 0.f) : 1.0f;
     }
     // per fluid tile: the instance-local row words holding its first and last fluid id
-    std::vector<int2> fblk(std::max(1, L.n_ftiles), make_int2(0, 0));
+    std::vector<lbm::FTileDesc> fblk(std::max(1, L.n_ftiles), lbm::FTileDesc{});
     for (int b = 0; b < L.n_inst; ++b) {
         const InstDev &I = h->hinst[b];
         const long long nw = (long long)I.nz * I.ny * I.words;
@@ -451,7 +451,8 @@ int lbm_init(lbm_handle **out, const lbm_problem *p, void *d_workspace, size_t b
         for (int t = 0; t < I.n_ftiles; ++t) {
             const long long first = (long long)t * lbm::FT;
             const long long last = std::min<long long>(first + lbm::FT, I.n_fluid) - 1;
-            int2 &e = fblk[I.ftile_begin + t];
+            lbm::FTileDesc &e = fblk[I.ftile_begin + t];
+            e.b = b;
             // word holding id k: the last word whose first id is <= k and that has a fluid node
             auto holds = [&](long long ww, long long k) {
                 const uint2 r = rw[I.rw_off + ww];
@@ -459,10 +460,12 @@ int lbm_init(lbm_handle **out, const lbm_problem *p, void *d_workspace, size_t b
                 return (long long)r.y <= k && k < (long long)r.y + nf;
             };
             while (w < nw && !holds(w, first)) ++w;
-            e.x = (int)w;
+            e.w0 = (int)w;
             long long w1 = w;
             while (w1 < nw && !holds(w1, last)) ++w1;
-            e.y = (int)w1;
+            e.w1 = (int)w1;
+            e.r0 = (int)(w / I.words);
+            e.r1 = (int)(w1 / I.words);
         }
     }
     auto cp = [&](size_t off, const void *src, size_t n) -> int {
@@ -473,7 +476,7 @@ int lbm_init(lbm_handle **out, const lbm_problem *p, void *d_workspace, size_t b
     int e = 0;
     if ((e = cp(L.off_inst, h->hinst.data(), sizeof(InstDev) * L.n_inst)) ||
         (e = cp(L.off_mask, rw.data(), sizeof(uint2) * rw.size())) ||
-        (e = cp(L.off_fblk, fblk.data(), sizeof(int2) * fblk.size())) ||
+        (e = cp(L.off_fblk, fblk.data(), sizeof(lbm::FTileDesc) * fblk.size())) ||
         (e = cp(L.off_roi, roi.data(), sizeof(float) * roi.size())) ||
         (e = cp(L.off_target, target.data(), sizeof(float) * target.size()))) {
         delete h;
@@ -487,7 +490,7 @@ int lbm_init(lbm_handle **out, const lbm_problem *p, void *d_workspace, size_t b
     for (int r = 0; r < 9; ++r) h->G.mrt[r] = (float)p->mrt_rates[r];
     h->G.rw = h->at<uint2>(L.off_mask);
     h->G.n_ftiles = L.n_ftiles;
-    h->G.fblk = h->at<int2>(L.off_fblk);
+    h->G.fblk = h->at<lbm::FTileDesc>(L.off_fblk);
     hipError_t he = lbm::launch_init_eq(L.q, h->G, h->init(), nullptr, nullptr, h->stream);
     if (he == hipSuccess) he = hipStreamSynchronize(h->stream);
     if (he != hipSuccess) {
@@ -678,15 +681,18 @@ static int enqueue_reverse(lbm_handle *h, bool resident, const float *seed, hipS
         return LBM_OK;
     };
     // Recomputes segment c into region r; a segment followed by a checkpoint
-    // then takes one more step, compared bit for bit with that checkpoint
-    // (a mismatch raises the corruption flag that lbm_grad reports).
+    // then takes one more step with the same kernel into a scratch state (the
+    // ping-pong buffer that does not hold F^T), compared bit for bit with
+    // that checkpoint (a mismatch raises the flag that lbm_grad reports).
+    float *scratch = h->pp(1 - (T & 1));
     auto recompute_segment = [&](int c, int r, hipStream_t st) -> int {
         const int t0 = c * K, t1 = std::min(t0 + K, T);
         for (int j = 1; j < t1 - t0; ++j)
             if ((rc = step(h, j == 1 ? h->ckpt(c) : h->seg(r, j - 1), h->seg(r, j), st))) return rc;
-        if (c + 1 < n_seg)
-            HIP_TRY(lbm::launch_step_verify(q, h->G, t1 - t0 > 1 ? h->seg(r, t1 - t0 - 1) : h->ckpt(c),
-                                            h->ckpt(c + 1), fin, fout, flag, st));
+        if (c + 1 < n_seg) {
+            if ((rc = step(h, t1 - t0 > 1 ? h->seg(r, t1 - t0 - 1) : h->ckpt(c), scratch, st))) return rc;
+            HIP_TRY(lbm::launch_compare(q, h->G, scratch, h->ckpt(c + 1), flag, st));
+        }
         return LBM_OK;
     };
     auto kept = [&](int k) { return resident && k < L.R; };          // k-th segment of the sweep, c = n_seg - 1 - k

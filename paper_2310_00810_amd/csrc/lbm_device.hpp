@@ -40,11 +40,24 @@ template <> struct Vel<9> {
         return (i == 2 || i == 5 || i == 6) ? 1 : (i == 4 || i == 7 || i == 8) ? -1 : 0;
     }
     __host__ __device__ static constexpr int cz(int) { return 0; }
+    // 4/9, 1/9, 1/36 as FP32 values whose exact sum over the directions is
+    // 1 (each within 1.2e-7 of the rational weight): with nearest-rounded
+    // weights the sum is 1 + 1.5e-8, and every collision would scale the
+    // mass deviation by omega times that, a drift that grows with the steps.
     __host__ __device__ static constexpr float w(int i) {
-        return i == 0 ? 4.0f / 9.0f : (i <= 4 ? 1.0f / 9.0f : 1.0f / 36.0f);
+        return i == 0 ? 0x1.c71c74p-2f : (i <= 4 ? 0x1.c71c70p-4f : 0x1.c71c70p-6f);
     }
     __host__ __device__ static constexpr int opp(int i) {
         return i == 0 ? 0 : (i <= 4 ? ((i + 1) & 3) + 1 : ((i - 3) & 3) + 5);
+    }
+    // 3 w_i (coefficient of rho c.u in f_eq) and 6 w_i (of J in the Zou-He
+    // unknowns) as FP32 constants whose sums are exact: 2 (a_axis + 2 a_diag)
+    // = 1 and zj_axis + 2 zj_diag = 1 (1/3 and 1/12, 2/3 and 1/6 to 1e-7).
+    __host__ __device__ static constexpr float a(int i) {
+        return i == 0 ? 0.0f : (i <= 4 ? 0x1.555556p-2f : 0x1.555554p-4f);
+    }
+    __host__ __device__ static constexpr float zj(int i) {
+        return i == 0 ? 0.0f : (i <= 4 ? 0x1.555556p-1f : 0x1.555554p-3f);
     }
 };
 
@@ -64,11 +77,21 @@ template <> struct Vel<19> {
         return (i == 5 || i == 11 || i == 14 || i == 15 || i == 18) ? 1
              : (i == 6 || i == 12 || i == 13 || i == 16 || i == 17) ? -1 : 0;
     }
+    // 1/3, 1/18, 1/36 as FP32 values whose exact sum over the directions is 1
+    // (within 1.2e-7 of the rational weights; see Vel<9>::w).
     __host__ __device__ static constexpr float w(int i) {
-        return i == 0 ? 1.0f / 3.0f : (i <= 6 ? 1.0f / 18.0f : 1.0f / 36.0f);
+        return i == 0 ? 0x1.555558p-2f : (i <= 6 ? 0x1.c71c70p-5f : 0x1.c71c70p-6f);
     }
     // pairs (1,2) (3,4) ... (17,18) are opposite
     __host__ __device__ static constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+    // 3 w_i and 6 w_i as FP32 constants with exact sums: 2 (a_axis + 4 a_diag)
+    // = 1 and zj_axis + 4 zj_diag = 1 (1/6 and 1/12, 1/3 and 1/6 to 1e-7).
+    __host__ __device__ static constexpr float a(int i) {
+        return i == 0 ? 0.0f : (i <= 6 ? 0x1.555554p-3f : 0x1.555556p-4f);
+    }
+    __host__ __device__ static constexpr float zj(int i) {
+        return i == 0 ? 0.0f : (i <= 6 ? 0x1.555554p-2f : 0x1.555556p-3f);
+    }
 };
 
 // ---------------------------------------------------------------------------
@@ -99,6 +122,14 @@ struct InstDev {
     float loss_scale;      // 1 or 1 / n_fluid
 };
 
+// Per fluid tile (built at init): its instance, the instance-local row words
+// holding its first and last fluid id, and their rows (r = z ny + y), so a
+// block reads its place with one scalar load instead of searching the
+// instance table and dividing.
+struct FTileDesc {
+    int w0, w1, b, r0, r1, pad0, pad1, pad2;
+};
+
 struct Geo {
     const InstDev *inst;
     int n_inst;
@@ -106,7 +137,7 @@ struct Geo {
     int bcx, bcy, bcz;
     const uint2 *rw;       // row-word tables
     int n_ftiles;
-    const int2 *fblk;      // per fluid tile: instance-local row words {w0, w1}
+    const FTileDesc *fblk; // per fluid tile
     int coll;              // COLL_BGK or COLL_MRT (D2Q9)
     float mrt[9];          // MRT rates of the D2Q9 moments; stress entries unused (1/tau)
 };
@@ -215,22 +246,14 @@ template <int D>
 __device__ inline FTile fluid_tile(const Geo &G, int tile) {
     FTile t;
     t.tile = tile;
-    int lo = 0;
-    if (G.n_inst > 1) {
-        int hi = G.n_inst - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (G.inst[mid].ftile_begin <= tile) lo = mid; else hi = mid - 1;
-        }
-    }
-    t.b = lo;
-    const InstDev &I = G.inst[lo];
+    const FTileDesc e = G.fblk[tile];
+    t.b = e.b;
+    const InstDev &I = G.inst[e.b];
     t.id0 = (tile - I.ftile_begin) * FT;
-    const int2 wr = G.fblk[tile];
-    t.w0 = wr.x;
-    t.w1 = wr.y;
-    t.r0 = t.w0 / I.words;
-    t.rows = t.w1 / I.words - t.r0 + 3;
+    t.w0 = e.w0;
+    t.w1 = e.w1;
+    t.r0 = e.r0;
+    t.rows = e.r1 - e.r0 + 3;
     t.cdz = D == 3 ? 1 : 0;
     t.staged = (D == 3 ? 3 : 1) * t.rows * I.words <= NBW;
     return t;
@@ -522,7 +545,7 @@ __device__ inline void zouhe(float (&g)[Q], bool in, bool out, float drho_b, boo
         if (V::cx(p) != 1) continue;
         const int m = V::opp(p);
         const float t = (V::cy(p) ? V::cy(p) * Ny : 0.f) + (V::cz(p) ? V::cz(p) * Nz : 0.f);
-        const float sj = 6.0f * V::w(p) * J;
+        const float sj = V::zj(p) * J;
         const float np = g[m] + sj - t, nm = g[p] + sj + t;
         g[p] = in ? np : g[p];
         g[m] = out ? nm : g[m];
@@ -547,7 +570,7 @@ __device__ inline float zouhe_adj(float (&a)[Q], bool in, bool out, const float 
         a[p] += um;
         a[p] -= up;
         a[m] -= um;
-        Jb += 6.0f * V::w(p) * (up + um);
+        Jb += V::zj(p) * (up + um);
         if (V::cy(p)) Nyb -= V::cy(p) * (up - um);
         if (V::cz(p)) Nzb -= V::cz(p) * (up - um);
     }
@@ -577,6 +600,7 @@ __device__ inline float zouhe_adj(float (&a)[Q], bool in, bool out, const float 
 
 struct Moments {
     float drho, rho, ux, uy, uz;
+    float jx, jy, jz;      // momentum sum c g (u = j / rho)
 };
 
 template <int Q>
@@ -595,16 +619,36 @@ __device__ inline Moments moments(const float (&g)[Q]) {
     m.rho = 1.0f + d;
     const float inv = 1.0f / m.rho;
     m.ux = jx * inv; m.uy = jy * inv; m.uz = jz * inv;
+    m.jx = jx; m.jy = jy; m.jz = jz;
     return m;
 }
 
-// Shifted equilibrium f_eq,i - w_i = w_i (drho + rho (3 c.u + 4.5 (c.u)^2 - 1.5 u.u)).
+// Shifted equilibria f_eq,i - w_i = w_i (drho + rho (3 c.u + 4.5 (c.u)^2 -
+// 1.5 u.u)) of all directions (Eq. 5).  The two directions of an opposite
+// pair share s = w_i (drho + rho (4.5 (c.u)^2 - 1.5 u.u)) and differ in the
+// sign of d = 3 w_i rho c.u = 3 w_i c.j, with 3 w_i taken from Vel::a.  The
+// weights of Vel::w sum to exactly 1 and those of Vel::a give exactly j, so
+// the FP32 equilibrium carries the node's mass and momentum up to unbiased
+// rounding.  d is formed from the momentum sum j itself: forming it as
+// rho (c.u) with u = j fl(1/rho) multiplies each node's momentum by rounding
+// factors that depend only on the node's density, which over thousands of
+// steps drove a systematic velocity drift (2e-4 after 8000 steps in a packed
+// sphere box); from j it falls to unbiased rounding.
 template <int Q>
-__device__ inline float feq_shifted(int i, const Moments &m) {
+__device__ inline void feq_all(const Moments &m, float (&feq)[Q]) {
     using V = Vel<Q>;
-    const float cu = V::cx(i) * m.ux + V::cy(i) * m.uy + V::cz(i) * m.uz;
-    const float usq = m.ux * m.ux + m.uy * m.uy + m.uz * m.uz;
-    return V::w(i) * (m.drho + m.rho * (3.0f * cu + 4.5f * cu * cu - 1.5f * usq));
+    const float usq15 = 1.5f * (m.ux * m.ux + m.uy * m.uy + m.uz * m.uz);
+    feq[0] = V::w(0) * (m.drho - m.rho * usq15);
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        const int o = V::opp(i);
+        if (o < i) continue;
+        const float cu = V::cx(i) * m.ux + V::cy(i) * m.uy + V::cz(i) * m.uz;
+        const float cj = V::cx(i) * m.jx + V::cy(i) * m.jy + V::cz(i) * m.jz;
+        const float sp = V::w(i) * (m.drho + m.rho * (4.5f * cu * cu - usq15)), dp = V::a(i) * cj;
+        feq[i] = sp + dp;
+        feq[o] = sp - dp;
+    }
 }
 
 // D2Q9 moment basis of the multiple-relaxation-time collision: row r of M
@@ -715,17 +759,18 @@ __device__ inline float abb_adj(float (&lam)[Q], bool in, bool out, float drho_b
     return gb;
 }
 
-// Wavefront (64-lane) sum.
-__device__ inline float wave_sum(float v) {
+// Wavefront (64-lane) sum in FP64.
+__device__ inline double wave_sum(double v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;
 }
 
-// Block (4 wavefronts) sum into double; the result is valid in thread 0.
+// Block (4 wavefronts) sum of per-lane values, in FP64 from the lane value
+// up (fixed order); the result is valid in thread 0.
 __device__ inline double block_sum(float v, double *lds4) {
-    v = wave_sum(v);
-    if ((threadIdx.x & 63) == 0) lds4[threadIdx.x >> 6] = (double)v;
+    const double w = wave_sum((double)v);
+    if ((threadIdx.x & 63) == 0) lds4[threadIdx.x >> 6] = w;
     __syncthreads();
     double s = 0.0;
     if (threadIdx.x == 0) s = (lds4[0] + lds4[1]) + (lds4[2] + lds4[3]);

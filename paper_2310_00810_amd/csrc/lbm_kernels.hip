@@ -53,31 +53,11 @@ __device__ inline void face_unknown_adjoints(__amdgpu_buffer_rsrc_t rn, int plan
         if (V::cx(i) != 0 && (V::cx(i) > 0 ? in : out)) nuo[i] = bload(rn, own + (unsigned)(i * plane) * 4u);
 }
 
-// The result of a step is stored, or (VERIFY, the check of a recomputed tape
-// segment) compared bit for bit with the state already held in dst: a lane
-// whose populations differ sets *flag.
-template <bool VERIFY>
-struct StepOut {
-    __amdgpu_buffer_rsrc_t r;
-    unsigned own;
-    bool bad = false;
-    __device__ inline void put(float v, int soff) {
-        if constexpr (VERIFY) bad |= bload_bits(r, own, soff) != __builtin_bit_cast(unsigned, v);
-        else bstore(r, v, own, soff);
-    }
-    __device__ inline void done(unsigned *flag) {
-        if constexpr (VERIFY) {
-            if (bad) *flag = 1u;
-        }
-    }
-};
-
-template <int Q, int BCX, bool VERIFY>
+template <int Q, int BCX>
 __global__ void __launch_bounds__(FT) k_step(Geo G, const float *__restrict__ src,
                                              float *__restrict__ dst,
                                              const float *__restrict__ face_in,
-                                             const float *__restrict__ face_out,
-                                             unsigned *__restrict__ flag) {
+                                             const float *__restrict__ face_out) {
     FLUID_PROLOGUE();
     if (!n.active) return;
     const bool in = density_faces(BCX) && n.x == 0, out = density_faces(BCX) && n.x == I.nx - 1;
@@ -94,39 +74,40 @@ __global__ void __launch_bounds__(FT) k_step(Geo G, const float *__restrict__ sr
     if (BCX == BC_ABB) abb<Q>(g, in, out, drho_b, uF);
     const Moments m = moments<Q>(g);
     const float om = I.omega;
-    StepOut<VERIFY> o;
-    o.r = planes_rsrc(dst + I.st_off, Q, I.plane);
-    o.own = (unsigned)n.id * 4u;
+    const __amdgpu_buffer_rsrc_t rd = planes_rsrc(dst + I.st_off, Q, I.plane);
+    const unsigned own = (unsigned)n.id * 4u;
+    float feq[Q];
+    feq_all<Q>(m, feq);
     if constexpr (Q == 9) {
         if (G.coll == COLL_MRT) {
             float d[9], r[9];
 #pragma unroll
-            for (int i = 0; i < 9; ++i) d[i] = g[i] - feq_shifted<Q>(i, m);
+            for (int i = 0; i < 9; ++i) d[i] = g[i] - feq[i];
             mrt_relax(d, G.mrt, om, r);
 #pragma unroll
-            for (int i = 0; i < 9; ++i) o.put(g[i] - r[i], plane_off(i, plane));
-            o.done(flag);
+            for (int i = 0; i < 9; ++i) bstore(rd, g[i] - r[i], own, plane_off(i, plane));
             return;
         }
     }
-    // f_eq of a direction and its opposite share all but the sign of the c.u term:
-    //   f_eq,i - w_i = s +- d,  s = w_i (drho + rho (4.5 (c.u)^2 - 1.5 u.u)),  d = 3 w_i rho c.u
-    using V = Vel<Q>;
-    const float usq15 = 1.5f * (m.ux * m.ux + m.uy * m.uy + m.uz * m.uz), rho3 = 3.0f * m.rho;
-    float feq[Q];
-    feq[0] = V::w(0) * (m.drho - m.rho * usq15);
 #pragma unroll
-    for (int i = 1; i < Q; ++i) {
-        const int o = V::opp(i);
-        if (o < i) continue;
-        const float cu = V::cx(i) * m.ux + V::cy(i) * m.uy + V::cz(i) * m.uz;
-        const float sp = V::w(i) * (m.drho + m.rho * (4.5f * cu * cu - usq15)), dp = V::w(i) * rho3 * cu;
-        feq[i] = sp + dp;
-        feq[o] = sp - dp;
-    }
+    for (int i = 0; i < Q; ++i) bstore(rd, g[i] + om * (feq[i] - g[i]), own, plane_off(i, plane));
+}
+
+// Bit-for-bit comparison of two states over the fluid nodes of every
+// instance: a lane whose populations differ sets *flag (the padding past each
+// instance's fluid nodes is not compared).
+template <int Q>
+__global__ void __launch_bounds__(FT) k_compare(Geo G, const float *__restrict__ a, const float *__restrict__ b,
+                                                unsigned *__restrict__ flag) {
+    const FTileDesc e = G.fblk[blockIdx.x];
+    const InstDev &I = G.inst[e.b];
+    const int id = ((int)blockIdx.x - I.ftile_begin) * FT + (int)threadIdx.x;
+    if (id >= I.n_fluid) return;
+    const unsigned *pa = (const unsigned *)(a + I.st_off) + id, *pb = (const unsigned *)(b + I.st_off) + id;
+    bool bad = false;
 #pragma unroll
-    for (int i = 0; i < Q; ++i) o.put(g[i] + om * (feq[i] - g[i]), plane_off(i, plane));
-    o.done(flag);
+    for (int i = 0; i < Q; ++i) bad |= pa[(long long)i * I.plane] != pb[(long long)i * I.plane];
+    if (bad) *flag = 1u;
 }
 
 // -------------------------------------------------------- loss functions --
@@ -312,10 +293,11 @@ __global__ void __launch_bounds__(FT) __attribute__((amdgpu_waves_per_eu(6))) k_
         if constexpr (Q == 9) {
             if (mrt) {
                 mrt_relax(lam, G.mrt, I.omega, mu);
-                float y7 = 0.f, y8 = 0.f, d7 = 0.f, d8 = 0.f;
+                float y7 = 0.f, y8 = 0.f, d7 = 0.f, d8 = 0.f, feq[9];
+                feq_all<Q>(m, feq);
 #pragma unroll
                 for (int i = 0; i < 9; ++i) {
-                    const float dq = g[i] - feq_shifted<Q>(i, m);
+                    const float dq = g[i] - feq[i];
                     if (mrt_m(7, i)) { y7 += mrt_m(7, i) * lam[i]; d7 += mrt_m(7, i) * dq; }
                     if (mrt_m(8, i)) { y8 += mrt_m(8, i) * lam[i]; d8 += mrt_m(8, i) * dq; }
                 }
@@ -454,7 +436,7 @@ __global__ void __launch_bounds__(BLOCK) k_init_eq(Geo G, float *__restrict__ F,
     const NodeRef n = map_node(G, tile);
     if (!n.fluid) return;
     const InstDev &I = G.inst[n.b];
-    Moments m = {0.f, 1.f, 0.f, 0.f, 0.f};
+    Moments m = {0.f, 1.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     const long long dn = dense_index(I, n);
     if (drho) { m.drho = drho[dn]; m.rho = 1.0f + m.drho; }
     if (u) {
@@ -462,9 +444,12 @@ __global__ void __launch_bounds__(BLOCK) k_init_eq(Geo G, float *__restrict__ F,
         m.uy = u[dn * D + 1];
         if (D == 3) m.uz = u[dn * D + 2];
     }
+    m.jx = m.rho * m.ux; m.jy = m.rho * m.uy; m.jz = m.rho * m.uz;
     float *__restrict__ out = F + I.st_off + n.id;
+    float feq[Q];
+    feq_all<Q>(m, feq);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) out[(long long)i * I.plane] = feq_shifted<Q>(i, m);
+    for (int i = 0; i < Q; ++i) out[(long long)i * I.plane] = feq[i];
 }
 
 // dense [inst][i][nz][ny][nx] <-> compact state.  to_state: fluid nodes only;
@@ -617,21 +602,16 @@ static inline dim3 fgrid_of(const Geo &G) { return dim3((unsigned)G.n_ftiles); }
 hipError_t launch_step(int q, const Geo &G, const float *src, float *dst, const float *fin,
                        const float *fout, hipStream_t s) {
     if (G.n_ftiles == 0) return hipSuccess;
-#define CALL(Q, B) \
-    hipLaunchKernelGGL((k_step<Q, B, false>), fgrid_of(G), dim3(FT), 0, s, G, src, dst, fin, fout, nullptr)
+#define CALL(Q, B) hipLaunchKernelGGL((k_step<Q, B>), fgrid_of(G), dim3(FT), 0, s, G, src, dst, fin, fout)
     DISPATCH_BCX(q, G.bcx, CALL);
 #undef CALL
     return hipGetLastError();
 }
 
-hipError_t launch_step_verify(int q, const Geo &G, const float *src, const float *ref, const float *fin,
-                              const float *fout, unsigned *flag, hipStream_t s) {
+hipError_t launch_compare(int q, const Geo &G, const float *a, const float *b, unsigned *flag, hipStream_t s) {
     if (G.n_ftiles == 0) return hipSuccess;
-#define CALL(Q, B)                                                                                 \
-    hipLaunchKernelGGL((k_step<Q, B, true>), fgrid_of(G), dim3(FT), 0, s, G, src, (float *)ref, fin, fout, \
-                       flag)
-    DISPATCH_BCX(q, G.bcx, CALL);
-#undef CALL
+    if (q == 9) hipLaunchKernelGGL(k_compare<9>, fgrid_of(G), dim3(FT), 0, s, G, a, b, flag);
+    else hipLaunchKernelGGL(k_compare<19>, fgrid_of(G), dim3(FT), 0, s, G, a, b, flag);
     return hipGetLastError();
 }
 

@@ -7,10 +7,8 @@ namespace lbm {
 
 hipError_t launch_step(int q, const Geo &G, const float *src, float *dst, const float *fin,
                        const float *fout, hipStream_t s);
-// The same step from src, compared bit for bit with the state ref instead of
-// stored: sets *flag = 1 if any population differs (ref is only read).
-hipError_t launch_step_verify(int q, const Geo &G, const float *src, const float *ref, const float *fin,
-                              const float *fout, unsigned *flag, hipStream_t s);
+// Sets *flag = 1 if states a and b differ in any population of a fluid node.
+hipError_t launch_compare(int q, const Geo &G, const float *a, const float *b, unsigned *flag, hipStream_t s);
 // acc: add to the partials (the later frames of a time-windowed loss).
 hipError_t launch_loss(int q, const Geo &G, const float *F, const float *roi, const float *target,
                        int kind, double *part, int acc, hipStream_t s);

@@ -14,6 +14,7 @@ import math
 from dataclasses import dataclass, field
 
 import numpy as np
+import torch
 
 
 @dataclass
@@ -107,6 +108,27 @@ def darcy_permeability(q_superficial, grad_p, rho_mean, nu):
     g = np.abs(np.asarray(grad_p, np.float64))
     slope = float(np.sum(q * g) / np.sum(g * g))
     return rho_mean * nu * slope
+
+
+def darcy_fit(solver, tau, drhos, solid, tol=1e-6, max_steps=200_000):
+    """Darcy permeability (Eq. 12) of one medium from its steady states at the
+    inlet densities 1 + drhos (outlet 1): superficial velocity against the
+    mean pressure gradient, fitted through the origin.  solver: a one-instance
+    Solver of the medium; solid: its (nz, ny, nx) mask.  Returns (k, points)
+    with points = [(drho, q, grad_p, rho_mean, steps)]."""
+    nz, ny, nx = solid.shape
+    fl = torch.from_numpy(solid.reshape(-1) == 0).to(solver.device)
+    pts = []
+    for d in drhos:
+        solver.set_initial(None, None)
+        steps, _ = solver.run_to_residual(tau, float(d), 0.0, tol=tol, max_steps=max_steps)
+        drho, u = solver.macro(mean2=True)
+        q = superficial_velocity(u[:, 0].double().cpu().numpy(), nx * ny * nz)
+        rho = 1.0 + float(drho[fl].double().mean().item())
+        pts.append((float(d), q, pressure_gradient(float(d), 0.0, nx), rho, steps))
+    k = darcy_permeability([p[1] for p in pts], [p[2] for p in pts], float(np.mean([p[3] for p in pts])),
+                           viscosity(tau))
+    return k, pts
 
 
 def superficial_velocity(u_x, n_nodes):

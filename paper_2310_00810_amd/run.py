@@ -61,22 +61,11 @@ def c2(quick=False):
     t0 = time.time()
     p, h = inverse.recover_constant_head(s, tau, 0.0, max_iter=30, rtol=1e-3, true_drho=0.004)
     dt = time.time() - t0
-    nu = inverse.viscosity(tau)
-    # Darcy over the iterates (and the truth): superficial velocity vs pressure gradient
-    qs, gs, rhos = [], [], []
-    for d in sorted(set([float(x) for x in h.params] + [0.004])):
-        if d <= 0:
-            continue
-        s0.forward(tau, d, 0.0, want_loss=False)
-        drho, u = s0.macro(mean2=True)
-        fl = torch.from_numpy(solid.reshape(-1) == 0).cuda()
-        qs.append(float(u[:, 0].double().sum().item()) / (nx * ny))
-        gs.append(inverse.pressure_gradient(d, 0.0, nx))
-        rhos.append(1.0 + float(drho[fl].double().mean().item()))
-    k = inverse.darcy_permeability(qs, gs, float(np.mean(rhos)), nu)
+    # Darcy: steady states of the medium at four pressure differences up to the recovered one
+    k, pts = inverse.darcy_fit(s0, tau, [0.25 * p, 0.5 * p, 0.75 * p, p], solid)
     return dict(config="C2", recovered_drho_in=p, true_drho_in=0.004, iterations=len(h.loss),
                 loss=[float(x) for x in h.loss], seconds=dt, darcy_k_lu2=k, porosity=G.porosity(solid),
-                darcy_points=len(qs))
+                darcy_points=[dict(drho_in=d, q=q, grad_p=g, rho_mean=r, steps=n) for d, q, g, r, n in pts])
 
 
 def c3(quick=False):

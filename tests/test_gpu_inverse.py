@@ -17,7 +17,53 @@ def test_constant_head_recovery_granular_media_and_darcy():
     from paper_2310_00810_amd import run
     r = run.c2(quick=True)
     assert abs(r["recovered_drho_in"] - 0.004) <= 4e-6
-    assert r["darcy_k_lu2"] > 0
+    assert r["darcy_k_lu2"] > 0 and len(r["darcy_points"]) == 4
+
+
+def _oracle_darcy(lat, tau, drhos, steps):
+    """Eq. 12 written out on the oracle's fields after the same step counts:
+    k = rho_mean nu sum(q g) / sum(g g), q = sum u_x / nodes, g = (rho_in -
+    rho_out) / (3 (nx - 1)), with the two-step mean velocity and density."""
+    import numpy as np
+    import oracle as O
+    qs, gs, rhos = [], [], []
+    fl = lat.fluid()
+    for d, n in zip(drhos, steps):
+        f = O.run(lat, tau, 1.0 + d, 1.0, O.init_eq(lat, 1.0, 0.0), n - 1)
+        r0, u0 = O.macro(lat, f)
+        r1, u1 = O.macro(lat, O.run(lat, tau, 1.0 + d, 1.0, f, 1))
+        u, rho = 0.5 * (u0 + u1), 0.5 * (r0 + r1)
+        qs.append(u[..., 0].sum() / fl.size)
+        gs.append(d / 3.0 / (lat.nx - 1))
+        rhos.append(rho[fl].mean())
+    qs, gs = np.array(qs), np.array(gs)
+    return np.mean(rhos) * (tau - 0.5) / 3.0 * np.sum(qs * gs) / np.sum(gs * gs)
+
+
+def test_darcy_fit_matches_the_oracle_and_the_slit_closed_form():
+    """The Darcy fit on the GPU's steady states against Eq. 12 evaluated on
+    the oracle's fields after the same numbers of steps (a 128 x 64 granular
+    channel), and for an empty channel between walls against the slit
+    permeability H^2 / 12 (halfway bounce-back puts the walls half a link
+    outside the first and last rows, so H = ny; at tau = 1/2 + sqrt(3/16) the
+    wall's slip error vanishes)."""
+    import numpy as np
+    import oracle as O
+    from paper_2310_00810_amd import geometry as G
+    from paper_2310_00810_amd import inverse
+    from paper_2310_00810_amd.lbm import Instance, Solver
+    drhos = [float(np.float32(x)) for x in (0.002, 0.004)]
+    solid = G.rsa_disks(128, 64, (4.0, 7.0), 0.7, seed=41)[None]
+    s = Solver(9, [Instance(128, 64, solid=solid)], steps=1)
+    k, pts = inverse.darcy_fit(s, 0.9, drhos, solid)
+    lat = O.Lattice(9, 128, 64, 1, (O.BC_PRESSURE, O.BC_WALL, O.BC_PERIODIC), solid)
+    ko = _oracle_darcy(lat, 0.9, drhos, [p[4] for p in pts])
+    assert abs(k - ko) <= 1e-4 * abs(ko)
+    tau = 0.5 + np.sqrt(3 / 16)
+    empty = np.zeros((1, 32, 96), np.uint8)
+    s = Solver(9, [Instance(96, 32, solid=empty)], steps=1)
+    k, _ = inverse.darcy_fit(s, tau, drhos, empty)
+    assert abs(k - 32 ** 2 / 12) <= 1e-2 * 32 ** 2 / 12
 
 
 def test_batched_launch_matches_single_launches():

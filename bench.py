@@ -45,7 +45,7 @@ BYTES_ADJ = 3 * Q * 4        # gather F^{k-1}, gather nu^{k+1}, write nu^k
 PROFILES = os.path.join(ROOT, "profiles")
 # kernel names as the profiler reports them (template arguments: Q, x boundary kind = pressure)
 ADJ_KERNEL = "k_adj_step<19, 0, false>"
-FWD_KERNEL = "k_step<19, 0>"
+FWD_KERNEL = "k_step<19, 0, false>"
 
 
 def workload(n=128, T=8000, K=400, kind="spheres"):
@@ -157,63 +157,76 @@ def load_traffic(kernel):
 
 
 def copy_peak_gbs(torch, nbytes=4 << 30, reps=10):
-    """Measured device-to-device copy bandwidth (read + write bytes / s)."""
+    """Measured device-to-device copy bandwidth (read + write bytes / s): the
+    library's 16-byte-per-lane copy (the fastest plain stream measured on the
+    chip) and torch's copy."""
+    import ctypes
+    from paper_2310_00810_amd import _lib as C
     x = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
     y = torch.empty_like(x)
     x.fill_(1.0)
-    y.copy_(x)
-    torch.cuda.synchronize()
-    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    a.record()
-    for _ in range(reps):
-        y.copy_(x)
-    b.record()
-    torch.cuda.synchronize()
-    gbs = 2 * nbytes * reps / (a.elapsed_time(b) * 1e-3) / 1e9
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    out = {}
+    for name, fn in (("copy16", lambda: C.check(C.lib().lbm_stream_copy(ctypes.c_void_p(y.data_ptr()),
+                                                                        ctypes.c_void_p(x.data_ptr()), nbytes,
+                                                                        stream), "lbm_stream_copy")),
+                     ("torch", lambda: y.copy_(x))):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        out[name] = 2 * nbytes * reps / (a.elapsed_time(b) * 1e-3) / 1e9
     del x, y
     torch.cuda.empty_cache()
-    return gbs
+    return out
 
 
-def warm_vs_cold(torch, n_cases=4):
+def warm_vs_cold(torch, n2d=8, n3d=4):
     """Warm start (committed trained U-Nets) against cold start on held-out
-    media: seconds to the 1e-6 two-step-mean residual, inference included."""
+    media (test seeds 700000+): seconds to the 1e-6 residual, inference
+    included, compared over the cases where both starts reach it; plus the
+    training run's own evaluation over its 100 held-out media."""
     from paper_2310_00810_amd import warmstart as W
     from paper_2310_00810_amd.unet import UNet
     out = {}
-    for dims, cases in ((2, n_cases), (3, max(1, n_cases // 2))):
+    for dims, cases in ((2, n2d), (3, n3d)):
         path = os.path.join(ROOT, "paper_2310_00810_amd", "weights", f"unet{dims}d.npz")
         if not os.path.exists(path):
             continue
         net = UNet.load(path)
         res = [W.warm_vs_cold(net, W.sample(dims, W.SEED_TEST + i), tol=1e-6, max_steps=100_000)
                for i in range(cases)]
-        c = float(np.mean([r["cold_s"] for r in res]))
-        wm = float(np.mean([r["warm_s"] for r in res]))
-        out[f"{dims}d"] = {"cases": cases, "cold_s_mean": round(c, 4), "warm_s_mean": round(wm, 4),
-                           "speedup": round(c / wm, 2),
-                           "cold_steps_mean": float(np.mean([r["cold_steps"] for r in res])),
-                           "warm_steps_mean": float(np.mean([r["warm_steps"] for r in res])),
-                           "workload": ("D2Q9 256^2 Boolean disks" if dims == 2 else "D3Q19 64^3 Boolean spheres")
-                           + ", porosity U[0.4,0.8], test seeds 700000+"}
+        entry = {"cases": cases, "workload": ("D2Q9 256^2 Boolean disks" if dims == 2 else
+                                              "D3Q19 64^3 Boolean spheres") + ", porosity U[0.4,0.8], test seeds 700000+"}
+        entry.update({k: (round(v, 5) if isinstance(v, float) else v) for k, v in W.summarize(res, 1e-6).items()})
+        try:
+            entry["training_run_evaluation"] = json.load(open(path[:-4] + ".json"))["summary"]
+        except (OSError, ValueError, KeyError):
+            pass
+        out[f"{dims}d"] = entry
         del net
     return out
 
 
-def cpu_baseline(w, budget_steps=8):
-    """The FP64 oracle's gradient evaluation (forward + reverse) on the same
-    128^3 problem for a bounded number of steps, timed on the host cores."""
+def cpu_baseline(w, cold_steps_2d=None):
+    """The FP64 oracle on the host cores, built with -O3 -march=native for
+    this host, timed on bounded samples of the workloads: all host threads
+    (OMP_NUM_THREADS, else the CPU count) and, for the benchmark's own
+    workload, one thread.  value: forward + reverse gradient MLUPS of the
+    benchmark's 128^3 problem (a few steps)."""
+    import tempfile
     import oracle as O
-    n = w["n"]
-    lat = O.Lattice(19, n, n, n, (O.BC_PRESSURE, O.BC_PERIODIC, O.BC_PERIODIC), w["solid"])
-    f0 = O.init_eq(lat, 1.0, 0.0)
-    tgt = np.zeros(lat.shape + (3,))
-    rin = 1.0 + w["din"].astype(np.float64)
-    nfl = int(lat.fluid().sum())
-    t0 = time.perf_counter()
-    O.grad(lat, w["tau"], rin, 1.0, f0, budget_steps, tgt, scale=1.0 / nfl, K=budget_steps)
-    dt = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    from oracle import build as ob
+    from paper_2310_00810_amd import geometry as G
+    from paper_2310_00810_amd import warmstart as W
+    tmp = tempfile.mkdtemp()
+    O.load(ob.build(out=os.path.join(tmp, "liblbm_oracle_native.so"), native=True))
+    cores = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
+    O.set_threads(cores)
     model = "unknown CPU"
     try:
         for line in open("/proc/cpuinfo"):
@@ -222,9 +235,68 @@ def cpu_baseline(w, budget_steps=8):
                 break
     except OSError:
         pass
-    return {"value": n ** 3 * budget_steps / dt / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
-            "sample": f"FP64 oracle forward+reverse gradient of the same 128^3 D3Q19 sphere-box problem, "
-                      f"{budget_steps} steps (K={budget_steps}), {dt:.1f} s, OpenMP on {cores} threads of {model}"}
+
+    def timed(fn):
+        t0 = time.perf_counter()
+        fn()
+        return time.perf_counter() - t0
+
+    def pair(lat, tau, rin, steps_f, steps_g, K=0, scale=1.0):
+        f0 = O.init_eq(lat, 1.0, 0.0)
+        tgt = np.zeros(lat.shape + (3,))
+        nodes = lat.nx * lat.ny * lat.nz
+        tf = timed(lambda: O.run(lat, tau, rin, 1.0, f0, steps_f))
+        tg = timed(lambda: O.grad(lat, tau, rin, 1.0, f0, steps_g, tgt, scale=scale, K=K or steps_g))
+        return nodes * steps_f / tf / 1e6, nodes * steps_g / tg / 1e6, tf + tg
+
+    walls = (O.BC_PRESSURE, O.BC_WALL, O.BC_PERIODIC)
+    n = w["n"]
+    lat3 = O.Lattice(19, n, n, n, (O.BC_PRESSURE, O.BC_PERIODIC, O.BC_PERIODIC), w["solid"])
+    nfl = int(lat3.fluid().sum())
+    rin3 = 1.0 + w["din"].astype(np.float64)
+    c3f, c3g, c3t = pair(lat3, w["tau"], rin3, 12, 4, scale=1.0 / nfl)
+    O.set_threads(1)
+    f0 = O.init_eq(lat3, 1.0, 0.0)
+    t1 = timed(lambda: O.grad(lat3, w["tau"], rin3, 1.0, f0, 1, np.zeros(lat3.shape + (3,)), scale=1.0 / nfl, K=1))
+    O.set_threads(cores)
+    configs = {"c3_128_spheres": {"fwd_mlups": round(c3f, 3), "fwd_adj_mlups": round(c3g, 3),
+                                  "fwd_adj_mlups_1_thread": round(n ** 3 / t1 / 1e6, 3),
+                                  "sample": "128^3 spheres: 12 forward steps; 4-step gradient; 1-step gradient on "
+                                            "one thread"}}
+    lat1 = O.Lattice(9, 64, 32, 1, walls)
+    f, g, _ = pair(lat1, 0.8, 1.005, 2000, 2000, K=45)
+    configs["c1_64x32_channel"] = {"fwd_mlups": round(f, 3), "fwd_adj_mlups": round(g, 3),
+                                   "sample": "full T = 2000 (K = 45)"}
+    lat2 = O.Lattice(9, 512, 256, 1, walls, G.rsa_disks(512, 256, (6.0, 14.0), 0.70, seed=2)[None])
+    f, g, _ = pair(lat2, 0.9, 1.004, 200, 200, K=20)
+    configs["c2_512x256_grains"] = {"fwd_mlups": round(f, 3), "fwd_adj_mlups": round(g, 3),
+                                    "sample": "200 of the 10 000 steps (K = 20)"}
+    media = G.c4_media(8)
+    fsum = gsum = work = 0.0
+    for m in media:
+        lat = O.Lattice(9, m["nx"], m["ny"], 1, walls, m["solid"])
+        f, g, _ = pair(lat, m["tau"], 1.0 + m["drho_in"], 100, 100, K=10)
+        nodes = m["nx"] * m["ny"] * 100
+        fsum += nodes / f
+        gsum += nodes / g
+        work += nodes
+    configs["c4_batch"] = {"fwd_mlups": round(work / fsum, 3), "fwd_adj_mlups": round(work / gsum, 3),
+                           "sample": "the first 8 of the 64 media, 100 steps each, one after another"}
+    solid, din, dout, tau = W.sample(2, W.SEED_TEST)
+    lat5 = O.Lattice(9, 256, 256, 1, walls, solid)
+    f0 = O.init_eq(lat5, 1.0, 0.0)
+    t5 = timed(lambda: O.run(lat5, tau, 1.0 + din, 1.0 + dout, f0, 500))
+    c5 = {"fwd_mlups": round(256 * 256 * 500 / t5 / 1e6, 3), "s_per_step": t5 / 500,
+          "sample": "held-out 2D medium (seed 700000), 500 forward steps"}
+    if cold_steps_2d:
+        c5["cold_start_s_extrapolated"] = round(t5 / 500 * cold_steps_2d, 2)
+        c5["cold_steps"] = int(cold_steps_2d)
+    configs["c5_2d_cold_start"] = c5
+    return {"value": round(c3g, 3), "unit": "MLUPS", "cores": cores, "kind": "oracle",
+            "sample": f"FP64 oracle (-O3 -march=native) forward + reverse gradient of the benchmark's 128^3 "
+                      f"D3Q19 problem over 4 steps (K = 4), OpenMP on {cores} threads of {model}; per-workload "
+                      f"samples in configs",
+            "configs": configs}
 
 
 def main():
@@ -357,16 +429,27 @@ def main():
         print("[bench] D2Q9 grain-media batch ...", file=sys.stderr, flush=True)
         out["d2q9_batch"] = d2q9_batch(torch)
     if not args.no_copy:
-        out["copy_peak_gbs"] = round(copy_peak_gbs(torch), 1)
+        cp = copy_peak_gbs(torch)
+        out["copy_peak_gbs"] = round(cp["copy16"], 1)
+        out["copy_torch_gbs"] = round(cp["torch"], 1)
     if not args.no_warm:
         print("[bench] warm vs cold start ...", file=sys.stderr, flush=True)
         out["warm_vs_cold"] = warm_vs_cold(torch)
         # the warm start's network kernels (BF16 MFMA convolutions) against their roofline
         from paper_2310_00810_amd.unet import measure
-        out["unet_mfma"] = [measure(2, 16, 256), measure(3, 2, 64)]
+        out["unet_mfma"] = []
+        for m in (measure(2, 16, 256), measure(3, 2, 64)):
+            m["ops_shown"] = f"the 8 longest of {len(m['ops'])} operations of a training step"
+            m["ops"] = m["ops"][:8]
+            out["unet_mfma"].append(m)
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(w)
+        cold = None
+        try:
+            cold = out["warm_vs_cold"]["2d"]["training_run_evaluation"]["cold_steps_median"]
+        except (TypeError, KeyError):
+            pass
+        out["cpu_baseline"] = cpu_baseline(w, cold)
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)

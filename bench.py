@@ -45,7 +45,7 @@ BYTES_ADJ = 3 * Q * 4        # gather F^{k-1}, gather nu^{k+1}, write nu^k
 PROFILES = os.path.join(ROOT, "profiles")
 # kernel names as the profiler reports them (template arguments: Q, x boundary kind = pressure)
 ADJ_KERNEL = "k_adj_step<19, 0, false>"
-FWD_KERNEL = "k_step<19, 0, false>"
+FWD_KERNEL = "k_step<19, 0>"
 
 
 def workload(n=128, T=8000, K=400, kind="spheres"):

@@ -31,6 +31,13 @@ namespace lbm {
     __syncthreads();                                                        \
     const FLane n = fluid_lane(G, I, t, L)
 
+// True when some lane of the wavefront sits on an inlet or outlet face: the
+// step and seed kernels skip the (branch-free) Zou-He closure in wavefronts
+// without face nodes, most of them in rows much wider than a wavefront.  The
+// adjoint step keeps it unconditional: with the branch it spills registers
+// and ran 20 % slower.
+__device__ inline bool wave_has_face(bool face) { return __builtin_amdgcn_ballot_w64(face) != 0; }
+
 // Face density of a node on a Zou-He face (issued before the gathers).
 template <int BCX>
 __device__ inline float face_density(const InstDev &I, const FLane &n, bool in, bool out,
@@ -70,7 +77,7 @@ __global__ void __launch_bounds__(FT) k_step(Geo G, const float *__restrict__ sr
     links<Q, BCX>(G, I, t, L, n, k);
     float g[Q];
     gather_fwd<Q, BCX>(rs, plane, k, g);
-    if (zouhe_faces(BCX)) zouhe<Q>(g, in, out, drho_b, BCX == BC_VELOCITY);
+    if (zouhe_faces(BCX) && wave_has_face(in || out)) zouhe<Q>(g, in, out, drho_b, BCX == BC_VELOCITY);
     if (BCX == BC_ABB) abb<Q>(g, in, out, drho_b, uF);
     const Moments m = moments<Q>(g);
     const float om = I.omega;
@@ -196,7 +203,7 @@ __global__ void __launch_bounds__(FT) k_adj_seed(Geo G, const float *__restrict_
     links<Q, BCX>(G, I, t, L, n, k);
     float g[Q];
     gather_fwd<Q, BCX>(rs, plane, k, g);
-    if (zouhe_faces(BCX)) zouhe<Q>(g, in, out, drho_b, BCX == BC_VELOCITY);
+    if (zouhe_faces(BCX) && wave_has_face(in || out)) zouhe<Q>(g, in, out, drho_b, BCX == BC_VELOCITY);
     if (BCX == BC_ABB) abb<Q>(g, in, out, drho_b, uF);
     const Moments m = moments<Q>(g);
     const float u[3] = {m.ux, m.uy, m.uz};
@@ -217,7 +224,7 @@ __global__ void __launch_bounds__(FT) k_adj_seed(Geo G, const float *__restrict_
     for (int i = 0; i < Q; ++i)
         a[i] = inv * (dldu[0] * (V::cx(i) - m.ux) + dldu[1] * (V::cy(i) - m.uy) +
                       (D == 3 ? dldu[2] * (V::cz(i) - m.uz) : 0.f));
-    if (zouhe_faces(BCX)) {
+    if (zouhe_faces(BCX) && wave_has_face(in || out)) {
         const float jb = zouhe_adj<Q>(a, in, out, g, drho_b, BCX == BC_VELOCITY);
         if (in) grad_in[I.face_off + n.r] += (double)jb;
         else if (out) grad_out[I.face_off + n.r] += (double)jb;

@@ -457,6 +457,14 @@ __global__ void __launch_bounds__(256) k_conv3x3_halo(ConvArgs a) {
 // stage's global loads are issued before the current stage's MFMAs.
 constexpr int WPB = 128, WLD = WPB + 8;          // pixels per stage; LDS rows padded by 16 B
 
+// Column (in halfwords) of pixel col of LDS row `row`: the 16-byte granules
+// of a row are XOR-swizzled by (row >> 3) & 7.  The staging writes put 4
+// pixels of 8 rows that are 8 apart; unswizzled, those rows alias onto two
+// bank groups (the 272-byte row stride times 8 is a multiple of 128 banks'
+// worth of bytes), swizzled they spread over all banks; the MFMA operand
+// reads (16 consecutive rows, one granule) stay conflict-free.
+__device__ inline int wcol(int row, int col) { return (((col >> 3) ^ ((row >> 3) & 7)) << 3) | (col & 7); }
+
 // v[j] = 8 channels of pixel j (j = 0..3) -> o[e] = channel e of pixels 0..3.
 __device__ inline void transpose_4x8(const uint4 (&v)[4], uint2 (&o)[8]) {
 #pragma unroll
@@ -539,13 +547,13 @@ __global__ void __launch_bounds__(256) k_wgrad(ConvArgs a, const uint16_t *__res
             if (g_rows) {
                 transpose_4x8(gv, o);
 #pragma unroll
-                for (int e = 0; e < 8; ++e) *(uint2 *)&Gs[cg + e][4 * pg] = o[e];
+                for (int e = 0; e < 8; ++e) *(uint2 *)&Gs[cg + e][wcol(cg + e, 4 * pg)] = o[e];
             }
 #pragma unroll
             for (int n = 0; n < NT; ++n) {
                 transpose_4x8(tv[n], o);
 #pragma unroll
-                for (int e = 0; e < 8; ++e) *(uint2 *)&Ts[64 * n + cg + e][4 * pg] = o[e];
+                for (int e = 0; e < 8; ++e) *(uint2 *)&Ts[64 * n + cg + e][wcol(64 * n + cg + e, 4 * pg)] = o[e];
             }
         }
         __syncthreads();
@@ -555,10 +563,14 @@ __global__ void __launch_bounds__(256) k_wgrad(ConvArgs a, const uint16_t *__res
             const int kr = kh + (lane >> 4) * 8;
             bf16x8 fb[2];
 #pragma unroll
-            for (int j = 0; j < 2; ++j) fb[j] = as_bf16x8(*(const uint4 *)&Ts[wn * 32 + j * 16 + (lane & 15)][kr]);
+            for (int j = 0; j < 2; ++j) {
+                const int tr = wn * 32 + j * 16 + (lane & 15);
+                fb[j] = as_bf16x8(*(const uint4 *)&Ts[tr][wcol(tr, kr)]);
+            }
 #pragma unroll
             for (int i = 0; i < 2; ++i) {
-                const bf16x8 fa = as_bf16x8(*(const uint4 *)&Gs[wm * 32 + i * 16 + (lane & 15)][kr]);
+                const int gr = wm * 32 + i * 16 + (lane & 15);
+                const bf16x8 fa = as_bf16x8(*(const uint4 *)&Gs[gr][wcol(gr, kr)]);
 #pragma unroll
                 for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, fb[j], acc[i][j], 0, 0, 0);
             }

@@ -5,6 +5,7 @@
         <copy_bytes> <out.json> <out.md> "<command>"
     python -m paper_2310_00810_amd.profiling sq <sq_counters.csv> <out.md> "<command>"
     python -m paper_2310_00810_amd.profiling overlap <kernel_trace.csv> <out.md>
+    python -m paper_2310_00810_amd.profiling mfma <counters.csv> <out.md> "<command>"
 
 `trace` turns a `--kernel-trace --stats --output-format csv` kernel-stats file
 into a Markdown table.  `traffic` turns two `--pmc FETCH_SIZE` / `--pmc
@@ -147,7 +148,44 @@ def sq(counters_csv, out_md, command):
                     f" | {valu_us:.1f} |\n")
 
 
+def mfma(counters_csv, out_md, command, prefixes=("k_conv", "k_wgrad")):
+    """Per network kernel: MFMA-busy and LDS counters.  MFMA busy =
+    SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE x 256 CUs x 4 SIMDs), the
+    share of all SIMD cycles of the launch in which an MFMA pipe was busy;
+    LDS bank-conflict cycles per LDS instruction; BF16 MFMA work in units of
+    512 operations per wavefront."""
+    agg = collections.defaultdict(lambda: collections.defaultdict(float))
+    calls = collections.Counter()
+    for r in csv.DictReader(open(counters_csv)):
+        k = short_name(r["Kernel_Name"])
+        if not k.startswith(prefixes):
+            continue
+        agg[k][r["Counter_Name"]] += float(r["Counter_Value"])
+        if r["Counter_Name"] == "SQ_WAVES":
+            calls[k] += 1
+    with open(out_md, "w") as f:
+        f.write("# MFMA and LDS counters of the network kernels (rocprofv3)\n\n")
+        f.write(f"Command:\n\n    {command}\n\n")
+        f.write("| kernel | launches | waves / launch | MFMA busy | LDS insts / wave | bank-conflict cycles / LDS inst "
+                "| LDS wait cycles / wave | BF16 MOPS / wave |\n|---|---|---|---|---|---|---|---|\n")
+        for k in sorted(agg, key=lambda k: -agg[k].get("GRBM_GUI_ACTIVE", 0.0)):
+            m = agg[k]
+            w = m.get("SQ_WAVES", 0.0)
+            if not w:
+                continue
+            gui = m.get("GRBM_GUI_ACTIVE", 0.0)
+            mb = m.get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0) / (gui * 256 * 4) if gui else 0.0
+            lds = m.get("SQ_INSTS_LDS", 0.0)
+            f.write(f"| `{k}` | {calls[k]} | {w / max(calls[k], 1):.0f} | {mb:.3f} | {lds / w:.1f} | "
+                    f"{m.get('SQ_LDS_BANK_CONFLICT', 0.0) / max(lds, 1):.2f} | "
+                    f"{m.get('SQ_WAIT_INST_LDS', 0.0) / w:.0f} | "
+                    f"{m.get('SQ_INSTS_VALU_MFMA_MOPS_BF16', 0.0) / w:.1f} |\n")
+
+
 if __name__ == "__main__":
+    if sys.argv[1] == "mfma":
+        mfma(sys.argv[2], sys.argv[3], sys.argv[4])
+        sys.exit(0)
     if sys.argv[1] == "trace":
         trace(sys.argv[2], sys.argv[3], sys.argv[4])
     elif sys.argv[1] == "traffic":

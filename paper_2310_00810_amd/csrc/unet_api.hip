@@ -27,6 +27,11 @@ int check_desc(const lbmnn_conv_desc *c, bool need_out) {
     if (c->dims == 2 && c->d != 1) return lbm_fail(LBM_EINVAL, "d must be 1 in 2D");
     if ((long long)c->n * c->d * c->h * c->w >= (1LL << 31))
         return lbm_fail(LBM_EINVAL, "the grid must have fewer than 2^31 pixels");
+    if ((c->flags & (LBMNN_S2D | LBMNN_D2S | LBMNN_S2D_G)) &&
+        ((long long)c->n * c->d * c->h * c->w << c->dims) >= (1LL << 31))
+        return lbm_fail(LBM_EINVAL, "the fine grid of an S2D / D2S mode must have fewer than 2^31 pixels");
+    if (((c->dims == 3 ? 4LL * c->h * c->w : 0) + 2LL * c->w + 2) * c->in_cstride >= (1LL << 31))
+        return lbm_fail(LBM_EINVAL, "a stencil tap's element offset must fit in 32 bits");
     if (!mult8(c->cin) || c->cin == 0) return lbm_fail(LBM_EINVAL, "cin must be a positive multiple of 8");
     if (!mult8(c->in_cstride) || !mult8(c->in_coff)) return lbm_fail(LBM_EINVAL, "input stride/offset must be multiples of 8");
     if (!c->in || !aligned16(c->in)) return lbm_fail(LBM_EINVAL, "input must be a 16-byte aligned device pointer");

@@ -123,6 +123,28 @@ __device__ inline uint4 im2col_load(const ConvArgs &a, const Row &r, const KOff 
     return ok ? *(const uint4 *)(a.in + r.base + o.delta) : make_uint4(0, 0, 0, 0);
 }
 
+// (b, z, y, x) of a flat pixel index kept as a mixed-radix counter: adding
+// a fixed step digit by digit needs one carry per digit (each digit of the
+// step is below its radix) and no division.
+struct Cursor { int x, y, z, b; };
+__device__ inline Cursor cursor_of(unsigned m, const ConvArgs &a) {
+    const Pix p = pix_of(m, a.d, a.h, a.w);
+    return Cursor{p.x, p.y, p.z, p.b};
+}
+__device__ inline void cursor_add(Cursor &c, const Cursor &s, const ConvArgs &a) {
+    c.x += s.x;
+    int k = c.x >= a.w;
+    c.x -= k ? a.w : 0;
+    c.y += s.y + k;
+    k = c.y >= a.h;
+    c.y -= k ? a.h : 0;
+    c.z += s.z + k;
+    k = c.z >= a.d;
+    c.z -= k ? a.d : 0;
+    c.b += s.b + k;
+}
+__device__ inline void cursor_inc(Cursor &c, const ConvArgs &a) { cursor_add(c, Cursor{1, 0, 0, 0}, a); }
+
 __device__ inline bf16x8 as_bf16x8(uint4 v) { return __builtin_bit_cast(bf16x8, v); }
 
 // Output element of GEMM cell (m, c): returns the flat index and the bias
@@ -471,10 +493,9 @@ __device__ inline void transpose_4x8(const uint4 (&v)[4], uint2 (&o)[8]) {
     for (int e = 0; e < 8; ++e) {
         const int d = e >> 1;
         const uint32_t a0 = (&v[0].x)[d], a1 = (&v[1].x)[d], a2 = (&v[2].x)[d], a3 = (&v[3].x)[d];
-        if (e & 1)
-            o[e] = make_uint2((a0 >> 16) | (a1 & 0xffff0000u), (a2 >> 16) | (a3 & 0xffff0000u));
-        else
-            o[e] = make_uint2((a0 & 0xffffu) | (a1 << 16), (a2 & 0xffffu) | (a3 << 16));
+        // v_perm_b32 picks bytes of {hi, lo}: 0x05040100 = low halves (lo, hi), 0x07060302 = high halves
+        const uint32_t sel = (e & 1) ? 0x07060302u : 0x05040100u;
+        o[e] = make_uint2(__builtin_amdgcn_perm(a1, a0, sel), __builtin_amdgcn_perm(a3, a2, sel));
     }
 }
 
@@ -503,41 +524,64 @@ __global__ void __launch_bounds__(256) k_wgrad(ConvArgs a, const uint16_t *__res
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const bool s2d_g = (a.flags & FLAG_S2D_G) != 0;
-    // the thread's im2col columns (tap, channel) and G channels are fixed over the pixel loop
-    KOff ko[NT];
+    const bool s2d_g = (a.flags & FLAG_S2D_G) != 0, s2d = (a.flags & FLAG_S2D) != 0;
+    // the thread's im2col columns (tap, channel) and G channel are fixed over
+    // the pixel loop: tap displacement, 32-bit offset from the pixel's first
+    // channel, and the fine-grid sub-pixel of an S2D_G row
+    int dx[NT], dy[NT], dz[NT], dl[NT];
+    bool kv[NT];
 #pragma unroll
-    for (int n = 0; n < NT; ++n) ko[n] = koff_of(a, c0 + 64 * n + cg);
+    for (int n = 0; n < NT; ++n) {
+        const KOff o = koff_of(a, c0 + 64 * n + cg);
+        dx[n] = o.dx; dy[n] = o.dy; dz[n] = o.dz; dl[n] = (int)o.delta; kv[n] = o.valid;
+    }
     const int r = r0 + cg;
-    const bool g_rows = cg < RM;                    // this thread stages rows of G
+    const bool g_rows = cg < RM && r < rows;        // this thread stages rows of G
+    int gch = r, gsx = 0, gsy = 0, gsz = 0;
+    if (s2d_g) {
+        const int cr = rows >> a.dims, sub = r / cr;
+        gch = r - sub * cr; gsx = sub & 1; gsy = (sub >> 1) & 1; gsz = (sub >> 2) & 1;
+    }
+    const int fd = a.dims == 3 ? 2 * a.d : 1, fh = 2 * a.h, fw = 2 * a.w;
+    // coordinates of the thread's first pixel of the next stage; a stage
+    // advances them by WPB pixels through the step's own digits
+    Cursor cur = cursor_of((unsigned)(mb + 4 * pg), a);
+    const Cursor step = cursor_of((unsigned)WPB, a);
     uint4 gv[4], tv[NT][4];
     auto load = [&](long long mm) {
+        const long long m0 = mm + 4 * pg;
+        const uint16_t *tp = a.in + a.in_co + m0 * a.in_cs;
+        const uint16_t *gp = g + g_co + gch + m0 * g_cs;
+        Cursor c = cur;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const long long m = mm + 4 * pg + j;
+            if (j) cursor_inc(c, a);
+            const bool mv = m0 + j < me;
             gv[j] = make_uint4(0, 0, 0, 0);
-#pragma unroll
-            for (int n = 0; n < NT; ++n) tv[n][j] = make_uint4(0, 0, 0, 0);
-            if (m >= me) continue;
-            if (g_rows && r < rows) {
-                long long src = m;
-                int ch = r;
+            if (g_rows && mv) {
+                const uint16_t *src = gp + j * g_cs;
                 if (s2d_g) {
-                    const int cr = rows >> a.dims;
-                    const int sub = r / cr;
-                    ch = r - sub * cr;
-                    const Pix p = pix_of(m, a.d, a.h, a.w);
-                    const int sx = sub & 1, sy = (sub >> 1) & 1, sz = (sub >> 2) & 1;
-                    const int fd = a.dims == 3 ? 2 * a.d : 1, fh = 2 * a.h, fw = 2 * a.w;
-                    const int zf = a.dims == 3 ? 2 * p.z + sz : 0;
-                    src = (((long long)p.b * fd + zf) * fh + 2 * p.y + sy) * fw + 2 * p.x + sx;
+                    const int zf = a.dims == 3 ? 2 * c.z + gsz : 0;
+                    const int f = ((c.b * fd + zf) * fh + 2 * c.y + gsy) * fw + 2 * c.x + gsx;
+                    src = g + g_co + gch + (long long)f * g_cs;
                 }
-                gv[j] = *(const uint4 *)(g + src * g_cs + g_co + ch);
+                gv[j] = *(const uint4 *)src;
             }
-            const Row rw = row_of(a, m);
+            const uint16_t *pix = tp + j * a.in_cs;
+            if (s2d) {
+                const int px = ((c.b * fd + (a.dims == 3 ? 2 * c.z : 0)) * fh + 2 * c.y) * fw + 2 * c.x;
+                pix = a.in + a.in_co + (long long)px * a.in_cs;
+            }
 #pragma unroll
-            for (int n = 0; n < NT; ++n) tv[n][j] = im2col_load(a, rw, ko[n]);
+            for (int n = 0; n < NT; ++n) {
+                bool ok = mv && kv[n];
+                if (!s2d)
+                    ok = ok && (unsigned)(c.x + dx[n]) < (unsigned)a.w && (unsigned)(c.y + dy[n]) < (unsigned)a.h &&
+                         (unsigned)(c.z + dz[n]) < (unsigned)a.d;
+                tv[n][j] = ok ? *(const uint4 *)(pix + dl[n]) : make_uint4(0, 0, 0, 0);
+            }
         }
+        cursor_add(cur, step, a);
     };
     load(mb);
     for (long long mm = mb; mm < me; mm += WPB) {

@@ -635,6 +635,153 @@ __global__ void __launch_bounds__(256) k_wgrad(ConvArgs a, const uint16_t *__res
         }
 }
 
+// Weight gradient of a 2D 3 x 3 convolution from halo-staged patches.  The
+// generic kernel above gathers the im2col matrix, i.e. every input pixel 9
+// times, and transposes it in registers.  Here a stage is a patch of
+// PH x PW = 128 pixels of one image: its G rows and its input pixels with
+// the one-pixel halo are copied into LDS once, pixel-major as they lie in
+// memory (16-byte chunks, no transposes), and the nine taps are LDS row
+// offsets of the same halo tile.  The MFMA operands, which run over pixels
+// (the contraction index), come out of LDS through the gfx950 transposing
+// read ds_read_b64_tr_b16.
+//
+// Lane layout of that read: in each group of 16 lanes, lane 4e + c names the
+// 8-byte block holding columns 4c .. 4c + 3 of row e, and lane i receives
+// column i of the rows 0 .. 3.  An MFMA 16x16x32 operand (lane l: tile row
+// or column l & 15, K entries 8 (l >> 4) .. + 7) is the pair of reads
+// h = 0, 1 in which lane 16 G + 4 e + c names K entry 8 G + 4 h + e, column
+// block c.
+//
+// Block: RB = 32 WR rows x CB = 16 WC input channels x all 9 taps; wavefront
+// w takes 32 rows (two m tiles) x 16 channels (one n tile) x the taps of
+// its group (4 / (WR WC) groups split the 9 taps).  blockIdx.z takes a
+// contiguous range of `per` patches.
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef short v8s __attribute__((ext_vector_type(8)));
+__device__ inline v4s lds_tr(const uint16_t *p) {
+    return __builtin_amdgcn_ds_read_tr16_b64_v4i16((__attribute__((address_space(3))) v4s *)p);
+}
+__device__ inline bf16x8 tr_operand(const uint16_t *p0, const uint16_t *p1) {
+    const v8s v = __builtin_shufflevector(lds_tr(p0), lds_tr(p1), 0, 1, 2, 3, 4, 5, 6, 7);
+    return __builtin_bit_cast(bf16x8, v);
+}
+
+// The MFMAs of one stage for taps T0 .. T1 - 1: x0 / x1 and g0 / g1 are the
+// lane's read addresses (h = 0, 1) for the patch's first 32 pixels; the
+// other 32-pixel chunks and the taps are constant offsets.
+template <int PW, int XS, int GS, int T0, int T1, int NTAP>
+__device__ inline void wgrad_halo_stage(const uint16_t *x0, const uint16_t *x1, const uint16_t *g0,
+                                        const uint16_t *g1, f32x4 (&acc)[NTAP][2]) {
+    constexpr int HW = PW + 2;
+#pragma unroll
+    for (int kc = 0; kc < 4; ++kc) {
+        const int go = kc * 32 * GS, xo = kc * (32 / PW) * HW * XS;
+        bf16x8 fa[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) fa[i] = tr_operand(g0 + go + 16 * i, g1 + go + 16 * i);
+#pragma unroll
+        for (int tap = T0; tap < T1; ++tap) {
+            const int o = xo + ((tap / 3 - 1) * HW + tap % 3 - 1) * XS;
+            const bf16x8 fb = tr_operand(x0 + o, x1 + o);
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+                acc[tap - T0][i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fb, acc[tap - T0][i], 0, 0, 0);
+        }
+    }
+}
+
+template <int PW, int WR, int WC>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_wgrad_halo(ConvArgs a, const uint16_t *__restrict__ g, int g_cs,
+                                                    int g_co, int rows, float *__restrict__ part, int per) {
+    constexpr int PH = 128 / PW, HW = PW + 2, HP = (PH + 2) * HW;
+    constexpr int RB = 32 * WR, CB = 16 * WC, WT = 4 / (WR * WC);
+    constexpr int NTAP = (9 + WT - 1) / WT;
+    constexpr int XS = CB + 8, GS = RB + 8;              // LDS row strides (halfwords), rows padded by 16 B
+    constexpr int XCH = CB / 8, GCH = RB / 8;            // 16-byte chunks per pixel
+    constexpr int XN = (HP * XCH + 255) / 256, GN = 128 * GCH / 256;
+    static_assert(WT == 1 || WT == 2, "taps split over at most two wavefront groups");
+    __shared__ __align__(16) uint16_t Xs[HP * XS];
+    __shared__ __align__(16) uint16_t Gs[128 * GS];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int wr = wave % WR, wc = (wave / WR) % WC, wt = wave / (WR * WC);
+    const int r0 = blockIdx.x * RB, ci0 = blockIdx.y * CB;
+    const int npx = (a.w + PW - 1) / PW, npy = (a.h + PH - 1) / PH;
+    const int pb = blockIdx.z * per, pe = min(pb + per, a.n * npx * npy);
+    // the lane's transposing-read addresses for the first 32 pixels
+    const int G = lane >> 4, e = (lane >> 2) & 3, c = lane & 3;
+    const uint16_t *xr[2], *gr[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int q = 8 * G + 4 * h + e;                 // pixel q of the patch (row q / PW, column q % PW)
+        xr[h] = Xs + ((q / PW + 1) * HW + q % PW + 1) * XS + 16 * wc + 4 * c;
+        gr[h] = Gs + q * GS + 32 * wr + 4 * c;
+    }
+    f32x4 acc[NTAP][2];
+#pragma unroll
+    for (int j = 0; j < NTAP; ++j) acc[j][0] = acc[j][1] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const uint16_t *xin = a.in + a.in_co + ci0;
+    const uint16_t *gin = g + g_co + r0;
+    uint4 xv[XN], gv[GN];
+    auto load = [&](int P) {
+        const int px0 = (P % npx) * PW, rest = P / npx;
+        const int py0 = (rest % npy) * PH, b = rest / npy;
+        const int base = (b * a.h + py0) * a.w + px0;    // the patch's first pixel
+#pragma unroll
+        for (int i = 0; i < XN; ++i) {
+            const int idx = t + 256 * i, hp = idx / XCH, cc = idx % XCH;
+            const int y = py0 - 1 + hp / HW, x = px0 - 1 + hp % HW;
+            const bool ok = idx < HP * XCH && (unsigned)y < (unsigned)a.h && (unsigned)x < (unsigned)a.w;
+            const long long pix = base + (hp / HW - 1) * a.w + hp % HW - 1;
+            xv[i] = ok ? *(const uint4 *)(xin + pix * a.in_cs + 8 * cc) : make_uint4(0, 0, 0, 0);
+        }
+#pragma unroll
+        for (int i = 0; i < GN; ++i) {
+            const int idx = t + 256 * i, p = idx / GCH, cc = idx % GCH;
+            const bool ok = py0 + p / PW < a.h && px0 + p % PW < a.w;
+            const long long pix = base + (p / PW) * a.w + p % PW;
+            gv[i] = ok ? *(const uint4 *)(gin + pix * g_cs + 8 * cc) : make_uint4(0, 0, 0, 0);
+        }
+    };
+    if (pb < pe) load(pb);
+    for (int P = pb; P < pe; ++P) {
+        __syncthreads();                                 // the previous stage's operand reads are done
+#pragma unroll
+        for (int i = 0; i < XN; ++i) {
+            const int idx = t + 256 * i;
+            if (idx < HP * XCH) *(uint4 *)&Xs[(idx / XCH) * XS + 8 * (idx % XCH)] = xv[i];
+        }
+#pragma unroll
+        for (int i = 0; i < GN; ++i) {
+            const int idx = t + 256 * i;
+            *(uint4 *)&Gs[(idx / GCH) * GS + 8 * (idx % GCH)] = gv[i];
+        }
+        __syncthreads();
+        if (P + 1 < pe) load(P + 1);
+        if (WT == 1) {
+            wgrad_halo_stage<PW, XS, GS, 0, 9, NTAP>(xr[0], xr[1], gr[0], gr[1], acc);
+        } else if (wt == 0) {
+            wgrad_halo_stage<PW, XS, GS, 0, 4, NTAP>(xr[0], xr[1], gr[0], gr[1], acc);
+        } else {
+            wgrad_halo_stage<PW, XS, GS, 4, 9, NTAP>(xr[0], xr[1], gr[0], gr[1], acc);
+        }
+    }
+    // acc[j][i][q]: row r0 + 32 wr + 16 i + 4 (lane >> 4) + q, channel ci0 + 16 wc + (lane & 15), tap T0 + j
+    float *dst = part + (long long)blockIdx.z * rows * a.K;
+    const int t0 = WT == 1 ? 0 : 4 * wt, nt = WT == 1 ? 9 : (wt == 0 ? 4 : 5);
+    const int ci = ci0 + 16 * wc + (lane & 15);
+#pragma unroll
+    for (int j = 0; j < NTAP; ++j) {
+        if (j >= nt) break;
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int rr = r0 + 32 * wr + 16 * i + 4 * (lane >> 4) + q;
+                if (rr < rows) dst[(long long)rr * a.K + (t0 + j) * a.cin + ci] = acc[j][i][q];
+            }
+    }
+}
+
 // Sum of split partials: a block takes 64 outputs, its four wavefronts the
 // splits z = w, w + 4, ... (coalesced 64-float rows), combined in a fixed
 // order (deterministic).
@@ -956,10 +1103,49 @@ static hipError_t sum_splits(const float *part, int z, long long n, float *out, 
     return hipGetLastError();
 }
 
+// The halo kernel's block shape for a layer, or 0: (WR, WC) = (2, 2) for
+// 64-row multiples, (1, 4) for 32 rows of 64-channel multiples, (1, 2) (taps
+// split over two wavefront pairs) for 32 rows of 32-channel multiples.
+static int halo_shape(const ConvArgs &a, int rows) {
+    if (a.dims != 2 || a.ks != 3 || (a.flags & (FLAG_S2D | FLAG_D2S | FLAG_S2D_G)) || a.w < 16) return 0;
+    if (rows % 64 == 0 && a.cin % 32 == 0) return 22;
+    if (rows % 32 == 0 && a.cin % 64 == 0) return 14;
+    if (rows % 32 == 0 && a.cin % 32 == 0) return 12;
+    return 0;
+}
+
+template <int PW>
+static void launch_wgrad_halo(int shape, const ConvArgs &a, const uint16_t *g, int g_cs, int g_co, int rows,
+                              float *part, int z, int per, hipStream_t s) {
+    const int RB = shape == 22 ? 64 : 32, CB = shape == 22 ? 32 : shape == 14 ? 64 : 32;
+    const dim3 grid((unsigned)(rows / RB), (unsigned)(a.cin / CB), (unsigned)z);
+    if (shape == 22)
+        hipLaunchKernelGGL((k_wgrad_halo<PW, 2, 2>), grid, dim3(256), 0, s, a, g, g_cs, g_co, rows, part, per);
+    else if (shape == 14)
+        hipLaunchKernelGGL((k_wgrad_halo<PW, 1, 4>), grid, dim3(256), 0, s, a, g, g_cs, g_co, rows, part, per);
+    else
+        hipLaunchKernelGGL((k_wgrad_halo<PW, 1, 2>), grid, dim3(256), 0, s, a, g, g_cs, g_co, rows, part, per);
+}
+
 hipError_t wgrad(const ConvArgs &a, const uint16_t *g, int g_cs, int g_co, int rows, float *part, int splits,
                  float *dw, int accumulate, hipStream_t s) {
     const long long chunk = wgrad_chunk(a.M, splits);
-    const int z = (int)((a.M + chunk - 1) / chunk);
+    int z = (int)((a.M + chunk - 1) / chunk);
+    if (const int shape = halo_shape(a, rows)) {
+        // patches of 4 x 32 (or 8 x 16 when w <= 16) pixels, split into at
+        // most as many ranges as the workspace holds partials for
+        const int pw = a.w > 16 ? 32 : 16, ph = 128 / pw;
+        const long long npt = (long long)a.n * ((a.h + ph - 1) / ph) * ((a.w + pw - 1) / pw);
+        const int per = (int)((npt + z - 1) / z);
+        z = (int)((npt + per - 1) / per);
+        if (pw == 32)
+            launch_wgrad_halo<32>(shape, a, g, g_cs, g_co, rows, part, z, per, s);
+        else
+            launch_wgrad_halo<16>(shape, a, g, g_cs, g_co, rows, part, z, per, s);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        return sum_splits(part, z, (long long)rows * a.K, dw, accumulate, s);
+    }
     if (rows <= 32) {
         const dim3 grid(1u, (unsigned)((a.K + 127) / 128), (unsigned)z);
         hipLaunchKernelGGL(k_wgrad<true>, grid, dim3(256), 0, s, a, g, g_cs, g_co, rows, part, chunk);

@@ -57,17 +57,17 @@ def conv_call(x, W, bias, ks, dims, cout, flags=0, out32=True, grid=None, cin=No
     return out
 
 
-def wgrad_call(x, g, ks, dims, rows, flags=0, grid=None, splits=7, g_cs=None):
+def wgrad_call(x, g, ks, dims, rows, flags=0, grid=None, splits=7, g_cs=None, cin=None, in_co=0, g_co=0):
     C = C_()
     L = C.nnlib()
     n, d, h, w = grid if grid is not None else x.shape[:4]
-    cin = x.shape[-1]
+    cin = cin or x.shape[-1]
     K = cin * ks ** dims
     need = L.lbmnn_wgrad_workspace_bytes(n * d * h * w, rows, K, splits)
     ws = torch.empty(need // 4 + 1, dtype=torch.float32, device="cuda")
     dw = torch.zeros(rows, K, dtype=torch.float32, device="cuda")
-    desc = C.lbmnn_conv_desc(n, d, h, w, dims, ks, cin, 0, flags, x.data_ptr(), cin, 0, None, None, 0, 0)
-    C.check(L.lbmnn_conv_wgrad(ctypes.byref(desc), ctypes.c_void_p(g.data_ptr()), g_cs or g.shape[-1], 0, rows,
+    desc = C.lbmnn_conv_desc(n, d, h, w, dims, ks, cin, 0, flags, x.data_ptr(), x.shape[-1], in_co, None, None, 0, 0)
+    C.check(L.lbmnn_conv_wgrad(ctypes.byref(desc), ctypes.c_void_p(g.data_ptr()), g_cs or g.shape[-1], g_co, rows,
                                ctypes.c_void_p(dw.data_ptr()), 0, ctypes.c_void_p(ws.data_ptr()), ws.numel() * 4,
                                splits, stream()), "wgrad")
     torch.cuda.synchronize()
@@ -145,6 +145,28 @@ def test_conv_weight_gradient(dims, ks, grid, cin, cout):
     g = bf(rng.standard_normal(grid + (cout,)))
     dw = wgrad_call(dev_bf(x), dev_bf(g), ks, dims, cout)
     ref, _ = N.conv_wgrad(x, g, ks, dims)
+    assert rel(dw.cpu().numpy(), ref.reshape(cout, -1)) <= 1e-5
+
+
+# 2D 3x3 layers whose rows and channels come in multiples of 32 take the
+# halo-staged kernel: 64-row blocks, 32-row blocks of 64 channels, and 32-row
+# blocks of 32 channels with the taps split over two wavefront pairs; patches
+# of 4 x 32 pixels (w > 16) or 8 x 16 (w <= 16), ragged at the right and
+# bottom edges, several per block (splits) or all in one (splits = 1); the
+# operands are channel slices of wider buffers.  w < 16 takes the generic
+# kernel.
+HALO = [((3, 1, 18, 45), 64, 64, 7), ((2, 1, 13, 16), 32, 32, 5), ((1, 1, 30, 40), 128, 32, 3),
+        ((1, 1, 16, 16), 64, 128, 1), ((2, 1, 37, 70), 32, 32, 64), ((2, 1, 9, 12), 32, 64, 2),
+        ((1, 1, 5, 33), 96, 64, 1)]
+
+
+@pytest.mark.parametrize("grid,cin,cout,splits", HALO)
+def test_halo_weight_gradient(grid, cin, cout, splits):
+    rng = np.random.default_rng(14)
+    x = bf(rng.standard_normal(grid + (cin + 16,)))
+    g = bf(rng.standard_normal(grid + (cout + 8,)))
+    dw = wgrad_call(dev_bf(x), dev_bf(g), 3, 2, cout, splits=splits, cin=cin, in_co=16, g_co=8)
+    ref, _ = N.conv_wgrad(x[..., 16:], g[..., 8:], 3, 2)
     assert rel(dw.cpu().numpy(), ref.reshape(cout, -1)) <= 1e-5
 
 

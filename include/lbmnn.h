@@ -63,6 +63,21 @@ typedef struct lbmnn_conv_desc {
  * bias: [cout] (D2S: [cout >> dims]) FP32, nullable. */
 int lbmnn_conv(const lbmnn_conv_desc *c, const void *w, const float *bias, void *stream);
 
+/* lbmnn_conv with a workspace for the layers whose implicit GEMM has too few
+ * output tiles to fill the GPU (the deep, low-resolution levels, whose long
+ * K = taps x cin loop would otherwise run on a few CUs): their contraction is
+ * split into K ranges whose FP32 products go to ws, summed in range order
+ * (deterministic) by a second kernel that applies the bias, ReLU /
+ * accumulate and output layout of lbmnn_conv.  Every other layer runs as
+ * lbmnn_conv and ignores ws.  ws: device memory of at least
+ * lbmnn_conv_workspace_bytes(c) bytes (0 when the layer is not split; c is
+ * validated as by lbmnn_conv, 0 for an invalid c); LBM_EINVAL for a NULL ws
+ * that is needed, LBM_ENOMEM for a smaller one.  Arguments, results and other
+ * errors as lbmnn_conv. */
+size_t lbmnn_conv_workspace_bytes(const lbmnn_conv_desc *c);
+int lbmnn_conv_ws(const lbmnn_conv_desc *c, const void *w, const float *bias, float *ws, size_t ws_bytes,
+                  void *stream);
+
 /* Weight gradient dW[r][k] = sum_m G[m][r] A[m][k] for the A operand that c
  * describes (c->cout is ignored), G = gradient of the GEMM output with
  * channel stride/offset g_cstride / g_coff and `rows` columns (LBMNN_S2D_G in

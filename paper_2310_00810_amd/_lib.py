@@ -110,7 +110,8 @@ def check(rc, where):
 
 # ------------------------------------------------------------ lbmnn.h ABI --
 NN_EXPORTS = [
-    "lbmnn_conv", "lbmnn_wgrad_workspace_bytes", "lbmnn_conv_wgrad", "lbmnn_conv_wgrad_noalloc",
+    "lbmnn_conv", "lbmnn_conv_workspace_bytes", "lbmnn_conv_ws", "lbmnn_wgrad_workspace_bytes", "lbmnn_conv_wgrad",
+    "lbmnn_conv_wgrad_noalloc",
     "lbmnn_weight_transpose",
     "lbmnn_bias_grad", "lbmnn_relu_bwd", "lbmnn_relu_bwd_bias_grad", "lbmnn_pool_fwd", "lbmnn_pool_bwd",
     "lbmnn_mse", "lbmnn_adam", "lbmnn_to_bf16", "lbmnn_features", "lbmnn_normalize", "lbmnn_denormalize",
@@ -138,6 +139,9 @@ def nnlib():
         vp, ip, ll, fl = ctypes.c_void_p, ctypes.c_int, ctypes.c_longlong, ctypes.c_float
         dp = ctypes.POINTER(lbmnn_conv_desc)
         L.lbmnn_conv.argtypes = [dp, vp, vp, vp]
+        L.lbmnn_conv_workspace_bytes.argtypes = [dp]
+        L.lbmnn_conv_workspace_bytes.restype = ctypes.c_size_t
+        L.lbmnn_conv_ws.argtypes = [dp, vp, vp, vp, ctypes.c_size_t, vp]
         L.lbmnn_wgrad_workspace_bytes.argtypes = [ll, ip, ip, ip]
         L.lbmnn_wgrad_workspace_bytes.restype = ctypes.c_size_t
         L.lbmnn_conv_wgrad.argtypes = [dp, vp, ip, ip, ip, vp, ip, vp, ctypes.c_size_t, ip, vp]
@@ -155,7 +159,7 @@ def nnlib():
         L.lbmnn_normalize.argtypes = [vp, vp, vp, vp, ll, ip, ll, vp, vp, vp]
         L.lbmnn_denormalize.argtypes = [vp, ip, vp, vp, ll, ip, ll, vp, vp, vp]
         for n in NN_EXPORTS:
-            if n != "lbmnn_wgrad_workspace_bytes":
+            if n not in ("lbmnn_wgrad_workspace_bytes", "lbmnn_conv_workspace_bytes"):
                 getattr(L, n).restype = ctypes.c_int
         _nn_ready = True
     return L

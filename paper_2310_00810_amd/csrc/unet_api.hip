@@ -135,6 +135,31 @@ int lbmnn_conv(const lbmnn_conv_desc *c, const void *w, const float *bias, void 
     return LBM_OK;
 }
 
+size_t lbmnn_conv_workspace_bytes(const lbmnn_conv_desc *c) {
+    if (check_desc(c, true)) return 0;
+    const nn::ConvArgs a = to_args(c, nullptr, nullptr);
+    const int S = nn::conv_splits(a);
+    return S > 1 ? sizeof(float) * (size_t)S * (size_t)a.M * (size_t)a.ncols : 0;
+}
+
+int lbmnn_conv_ws(const lbmnn_conv_desc *c, const void *w, const float *bias, float *ws, size_t ws_bytes,
+                  void *stream) {
+    int rc = check_desc(c, true);
+    if (rc) return rc;
+    if (!w || !aligned16(w)) return lbm_fail(LBM_EINVAL, "weights must be a 16-byte aligned device pointer");
+    const nn::ConvArgs a = to_args(c, w, bias);
+    const int S = nn::conv_splits(a);
+    if (S > 1) {
+        const size_t need = sizeof(float) * (size_t)S * (size_t)a.M * (size_t)a.ncols;
+        if (!ws) return lbm_fail(LBM_EINVAL, "workspace is NULL");
+        if (ws_bytes < need) return lbm_fail(LBM_ENOMEM, "conv workspace of %zu bytes, %zu needed", ws_bytes, need);
+        NN_TRY(nn::conv_split(a, ws, S, (hipStream_t)stream));
+    } else {
+        NN_TRY(nn::conv(a, (hipStream_t)stream));
+    }
+    return LBM_OK;
+}
+
 size_t lbmnn_wgrad_workspace_bytes(long long pixels, int rows, int K, int splits) {
     if (splits < 1) splits = 1;
     const long long chunk = nn::wgrad_chunk(pixels, splits);

@@ -172,8 +172,11 @@ __device__ inline long long out_index(const ConvArgs &a, long long m, int c, int
 // before the current step's MFMAs and land in the other buffer, so a step
 // needs one barrier.  64 x 32 tiles serve the 32- and 8-channel layers
 // without computing zero columns (and keep 5 blocks per CU).
-template <int TBM, int TBN>
-__global__ void __launch_bounds__(256) k_conv(ConvArgs a) {
+// SPLIT: blockIdx.z takes K steps [z sper, (z + 1) sper) and the block
+// stores its raw FP32 products to part[z][m][c] (k_conv_reduce adds the
+// splits and applies the epilogue).
+template <int TBM, int TBN, bool SPLIT = false>
+__global__ void __launch_bounds__(256) k_conv(ConvArgs a, float *__restrict__ part = nullptr, int sper = 0) {
     constexpr int KB = 64, LD = KB + 8;             // LDS rows padded by 16 B
     constexpr int WM = TBM / 2, WN = TBN / 2;
     constexpr int TI = WM / 16, TJ = WN / 16;
@@ -213,11 +216,12 @@ __global__ void __launch_bounds__(256) k_conv(ConvArgs a) {
     for (int i = 0; i < TI; ++i)
 #pragma unroll
         for (int j = 0; j < TJ; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const int steps = (a.K + KB - 1) / KB;
-    load(0);
-    stash(0);
+    const int s0 = SPLIT ? (int)blockIdx.z * sper : 0;
+    const int steps = SPLIT ? min((a.K + KB - 1) / KB, s0 + sper) : (a.K + KB - 1) / KB;
+    load(s0 * KB);
+    stash(s0 & 1);
     __syncthreads();
-    for (int s = 0; s < steps; ++s) {
+    for (int s = s0; s < steps; ++s) {
         const int buf = s & 1;
         if (s + 1 < steps) load((s + 1) * KB);
 #pragma unroll
@@ -235,6 +239,22 @@ __global__ void __launch_bounds__(256) k_conv(ConvArgs a) {
         }
         if (s + 1 < steps) stash(buf ^ 1);
         __syncthreads();
+    }
+    if (SPLIT) {
+        float *dst = part + (long long)blockIdx.z * a.M * a.ncols;
+#pragma unroll
+        for (int i = 0; i < TI; ++i)
+#pragma unroll
+            for (int j = 0; j < TJ; ++j) {
+                const int c = n0 + wn * WN + j * 16 + (lane & 15);
+                if (c >= a.ncols) continue;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const long long m = m0 + wm * WM + i * 16 + (lane >> 4) * 4 + q;
+                    if (m < a.M) dst[m * a.ncols + c] = acc[i][j][q];
+                }
+            }
+        return;
     }
     const bool d2s = (a.flags & FLAG_D2S) != 0;
     const int cr = d2s ? a.ncols >> a.dims : a.ncols;      // D2S: columns sub * cr + co
@@ -655,7 +675,8 @@ __global__ void __launch_bounds__(256) k_wgrad(ConvArgs a, const uint16_t *__res
 // Block: RB = 32 WR rows x CB = 16 WC input channels x all 9 taps; wavefront
 // w takes 32 rows (two m tiles) x 16 channels (one n tile) x the taps of
 // its group (4 / (WR WC) groups split the 9 taps).  blockIdx.z takes a
-// contiguous range of `per` patches.
+// contiguous range of `per` patches.  A layer of 8 input channels runs as a
+// 16-channel tile whose upper 8 channels are staged as zeros and not stored.
 typedef short v4s __attribute__((ext_vector_type(4)));
 typedef short v8s __attribute__((ext_vector_type(8)));
 __device__ inline v4s lds_tr(const uint16_t *p) {
@@ -692,21 +713,22 @@ __device__ inline void wgrad_halo_stage(const uint16_t *x0, const uint16_t *x1, 
 
 template <int PW, int WR, int WC>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_wgrad_halo(ConvArgs a, const uint16_t *__restrict__ g, int g_cs,
-                                                    int g_co, int rows, float *__restrict__ part, int per) {
+                                                    int g_co, int rows, float *__restrict__ part, int per,
+                                                    int dz) {
     constexpr int PH = 128 / PW, HW = PW + 2, HP = (PH + 2) * HW;
     constexpr int RB = 32 * WR, CB = 16 * WC, WT = 4 / (WR * WC);
     constexpr int NTAP = (9 + WT - 1) / WT;
     constexpr int XS = CB + 8, GS = RB + 8;              // LDS row strides (halfwords), rows padded by 16 B
     constexpr int XCH = CB / 8, GCH = RB / 8;            // 16-byte chunks per pixel
     constexpr int XN = (HP * XCH + 255) / 256, GN = 128 * GCH / 256;
-    static_assert(WT == 1 || WT == 2, "taps split over at most two wavefront groups");
+    static_assert(WT == 1 || WT == 2 || WT == 4, "taps split over 1, 2 or 4 wavefront groups");
     __shared__ __align__(16) uint16_t Xs[HP * XS];
     __shared__ __align__(16) uint16_t Gs[128 * GS];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int wr = wave % WR, wc = (wave / WR) % WC, wt = wave / (WR * WC);
     const int r0 = blockIdx.x * RB, ci0 = blockIdx.y * CB;
     const int npx = (a.w + PW - 1) / PW, npy = (a.h + PH - 1) / PH;
-    const int pb = blockIdx.z * per, pe = min(pb + per, a.n * npx * npy);
+    const int pb = blockIdx.z * per, pe = min(pb + per, a.n * a.d * npx * npy);
     // the lane's transposing-read addresses for the first 32 pixels
     const int G = lane >> 4, e = (lane >> 2) & 3, c = lane & 3;
     const uint16_t *xr[2], *gr[2];
@@ -724,14 +746,18 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
     uint4 xv[XN], gv[GN];
     auto load = [&](int P) {
         const int px0 = (P % npx) * PW, rest = P / npx;
-        const int py0 = (rest % npy) * PH, b = rest / npy;
-        const int base = (b * a.h + py0) * a.w + px0;    // the patch's first pixel
+        const int py0 = (rest % npy) * PH, img = rest / npy;   // img = sample * d + plane
+        const int base = (img * a.h + py0) * a.w + px0;  // the patch's first pixel
+        // input plane z + dz (3D), zero outside the volume
+        const bool zok = (unsigned)(img % a.d + dz) < (unsigned)a.d;
+        const int xbase = base + dz * a.h * a.w;
 #pragma unroll
         for (int i = 0; i < XN; ++i) {
             const int idx = t + 256 * i, hp = idx / XCH, cc = idx % XCH;
             const int y = py0 - 1 + hp / HW, x = px0 - 1 + hp % HW;
-            const bool ok = idx < HP * XCH && (unsigned)y < (unsigned)a.h && (unsigned)x < (unsigned)a.w;
-            const long long pix = base + (hp / HW - 1) * a.w + hp % HW - 1;
+            const bool ok = zok && idx < HP * XCH && (unsigned)y < (unsigned)a.h && (unsigned)x < (unsigned)a.w &&
+                            ci0 + 8 * cc < a.cin;
+            const long long pix = xbase + (hp / HW - 1) * a.w + hp % HW - 1;
             xv[i] = ok ? *(const uint4 *)(xin + pix * a.in_cs + 8 * cc) : make_uint4(0, 0, 0, 0);
         }
 #pragma unroll
@@ -757,18 +783,25 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
         }
         __syncthreads();
         if (P + 1 < pe) load(P + 1);
+        // wavefront group wt takes taps 9 wt / WT .. 9 (wt + 1) / WT - 1
         if (WT == 1) {
             wgrad_halo_stage<PW, XS, GS, 0, 9, NTAP>(xr[0], xr[1], gr[0], gr[1], acc);
-        } else if (wt == 0) {
-            wgrad_halo_stage<PW, XS, GS, 0, 4, NTAP>(xr[0], xr[1], gr[0], gr[1], acc);
+        } else if (WT == 2) {
+            if (wt == 0) wgrad_halo_stage<PW, XS, GS, 0, 4, NTAP>(xr[0], xr[1], gr[0], gr[1], acc);
+            else wgrad_halo_stage<PW, XS, GS, 4, 9, NTAP>(xr[0], xr[1], gr[0], gr[1], acc);
         } else {
-            wgrad_halo_stage<PW, XS, GS, 4, 9, NTAP>(xr[0], xr[1], gr[0], gr[1], acc);
+            if (wt == 0) wgrad_halo_stage<PW, XS, GS, 0, 2, NTAP>(xr[0], xr[1], gr[0], gr[1], acc);
+            else if (wt == 1) wgrad_halo_stage<PW, XS, GS, 2, 4, NTAP>(xr[0], xr[1], gr[0], gr[1], acc);
+            else if (wt == 2) wgrad_halo_stage<PW, XS, GS, 4, 6, NTAP>(xr[0], xr[1], gr[0], gr[1], acc);
+            else wgrad_halo_stage<PW, XS, GS, 6, 9, NTAP>(xr[0], xr[1], gr[0], gr[1], acc);
         }
     }
     // acc[j][i][q]: row r0 + 32 wr + 16 i + 4 (lane >> 4) + q, channel ci0 + 16 wc + (lane & 15), tap T0 + j
     float *dst = part + (long long)blockIdx.z * rows * a.K;
-    const int t0 = WT == 1 ? 0 : 4 * wt, nt = WT == 1 ? 9 : (wt == 0 ? 4 : 5);
+    // 3D: the launch of plane offset dz holds taps 9 (dz + 1) .. 9 (dz + 1) + 8
+    const int t0 = 9 * wt / WT + (a.dims == 3 ? 9 * (dz + 1) : 0), nt = 9 * (wt + 1) / WT - 9 * wt / WT;
     const int ci = ci0 + 16 * wc + (lane & 15);
+    if (ci >= a.cin) return;                              // the zero channels of a 16-channel tile over 8
 #pragma unroll
     for (int j = 0; j < NTAP; ++j) {
         if (j >= nt) break;
@@ -1064,10 +1097,69 @@ static bool halo_ok(const ConvArgs &a) {
            (ob & 15) == 0;
 }
 
+// Sum of the K splits of a convolution, in split order, then the epilogue
+// of k_conv (bias, ReLU, accumulate, FP32 or BF16 output, D2S scatter): one
+// thread per output element.
+__global__ void __launch_bounds__(256) k_conv_reduce(ConvArgs a, const float *__restrict__ part, int S) {
+    const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (e >= a.M * a.ncols) return;
+    const long long m = e / a.ncols;
+    const int c = (int)(e - m * a.ncols);
+    float v = 0.f;
+    for (int z = 0; z < S; ++z) v += part[(long long)z * a.M * a.ncols + e];
+    int bc;
+    const long long o = out_index(a, m, c, bc);
+    v += a.bias ? a.bias[bc] : 0.f;
+    if (a.flags & FLAG_RELU) v = v > 0.f ? v : 0.f;
+    if (a.out32) {
+        a.out32[o] = (a.flags & FLAG_ACC) ? a.out32[o] + v : v;
+    } else {
+        if (a.flags & FLAG_ACC) v += bf2f(a.out[o]);
+        a.out[o] = f2bf(v);
+    }
+}
+
+// K splits for a convolution whose output tiles are too few to fill the
+// GPU (the deep, low-resolution layers, whose long K loop would run on a
+// few CUs): enough splits for about 1024 blocks, each at least 4 K steps of
+// 64; 1 when the layer has 512 tiles or more, or takes the halo kernel.
+static long long conv_tiles(const ConvArgs &a) {
+    return (long long)blocks(a.M, 64) * (a.ncols <= 32 ? 1 : (a.ncols + 63) / 64);
+}
+static bool conv_halo(const ConvArgs &a) {
+    const long long tiles = halo_ok(a) ? (long long)a.n * a.d * (a.h / HY) * (a.w / HX) : 0;
+    return tiles * (a.ncols <= 32 ? 1 : (a.ncols + 63) / 64) >= 512;
+}
+int conv_splits(const ConvArgs &a) {
+    const long long tiles = conv_tiles(a);
+    if (conv_halo(a) || tiles >= 512) return 1;
+    const int steps = (a.K + 63) / 64;
+    long long sp = (1024 + tiles - 1) / tiles;
+    sp = sp < steps / 4 ? sp : steps / 4;
+    if (sp < 2) return 1;
+    const int sper = (int)((steps + sp - 1) / sp);
+    return (steps + sper - 1) / sper;
+}
+
+hipError_t conv_split(const ConvArgs &a, float *part, int S, hipStream_t s) {
+    const int steps = (a.K + 63) / 64, sper = (steps + S - 1) / S;
+    if (a.ncols <= 32) {
+        dim3 grid(blocks(a.M, 64), (unsigned)((a.ncols + 31) / 32), (unsigned)S);
+        hipLaunchKernelGGL((k_conv<64, 32, true>), grid, dim3(256), 0, s, a, part, sper);
+    } else {
+        dim3 grid(blocks(a.M, 64), (unsigned)((a.ncols + 63) / 64), (unsigned)S);
+        hipLaunchKernelGGL((k_conv<64, 64, true>), grid, dim3(256), 0, s, a, part, sper);
+    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_conv_reduce, dim3(blocks(a.M * a.ncols, 256)), dim3(256), 0, s, a, part, S);
+    return hipGetLastError();
+}
+
 hipError_t conv(const ConvArgs &a, hipStream_t s) {
     // the halo kernel holds 2 - 3 blocks per CU: below 512 blocks the im2col kernel fills the chip better
     const long long tiles = halo_ok(a) ? (long long)a.n * a.d * (a.h / HY) * (a.w / HX) : 0;
-    if (tiles * (a.ncols <= 32 ? 1 : (a.ncols + 63) / 64) >= 512) {
+    if (conv_halo(a)) {
         const dim3 grid((unsigned)tiles, a.ncols <= 32 ? 1u : (unsigned)((a.ncols + 63) / 64));
         if (a.dims == 3) {
             if (a.ncols <= 32) hipLaunchKernelGGL((k_conv3x3_halo<32, 3>), grid, dim3(256), 0, s, a);
@@ -1105,26 +1197,30 @@ static hipError_t sum_splits(const float *part, int z, long long n, float *out, 
 
 // The halo kernel's block shape for a layer, or 0: (WR, WC) = (2, 2) for
 // 64-row multiples, (1, 4) for 32 rows of 64-channel multiples, (1, 2) (taps
-// split over two wavefront pairs) for 32 rows of 32-channel multiples.
+// split over two wavefront pairs) for 32 rows of 32-channel multiples, (1, 1)
+// (taps split over the four wavefronts) for 32 rows of 8 channels.
 static int halo_shape(const ConvArgs &a, int rows) {
-    if (a.dims != 2 || a.ks != 3 || (a.flags & (FLAG_S2D | FLAG_D2S | FLAG_S2D_G)) || a.w < 16) return 0;
+    if (a.ks != 3 || (a.flags & (FLAG_S2D | FLAG_D2S | FLAG_S2D_G)) || a.w < 16) return 0;
     if (rows % 64 == 0 && a.cin % 32 == 0) return 22;
     if (rows % 32 == 0 && a.cin % 64 == 0) return 14;
     if (rows % 32 == 0 && a.cin % 32 == 0) return 12;
+    if (rows % 32 == 0 && a.cin == 8) return 11;
     return 0;
 }
 
 template <int PW>
 static void launch_wgrad_halo(int shape, const ConvArgs &a, const uint16_t *g, int g_cs, int g_co, int rows,
-                              float *part, int z, int per, hipStream_t s) {
-    const int RB = shape == 22 ? 64 : 32, CB = shape == 22 ? 32 : shape == 14 ? 64 : 32;
-    const dim3 grid((unsigned)(rows / RB), (unsigned)(a.cin / CB), (unsigned)z);
+                              float *part, int z, int per, int dz, hipStream_t s) {
+    const int RB = shape == 22 ? 64 : 32, CB = shape == 22 ? 32 : shape == 14 ? 64 : shape == 12 ? 32 : 16;
+    const dim3 grid((unsigned)(rows / RB), (unsigned)((a.cin + CB - 1) / CB), (unsigned)z);
     if (shape == 22)
-        hipLaunchKernelGGL((k_wgrad_halo<PW, 2, 2>), grid, dim3(256), 0, s, a, g, g_cs, g_co, rows, part, per);
+        hipLaunchKernelGGL((k_wgrad_halo<PW, 2, 2>), grid, dim3(256), 0, s, a, g, g_cs, g_co, rows, part, per, dz);
     else if (shape == 14)
-        hipLaunchKernelGGL((k_wgrad_halo<PW, 1, 4>), grid, dim3(256), 0, s, a, g, g_cs, g_co, rows, part, per);
+        hipLaunchKernelGGL((k_wgrad_halo<PW, 1, 4>), grid, dim3(256), 0, s, a, g, g_cs, g_co, rows, part, per, dz);
+    else if (shape == 12)
+        hipLaunchKernelGGL((k_wgrad_halo<PW, 1, 2>), grid, dim3(256), 0, s, a, g, g_cs, g_co, rows, part, per, dz);
     else
-        hipLaunchKernelGGL((k_wgrad_halo<PW, 1, 2>), grid, dim3(256), 0, s, a, g, g_cs, g_co, rows, part, per);
+        hipLaunchKernelGGL((k_wgrad_halo<PW, 1, 1>), grid, dim3(256), 0, s, a, g, g_cs, g_co, rows, part, per, dz);
 }
 
 hipError_t wgrad(const ConvArgs &a, const uint16_t *g, int g_cs, int g_co, int rows, float *part, int splits,
@@ -1134,16 +1230,20 @@ hipError_t wgrad(const ConvArgs &a, const uint16_t *g, int g_cs, int g_co, int r
     if (const int shape = halo_shape(a, rows)) {
         // patches of 4 x 32 (or 8 x 16 when w <= 16) pixels, split into at
         // most as many ranges as the workspace holds partials for
+        // 3D: one launch per plane offset dz = -1, 0, 1, each the 9 taps of its
+        // plane pair, written to disjoint columns of the same partials
         const int pw = a.w > 16 ? 32 : 16, ph = 128 / pw;
-        const long long npt = (long long)a.n * ((a.h + ph - 1) / ph) * ((a.w + pw - 1) / pw);
+        const long long npt = (long long)a.n * a.d * ((a.h + ph - 1) / ph) * ((a.w + pw - 1) / pw);
         const int per = (int)((npt + z - 1) / z);
         z = (int)((npt + per - 1) / per);
-        if (pw == 32)
-            launch_wgrad_halo<32>(shape, a, g, g_cs, g_co, rows, part, z, per, s);
-        else
-            launch_wgrad_halo<16>(shape, a, g, g_cs, g_co, rows, part, z, per, s);
-        const hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
+        for (int dz = a.dims == 3 ? -1 : 0; dz <= (a.dims == 3 ? 1 : 0); ++dz) {
+            if (pw == 32)
+                launch_wgrad_halo<32>(shape, a, g, g_cs, g_co, rows, part, z, per, dz, s);
+            else
+                launch_wgrad_halo<16>(shape, a, g, g_cs, g_co, rows, part, z, per, dz, s);
+            const hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
         return sum_splits(part, z, (long long)rows * a.K, dw, accumulate, s);
     }
     if (rows <= 32) {

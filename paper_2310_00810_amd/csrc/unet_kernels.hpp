@@ -32,6 +32,8 @@ struct ConvArgs {
 };
 
 hipError_t conv(const ConvArgs &a, hipStream_t s);
+int conv_splits(const ConvArgs &a);
+hipError_t conv_split(const ConvArgs &a, float *part, int S, hipStream_t s);
 long long wgrad_chunk(long long M, int splits);
 hipError_t wgrad(const ConvArgs &a, const uint16_t *g, int g_cs, int g_co, int rows, float *part, int splits,
                  float *dw, int accumulate, hipStream_t s);

@@ -214,9 +214,14 @@ class UNet:
         M = n * d * h * w
         m_in = M << self.dims if flags & C.NN_S2D else M
         nbytes = 2 * m_in * cin + (4 if out32 is not None else 2) * M * cout + 2 * cout * taps * cin
+        # the deep levels split their K loop: FP32 partials in the shared workspace
+        need = self.L.lbmnn_conv_workspace_bytes(ctypes.byref(desc))
+        if self._ws.numel() * 4 < need:
+            self._ws = torch.empty(need // 4 + 1024, dtype=torch.float32, device=self.device)
         self._timed("dgrad" if transposed else "fwd", name, 2 * M * cout * taps * cin, nbytes,
-                    lambda: C.check(self.L.lbmnn_conv(ctypes.byref(desc), _ptr(wsrc, self.woff[name]), b,
-                                                      self._stream()), "lbmnn_conv"))
+                    lambda: C.check(self.L.lbmnn_conv_ws(ctypes.byref(desc), _ptr(wsrc, self.woff[name]), b,
+                                                         _ptr(self._ws), self._ws.numel() * 4, self._stream()),
+                                    "lbmnn_conv_ws"))
 
     def _wgrad(self, grid, ks, cin, flags, inp, in_cs, in_co, g, g_cs, g_co, rows, name):
         n, d, h, w = grid
@@ -241,8 +246,9 @@ class UNet:
                                                             self._stream()), "lbmnn_conv_wgrad"))
 
     def _bgrad(self, g, cs, co, pixels, Cn, name):
-        # about 512 pixels per split (enough blocks to keep HBM busy), bounded by the partials buffer
-        splits = max(1, min(-(-pixels // 512), self._bws.numel() // Cn))
+        # about 16K elements (32 KB) per split, enough blocks to keep HBM busy at every level,
+        # bounded by the partials buffer
+        splits = max(1, min(-(-pixels * Cn // 16384), self._bws.numel() // Cn))
         self._timed("bgrad", name, pixels * Cn, 2 * pixels * Cn + 4 * Cn,
                     lambda: C.check(self.L.lbmnn_bias_grad(ctypes.c_void_p(g.data_ptr()), cs, co, pixels, Cn,
                                                            _ptr(self.grad, self.boff[name]), 0, _ptr(self._bws),
@@ -250,7 +256,7 @@ class UNet:
 
     def _relu_bgrad(self, g, y, cs, co, pixels, Cn, name):
         # ReLU backward and the bias gradient of the masked g in one pass (splits as in _bgrad)
-        splits = max(1, min(-(-pixels // 512), self._bws.numel() // Cn))
+        splits = max(1, min(-(-pixels * Cn // 16384), self._bws.numel() // Cn))
         self._timed("relu_bgrad", name, 2 * pixels * Cn, 6 * pixels * Cn + 4 * Cn,
                     lambda: C.check(self.L.lbmnn_relu_bwd_bias_grad(ctypes.c_void_p(g.data_ptr()),
                                                                     ctypes.c_void_p(y.data_ptr()), cs, co, pixels, Cn,

@@ -42,6 +42,22 @@ def test_every_declared_network_symbol_is_exported(L):
         assert hasattr(L, n), n
 
 
+def test_conv_workspace_only_for_layers_with_few_output_tiles(L):
+    """Host-side split choice of lbmnn_conv_ws (no GPU call): a 3x3x3 layer on
+    2 x 8^3 pixels, 256 -> 256 channels, has 16 x 4 output tiles and a K loop of
+    108 steps of 64: 16 splits of 7 steps, 16 x 1024 x 256 FP32 partials.  A
+    2D layer on 16 x 256^2 pixels has 16 384 tiles and needs none; an invalid
+    descriptor reports 0."""
+    C.nnlib()
+    fake_in, fake_out = 1 << 20, 1 << 21          # aligned stand-ins, never dereferenced on the host
+    deep = C.lbmnn_conv_desc(2, 8, 8, 8, 3, 3, 256, 256, 0, fake_in, 256, 0, fake_out, None, 256, 0)
+    assert L.lbmnn_conv_workspace_bytes(ctypes.byref(deep)) == 16 * 1024 * 256 * 4
+    top = C.lbmnn_conv_desc(16, 1, 256, 256, 2, 3, 32, 32, 0, fake_in, 32, 0, fake_out, None, 32, 0)
+    assert L.lbmnn_conv_workspace_bytes(ctypes.byref(top)) == 0
+    bad = C.lbmnn_conv_desc(2, 8, 8, 8, 4, 3, 256, 256, 0, fake_in, 256, 0, fake_out, None, 256, 0)
+    assert L.lbmnn_conv_workspace_bytes(ctypes.byref(bad)) == 0
+
+
 def _problem(nx=64, ny=32, nz=1, q=9, steps=100, K=0, tape=0, solid=None, n=1, **kw):
     arr = (C.lbm_instance * n)()
     keep = []

@@ -193,3 +193,55 @@ def unet_backward(gout, params, cache, dims, quantize=None, base=32, levels=4):
             grads[f"e{lv}c{j}"] = conv_wgrad(xin, g, 3, dims)
             g = q(conv_dgrad(g, W, 3, dims, W.shape[2]))
     return grads
+
+
+# ------------------------------------------------------------ training ops --
+# The warm-start network's loss, optimiser and target scaling (the network is
+# the paper's future-work initial guess, Section 3.5; the scaling is the
+# Stokes reading of its targets).
+
+def masked_mse(pred, target, wpix, creal, scale):
+    """Loss L = scale * sum_p wpix[p] * sum_{c < creal} (pred[p, c] - target[p, c])^2
+    over pixels p (rows of pred, whose further columns are padding), and
+    dL/dpred (zero in the padding columns)."""
+    pred = np.asarray(pred, np.float64)
+    d = pred[:, :creal] - np.asarray(target, np.float64)[:, :creal]
+    w = np.asarray(wpix, np.float64)[:, None]
+    g = np.zeros_like(pred)
+    g[:, :creal] = 2.0 * scale * w * d
+    return scale * float(np.sum(w * d * d)), g
+
+
+def adam(w, g, m1, m2, lr, b1, b2, eps, t):
+    """One Adam step (Kingma and Ba, Algorithm 1): the moment estimates, their
+    bias corrections at step t (from 1) and the update; returns (w, m1, m2)."""
+    g = np.asarray(g, np.float64)
+    m1 = b1 * np.asarray(m1, np.float64) + (1.0 - b1) * g
+    m2 = b2 * np.asarray(m2, np.float64) + (1.0 - b2) * g * g
+    mh = m1 / (1.0 - b1 ** t)
+    vh = m2 / (1.0 - b2 ** t)
+    return np.asarray(w, np.float64) - lr * mh / (np.sqrt(vh) + eps), m1, m2
+
+
+def stokes_targets(drho, u, solid, drho_in, drho_out, tau):
+    """Network targets of one sample: t0 = (drho - drho_out) / (drho_in - drho_out)
+    and t_a = u_a nu / (c_s^2 (drho_in - drho_out)) with nu = (tau - 1/2) / 3 and
+    c_s^2 = 1/3 at fluid nodes, 0 at solid nodes; rows are nodes."""
+    dr = drho_in - drho_out
+    nu = (tau - 0.5) / 3.0
+    fl = (np.asarray(solid).reshape(-1) == 0)[:, None]
+    u = np.asarray(u, np.float64).reshape(fl.shape[0], -1)
+    t = np.concatenate([(np.asarray(drho, np.float64).reshape(-1, 1) - drho_out) / dr, u * nu / (dr / 3.0)], axis=1)
+    return np.where(fl, t, 0.0)
+
+
+def stokes_fields(pred, solid, drho_in, drho_out, tau, dims):
+    """Inverse of stokes_targets on the first 1 + dims columns of pred:
+    (drho, u) at fluid nodes, 0 at solid nodes."""
+    dr = drho_in - drho_out
+    nu = (tau - 0.5) / 3.0
+    fl = np.asarray(solid).reshape(-1) == 0
+    p = np.asarray(pred, np.float64)
+    drho = np.where(fl, drho_out + dr * p[:, 0], 0.0)
+    u = np.where(fl[:, None], p[:, 1:1 + dims] * (dr / 3.0) / nu, 0.0)
+    return drho, u

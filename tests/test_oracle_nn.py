@@ -148,3 +148,78 @@ def test_bf16_rounding_definition():
     assert np.all(np.abs(rv - v) <= 2.0 ** -8 * np.abs(v) * (1 + 1e-6))
     # values on the grid are fixed points
     assert np.array_equal(N.bf16_round(rv), rv)
+
+
+def test_masked_mse_gradient_and_special_cases():
+    """Masked MSE: dL/dpred against central differences of L; a zero-weight
+    pixel and the padding columns contribute nothing; one pixel, one column:
+    L = scale (p - t)^2."""
+    rng = np.random.default_rng(31)
+    P, pcs, creal = 7, 5, 3
+    pred = rng.standard_normal((P, pcs))
+    tgt = rng.standard_normal((P, creal))
+    w = rng.uniform(size=P)
+    w[2] = 0.0
+    L, g = N.masked_mse(pred, tgt, w, creal, 0.7)
+    h = 1e-6
+    for p in range(P):
+        for c in range(pcs):
+            e = np.zeros_like(pred)
+            e[p, c] = h
+            fd = (N.masked_mse(pred + e, tgt, w, creal, 0.7)[0] - N.masked_mse(pred - e, tgt, w, creal, 0.7)[0]) / (2 * h)
+            assert abs(fd - g[p, c]) <= 1e-8 * max(1.0, abs(fd))
+    assert np.all(g[2] == 0.0) and np.all(g[:, creal:] == 0.0)
+    pred2 = pred.copy()
+    pred2[2] += 5.0
+    pred2[:, creal:] -= 3.0
+    assert N.masked_mse(pred2, tgt, w, creal, 0.7)[0] == L
+    assert np.isclose(N.masked_mse(np.array([[2.0]]), np.array([[0.5]]), np.array([1.0]), 1, 0.25)[0], 0.25 * 1.5 ** 2)
+
+
+def test_adam_bias_corrections():
+    """Adam from zero moments: with a constant gradient g the bias-corrected
+    moments are exactly g and g^2 at every step, so each step moves a weight
+    by lr g / (|g| + eps); with b1 = b2 = 0 the same holds for any gradient
+    sequence; a zero gradient leaves the moments decaying and the step equal
+    to the corrected ratio."""
+    rng = np.random.default_rng(32)
+    n = 9
+    w0 = rng.standard_normal(n)
+    g = rng.standard_normal(n)
+    lr, eps = 1e-2, 1e-8
+    w, m1, m2 = w0, np.zeros(n), np.zeros(n)
+    for t in range(1, 6):
+        w, m1, m2 = N.adam(w, g, m1, m2, lr, 0.9, 0.999, eps, t)
+        assert np.allclose(w, w0 - t * lr * g / (np.abs(g) + eps), rtol=0, atol=1e-13)
+    w, m1, m2 = w0, np.zeros(n), np.zeros(n)
+    for t in range(1, 4):
+        gt = rng.standard_normal(n)
+        w_prev = w
+        w, m1, m2 = N.adam(w, gt, m1, m2, lr, 0.0, 0.0, eps, t)
+        assert np.allclose(w, w_prev - lr * gt / (np.abs(gt) + eps), rtol=0, atol=1e-15)
+    w1, m1, m2 = N.adam(w0, g, np.zeros(n), np.zeros(n), lr, 0.9, 0.999, eps, 1)
+    w2, m1b, m2b = N.adam(w1, np.zeros(n), m1, m2, lr, 0.9, 0.999, eps, 2)
+    assert np.allclose(m1b, 0.9 * m1) and np.allclose(m2b, 0.999 * m2)
+    mh, vh = m1b / (1 - 0.9 ** 2), m2b / (1 - 0.999 ** 2)
+    assert np.allclose(w2, w1 - lr * mh / (np.sqrt(vh) + eps))
+
+
+def test_stokes_scaling_round_trip_and_closed_form():
+    """The target scaling and its inverse are inverse at fluid nodes and 0 at
+    solid nodes; the density target is 1 at the inlet density and 0 at the
+    outlet's; the velocity target is u nu / (c_s^2 drho) (nu = 0.1 at tau = 0.8)."""
+    rng = np.random.default_rng(33)
+    P, D = 50, 3
+    solid = (rng.uniform(size=P) > 0.7).astype(np.uint8)
+    drho = rng.uniform(0, 0.004, P)
+    drho[0], drho[1] = 0.004, 0.001
+    solid[:2] = 0
+    u = rng.standard_normal((P, D)) * 1e-3
+    t = N.stokes_targets(drho, u, solid, 0.004, 0.001, 0.8)
+    assert t[0, 0] == 1.0 and t[1, 0] == 0.0
+    fl = solid == 0
+    assert np.allclose(t[fl, 1:], u[fl] * 0.1 / (0.003 / 3.0))
+    assert np.all(t[~fl] == 0.0)
+    r2, u2 = N.stokes_fields(np.concatenate([t, np.zeros((P, 2))], axis=1), solid, 0.004, 0.001, 0.8, D)
+    assert np.allclose(r2[fl], drho[fl], rtol=1e-13) and np.allclose(u2[fl], u[fl], rtol=1e-12)
+    assert np.all(r2[~fl] == 0.0) and np.all(u2[~fl] == 0.0)

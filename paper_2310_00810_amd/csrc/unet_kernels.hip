@@ -819,19 +819,33 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
 // splits z = w, w + 4, ... (coalesced 64-float rows), combined in a fixed
 // order (deterministic).
 __global__ void __launch_bounds__(256) k_sum_splits(const float *__restrict__ part, int splits, long long n,
-                                                    float *__restrict__ out, int accumulate) {
+                                                    long long row, float *__restrict__ out, int accumulate) {
     __shared__ float sh[4][64];
     const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
     const long long i = (long long)blockIdx.x * 64 + l;
     float s = 0.f;
     if (i < n)
-        for (int z = w; z < splits; z += 4) s += part[(long long)z * n + i];
+        for (int z = w; z < splits; z += 4) s += part[(long long)z * row + i];
     sh[w][l] = s;
     __syncthreads();
     if (w == 0 && i < n) {
         const float v = (sh[0][l] + sh[1][l]) + (sh[2][l] + sh[3][l]);
         out[i] = accumulate ? out[i] + v : v;
     }
+}
+
+// First pass of a long split sum: thread (i, c) adds the partials of splits
+// c S .. c S + S - 1 of output i in order and stores the sum over split
+// c S's own partial, which no other thread reads; k_sum_splits then adds
+// the chunk sums (row stride S n), in order.
+__global__ void __launch_bounds__(256) k_sum_split_chunks(float *__restrict__ part, int splits, long long n, int S) {
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const int z0 = (int)blockIdx.y * S, z1 = min(z0 + S, splits);
+    float s = 0.f;
+#pragma unroll 8
+    for (int z = z0; z < z1; ++z) s += part[(long long)z * n + i];
+    part[(long long)z0 * n + i] = s;
 }
 
 // Sum of split partials when there are few outputs: one block per output,
@@ -1185,13 +1199,25 @@ long long wgrad_chunk(long long M, int splits) {
     return (c + WPB - 1) / WPB * WPB;
 }
 
-// Sum of z split partials into n outputs: a thread per output when there are
-// many, a block per output when there are few.
-static hipError_t sum_splits(const float *part, int z, long long n, float *out, int accumulate, hipStream_t s) {
-    if (n <= 8192 && z > 16)
+// Sum of z split partials into n outputs: a block per output when there are
+// few; else a thread per output and four wavefronts over the splits, after a
+// first pass that adds chunks of 8 splits in place when there are more than
+// 32 (each partial is added once, in split order within a chunk and in chunk
+// order after; deterministic).
+static hipError_t sum_splits(float *part, int z, long long n, float *out, int accumulate, hipStream_t s) {
+    if (n <= 8192 && z > 16) {
         hipLaunchKernelGGL(k_sum_splits_narrow, dim3((unsigned)n), dim3(256), 0, s, part, z, n, out, accumulate);
-    else
-        hipLaunchKernelGGL(k_sum_splits, dim3(blocks(n, 64)), dim3(256), 0, s, part, z, n, out, accumulate);
+        return hipGetLastError();
+    }
+    long long row = n;
+    if (z > 32) {
+        constexpr int S = 8;
+        const int chunks = (z + S - 1) / S;
+        hipLaunchKernelGGL(k_sum_split_chunks, dim3(blocks(n, 256), (unsigned)chunks), dim3(256), 0, s, part, z, n, S);
+        z = chunks;
+        row = S * n;
+    }
+    hipLaunchKernelGGL(k_sum_splits, dim3(blocks(n, 64)), dim3(256), 0, s, part, z, n, row, out, accumulate);
     return hipGetLastError();
 }
 

@@ -149,11 +149,13 @@ def sq(counters_csv, out_md, command):
 
 
 def mfma(counters_csv, out_md, command, prefixes=("k_conv", "k_wgrad")):
-    """Per network kernel: MFMA-busy and LDS counters.  MFMA busy =
-    SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE x 256 CUs x 4 SIMDs), the
-    share of all SIMD cycles of the launch in which an MFMA pipe was busy;
-    LDS bank-conflict cycles per LDS instruction; BF16 MFMA work in units of
-    512 operations per wavefront."""
+    """Per network kernel: BF16 MFMA rate and LDS counters.  TFLOP/s =
+    SQ_INSTS_VALU_MFMA_MOPS_BF16 x 512 flop over the dispatches' own
+    durations (start / end timestamps of the counter rows), and its fraction
+    of the 2.5 PFLOP/s dense peak; MFMA busy = SQ_VALU_MFMA_BUSY_CYCLES /
+    (GRBM_GUI_ACTIVE / 8 x 1024 SIMDs): GRBM_GUI_ACTIVE comes summed over the
+    8 XCDs (it reads about 8 x the clock times the duration); LDS
+    bank-conflict cycles per LDS instruction; LDS wait cycles per wavefront."""
     agg = collections.defaultdict(lambda: collections.defaultdict(float))
     calls = collections.Counter()
     for r in csv.DictReader(open(counters_csv)):
@@ -163,23 +165,27 @@ def mfma(counters_csv, out_md, command, prefixes=("k_conv", "k_wgrad")):
         agg[k][r["Counter_Name"]] += float(r["Counter_Value"])
         if r["Counter_Name"] == "SQ_WAVES":
             calls[k] += 1
+            agg[k]["duration_ns"] += float(r["End_Timestamp"]) - float(r["Start_Timestamp"])
     with open(out_md, "w") as f:
         f.write("# MFMA and LDS counters of the network kernels (rocprofv3)\n\n")
         f.write(f"Command:\n\n    {command}\n\n")
-        f.write("| kernel | launches | waves / launch | MFMA busy | LDS insts / wave | bank-conflict cycles / LDS inst "
-                "| LDS wait cycles / wave | BF16 MOPS / wave |\n|---|---|---|---|---|---|---|---|\n")
-        for k in sorted(agg, key=lambda k: -agg[k].get("GRBM_GUI_ACTIVE", 0.0)):
+        f.write("| kernel | launches | waves / launch | avg launch (us) | BF16 TFLOP/s | of peak | MFMA busy "
+                "| LDS insts / wave | bank-conflict cycles / LDS inst | LDS wait cycles / wave |\n"
+                "|---|---|---|---|---|---|---|---|---|---|\n")
+        for k in sorted(agg, key=lambda k: -agg[k].get("duration_ns", 0.0)):
             m = agg[k]
             w = m.get("SQ_WAVES", 0.0)
             if not w:
                 continue
             gui = m.get("GRBM_GUI_ACTIVE", 0.0)
-            mb = m.get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0) / (gui * 256 * 4) if gui else 0.0
+            mb = m.get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0) * 8 / (gui * 1024) if gui else 0.0
             lds = m.get("SQ_INSTS_LDS", 0.0)
-            f.write(f"| `{k}` | {calls[k]} | {w / max(calls[k], 1):.0f} | {mb:.3f} | {lds / w:.1f} | "
+            dur = m.get("duration_ns", 0.0)
+            tf = m.get("SQ_INSTS_VALU_MFMA_MOPS_BF16", 0.0) * 512 / dur / 1e3 if dur else 0.0
+            f.write(f"| `{k}` | {calls[k]} | {w / max(calls[k], 1):.0f} | {dur / 1e3 / max(calls[k], 1):.1f} | "
+                    f"{tf:.0f} | {tf / 2500:.3f} | {mb:.3f} | {lds / w:.1f} | "
                     f"{m.get('SQ_LDS_BANK_CONFLICT', 0.0) / max(lds, 1):.2f} | "
-                    f"{m.get('SQ_WAIT_INST_LDS', 0.0) / w:.0f} | "
-                    f"{m.get('SQ_INSTS_VALU_MFMA_MOPS_BF16', 0.0) / w:.1f} |\n")
+                    f"{m.get('SQ_WAIT_INST_LDS', 0.0) / w:.0f} |\n")
 
 
 if __name__ == "__main__":

@@ -49,3 +49,26 @@ def test_overlap_chain(tmp_path):
 def test_short_names():
     assert P.short_name("void lbm::k_step<19, 0>(lbm::Geo, float const*)") == "k_step<19, 0>"
     assert P.short_name("void nn::k_wgrad<true>(nn::ConvArgs)") == "k_wgrad<true>"
+
+
+def test_mfma_summary_rates(tmp_path):
+    """One dispatch of 10 us with 1 000 wavefronts of 10 000 BF16 MOPS each:
+    5.12 GFLOP in 10 us = 512 TFLOP/s, 0.205 of the dense peak; MFMA busy
+    from cycles summed over the 8 XCDs."""
+    path = tmp_path / "c.csv"
+    fields = ["Kernel_Name", "Counter_Name", "Counter_Value", "Start_Timestamp", "End_Timestamp"]
+    gui = 8 * 2.4e9 * 10e-6                     # 8 XCDs x 2.4 GHz x 10 us
+    vals = {"SQ_WAVES": 1000, "SQ_INSTS_VALU_MFMA_MOPS_BF16": 1000 * 10_000, "GRBM_GUI_ACTIVE": gui,
+            "SQ_VALU_MFMA_BUSY_CYCLES": 0.25 * gui / 8 * 1024, "SQ_INSTS_LDS": 2000, "SQ_LDS_BANK_CONFLICT": 1000,
+            "SQ_WAIT_INST_LDS": 5000}
+    with open(path, "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=fields)
+        w.writeheader()
+        for name, v in vals.items():
+            w.writerow({"Kernel_Name": "void nn::k_wgrad_halo<32, 1, 4>(nn::ConvArgs)", "Counter_Name": name,
+                        "Counter_Value": v, "Start_Timestamp": 0, "End_Timestamp": 10_000})
+    out = tmp_path / "m.md"
+    P.mfma(str(path), str(out), "cmd")
+    row = [ln for ln in out.read_text().splitlines() if ln.startswith("| `k_wgrad_halo")][0]
+    cells = [c.strip() for c in row.strip("|").split("|")]
+    assert cells[1:] == ["1", "1000", "10.0", "512", "0.205", "0.250", "2.0", "0.50", "5"]

@@ -371,7 +371,7 @@ constexpr int HC = 32, HCP = HC + 8;                                 // chunk ch
 // the same staging and 9 taps for each of the three input planes z - 1, z,
 // z + 1 (taps dz * 9 + dy * 3 + dx), skipping planes outside the volume.
 template <int TN, int DIMS>
-__global__ void __launch_bounds__(256) k_conv3x3_halo(ConvArgs a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_conv3x3_halo(ConvArgs a) {
     constexpr int WNT = TN / 16;
     constexpr int PATCH = HP * HCP, WTS = 9 * TN * HCP;
     constexpr int TL = TN + 4;
@@ -393,30 +393,61 @@ __global__ void __launch_bounds__(256) k_conv3x3_halo(ConvArgs a) {
 #pragma unroll
         for (int j = 0; j < WNT; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     const int kq = (lane >> 4) * 8;
-    for (int c0 = 0; c0 < a.cin; c0 += HC)
-    for (int dz = 0; dz < (DIMS == 3 ? 3 : 1); ++dz) {
-        const int zz = DIMS == 3 ? z + dz - 1 : 0;
-        if ((unsigned)zz >= (unsigned)a.d) continue;        // a zero plane adds nothing (block-uniform)
-        const int tap0 = DIMS == 3 ? dz * 9 : 0;
-        for (int e = t; e < HP * 4; e += 256) {
+    // Stages are (chunk, input plane) pairs; a plane outside the volume adds
+    // nothing and is skipped (block-uniform).  A stage's patch and weights
+    // are loaded into registers in one batch (every load in flight at once)
+    // while the previous stage multiplies, then written to LDS.
+    constexpr int NDZ = DIMS == 3 ? 3 : 1;
+    constexpr int NPL = (HP * 4 + 255) / 256, NWL = (9 * TN * 4 + 255) / 256;
+    const int nst = (a.cin / HC) * NDZ;
+    auto plane_ok = [&](int st) { return DIMS == 2 || (unsigned)(z + st % NDZ - 1) < (unsigned)a.d; };
+    auto next_stage = [&](int st) {
+        do ++st; while (st < nst && !plane_ok(st));
+        return st;
+    };
+    uint4 pv[NPL], wv[NWL];
+    auto load = [&](int st) {
+        const int c0 = (st / NDZ) * HC, dz = st % NDZ;
+        const int zz = DIMS == 3 ? z + dz - 1 : 0, tap0 = DIMS == 3 ? dz * 9 : 0;
+#pragma unroll
+        for (int k = 0; k < NPL; ++k) {
+            const int e = t + 256 * k;
             const int pp = e >> 2, g8 = (e & 3) * 8;
             const int py = pp / HPX, px = pp - py * HPX;
             const int yy = y0 + py - 1, xx = x0 + px - 1;
-            uint4 v = make_uint4(0, 0, 0, 0);
-            if ((unsigned)yy < (unsigned)a.h && (unsigned)xx < (unsigned)a.w)
-                v = *(const uint4 *)(a.in + ((((long long)b * a.d + zz) * a.h + yy) * a.w + xx) * a.in_cs + a.in_co +
-                                     c0 + g8);
-            *(uint4 *)&P[pp * HCP + g8] = v;
+            pv[k] = make_uint4(0, 0, 0, 0);
+            if (e < HP * 4 && (unsigned)yy < (unsigned)a.h && (unsigned)xx < (unsigned)a.w)
+                pv[k] = *(const uint4 *)(a.in + ((((long long)b * a.d + zz) * a.h + yy) * a.w + xx) * a.in_cs +
+                                         a.in_co + c0 + g8);
         }
-        for (int e = t; e < 9 * TN * 4; e += 256) {
+#pragma unroll
+        for (int k = 0; k < NWL; ++k) {
+            const int e = t + 256 * k;
             const int g8 = (e & 3) * 8, r = e >> 2;
             const int tap = r / TN, n = r - tap * TN;
-            uint4 v = make_uint4(0, 0, 0, 0);
-            if (n0 + n < a.ncols)
-                v = *(const uint4 *)(a.wt + (long long)(n0 + n) * a.K + (tap0 + tap) * a.cin + c0 + g8);
-            *(uint4 *)&Wl[r * HCP + g8] = v;
+            wv[k] = make_uint4(0, 0, 0, 0);
+            if (e < 9 * TN * 4 && n0 + n < a.ncols)
+                wv[k] = *(const uint4 *)(a.wt + (long long)(n0 + n) * a.K + (tap0 + tap) * a.cin + c0 + g8);
+        }
+    };
+    int st = plane_ok(0) ? 0 : next_stage(0);
+    if (st < nst) load(st);
+    for (; st < nst;) {
+        __syncthreads();                                   // the previous stage's operand reads are done
+#pragma unroll
+        for (int k = 0; k < NPL; ++k) {
+            const int e = t + 256 * k;
+            if (e < HP * 4) *(uint4 *)&P[(e >> 2) * HCP + (e & 3) * 8] = pv[k];
+        }
+#pragma unroll
+        for (int k = 0; k < NWL; ++k) {
+            const int e = t + 256 * k;
+            if (e < 9 * TN * 4) *(uint4 *)&Wl[(e >> 2) * HCP + (e & 3) * 8] = wv[k];
         }
         __syncthreads();
+        const int nx = next_stage(st);
+        if (nx < nst) load(nx);
+        st = nx;
 #pragma unroll 1
         for (int tap = 0; tap < 9; ++tap) {
             const int dy = tap / 3, dx = tap - dy * 3;       // tap (dx - 1, dy - 1) reads patch (+dx, +dy)
@@ -432,8 +463,8 @@ __global__ void __launch_bounds__(256) k_conv3x3_halo(ConvArgs a) {
                 for (int j = 0; j < WNT; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, fb[j], acc[i][j], 0, 0, 0);
             }
         }
-        __syncthreads();
     }
+    __syncthreads();                                       // the last stage's operand reads are done
     // epilogue: tile pixel p = row * 32 + column, staged as floats in the same LDS
     float *T = reinterpret_cast<float *>(sm);
 #pragma unroll

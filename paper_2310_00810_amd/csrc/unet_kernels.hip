@@ -365,7 +365,14 @@ __global__ void __launch_bounds__(256) k_conv(ConvArgs a, float *__restrict__ pa
 // and all TN output columns.  The epilogue stages the tile in the same LDS and
 // stores 8 channels of a pixel with one 16-byte write.
 constexpr int HY = 8, HX = 32, HPX = HX + 2, HP = (HY + 2) * HPX;   // tile rows, columns, patch
-constexpr int HC = 32, HCP = HC + 8;                                 // chunk channels; padded LDS row
+constexpr int HC = 32;                                               // chunk channels (64-byte LDS rows)
+
+// Half-word offset of 16-byte granule g (0..3) of LDS row `row` in the halo
+// kernel's patch and weight tiles: the granules of a row are XOR-swizzled by
+// (row >> 2) & 3, so the 16 consecutive rows that an MFMA operand read
+// touches (one granule each) and the 4 rows x 4 granules of a staging write
+// fall on 16 distinct 16-byte bank groups.
+__device__ inline int hsw(int row, int g) { return row * HC + ((g ^ ((row >> 2) & 3)) << 3); }
 
 // In 3D a block takes one 8 x 32 tile of one plane z and, per chunk, runs
 // the same staging and 9 taps for each of the three input planes z - 1, z,
@@ -373,7 +380,7 @@ constexpr int HC = 32, HCP = HC + 8;                                 // chunk ch
 template <int TN, int DIMS>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_conv3x3_halo(ConvArgs a) {
     constexpr int WNT = TN / 16;
-    constexpr int PATCH = HP * HCP, WTS = 9 * TN * HCP;
+    constexpr int PATCH = HP * HC, WTS = 9 * TN * HC;
     constexpr int TL = TN + 4;
     constexpr int ELEMS = PATCH + WTS > 2 * 256 * TL ? PATCH + WTS : 2 * 256 * TL;
     __shared__ __align__(16) uint16_t sm[ELEMS];
@@ -392,7 +399,6 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < WNT; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const int kq = (lane >> 4) * 8;
     // Stages are (chunk, input plane) pairs; a plane outside the volume adds
     // nothing and is skipped (block-uniform).  A stage's patch and weights
     // are loaded into registers in one batch (every load in flight at once)
@@ -437,12 +443,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
 #pragma unroll
         for (int k = 0; k < NPL; ++k) {
             const int e = t + 256 * k;
-            if (e < HP * 4) *(uint4 *)&P[(e >> 2) * HCP + (e & 3) * 8] = pv[k];
+            if (e < HP * 4) *(uint4 *)&P[hsw(e >> 2, e & 3)] = pv[k];
         }
 #pragma unroll
         for (int k = 0; k < NWL; ++k) {
             const int e = t + 256 * k;
-            if (e < 9 * TN * 4) *(uint4 *)&Wl[(e >> 2) * HCP + (e & 3) * 8] = wv[k];
+            if (e < 9 * TN * 4) *(uint4 *)&Wl[hsw(e >> 2, e & 3)] = wv[k];
         }
         __syncthreads();
         const int nx = next_stage(st);
@@ -454,11 +460,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
             bf16x8 fb[WNT];
 #pragma unroll
             for (int j = 0; j < WNT; ++j)
-                fb[j] = as_bf16x8(*(const uint4 *)&Wl[(tap * TN + j * 16 + (lane & 15)) * HCP + kq]);
+                fb[j] = as_bf16x8(*(const uint4 *)&Wl[hsw(tap * TN + j * 16 + (lane & 15), lane >> 4)]);
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int pr = 2 * wave + (i >> 1), pc = (i & 1) * 16 + (lane & 15);
-                const bf16x8 fa = as_bf16x8(*(const uint4 *)&P[((pr + dy) * HPX + pc + dx) * HCP + kq]);
+                const bf16x8 fa = as_bf16x8(*(const uint4 *)&P[hsw((pr + dy) * HPX + pc + dx, lane >> 4)]);
 #pragma unroll
                 for (int j = 0; j < WNT; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, fb[j], acc[i][j], 0, 0, 0);
             }

@@ -1029,6 +1029,90 @@ __global__ void k_pool_bwd(const uint16_t *__restrict__ in, int in_cs, int in_co
     }
 }
 
+// The same two passes on 8 channels of a pixel per thread with 16-byte
+// accesses (channel counts, strides and offsets multiples of 8, 16-byte
+// aligned buffers); per channel the same operations in the same order.
+__device__ inline void unpack8(uint4 v, float (&f)[8]) {
+    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        f[2 * k] = bf2f((uint16_t)(w[k] & 0xffffu));
+        f[2 * k + 1] = bf2f((uint16_t)(w[k] >> 16));
+    }
+}
+__device__ inline uint4 pack8(const float (&f)[8]) {
+    uint32_t w[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) w[k] = (uint32_t)f2bf(f[2 * k]) | ((uint32_t)f2bf(f[2 * k + 1]) << 16);
+    return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+__global__ void __launch_bounds__(256) k_pool_fwd8(const uint16_t *__restrict__ in, int in_cs, int in_co,
+                                                   uint16_t *__restrict__ out, int out_cs, int out_co, int n, int d,
+                                                   int h, int w, int C, int dims) {
+    const int CG = C >> 3;
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long long)n * d * h * w * CG) return;
+    const long long m = i / CG;
+    const int c = (int)(i - m * CG) * 8;
+    const Pix p = pix_of(m, d, h, w);
+    const int fd = dims == 3 ? 2 * d : 1;
+    float best[8], v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) best[k] = -INFINITY;
+    for (int sub = 0; sub < (1 << dims); ++sub) {
+        const int sx = sub & 1, sy = (sub >> 1) & 1, sz = (sub >> 2) & 1;
+        const int zf = dims == 3 ? 2 * p.z + sz : 0;
+        const long long f = (((long long)p.b * fd + zf) * (2 * h) + 2 * p.y + sy) * (2 * w) + 2 * p.x + sx;
+        unpack8(*(const uint4 *)(in + f * in_cs + in_co + c), v);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) best[k] = fmaxf(best[k], v[k]);
+    }
+    *(uint4 *)(out + m * out_cs + out_co + c) = pack8(best);
+}
+
+__global__ void __launch_bounds__(256) k_pool_bwd8(const uint16_t *__restrict__ in, int in_cs, int in_co,
+                                                   const uint16_t *__restrict__ gout, int g_cs, int g_co,
+                                                   uint16_t *__restrict__ gin, int gi_cs, int gi_co, int n, int d,
+                                                   int h, int w, int C, int dims, int accumulate) {
+    const int CG = C >> 3;
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long long)n * d * h * w * CG) return;
+    const long long m = i / CG;
+    const int c = (int)(i - m * CG) * 8;
+    const Pix p = pix_of(m, d, h, w);
+    const int fd = dims == 3 ? 2 * d : 1;
+    float best[8], v[8], gv[8];
+    int arg[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) { best[k] = -INFINITY; arg[k] = 0; }
+    long long fidx[8];
+    for (int sub = 0; sub < (1 << dims); ++sub) {
+        const int sx = sub & 1, sy = (sub >> 1) & 1, sz = (sub >> 2) & 1;
+        const int zf = dims == 3 ? 2 * p.z + sz : 0;
+        fidx[sub] = (((long long)p.b * fd + zf) * (2 * h) + 2 * p.y + sy) * (2 * w) + 2 * p.x + sx;
+        unpack8(*(const uint4 *)(in + fidx[sub] * in_cs + in_co + c), v);
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            if (v[k] > best[k]) { best[k] = v[k]; arg[k] = sub; }
+    }
+    unpack8(*(const uint4 *)(gout + m * g_cs + g_co + c), gv);
+    for (int sub = 0; sub < (1 << dims); ++sub) {
+        uint16_t *o = gin + fidx[sub] * gi_cs + gi_co + c;
+        float r[8];
+        if (accumulate) {
+            unpack8(*(const uint4 *)o, r);
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                if (sub == arg[k]) r[k] = r[k] + gv[k];
+        } else {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) r[k] = sub == arg[k] ? gv[k] : 0.f;
+        }
+        *(uint4 *)o = pack8(r);
+    }
+}
+
 // Masked MSE over the first `creal` channels of an FP32 prediction with
 // channel stride pcs: loss = scale * sum_m w_m sum_c (p - t)^2 and the BF16
 // gradient (pad channels zero).  Per-block partial sums in FP64.
@@ -1355,9 +1439,18 @@ hipError_t relu_bwd(uint16_t *g, const uint16_t *y, int cs, int co, long long np
     return hipGetLastError();
 }
 
+static bool vec8(int a, int b, int c, int e, int f, const void *p, const void *q) {
+    return ((a | b | c | e | f) & 7) == 0 && (((uintptr_t)p | (uintptr_t)q) & 15) == 0;
+}
+
 hipError_t pool_fwd(const uint16_t *in, int in_cs, int in_co, uint16_t *out, int out_cs, int out_co, int n, int d,
                     int h, int w, int C, int dims, hipStream_t s) {
     const long long tot = (long long)n * d * h * w * C;
+    if (vec8(C, in_cs, in_co, out_cs, out_co, in, out)) {
+        hipLaunchKernelGGL(k_pool_fwd8, dim3(blocks(tot / 8, 256)), dim3(256), 0, s, in, in_cs, in_co, out, out_cs,
+                           out_co, n, d, h, w, C, dims);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_pool_fwd, dim3(blocks(tot, 256)), dim3(256), 0, s, in, in_cs, in_co, out, out_cs, out_co,
                        n, d, h, w, C, dims);
     return hipGetLastError();
@@ -1367,6 +1460,11 @@ hipError_t pool_bwd(const uint16_t *in, int in_cs, int in_co, const uint16_t *go
                     uint16_t *gin, int gi_cs, int gi_co, int n, int d, int h, int w, int C, int dims, int acc,
                     hipStream_t s) {
     const long long tot = (long long)n * d * h * w * C;
+    if (vec8(C, in_cs, in_co, g_cs, g_co, in, gout) && vec8(gi_cs, gi_co, 0, 0, 0, gin, nullptr)) {
+        hipLaunchKernelGGL(k_pool_bwd8, dim3(blocks(tot / 8, 256)), dim3(256), 0, s, in, in_cs, in_co, gout, g_cs,
+                           g_co, gin, gi_cs, gi_co, n, d, h, w, C, dims, acc);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_pool_bwd, dim3(blocks(tot, 256)), dim3(256), 0, s, in, in_cs, in_co, gout, g_cs, g_co, gin,
                        gi_cs, gi_co, n, d, h, w, C, dims, acc);
     return hipGetLastError();

@@ -274,28 +274,45 @@ def test_transposed_conv_all_passes(dims):
     assert rel(dw.cpu().numpy(), refw.reshape(S * cr, cin)) <= 1e-5
 
 
+# 16-byte kernels (channel count, strides and offsets multiples of 8) and the
+# per-element ones, overwriting and accumulating, on channel slices of wider buffers.
+POOL = [(8, 8, 0, 0), (16, 24, 8, 1), (12, 12, 0, 1), (6, 10, 2, 0)]
+
+
 @pytest.mark.parametrize("dims", [2, 3])
-def test_pooling_forward_backward(dims):
+@pytest.mark.parametrize("Cn,cs,co,acc", POOL)
+def test_pooling_forward_backward(dims, Cn, cs, co, acc):
     C = C_()
     L = C.nnlib()
     rng = np.random.default_rng(6)
     fine = (2, 1, 8, 12) if dims == 2 else (1, 4, 6, 8)
-    Cn = 8
-    x = bf(rng.standard_normal(fine + (Cn,)))
+    xw = bf(rng.standard_normal(fine + (cs,)))
+    x = xw[..., co:co + Cn]
     n, fd, fh, fw = fine
     coarse = (n, fd // 2 if dims == 3 else 1, fh // 2, fw // 2)
-    xd = dev_bf(x)
-    y = torch.empty(coarse + (Cn,), dtype=torch.bfloat16, device="cuda")
-    C.check(L.lbmnn_pool_fwd(xd.data_ptr(), Cn, 0, y.data_ptr(), Cn, 0, *coarse, Cn, dims, stream()), "pool")
+    xd = dev_bf(xw)
+    y = torch.zeros(coarse + (cs,), dtype=torch.bfloat16, device="cuda")
+    C.check(L.lbmnn_pool_fwd(xd.data_ptr(), cs, co, y.data_ptr(), cs, co, *coarse, Cn, dims, stream()), "pool")
     torch.cuda.synchronize()
-    assert np.array_equal(y.to(torch.float64).cpu().numpy(), N.pool_fwd(x, dims))
-    g = bf(rng.standard_normal(coarse + (Cn,)))
-    gi = dev_bf(np.ones(fine + (Cn,)))
-    gd = dev_bf(g)
-    C.check(L.lbmnn_pool_bwd(xd.data_ptr(), Cn, 0, gd.data_ptr(), Cn, 0, gi.data_ptr(), Cn, 0, *coarse, Cn,
-                             dims, 0, stream()), "pool_bwd")
+    yh = y.to(torch.float64).cpu().numpy()
+    assert np.array_equal(yh[..., co:co + Cn], N.pool_fwd(x, dims))
+    assert np.all(np.delete(yh, np.s_[co:co + Cn], axis=-1) == 0)
+    gw = bf(rng.standard_normal(coarse + (cs,)))
+    g = gw[..., co:co + Cn]
+    base = bf(rng.standard_normal(fine + (cs,)))
+    gi = dev_bf(base)
+    gd = dev_bf(gw)
+    C.check(L.lbmnn_pool_bwd(xd.data_ptr(), cs, co, gd.data_ptr(), cs, co, gi.data_ptr(), cs, co, *coarse, Cn,
+                             dims, acc, stream()), "pool_bwd")
     torch.cuda.synchronize()
-    assert np.array_equal(gi.to(torch.float64).cpu().numpy(), N.pool_bwd(x, g, dims))
+    got = gi.to(torch.float64).cpu().numpy()
+    routed = N.pool_bwd(x, g, dims)
+    if acc:
+        exp = np.where(routed != 0, N.bf16_round(base[..., co:co + Cn] + routed), base[..., co:co + Cn])
+    else:
+        exp = routed
+    assert np.array_equal(got[..., co:co + Cn], exp)
+    assert np.array_equal(np.delete(got, np.s_[co:co + Cn], axis=-1), np.delete(base, np.s_[co:co + Cn], axis=-1))
 
 
 def _oracle_params(net):

@@ -236,7 +236,7 @@ int lbm_adjoint(lbm_handle *h, const float *d_seed_du);
  * LBM_EDEVICE. */
 int lbm_grad(lbm_handle *h, double *d_rho_in, double *d_tau, double *d_rho_out);
 
-/* Steady state of the forward map (Section 3.1.1 judges it by the plateau
+/* Steady state of the forward map (Section 3.1.1 takes it from the plateau
  * of the kinetic energy): steps from the initial state until the velocity
  * residual of every instance is <= tol, testing every check_every steps
  * (even, >= 4), or until max_steps.  The residual at a check t is the mean

@@ -356,8 +356,9 @@ __global__ void __launch_bounds__(256) k_conv(ConvArgs a, float *__restrict__ pa
         }
 }
 
-// 3 x 3 convolution of a 2D layer whose input channels come in chunks of 32,
-// on tiles of 8 x 32 pixels (the image sizes must be multiples of those).  Per
+// 3 x 3 convolution of a 2D layer whose input channels come in chunks of 32
+// (a last, shorter chunk is zero-filled), on tiles of 8 x 32 pixels (the
+// image sizes must be multiples of those).  Per
 // chunk, the tile's input patch with its one-pixel halo (10 x 34 pixels) and
 // the chunk's weights of all 9 taps are staged in LDS once; the 9 taps then
 // read their MFMA operands from LDS, so each input pixel crosses L2 about
@@ -405,7 +406,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
     // while the previous stage multiplies, then written to LDS.
     constexpr int NDZ = DIMS == 3 ? 3 : 1;
     constexpr int NPL = (HP * 4 + 255) / 256, NWL = (9 * TN * 4 + 255) / 256;
-    const int nst = (a.cin / HC) * NDZ;
+    const int nst = ((a.cin + HC - 1) / HC) * NDZ;          // a last chunk of fewer channels is zero-filled
     auto plane_ok = [&](int st) { return DIMS == 2 || (unsigned)(z + st % NDZ - 1) < (unsigned)a.d; };
     auto next_stage = [&](int st) {
         do ++st; while (st < nst && !plane_ok(st));
@@ -422,7 +423,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
             const int py = pp / HPX, px = pp - py * HPX;
             const int yy = y0 + py - 1, xx = x0 + px - 1;
             pv[k] = make_uint4(0, 0, 0, 0);
-            if (e < HP * 4 && (unsigned)yy < (unsigned)a.h && (unsigned)xx < (unsigned)a.w)
+            if (e < HP * 4 && c0 + g8 < a.cin && (unsigned)yy < (unsigned)a.h && (unsigned)xx < (unsigned)a.w)
                 pv[k] = *(const uint4 *)(a.in + ((((long long)b * a.d + zz) * a.h + yy) * a.w + xx) * a.in_cs +
                                          a.in_co + c0 + g8);
         }
@@ -432,7 +433,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
             const int g8 = (e & 3) * 8, r = e >> 2;
             const int tap = r / TN, n = r - tap * TN;
             wv[k] = make_uint4(0, 0, 0, 0);
-            if (e < 9 * TN * 4 && n0 + n < a.ncols)
+            if (e < 9 * TN * 4 && c0 + g8 < a.cin && n0 + n < a.ncols)
                 wv[k] = *(const uint4 *)(a.wt + (long long)(n0 + n) * a.K + (tap0 + tap) * a.cin + c0 + g8);
         }
     };
@@ -1226,7 +1227,7 @@ static inline unsigned blocks(long long n, int b) { return (unsigned)((n + b - 1
 
 static bool halo_ok(const ConvArgs &a) {
     const uintptr_t ob = a.out32 ? (uintptr_t)a.out32 : (uintptr_t)a.out;
-    return (a.dims == 2 || a.dims == 3) && a.ks == 3 && !(a.flags & (FLAG_S2D | FLAG_D2S)) && a.cin % HC == 0 &&
+    return (a.dims == 2 || a.dims == 3) && a.ks == 3 && !(a.flags & (FLAG_S2D | FLAG_D2S)) && a.cin % 8 == 0 &&
            a.h % HY == 0 &&
            a.w % HX == 0 && ((a.in_cs | a.in_co | a.out_cs | a.out_co) & 7) == 0 && ((uintptr_t)a.in & 15) == 0 &&
            (ob & 15) == 0;

@@ -90,7 +90,8 @@ def transpose_call(W, rows, taps, cols, flip):
 CASES = [(2, 3, (2, 1, 20, 24), 16, 24), (2, 1, (2, 1, 8, 16), 32, 8), (2, 3, (2, 1, 256, 256), 64, 64),
          (3, 3, (1, 6, 8, 10), 8, 16), (2, 3, (1, 1, 64, 64), 64, 32), (2, 3, (2, 1, 256, 256), 32, 40),
          (2, 3, (2, 1, 256, 256), 32, 32), (3, 3, (2, 16, 64, 64), 32, 32), (3, 3, (4, 8, 64, 64), 64, 40),
-         (3, 3, (2, 32, 32, 32), 32, 64)]
+         (3, 3, (2, 32, 32, 32), 32, 64), (2, 3, (2, 1, 256, 256), 8, 32), (2, 3, (2, 1, 256, 256), 24, 32),
+         (3, 3, (2, 16, 64, 64), 8, 32)]
 
 
 @pytest.mark.parametrize("dims,ks,grid,cin,cout", CASES)

@@ -43,9 +43,10 @@ Q = 19
 BYTES_FWD = 2 * Q * 4        # read + write one population set per fluid node
 BYTES_ADJ = 3 * Q * 4        # gather F^{k-1}, gather nu^{k+1}, write nu^k
 PROFILES = os.path.join(ROOT, "profiles")
-# kernel names as the profiler reports them (template arguments: Q, x boundary kind = pressure)
-ADJ_KERNEL = "k_adj_step<19, 0, false>"
-FWD_KERNEL = "k_step<19, 0>"
+# kernel names as the profiler reports them (template arguments: Q, x boundary kind = pressure,
+# [adjoint: no loss frame on the step,] stores not non-temporal: the 128^3 states fit the Infinity Cache)
+ADJ_KERNEL = "k_adj_step<19, 0, false, false>"
+FWD_KERNEL = "k_step<19, 0, false>"
 
 
 def workload(n=128, T=8000, K=400, kind="spheres"):

@@ -490,6 +490,10 @@ int lbm_init(lbm_handle **out, const lbm_problem *p, void *d_workspace, size_t b
     for (int r = 0; r < 9; ++r) h->G.mrt[r] = (float)p->mrt_rates[r];
     h->G.rw = h->at<uint2>(L.off_mask);
     h->G.n_ftiles = L.n_ftiles;
+    // a step reads one state and writes another: when the two exceed the
+    // 256 MiB Infinity Cache the written lines only evict what the next step
+    // reads, so step and adjoint stores go out non-temporal
+    h->G.nt = 2 * L.state_bytes > ((size_t)256 << 20);
     h->G.fblk = h->at<lbm::FTileDesc>(L.off_fblk);
     hipError_t he = lbm::launch_init_eq(L.q, h->G, h->init(), nullptr, nullptr, h->stream);
     if (he == hipSuccess) he = hipStreamSynchronize(h->stream);

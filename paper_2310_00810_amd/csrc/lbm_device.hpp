@@ -140,6 +140,7 @@ struct Geo {
     const FTileDesc *fblk; // per fluid tile
     int coll;              // COLL_BGK or COLL_MRT (D2Q9)
     float mrt[9];          // MRT rates of the D2Q9 moments; stress entries unused (1/tau)
+    int nt;                // step and adjoint stores non-temporal (two states exceed the Infinity Cache)
 };
 
 // Block index -> tile index such that the blocks the hardware places on one
@@ -472,8 +473,13 @@ __device__ inline int plane_off(int i, int plane) { return (int)((unsigned)i * (
 __device__ inline float bload(__amdgpu_buffer_rsrc_t r, unsigned off) {
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
 }
+// NT: the store carries the non-temporal cache policy (cache-policy bit 1,
+// "nt" on gfx950), for states whose ping-pong pair does not fit the
+// Infinity Cache, where keeping the written lines only evicts lines the
+// next step reads.
+template <bool NT = false>
 __device__ inline void bstore(__amdgpu_buffer_rsrc_t r, float v, unsigned voff, int soff) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, NT ? 2 : 0);
 }
 __device__ inline unsigned bload_bits(__amdgpu_buffer_rsrc_t r, unsigned voff, int soff) {
     return __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0);

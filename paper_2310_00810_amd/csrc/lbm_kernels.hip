@@ -60,7 +60,7 @@ __device__ inline void face_unknown_adjoints(__amdgpu_buffer_rsrc_t rn, int plan
         if (V::cx(i) != 0 && (V::cx(i) > 0 ? in : out)) nuo[i] = bload(rn, own + (unsigned)(i * plane) * 4u);
 }
 
-template <int Q, int BCX>
+template <int Q, int BCX, bool NT>
 __global__ void __launch_bounds__(FT) k_step(Geo G, const float *__restrict__ src,
                                              float *__restrict__ dst,
                                              const float *__restrict__ face_in,
@@ -92,12 +92,12 @@ __global__ void __launch_bounds__(FT) k_step(Geo G, const float *__restrict__ sr
             for (int i = 0; i < 9; ++i) d[i] = g[i] - feq[i];
             mrt_relax(d, G.mrt, om, r);
 #pragma unroll
-            for (int i = 0; i < 9; ++i) bstore(rd, g[i] - r[i], own, plane_off(i, plane));
+            for (int i = 0; i < 9; ++i) bstore<NT>(rd, g[i] - r[i], own, plane_off(i, plane));
             return;
         }
     }
 #pragma unroll
-    for (int i = 0; i < Q; ++i) bstore(rd, g[i] + om * (feq[i] - g[i]), own, plane_off(i, plane));
+    for (int i = 0; i < Q; ++i) bstore<NT>(rd, g[i] + om * (feq[i] - g[i]), own, plane_off(i, plane));
 }
 
 // Bit-for-bit comparison of two states over the fluid nodes of every
@@ -243,7 +243,7 @@ __global__ void __launch_bounds__(FT) k_adj_seed(Geo G, const float *__restrict_
 // collision transpose is  a_i = (1 - omega) lam_i + omega (A + B . c_i)  with
 //   A   = sum_k lam_k dfeq_k/drho = S0 (1 + 1.5 u.u) - 4.5 u.S2.u,
 //   B_a = sum_k lam_k dfeq_k/dj_a = 3 S_a + 9 (S2 u)_a - 3 u_a S0.
-template <int Q, int BCX, bool SEED>
+template <int Q, int BCX, bool SEED, bool NT>
 __global__ void __launch_bounds__(FT) __attribute__((amdgpu_waves_per_eu(6))) k_adj_step(Geo G, const float *__restrict__ Fprev,
                                                  const float *__restrict__ nu_in,
                                                  float *__restrict__ nu_out,
@@ -372,7 +372,7 @@ __global__ void __launch_bounds__(FT) __attribute__((amdgpu_waves_per_eu(6))) k_
         }
         const __amdgpu_buffer_rsrc_t rd = planes_rsrc(nu_out + I.st_off, Q, I.plane);
 #pragma unroll
-        for (int i = 0; i < Q; ++i) bstore(rd, a[i], own, plane_off(i, plane));
+        for (int i = 0; i < Q; ++i) bstore<NT>(rd, a[i], own, plane_off(i, plane));
     }
     const double sum = block_sum(dtau, red);
     if (threadIdx.x == 0) dtau_part[t.tile] += sum;
@@ -609,7 +609,11 @@ static inline dim3 fgrid_of(const Geo &G) { return dim3((unsigned)G.n_ftiles); }
 hipError_t launch_step(int q, const Geo &G, const float *src, float *dst, const float *fin,
                        const float *fout, hipStream_t s) {
     if (G.n_ftiles == 0) return hipSuccess;
-#define CALL(Q, B) hipLaunchKernelGGL((k_step<Q, B>), fgrid_of(G), dim3(FT), 0, s, G, src, dst, fin, fout)
+#define CALL(Q, B)                                                                                 \
+    do {                                                                                           \
+        if (G.nt) hipLaunchKernelGGL((k_step<Q, B, true>), fgrid_of(G), dim3(FT), 0, s, G, src, dst, fin, fout); \
+        else hipLaunchKernelGGL((k_step<Q, B, false>), fgrid_of(G), dim3(FT), 0, s, G, src, dst, fin, fout); \
+    } while (0)
     DISPATCH_BCX(q, G.bcx, CALL);
 #undef CALL
     return hipGetLastError();
@@ -648,11 +652,14 @@ hipError_t launch_adj_step(int q, const Geo &G, const float *Fprev, const float 
 #define CALL(Q, B)                                                                                 \
     do {                                                                                           \
         if (target)                                                                                \
-            hipLaunchKernelGGL((k_adj_step<Q, B, true>), fgrid_of(G), dim3(FT), 0, s, G, Fprev, nu_in, nu_out, \
-                               fin, fout, gin, gout, dtau_part, roi, target, kind);                 \
+            hipLaunchKernelGGL((k_adj_step<Q, B, true, false>), fgrid_of(G), dim3(FT), 0, s, G, Fprev, nu_in, \
+                               nu_out, fin, fout, gin, gout, dtau_part, roi, target, kind);         \
+        else if (G.nt)                                                                             \
+            hipLaunchKernelGGL((k_adj_step<Q, B, false, true>), fgrid_of(G), dim3(FT), 0, s, G, Fprev, nu_in, \
+                               nu_out, fin, fout, gin, gout, dtau_part, roi, target, kind);         \
         else                                                                                       \
-            hipLaunchKernelGGL((k_adj_step<Q, B, false>), fgrid_of(G), dim3(FT), 0, s, G, Fprev, nu_in, nu_out, \
-                               fin, fout, gin, gout, dtau_part, roi, target, kind);                 \
+            hipLaunchKernelGGL((k_adj_step<Q, B, false, false>), fgrid_of(G), dim3(FT), 0, s, G, Fprev, nu_in, \
+                               nu_out, fin, fout, gin, gout, dtau_part, roi, target, kind);         \
     } while (0)
     DISPATCH_BCX(q, G.bcx, CALL);
 #undef CALL

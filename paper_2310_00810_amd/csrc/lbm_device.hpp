@@ -470,8 +470,10 @@ __device__ inline __amdgpu_buffer_rsrc_t planes_rsrc(const float *base, int q, l
     return __builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, (int)(unsigned)(q * plane * 4), 0x00020000);
 }
 __device__ inline int plane_off(int i, int plane) { return (int)((unsigned)i * (unsigned)plane * 4u); }
+// NT: the load carries the non-temporal cache policy (see bstore).
+template <bool NT = false>
 __device__ inline float bload(__amdgpu_buffer_rsrc_t r, unsigned off) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, NT ? 2 : 0));
 }
 // NT: the store carries the non-temporal cache policy (cache-policy bit 1,
 // "nt" on gfx950), for states whose ping-pong pair does not fit the
@@ -490,33 +492,33 @@ __device__ inline unsigned bload_bits(__amdgpu_buffer_rsrc_t r, unsigned voff, i
 //   open  -> 0 for Zou-He faces (the closure fills the slot), and F_k(x), the
 //            population that left through the face, for anti-bounce-back
 //            faces (the closure negates and corrects it).
-template <int Q, int BCX>
+template <int Q, int BCX, bool NTL = false>
 __device__ inline void gather_fwd(__amdgpu_buffer_rsrc_t r, int plane, const Links<Q> &k, float (&g)[Q]) {
     using V = Vel<Q>;
     const unsigned own = (unsigned)k.id * 4u;
-    g[0] = bload(r, own);
+    g[0] = bload<NTL>(r, own);
 #pragma unroll
     for (int q = 1; q < Q; ++q) {
         const int i = V::opp(q);
         const bool back = BCX == BC_ABB && V::cx(q) != 0 ? (k.wall[q] || k.open[q]) : k.wall[q];
         unsigned off = back ? own + (unsigned)(q * plane) * 4u : (unsigned)(i * plane + k.fid[q]) * 4u;
         if (zouhe_faces(BCX) && V::cx(q) != 0) off = k.open[q] ? OOB : off;
-        g[i] = bload(r, off);
+        g[i] = bload<NTL>(r, off);
     }
 }
 
 // Transpose of streaming (pull of nu from x + c_k): lam_k(x) =
 //   fluid -> nu_k(x + c_k);  wall -> nu_opp(k)(x);  open -> 0.
-template <int Q>
+template <int Q, bool NTL = false>
 __device__ inline void gather_adj(__amdgpu_buffer_rsrc_t r, int plane, const Links<Q> &k, float (&lam)[Q]) {
     using V = Vel<Q>;
     const unsigned own = (unsigned)k.id * 4u;
-    lam[0] = bload(r, own);
+    lam[0] = bload<NTL>(r, own);
 #pragma unroll
     for (int q = 1; q < Q; ++q) {
         unsigned off = k.wall[q] ? own + (unsigned)(V::opp(q) * plane) * 4u : (unsigned)(q * plane + k.fid[q]) * 4u;
         if (V::cx(q) != 0) off = k.open[q] ? OOB : off;
-        lam[q] = bload(r, off);
+        lam[q] = bload<NTL>(r, off);
     }
 }
 

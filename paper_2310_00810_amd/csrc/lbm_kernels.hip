@@ -76,7 +76,9 @@ __global__ void __launch_bounds__(FT) k_step(Geo G, const float *__restrict__ sr
     Links<Q> k;
     links<Q, BCX>(G, I, t, L, n, k);
     float g[Q];
-    gather_fwd<Q, BCX>(rs, plane, k, g);
+    // beyond the Infinity Cache D3Q19 gathers read non-temporal too; D2Q9 ones
+    // do not (other blocks reread their neighbouring rows' lines)
+    gather_fwd<Q, BCX, NT && Q == 19>(rs, plane, k, g);
     if (zouhe_faces(BCX) && wave_has_face(in || out)) zouhe<Q>(g, in, out, drho_b, BCX == BC_VELOCITY);
     if (BCX == BC_ABB) abb<Q>(g, in, out, drho_b, uF);
     const Moments m = moments<Q>(g);
@@ -278,8 +280,8 @@ __global__ void __launch_bounds__(FT) __attribute__((amdgpu_waves_per_eu(6))) k_
         Links<Q> k;
         links<Q, BCX>(G, I, t, L, n, k);
         float g[Q], lam[Q];
-        gather_fwd<Q, BCX>(rs, plane, k, g);
-        gather_adj<Q>(rn, plane, k, lam);
+        gather_fwd<Q, BCX, NT && Q == 19>(rs, plane, k, g);
+        gather_adj<Q, NT && Q == 19>(rn, plane, k, lam);
         if (zouhe_faces(BCX)) zouhe<Q>(g, in, out, drho_b, BCX == BC_VELOCITY);
         if (BCX == BC_ABB) abb<Q>(g, in, out, drho_b, uF);
         const Moments m = moments<Q>(g);

@@ -44,9 +44,12 @@ BYTES_FWD = 2 * Q * 4        # read + write one population set per fluid node
 BYTES_ADJ = 3 * Q * 4        # gather F^{k-1}, gather nu^{k+1}, write nu^k
 PROFILES = os.path.join(ROOT, "profiles")
 # kernel names as the profiler reports them (template arguments: Q, x boundary kind = pressure,
-# [adjoint: no loss frame on the step,] stores not non-temporal: the 128^3 states fit the Infinity Cache)
+# adjoint: no loss frame on the step, then the cache policy: the 128^3 states fit the Infinity
+# Cache, so steps into the ping-pong pair and the adjoint keep the default policy and steps into
+# the tape store non-temporal)
 ADJ_KERNEL = "k_adj_step<19, 0, false, false>"
-FWD_KERNEL = "k_step<19, 0, false>"
+FWD_KERNEL = "k_step<19, 0, *>"
+FWD_VARIANTS = ("k_step<19, 0, 0>", "k_step<19, 0, 1>")      # into the ping-pong pair, into the tape
 
 
 def workload(n=128, T=8000, K=400, kind="spheres"):
@@ -140,9 +143,11 @@ def d2q9_batch(torch, T=5000):
             "k_adj_step_frac": f(3 * 9 * 4, adj_ms), "k_adj_step_avg_launch_ms": round(adj_ms, 5)}
 
 
-def load_traffic(kernel):
+def load_traffic(kernel, weights=None):
     """HBM bytes per launch from the committed rocprofv3 --pmc summary of this
-    kernel, if it was taken on the current kernel source; else None."""
+    kernel, if it was taken on the current kernel source; else None.  With
+    weights {variant name: launches}, the launch-weighted mean over the
+    variants (all of them must have been measured)."""
     p = os.path.join(PROFILES, "pmc_traffic.json")
     if not os.path.exists(p):
         return None
@@ -151,10 +156,16 @@ def load_traffic(kernel):
     except Exception:
         return None
     from paper_2310_00810_amd.profiling import kernel_source_hash
-    e = d.get(kernel)
-    if not e or e.get("source_hash") != kernel_source_hash():
-        return None
-    return e.get("bytes_per_launch")
+    h = kernel_source_hash()
+    parts = weights or {kernel: 1}
+    tot = n = 0
+    for name, w in parts.items():
+        e = d.get(name)
+        if not e or e.get("source_hash") != h:
+            return None
+        tot += w * e["bytes_per_launch"]
+        n += w
+    return tot / n if n else None
 
 
 def copy_peak_gbs(torch, nbytes=4 << 30, reps=10):
@@ -379,6 +390,9 @@ def main():
     # all launches of one gradient evaluation is the dominant kernel's figure
     step_launches = tm["forward_launches"] + tm["recompute_launches"]
     step_ms = (tm["forward_ms"] + tm["recompute_ms"]) / max(step_launches, 1)
+    # launches into the ping-pong pair: the steps of the segments that are not kept (their first
+    # step writes a checkpoint) and the last step; every other launch writes the tape
+    pp_launches = max(-(-T // K) - s.resident_segments, 0) * (K - 1) + 1
     adj_bytes = BYTES_ADJ * n_fluid
     fwd_bytes = BYTES_FWD * n_fluid
     adj_gbs = adj_bytes / (adj_ms * 1e-3) / 1e9
@@ -406,7 +420,9 @@ def main():
                    "resident_segments": s.resident_segments, "recomputed_steps": tm["recompute_launches"],
                    "workspace_gib": round(s.workspace_bytes / 2 ** 30, 1)},
         "roofline": {"bound": "hbm", "achieved": round(step_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(step_gbs / HBM_PEAK_GBS, 4), "traffic": load_traffic(FWD_KERNEL),
+                     "frac": round(step_gbs / HBM_PEAK_GBS, 4),
+                     "traffic": load_traffic(FWD_KERNEL, {FWD_VARIANTS[0]: pp_launches,
+                                                          FWD_VARIANTS[1]: step_launches - pp_launches}),
                      "kernel": FWD_KERNEL, "bytes_per_launch": fwd_bytes, "avg_launch_ms": round(step_ms, 5),
                      "launches": "forward + segment recompute, one gradient evaluation"},
         "adj_roofline": {"kernel": ADJ_KERNEL, "achieved": round(adj_gbs, 1), "unit": "GB/s",

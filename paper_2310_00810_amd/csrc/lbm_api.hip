@@ -312,9 +312,11 @@ double elapsed(lbm_handle *h, int a, int b) {
     return ms;
 }
 
-int step(lbm_handle *h, const float *src, float *dst, hipStream_t s) {
+// tape: dst is a tape state (a checkpoint or a segment state), read again
+// only by the reverse sweep, long after it would have left the cache.
+int step(lbm_handle *h, const float *src, float *dst, hipStream_t s, bool tape = false) {
     HIP_TRY(lbm::launch_step(h->L.q, h->G, src, dst, h->at<float>(h->L.off_face_in),
-                             h->at<float>(h->L.off_face_out), s));
+                             h->at<float>(h->L.off_face_out), tape, s));
     return LBM_OK;
 }
 
@@ -591,7 +593,7 @@ static int enqueue_forward(lbm_handle *h, int record_tape, hipStream_t s) {
     const float *src = h->init();
     for (int t = 1; t <= L.T; ++t) {
         float *dst = fwd_dst(h, t, record_tape);
-        int rc = step(h, src, dst, s);
+        int rc = step(h, src, dst, s, dst != h->pp(0) && dst != h->pp(1));
         if (rc) return rc;
         const int m = t < L.T ? frame_of(L, t) : -1;
         if (m >= 0)
@@ -692,7 +694,7 @@ static int enqueue_reverse(lbm_handle *h, bool resident, const float *seed, hipS
     auto recompute_segment = [&](int c, int r, hipStream_t st) -> int {
         const int t0 = c * K, t1 = std::min(t0 + K, T);
         for (int j = 1; j < t1 - t0; ++j)
-            if ((rc = step(h, j == 1 ? h->ckpt(c) : h->seg(r, j - 1), h->seg(r, j), st))) return rc;
+            if ((rc = step(h, j == 1 ? h->ckpt(c) : h->seg(r, j - 1), h->seg(r, j), st, true))) return rc;
         if (c + 1 < n_seg) {
             if ((rc = step(h, t1 - t0 > 1 ? h->seg(r, t1 - t0 - 1) : h->ckpt(c), scratch, st))) return rc;
             HIP_TRY(lbm::launch_compare(q, h->G, scratch, h->ckpt(c + 1), flag, st));

@@ -60,7 +60,11 @@ __device__ inline void face_unknown_adjoints(__amdgpu_buffer_rsrc_t rn, int plan
         if (V::cx(i) != 0 && (V::cx(i) > 0 ? in : out)) nuo[i] = bload(rn, own + (unsigned)(i * plane) * 4u);
 }
 
-template <int Q, int BCX, bool NT>
+// NTM: 0 default cache policy, 1 non-temporal stores (a destination that no
+// later step reads while it could still be cached: a tape state, or any
+// state when two exceed the Infinity Cache), 2 non-temporal gathers too
+// (D3Q19 states beyond the Infinity Cache).
+template <int Q, int BCX, int NTM>
 __global__ void __launch_bounds__(FT) k_step(Geo G, const float *__restrict__ src,
                                              float *__restrict__ dst,
                                              const float *__restrict__ face_in,
@@ -76,9 +80,7 @@ __global__ void __launch_bounds__(FT) k_step(Geo G, const float *__restrict__ sr
     Links<Q> k;
     links<Q, BCX>(G, I, t, L, n, k);
     float g[Q];
-    // beyond the Infinity Cache D3Q19 gathers read non-temporal too; D2Q9 ones
-    // do not (other blocks reread their neighbouring rows' lines)
-    gather_fwd<Q, BCX, NT && Q == 19>(rs, plane, k, g);
+    gather_fwd<Q, BCX, NTM == 2>(rs, plane, k, g);
     if (zouhe_faces(BCX) && wave_has_face(in || out)) zouhe<Q>(g, in, out, drho_b, BCX == BC_VELOCITY);
     if (BCX == BC_ABB) abb<Q>(g, in, out, drho_b, uF);
     const Moments m = moments<Q>(g);
@@ -94,12 +96,12 @@ __global__ void __launch_bounds__(FT) k_step(Geo G, const float *__restrict__ sr
             for (int i = 0; i < 9; ++i) d[i] = g[i] - feq[i];
             mrt_relax(d, G.mrt, om, r);
 #pragma unroll
-            for (int i = 0; i < 9; ++i) bstore<NT>(rd, g[i] - r[i], own, plane_off(i, plane));
+            for (int i = 0; i < 9; ++i) bstore<(NTM >= 1)>(rd, g[i] - r[i], own, plane_off(i, plane));
             return;
         }
     }
 #pragma unroll
-    for (int i = 0; i < Q; ++i) bstore<NT>(rd, g[i] + om * (feq[i] - g[i]), own, plane_off(i, plane));
+    for (int i = 0; i < Q; ++i) bstore<(NTM >= 1)>(rd, g[i] + om * (feq[i] - g[i]), own, plane_off(i, plane));
 }
 
 // Bit-for-bit comparison of two states over the fluid nodes of every
@@ -609,12 +611,17 @@ static inline dim3 fgrid_of(const Geo &G) { return dim3((unsigned)G.n_ftiles); }
     } while (0)
 
 hipError_t launch_step(int q, const Geo &G, const float *src, float *dst, const float *fin,
-                       const float *fout, hipStream_t s) {
+                       const float *fout, bool tape, hipStream_t s) {
     if (G.n_ftiles == 0) return hipSuccess;
+    // beyond the Infinity Cache every step streams, and D3Q19 gathers read
+    // non-temporal too (D2Q9 ones do not: other blocks reread their
+    // neighbouring rows' lines); a step into the tape streams its stores
+    const int ntm = G.nt ? (q == 19 ? 2 : 1) : (tape ? 1 : 0);
 #define CALL(Q, B)                                                                                 \
     do {                                                                                           \
-        if (G.nt) hipLaunchKernelGGL((k_step<Q, B, true>), fgrid_of(G), dim3(FT), 0, s, G, src, dst, fin, fout); \
-        else hipLaunchKernelGGL((k_step<Q, B, false>), fgrid_of(G), dim3(FT), 0, s, G, src, dst, fin, fout); \
+        if (ntm == 2) hipLaunchKernelGGL((k_step<Q, B, 2>), fgrid_of(G), dim3(FT), 0, s, G, src, dst, fin, fout); \
+        else if (ntm == 1) hipLaunchKernelGGL((k_step<Q, B, 1>), fgrid_of(G), dim3(FT), 0, s, G, src, dst, fin, fout); \
+        else hipLaunchKernelGGL((k_step<Q, B, 0>), fgrid_of(G), dim3(FT), 0, s, G, src, dst, fin, fout); \
     } while (0)
     DISPATCH_BCX(q, G.bcx, CALL);
 #undef CALL

@@ -6,7 +6,7 @@
 namespace lbm {
 
 hipError_t launch_step(int q, const Geo &G, const float *src, float *dst, const float *fin,
-                       const float *fout, hipStream_t s);
+                       const float *fout, bool tape, hipStream_t s);
 // Sets *flag = 1 if states a and b differ in any population of a fluid node.
 hipError_t launch_compare(int q, const Geo &G, const float *a, const float *b, unsigned *flag, hipStream_t s);
 // acc: add to the partials (the later frames of a time-windowed loss).

@@ -69,6 +69,52 @@ def percolates(solid: np.ndarray) -> bool:
     return False
 
 
+def flowing(solid: np.ndarray, periodic=()) -> np.ndarray:
+    """Fluid nodes joined to both the x = 0 and the x = nx-1 face through
+    lattice links (x is the last axis): face and diagonal neighbours in 2D
+    (D2Q9), face and edge neighbours in 3D (D3Q19), also across the axes
+    listed in `periodic` (axis numbers of `solid`).  The rest of the pore
+    space is closed pockets, which no pressure drop moves.  A leading axis of
+    length 1 is taken as 2D."""
+    from scipy.sparse import coo_matrix
+    from scipy.sparse.csgraph import connected_components
+    solid = np.asarray(solid)
+    squeeze = solid.ndim == 3 and solid.shape[0] == 1
+    s2 = solid[0] if squeeze else solid
+    per = {a - 1 for a in periodic if a >= 1} if squeeze else set(periodic)
+    nd = s2.ndim
+    fluid = s2 == 0
+    struct = _ndi.generate_binary_structure(nd, nd if nd == 2 else 2)
+    lab, n = _ndi.label(fluid, structure=struct)
+    edges = []
+    offs = [np.array(o) - 1 for o in np.argwhere(struct)]
+    for a in per:
+        src = np.take(lab, -1, axis=a)
+        dst = np.take(lab, 0, axis=a)
+        rest = [b for b in range(nd) if b != a]
+        for o in offs:
+            if o[a] != 1:
+                continue
+            sh, ok = dst, np.ones(src.shape, bool)
+            for i, b in enumerate(rest):
+                if o[b] == 0:
+                    continue
+                sh = np.roll(sh, -o[b], axis=i)
+                if b not in per:
+                    idx = [slice(None)] * len(rest)
+                    idx[i] = slice(-1, None) if o[b] > 0 else slice(0, 1)
+                    ok[tuple(idx)] = False
+            m = ok & (src > 0) & (sh > 0)
+            edges.append(np.stack([src[m], sh[m]]))
+    e = np.concatenate(edges, axis=1) if edges else np.zeros((2, 0), int)
+    g = coo_matrix((np.ones(e.shape[1]), (e[0], e[1])), shape=(n + 1, n + 1))
+    _, comp = connected_components(g, directed=False)
+    cl = np.where(lab > 0, comp[lab], -1)
+    ends = (set(np.unique(cl[..., 0])) & set(np.unique(cl[..., -1]))) - {-1}
+    out = np.isin(cl, list(ends)) & fluid
+    return out[None] if squeeze else out
+
+
 def _paint_disk(solid, cx, cy, r):
     ny, nx = solid.shape
     x0, x1 = max(int(np.floor(cx - r)), 0), min(int(np.ceil(cx + r)), nx - 1)

@@ -58,6 +58,12 @@ def bc_of(dims):
     return ("pressure", "wall", "periodic") if dims == 2 else ("pressure", "periodic", "periodic")
 
 
+def periodic_axes(dims):
+    """Axes of a (nz, ny, nx) mask that bc_of(dims) makes periodic."""
+    _, by, bz = bc_of(dims)
+    return tuple(a for a, b in ((1, by), (0, bz)) if b == "periodic")
+
+
 class Dataset:
     """Network inputs and Stokes-scaled targets, resident on the GPU, with the
     per-sample fluid pixel counts on the host."""
@@ -65,7 +71,7 @@ class Dataset:
     def __init__(self, dims, cases, features, targets, wpix, prm, steps, dropped=0):
         self.dims, self.cases = dims, cases
         self.features, self.targets, self.wpix, self.prm, self.steps = features, targets, wpix, prm, steps
-        self.nfluid = np.array([int((c[0] == 0).sum()) for c in cases], np.int64)
+        self.nfluid = wpix.reshape(wpix.shape[0], -1).sum(1).round().long().cpu().numpy()
         self.dropped = dropped
 
     def __len__(self):
@@ -83,13 +89,15 @@ def features_of(solid_dev, prm_dev, n, d, h, w):
     return out
 
 
-def generate(dims, seeds, batch=32, tol=1e-6, max_steps=100_000, check_every=100):
+def generate(dims, seeds, batch=32, tol=1e-6, max_steps=100_000, check_every=100, flowing_only=False):
     """Runs the batched solver to the residual threshold for every seed and
     returns a Dataset (features, targets and fluid weights on the GPU) of the
     cases that reached it; cases still above the threshold at max_steps are
     left out (counted in Dataset.dropped).  A batch runs until its slowest
     case converges, and the steps to converge scale with 1 / nu, so the cases
-    are batched in order of tau."""
+    are batched in order of tau.  flowing_only: closed pockets of the pore
+    space (geometry.flowing) get weight 0, since their state is the initial
+    one and not a response to the pressure drop."""
     D = dims
     feats, tgts, wps, prms, steps, cases = [], [], [], [], [], []
     dropped = 0
@@ -115,6 +123,9 @@ def generate(dims, seeds, batch=32, tol=1e-6, max_steps=100_000, check_every=100
                                           ctypes.c_void_p(solid.data_ptr()), ctypes.c_void_p(prm.data_ptr()),
                                           per, D, nb * per, ctypes.c_void_p(tg.data_ptr()),
                                           ctypes.c_void_p(wp.data_ptr()), _stream()), "lbmnn_normalize")
+        if flowing_only:
+            fm = np.stack([G.flowing(c[0], periodic=periodic_axes(dims)) for c in chunk])
+            wp *= torch.from_numpy(fm.reshape(-1).astype(np.float32)).cuda()
         kd = torch.from_numpy(keep).cuda()
         feats.append(features_of(solid, prm, nb, nz, ny, nx).index_select(0, kd))
         tgts.append(tg.view(nb, nz, ny, nx, 1 + D).index_select(0, kd))
@@ -156,6 +167,25 @@ def mirrored(x, tg, wp, axis, dims):
     return x.flip(axis).contiguous(), (tg.flip(axis) * sign).contiguous(), wp.flip(axis).contiguous()
 
 
+def reversed_flow(x, tg, wp, s0):
+    """A batch reflected across the mid-plane normal to the flow (x), with
+    the pressure drop turned back to its usual direction.  The creeping-flow
+    steady state is linear in the drop and the inlet and outlet closures
+    mirror each other, so the reflected medium's normalised state is the
+    reflection of this one with t0 -> 1 - t0, the streamwise velocity kept
+    and the transverse velocities negated.  The positional input channel
+    (x / (w - 1)) stays as it is.  s0: the density channel's standardisation
+    scale (the targets are divided by it)."""
+    xf = x.flip(3)
+    xf[..., 1] = x[..., 1]
+    sign = torch.full((tg.shape[-1],), -1.0, device=tg.device)
+    sign[1] = 1.0
+    tf = tg.flip(3) * sign
+    wf = wp.flip(3).contiguous()
+    tf[..., 0] += wf / s0
+    return xf.contiguous(), tf.contiguous(), wf
+
+
 def evaluate_loss(net, ds, batch):
     tot, n = 0.0, 0
     for b0 in range(0, len(ds), batch):
@@ -169,9 +199,12 @@ def evaluate_loss(net, ds, batch):
     return tot / max(n, 1)
 
 
-def train(net, ds, val, epochs, batch, lr, seed=0, augment=True):
+def train(net, ds, val, epochs, batch, lr, seed=0, augment=True, reverse_s0=None):
     """Adam with a cosine learning-rate schedule.  augment: each batch is
-    reflected across a transverse mid-plane with probability 1/2 per axis.
+    reflected across a transverse mid-plane with probability 1/2 per axis,
+    and, given reverse_s0 (the density channel's scale), across the
+    streamwise mid-plane with the drop reversed (reversed_flow) with
+    probability 1/2.
     With a validation set the weights of the epoch with the lowest validation
     loss are kept."""
     g = torch.Generator(device="cpu").manual_seed(seed)
@@ -194,6 +227,8 @@ def train(net, ds, val, epochs, batch, lr, seed=0, augment=True):
                 for ax in axes:
                     if torch.rand((), generator=g).item() < 0.5:
                         x, tg, wp = mirrored(x, tg, wp, ax, ds.dims)
+                if reverse_s0 is not None and torch.rand((), generator=g).item() < 0.5:
+                    x, tg, wp = reversed_flow(x, tg, wp, reverse_s0)
             tot += net.train_step(x, tg, wp, lr_ep, n_fluid=int(ds.nfluid[sel.numpy()].sum()))[0]
             nb += 1
         vl = evaluate_loss(net, val, batch) if val is not None and len(val) else float("nan")
@@ -295,6 +330,9 @@ def main():
     ap.add_argument("--out", default="")
     ap.add_argument("--max-steps", type=int, default=100_000)
     ap.add_argument("--levels", type=int, default=4, help="U-Net levels (the deepest runs at 1 / 2^(levels-1) size)")
+    ap.add_argument("--reverse-flow", action="store_true",
+                    help="also augment with the streamwise reflection and reversed drop (reversed_flow); "
+                         "closed pockets of the pore space then carry no weight in the loss")
     args = ap.parse_args()
     dims = args.dims
     # 3D: batch 4 at lr 5e-4; at batch 2 and lr 2e-3 the 1000 Adam steps of an epoch over 2000
@@ -303,15 +341,18 @@ def main():
     lr = args.lr or (2e-3 if dims == 2 else 5e-4)
     gb = args.gen_batch or 64
     t0 = time.time()
-    tr = generate(dims, [SEED_TRAIN + i for i in range(args.train)], batch=gb, max_steps=args.max_steps)
-    va = generate(dims, [SEED_VAL + i for i in range(args.val)], batch=gb, max_steps=args.max_steps) if args.val else None
+    fo = args.reverse_flow
+    tr = generate(dims, [SEED_TRAIN + i for i in range(args.train)], batch=gb, max_steps=args.max_steps,
+                  flowing_only=fo)
+    va = generate(dims, [SEED_VAL + i for i in range(args.val)], batch=gb, max_steps=args.max_steps,
+                  flowing_only=fo) if args.val else None
     gen_s = time.time() - t0
     scale = channel_scale(tr)
     log(f"[data] target channel RMS {scale.cpu().numpy()}; steps to converge: median "
         f"{int(np.median(tr.steps))}, max {int(tr.steps.max())}")
     net = UNet(dims, levels=args.levels, seed=0)
     hist = train(net, standardized(tr, scale), standardized(va, scale) if va is not None else None, args.epochs,
-                 batch, lr)
+                 batch, lr, reverse_s0=float(scale[0]) if args.reverse_flow else None)
     net.fold_output_scale(scale)
     train_s = time.time() - t0 - gen_s
     res = []

@@ -84,3 +84,86 @@ def test_hydrodynamic_disk_is_the_smaller_disk():
     G._paint_disk(m, 19.3, 20.1, 0.9 * 8.0)
     yy, xx = np.mgrid[0:40, 0:40]
     assert np.array_equal(m, ((xx - 19.3) ** 2 + (yy - 20.1) ** 2 <= (0.9 * 8.0) ** 2).astype(np.uint8))
+
+
+def _bfs_flowing(solid, links, periodic):
+    """Brute force: breadth-first search over the lattice links from every
+    fluid node of the x = 0 face, and again from the x = nx-1 face."""
+    from collections import deque
+    fluid = solid == 0
+    shape = fluid.shape
+
+    def reach(face):
+        seen = np.zeros(shape, bool)
+        dq = deque()
+        for idx in zip(*np.nonzero(fluid)):
+            if idx[-1] == face:
+                seen[idx] = True
+                dq.append(idx)
+        while dq:
+            p = dq.popleft()
+            for c in links:
+                q = []
+                for a, (pa, ca) in enumerate(zip(p, c)):
+                    v = pa + ca
+                    if a in periodic:
+                        v %= shape[a]
+                    elif not 0 <= v < shape[a]:
+                        break
+                    q.append(v)
+                else:
+                    q = tuple(q)
+                    if fluid[q] and not seen[q]:
+                        seen[q] = True
+                        dq.append(q)
+        return seen
+
+    return reach(0) & reach(shape[-1] - 1)
+
+
+D2Q9_LINKS = [(a, b) for a in (-1, 0, 1) for b in (-1, 0, 1) if (a, b) != (0, 0)]
+D3Q19_LINKS = [(a, b, c) for a in (-1, 0, 1) for b in (-1, 0, 1) for c in (-1, 0, 1)
+               if 0 < abs(a) + abs(b) + abs(c) <= 2]
+
+
+def test_flowing_takes_diagonal_links_in_2d_and_edge_links_only_in_3d():
+    s = np.ones((4, 6), np.uint8)
+    s[1, 0:3] = 0
+    s[2, 3:6] = 0               # joined to row 1 only through the diagonal (1,2)-(2,3)
+    s[3, 0] = 0                 # a pocket on the inlet face
+    f = G.flowing(s)
+    assert f[1, 0:3].all() and f[2, 3:6].all() and not f[3, 0] and f.sum() == 6
+    v = np.ones((3, 3, 6), np.uint8)
+    v[0, 0, 0:3] = 0
+    v[1, 1, 3:6] = 0            # a vertex contact only: no D3Q19 link
+    assert not G.flowing(v).any()
+    v[1, 0, 3] = 0              # an edge contact (0,0,2)-(1,0,3)
+    assert G.flowing(v)[1, 1, 3:6].all()
+
+
+def test_flowing_crosses_periodic_axes():
+    v = np.ones((3, 4, 6), np.uint8)
+    v[0, 0, 0:3] = 0
+    v[0, 3, 3:6] = 0            # joined to the first run only across y = 3 -> 0
+    v[0, 3, 2] = 1
+    assert not G.flowing(v).any()
+    f = G.flowing(v, periodic=(1,))
+    assert f[0, 0, 0:3].all() and f[0, 3, 3:6].all()
+
+
+@pytest.mark.parametrize("dims", [2, 3])
+def test_flowing_matches_a_breadth_first_search(dims):
+    rng = np.random.default_rng(5)
+    for trial in range(12):
+        if dims == 2:
+            s = (rng.random((9, 13)) < 0.45).astype(np.uint8)
+            per = {0} if trial % 2 else set()
+            links = D2Q9_LINKS
+        else:
+            s = (rng.random((5, 6, 9)) < 0.72).astype(np.uint8)
+            per = [set(), {0}, {1}, {0, 1}][trial % 4]
+            links = D3Q19_LINKS
+        got = G.flowing(s, periodic=tuple(per))
+        assert np.array_equal(got, _bfs_flowing(s, links, per)), (dims, trial)
+    s2 = (rng.random((1, 9, 13)) < 0.45).astype(np.uint8)
+    assert np.array_equal(G.flowing(s2)[0], _bfs_flowing(s2[0], D2Q9_LINKS, set()))

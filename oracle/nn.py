@@ -245,3 +245,34 @@ def stokes_fields(pred, solid, drho_in, drho_out, tau, dims):
     drho = np.where(fl, drho_out + dr * p[:, 0], 0.0)
     u = np.where(fl[:, None], p[:, 1:1 + dims] * (dr / 3.0) / nu, 0.0)
     return drho, u
+
+
+def flux_balance(u, solid, lo=0.25, hi=4.0, floor=0.1):
+    """Cross-section flux balance of a predicted velocity field (one sample;
+    an addition to the network initial guess of Section 3.5, from mass
+    conservation: a steady flow carries the same flux through every
+    cross-section normal to the flow direction x).
+
+    solid: (d, h, w); u: (d, h, w, D), or (nodes, D) in that order.  With
+    Q(x) the sum of u_x over the fluid nodes of section x (all y, z) and
+    Qbar the mean of Q over the w sections, every velocity component of every
+    node of section x is multiplied by
+        s(x) = min(max(Qbar / max(Q(x), floor * Qbar), lo), hi);
+    if Qbar <= 0 the field is returned unchanged."""
+    solid = np.asarray(solid)
+    d, h, w = solid.shape
+    u = np.asarray(u, np.float64)
+    shape = u.shape
+    u = u.reshape(d, h, w, -1).copy()
+    fluid = solid == 0
+    Q = np.zeros(w)
+    for x in range(w):
+        Q[x] = np.sum(u[:, :, x, 0][fluid[:, :, x]])
+    qbar = np.sum(Q) / w
+    if not qbar > 0.0:
+        return u.reshape(shape)
+    for x in range(w):
+        s = qbar / max(Q[x], floor * qbar)
+        s = min(max(s, lo), hi)
+        u[:, :, x, :] *= s
+    return u.reshape(shape)

@@ -223,3 +223,61 @@ def test_stokes_scaling_round_trip_and_closed_form():
     r2, u2 = N.stokes_fields(np.concatenate([t, np.zeros((P, 2))], axis=1), solid, 0.004, 0.001, 0.8, D)
     assert np.allclose(r2[fl], drho[fl], rtol=1e-13) and np.allclose(u2[fl], u[fl], rtol=1e-12)
     assert np.all(r2[~fl] == 0.0) and np.all(u2[~fl] == 0.0)
+
+
+# ---- cross-section flux balance of the warm start's predicted velocity ----
+
+def _field(rng, d, h, w, D, porosity=0.6):
+    solid = (rng.random((d, h, w)) > porosity).astype(np.uint8)
+    u = rng.random((d, h, w, D)) + 0.1
+    u[..., 1:] -= 0.6
+    u[solid == 1] = 0.0
+    return solid, u
+
+
+def _fluxes(u, solid):
+    return np.array([u[:, :, x, 0][solid[:, :, x] == 0].sum() for x in range(solid.shape[2])])
+
+
+@pytest.mark.parametrize("d,D", [(1, 2), (3, 3)])
+def test_flux_balance_makes_every_section_carry_the_mean_flux(d, D):
+    rng = np.random.default_rng(4)
+    solid, u = _field(rng, d, 9, 12, D)
+    q0 = _fluxes(u, solid)
+    out = N.flux_balance(u, solid)
+    q1 = _fluxes(out, solid)
+    # no factor is clamped for these fields: every section now carries the old mean flux
+    assert q0.min() > 0.1 * q0.mean() and (q0.mean() / q0).max() < 4 and (q0.mean() / q0).min() > 0.25
+    assert np.allclose(q1, q0.mean(), rtol=1e-13, atol=0)
+    # one factor per section, the same for every component and node of the section
+    for x in range(12):
+        fl = solid[:, :, x] == 0
+        r = out[:, :, x][fl] / u[:, :, x][fl]
+        assert np.allclose(r, q0.mean() / q0[x], rtol=1e-13)
+    assert np.all(out[solid == 1] == 0)
+
+
+def test_flux_balance_keeps_a_balanced_field_and_ignores_solid_nodes():
+    solid = np.zeros((1, 3, 4), np.uint8)
+    solid[0, 1, 2] = 1
+    u = np.zeros((1, 3, 4, 2))
+    u[0, :, :, 0] = [[1.0, 2.0, 3.0, 1.0], [2.0, 2.0, 99.0, 2.0], [3.0, 2.0, 3.0, 3.0]]   # each section: 6
+    u[0, :, :, 1] = 0.5
+    out = N.flux_balance(u, solid)
+    assert np.array_equal(out, u)                      # factors exactly 1: the solid node's 99 is not counted
+
+
+def test_flux_balance_clamps_and_leaves_reverse_flow_alone():
+    solid = np.zeros((1, 1, 3), np.uint8)
+    u = np.zeros((1, 1, 3, 2))
+    u[0, 0, :, 0] = [1.0, 1.9, 0.01]                   # Qbar = 0.97; sections scale by 0.97, 0.97/1.9, 4 (clamped)
+    u[0, 0, :, 1] = 1.0
+    out = N.flux_balance(u, solid)
+    qb = 2.91 / 3
+    assert np.allclose(out[0, 0, :, 0], [qb, 1.9 * qb / 1.9, 0.04], rtol=1e-14)
+    assert np.allclose(out[0, 0, :, 1], [qb, qb / 1.9, 4.0], rtol=1e-14)
+    u[0, 0, 2, 0] = 1.0                                  # Q = 1, 1.9, 1 -> factor 1.3 / 1.9 above the floor
+    out = N.flux_balance(u, solid, lo=0.8)
+    assert np.allclose(out[0, 0, :, 0], [1.3, 1.9 * 0.8, 1.3], rtol=1e-14)   # the middle factor clamped to lo
+    u[0, 0, :, 0] = [-1.0, 0.5, 0.2]                     # no net forward flow: unchanged
+    assert np.array_equal(N.flux_balance(u, solid), u)

@@ -167,6 +167,24 @@ int lbmnn_normalize(const float *drho, const float *u, const uint8_t *solid, con
 int lbmnn_denormalize(const float *pred, int pcs, const uint8_t *solid, const float *prm, long long per_sample,
                       int D, long long pixels, float *drho, float *u, void *stream);
 
+/* Cross-section flux balance of a predicted velocity field, applied to the
+ * network initial guess of Section 3.5 before it initialises the
+ * populations: a steady flow conserves mass (Eq. 1-2 moments of a steady
+ * state), so every cross-section normal to the flow direction x carries the
+ * same flux.  Per sample, Q(x) = sum of u_x over the fluid nodes of section
+ * x (all y, z; FP64, a fixed order) and Qbar = the mean of Q over the w
+ * sections; every velocity component at every node of section x is
+ * multiplied by min(max(Qbar / max(Q(x), Qbar / 10), 1/4), 4).  A sample
+ * with Qbar <= 0 is left unchanged.  u: device FP32 [n][d][h][w][D] (D = 2
+ * or 3), in place; solid: device uint8 [n][d][h][w]; n <= 65535,
+ * 1 <= w <= 2048, d * h < 2^31; ws: device workspace of at least
+ * lbmnn_flux_balance_workspace_bytes(n, d, h, w) bytes, 8-byte aligned,
+ * owned by the caller (the section sums and factors).  Enqueued on `stream`;
+ * LBM_EINVAL for other arguments, LBM_ENOMEM for a short workspace. */
+long long lbmnn_flux_balance_workspace_bytes(int n, int d, int h, int w);   /* 0 for invalid sizes */
+int lbmnn_flux_balance(const uint8_t *solid, int n, int d, int h, int w, int D, float *u, void *ws,
+                       long long ws_bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -115,6 +115,7 @@ NN_EXPORTS = [
     "lbmnn_weight_transpose",
     "lbmnn_bias_grad", "lbmnn_relu_bwd", "lbmnn_relu_bwd_bias_grad", "lbmnn_pool_fwd", "lbmnn_pool_bwd",
     "lbmnn_mse", "lbmnn_adam", "lbmnn_to_bf16", "lbmnn_features", "lbmnn_normalize", "lbmnn_denormalize",
+    "lbmnn_flux_balance_workspace_bytes", "lbmnn_flux_balance",
 ]
 NN_RELU, NN_ACCUMULATE, NN_S2D, NN_D2S, NN_S2D_G = 1, 2, 4, 8, 16
 LBMNN_NOALLOC_SCRATCH_BYTES = 32 << 20
@@ -158,6 +159,9 @@ def nnlib():
         L.lbmnn_features.argtypes = [vp, vp, ip, ip, ip, ip, vp, vp]
         L.lbmnn_normalize.argtypes = [vp, vp, vp, vp, ll, ip, ll, vp, vp, vp]
         L.lbmnn_denormalize.argtypes = [vp, ip, vp, vp, ll, ip, ll, vp, vp, vp]
+        L.lbmnn_flux_balance_workspace_bytes.argtypes = [ip, ip, ip, ip]
+        L.lbmnn_flux_balance_workspace_bytes.restype = ll
+        L.lbmnn_flux_balance.argtypes = [vp, ip, ip, ip, ip, ip, vp, vp, ll, vp]
         for n in NN_EXPORTS:
             if n not in ("lbmnn_wgrad_workspace_bytes", "lbmnn_conv_workspace_bytes"):
                 getattr(L, n).restype = ctypes.c_int

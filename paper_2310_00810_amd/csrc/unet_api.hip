@@ -290,4 +290,20 @@ int lbmnn_denormalize(const float *pred, int pcs, const uint8_t *solid, const fl
     return LBM_OK;
 }
 
+long long lbmnn_flux_balance_workspace_bytes(int n, int d, int h, int w) {
+    if (n < 1 || d < 1 || h < 1 || w < 1 || w > 2048 || (long long)d * h > 0x7fffffffLL) return 0;
+    return nn::flux_balance_workspace_bytes(n, (long long)d * h, w);
+}
+
+int lbmnn_flux_balance(const uint8_t *solid, int n, int d, int h, int w, int D, float *u, void *ws,
+                       long long ws_bytes, void *stream) {
+    if (!solid || !u || !ws || n < 1 || n > 65535 || d < 1 || h < 1 || w < 1 || w > 2048 || (D != 2 && D != 3) ||
+        (long long)d * h > 0x7fffffffLL || ((uintptr_t)ws & 7))
+        return lbm_fail(LBM_EINVAL, "bad flux-balance arguments");
+    if (ws_bytes < lbmnn_flux_balance_workspace_bytes(n, d, h, w))
+        return lbm_fail(LBM_ENOMEM, "flux-balance workspace too small");
+    NN_TRY(nn::flux_balance(solid, n, d * h, w, D, u, ws, (hipStream_t)stream));
+    return LBM_OK;
+}
+
 }  // extern "C"

@@ -1222,6 +1222,86 @@ __global__ void k_denormalize(const float *__restrict__ pred, int pcs, const uin
     for (int a = 0; a < D; ++a) u[m * D + a] = fl ? pred[m * pcs + 1 + a] * su : 0.f;
 }
 
+// Cross-section flux balance in three launches, FP64 sums in a fixed order:
+// block (p, b) sums u_x over the fluid nodes of each section x within row
+// chunk p of sample b (thread t of a pass over `cols` sections takes the
+// rows t / cols, t / cols + groups, ... of section t % cols; the groups are
+// then added in order) into part[b][p][x]; one block per sample adds the
+// chunks in order to Q(x), averages Q over the sections to Qbar and writes
+// the scale factors S[b][x] = clamp(Qbar / max(Q(x), Qbar / 10), 1/4, 4)
+// (all 1 when Qbar <= 0); the last launch scales every value.
+constexpr int FB_MAX_W = 2048, FB_MAX_CHUNKS = 64, FB_MIN_ROWS = 16;
+
+__host__ __device__ inline int fb_chunks(long long rows) {
+    const long long c = (rows + FB_MIN_ROWS - 1) / FB_MIN_ROWS;
+    return (int)(c < FB_MAX_CHUNKS ? c : FB_MAX_CHUNKS);
+}
+
+__global__ void __launch_bounds__(256) k_fb_partial(const uint8_t *__restrict__ solid, const float *__restrict__ u,
+                                                    int rows, int w, int D, double *__restrict__ part) {
+    __shared__ double red[256];
+    const int t = threadIdx.x, p = blockIdx.x, b = blockIdx.y, P = gridDim.x;
+    const long long per = (long long)rows * w;
+    const int r0 = (int)((long long)rows * p / P), r1 = (int)((long long)rows * (p + 1) / P);
+    for (int x0 = 0; x0 < w; x0 += 256) {
+        const int cols = w - x0 < 256 ? w - x0 : 256, groups = 256 / cols;
+        const int x = x0 + t % cols, g = t / cols;
+        double acc = 0.0;
+        if (g < groups)
+            for (int r = r0 + g; r < r1; r += groups) {
+                const long long m = b * per + (long long)r * w + x;
+                const float v = u[m * D];
+                acc += solid[m] ? 0.0 : (double)v;
+            }
+        red[t] = acc;
+        __syncthreads();
+        if (t < cols) {
+            double q = 0.0;
+            for (int k = 0; k < groups; ++k) q += red[k * cols + t];
+            part[((long long)b * P + p) * w + x0 + t] = q;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(256) k_fb_factors(const double *__restrict__ part, int P, int w,
+                                                    float *__restrict__ S) {
+    __shared__ double Q[FB_MAX_W];
+    __shared__ double qbar;
+    const int t = threadIdx.x, b = blockIdx.x;
+    for (int x = t; x < w; x += 256) {
+        double q = 0.0;
+        for (int p = 0; p < P; ++p) q += part[((long long)b * P + p) * w + x];
+        Q[x] = q;
+    }
+    __syncthreads();
+    if (t == 0) {
+        double q = 0.0;
+        for (int x = 0; x < w; ++x) q += Q[x];
+        qbar = q / w;
+    }
+    __syncthreads();
+    const double qb = qbar;
+    for (int x = t; x < w; x += 256) {
+        double sc = 1.0;
+        if (qb > 0.0) {
+            sc = qb / (Q[x] > 0.1 * qb ? Q[x] : 0.1 * qb);
+            sc = sc < 0.25 ? 0.25 : (sc > 4.0 ? 4.0 : sc);
+        }
+        S[(long long)b * w + x] = (float)sc;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_fb_apply(float *__restrict__ u, const float *__restrict__ S, long long n,
+                                                  long long per, int w, int D) {
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const long long node = i / D;                      // node of the whole batch, per nodes per sample
+    const long long b = node / per;
+    const int x = (int)(node % w);
+    u[i] *= S[b * w + x];
+}
+
 // ------------------------------------------------------------ launchers --
 static inline unsigned blocks(long long n, int b) { return (unsigned)((n + b - 1) / b); }
 
@@ -1502,6 +1582,21 @@ hipError_t normalize(const float *drho, const float *u, const uint8_t *solid, co
                      int D, long long npix, float *tgt, float *wpix, hipStream_t s) {
     hipLaunchKernelGGL(k_normalize, dim3(blocks(npix, 256)), dim3(256), 0, s, drho, u, solid, prm, per_sample, D, npix,
                        tgt, wpix);
+    return hipGetLastError();
+}
+
+long long flux_balance_workspace_bytes(int n, long long rows, int w) {
+    return (long long)n * w * (fb_chunks(rows) * (long long)sizeof(double) + (long long)sizeof(float));
+}
+
+hipError_t flux_balance(const uint8_t *solid, int n, int rows, int w, int D, float *u, void *ws, hipStream_t s) {
+    const int P = fb_chunks(rows);
+    double *part = (double *)ws;
+    float *S = (float *)(part + (long long)n * P * w);
+    hipLaunchKernelGGL(k_fb_partial, dim3((unsigned)P, (unsigned)n), dim3(256), 0, s, solid, u, rows, w, D, part);
+    hipLaunchKernelGGL(k_fb_factors, dim3((unsigned)n), dim3(256), 0, s, part, P, w, S);
+    const long long per = (long long)rows * w, tot = (long long)n * per * D;
+    hipLaunchKernelGGL(k_fb_apply, dim3(blocks(tot, 256)), dim3(256), 0, s, u, S, tot, per, w, D);
     return hipGetLastError();
 }
 

@@ -56,6 +56,8 @@ hipError_t features(const uint8_t *solid, const float *prm, int n, int d, int h,
                     hipStream_t s);
 hipError_t normalize(const float *drho, const float *u, const uint8_t *solid, const float *prm, long long per_sample,
                      int D, long long npix, float *tgt, float *wpix, hipStream_t s);
+long long flux_balance_workspace_bytes(int n, long long rows, int w);
+hipError_t flux_balance(const uint8_t *solid, int n, int rows, int w, int D, float *u, void *ws, hipStream_t s);
 hipError_t denormalize(const float *pred, int pcs, const uint8_t *solid, const float *prm, long long per_sample,
                        int D, long long npix, float *drho, float *u, hipStream_t s);
 

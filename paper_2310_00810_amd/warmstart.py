@@ -4,7 +4,9 @@ The paper suggests a neural-network initial guess to speed up its inverse
 runs (Section 3.1.2 end, Section 3.5).  Here a U-Net (unet.py) learns the
 map (solid mask, drho_in, drho_out, tau) -> Stokes-scaled steady (rho, u)
 from steady states that the batched GPU solver itself produces; its
-prediction initialises equilibrium populations (Eq. 5) and the plain LBM
+prediction, with the velocity of every cross-section rescaled to the mean
+predicted flux (a steady flow carries the same flux through every section),
+initialises equilibrium populations (Eq. 5) and the plain LBM
 then runs to the residual threshold, so the converged state is the
 solver's whatever the network predicts, and a poor prediction only costs
 steps.
@@ -243,8 +245,11 @@ def train(net, ds, val, epochs, batch, lr, seed=0, augment=True, reverse_s0=None
     return hist
 
 
-def predict_fields(net, solid, din, dout, tau):
-    """Network prediction for one case -> (drho (nodes,), u (nodes, D)) on the GPU."""
+def predict_fields(net, solid, din, dout, tau, balance=True):
+    """Network prediction for one case -> (drho (nodes,), u (nodes, D)) on the GPU.
+    balance: rescale the velocity of each cross-section so that every section
+    carries the mean predicted flux (lbmnn_flux_balance), as the steady state
+    does."""
     nz, ny, nx = solid.shape
     D = net.dims
     sd = torch.from_numpy(solid[None]).cuda()
@@ -258,6 +263,12 @@ def predict_fields(net, solid, din, dout, tau):
                                         ctypes.c_void_p(prm.data_ptr()), per, D, per,
                                         ctypes.c_void_p(drho.data_ptr()), ctypes.c_void_p(u.data_ptr()),
                                         _stream()), "lbmnn_denormalize")
+    if balance:
+        L = C.nnlib()
+        nb = L.lbmnn_flux_balance_workspace_bytes(1, nz, ny, nx)
+        ws = torch.empty(-(-nb // 8), dtype=torch.float64, device="cuda")
+        C.check(L.lbmnn_flux_balance(ctypes.c_void_p(sd.data_ptr()), 1, nz, ny, nx, D, ctypes.c_void_p(u.data_ptr()),
+                                     ctypes.c_void_p(ws.data_ptr()), nb, _stream()), "lbmnn_flux_balance")
     return drho, u
 
 
@@ -317,6 +328,39 @@ def summarize(res, tol):
     }
 
 
+def held_out(net, n, max_steps):
+    res = []
+    for i in range(n):
+        case = sample(net.dims, SEED_TEST + i)
+        r = warm_vs_cold(net, case, max_steps=max_steps)
+        res.append(r)
+        log(f"[test] {i}: cold {r['cold_steps']} steps {r['cold_s']:.3f} s, warm {r['warm_steps']} steps "
+            f"{r['warm_s']:.3f} s, net err {r['net_rel_l2_u']:.3f}, warm/cold fixed point {r['warm_cold_rel_l2']:.1e}")
+    return res
+
+
+def evaluate_saved(args):
+    """The held-out evaluation of saved weights with the current warm start;
+    the training figures of their metadata are kept, the evaluation figures
+    replaced (the previous ones kept under summary_before_reevaluation)."""
+    net = UNet.load(args.eval_weights)
+    res = held_out(net, args.test, args.max_steps)
+    path = args.eval_weights[:-4] + ".json"
+    meta = json.load(open(path))
+    new = summarize(res, 1e-6)
+    old = meta["summary"]
+    meta["summary_before_reevaluation"] = {k: old[k] for k in new if k in old}
+    old.update(new)
+    old["test"] = args.test
+    meta["tests"] = res
+    meta["evaluation_command"] = "python -m paper_2310_00810_amd.warmstart " + " ".join(sys.argv[1:])
+    print(json.dumps(old), flush=True)
+    out = args.out or path
+    os.makedirs(os.path.dirname(out) or ".", exist_ok=True)
+    with open(out, "w") as f:
+        json.dump(meta, f)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--dims", type=int, default=2)
@@ -330,10 +374,16 @@ def main():
     ap.add_argument("--out", default="")
     ap.add_argument("--max-steps", type=int, default=100_000)
     ap.add_argument("--levels", type=int, default=4, help="U-Net levels (the deepest runs at 1 / 2^(levels-1) size)")
+    ap.add_argument("--eval-weights", default="",
+                    help="only re-run the held-out evaluation of saved weights (.npz) and rewrite the summary of "
+                         "their .json (to --out if given)")
     ap.add_argument("--reverse-flow", action="store_true",
                     help="also augment with the streamwise reflection and reversed drop (reversed_flow); "
                          "closed pockets of the pore space then carry no weight in the loss")
     args = ap.parse_args()
+    if args.eval_weights:
+        evaluate_saved(args)
+        return
     dims = args.dims
     # 3D: batch 4 at lr 5e-4; at batch 2 and lr 2e-3 the 1000 Adam steps of an epoch over 2000
     # samples drove the network into a constant prediction
@@ -355,13 +405,7 @@ def main():
                  batch, lr, reverse_s0=float(scale[0]) if args.reverse_flow else None)
     net.fold_output_scale(scale)
     train_s = time.time() - t0 - gen_s
-    res = []
-    for i in range(args.test):
-        case = sample(dims, SEED_TEST + i)
-        r = warm_vs_cold(net, case, max_steps=args.max_steps)
-        res.append(r)
-        log(f"[test] {i}: cold {r['cold_steps']} steps {r['cold_s']:.3f} s, warm {r['warm_steps']} steps "
-            f"{r['warm_s']:.3f} s, net err {r['net_rel_l2_u']:.3f}, warm/cold fixed point {r['warm_cold_rel_l2']:.1e}")
+    res = held_out(net, args.test, args.max_steps)
     summ = {"dims": dims, "levels": args.levels, "train": len(tr), "train_dropped": tr.dropped, "val": len(va) if va is not None else 0,
             "test": args.test, "epochs": args.epochs, "max_steps": args.max_steps, "gen_seconds": gen_s,
             "train_seconds": train_s, "final_train_loss": hist[-1][1] if hist else None,

@@ -193,3 +193,14 @@ def test_calls_without_handle_fail_cleanly(L):
     assert L.lbm_adjoint(None, None) == C.LBM_EINVAL
     assert L.lbm_grad(None, None, None, None) == C.LBM_EINVAL
     assert L.lbm_destroy(None) == C.LBM_OK
+
+
+def test_flux_balance_workspace_bytes(L):
+    """Per sample and section: one FP64 partial per chunk of at least 16 node
+    rows (at most 64 chunks) and one FP32 factor; 0 for invalid sizes."""
+    C.nnlib()
+    f = L.lbmnn_flux_balance_workspace_bytes
+    assert f(1, 1, 256, 256) == 256 * (16 * 8 + 4)          # 256 rows: 16 chunks
+    assert f(2, 64, 64, 64) == 2 * 64 * (64 * 8 + 4)        # 4096 rows: capped at 64 chunks
+    assert f(3, 1, 5, 300) == 3 * 300 * (1 * 8 + 4)         # 5 rows: one chunk
+    assert f(1, 1, 4, 2049) == 0 and f(0, 1, 1, 1) == 0

@@ -382,6 +382,43 @@ def test_unet_forward_and_gradients_match_the_oracle(dims, shape, base, levels, 
         assert ew <= bar_g and eb <= bar_g, (name, ew, eb)
 
 
+# (n, d, h, w, D): ragged sections, several row groups per section (w < 1024), two section chunks
+# (w = 2048, the largest accepted), and 3D
+FLUX = [(3, 1, 37, 300, 2), (2, 5, 6, 64, 3), (1, 1, 4, 2048, 2), (2, 64, 64, 64, 3), (1, 1, 256, 256, 2)]
+
+
+@pytest.mark.parametrize("n,d,h,w,D", FLUX)
+def test_flux_balance_matches_the_oracle(n, d, h, w, D):
+    C = C_()
+    rng = np.random.default_rng(n * 1000 + w)
+    solid = (rng.random((n, d, h, w)) > 0.6).astype(np.uint8)
+    u = (rng.random((n, d, h, w, D)) + 0.05).astype(np.float32)
+    u[..., 1:] -= 0.55
+    u[..., 0] *= rng.uniform(0.02, 3.0, (n, 1, 1, w)).astype(np.float32)   # uneven sections, some clamped
+    u[solid == 1] = 7.0                                                     # not counted in the fluxes
+    if n > 1:
+        u[1, ..., 0] *= -1.0                                                # a sample with no forward flow
+    ud = torch.from_numpy(u).cuda()
+    sd = torch.from_numpy(solid).cuda()
+    L = C.nnlib()
+    nb = L.lbmnn_flux_balance_workspace_bytes(n, d, h, w)
+    ws = torch.full((nb // 8 + 1,), float("nan"), dtype=torch.float64, device="cuda")   # nothing read before written
+    C.check(L.lbmnn_flux_balance(sd.data_ptr(), n, d, h, w, D, ud.data_ptr(), ws.data_ptr(), nb, stream()),
+            "flux balance")
+    torch.cuda.synchronize()
+    got = ud.cpu().numpy()
+    for b in range(n):
+        exp = N.flux_balance(u[b].astype(np.float64), solid[b])
+        assert np.allclose(got[b], exp, rtol=3e-7, atol=0), b
+    if n > 1:
+        assert np.array_equal(got[1], u[1])
+    args = (sd.data_ptr(), n, d, h)
+    assert L.lbmnn_flux_balance(*args, w, D, None, ws.data_ptr(), nb, stream()) == C.LBM_EINVAL
+    assert L.lbmnn_flux_balance(*args, 2049, D, ud.data_ptr(), ws.data_ptr(), nb, stream()) == C.LBM_EINVAL
+    assert L.lbmnn_flux_balance(*args, w, 4, ud.data_ptr(), ws.data_ptr(), nb, stream()) == C.LBM_EINVAL
+    assert L.lbmnn_flux_balance(*args, w, D, ud.data_ptr(), ws.data_ptr(), nb - 8, stream()) == C.LBM_ENOMEM
+
+
 def test_mse_adam_and_feature_maps():
     C = C_()
     L = C.nnlib()

@@ -330,7 +330,7 @@ def main():
     ap.add_argument("--no-d2q9", action="store_true", help="skip the D2Q9 grain-media batch")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU (the several-GPU slab decomposition is design only); --gpus must be 1"}))
         sys.exit(2)
 
     import torch

@@ -108,10 +108,14 @@ def flowing(solid: np.ndarray, periodic=()) -> np.ndarray:
             edges.append(np.stack([src[m], sh[m]]))
     e = np.concatenate(edges, axis=1) if edges else np.zeros((2, 0), int)
     g = coo_matrix((np.ones(e.shape[1]), (e[0], e[1])), shape=(n + 1, n + 1))
-    _, comp = connected_components(g, directed=False)
-    cl = np.where(lab > 0, comp[lab], -1)
+    ncomp, comp = connected_components(g, directed=False)
+    comp = comp.copy()
+    comp[0] = -1                                       # label 0: solid
+    cl = comp[lab]
     ends = (set(np.unique(cl[..., 0])) & set(np.unique(cl[..., -1]))) - {-1}
-    out = np.isin(cl, list(ends)) & fluid
+    keep = np.zeros(ncomp + 1, bool)                   # index -1: the solid entry
+    keep[list(ends)] = True
+    out = keep[cl] & fluid
     return out[None] if squeeze else out
 
 

@@ -43,3 +43,29 @@ def test_reversed_flow_maps_each_channel(dims):
     for a in range(2, 1 + dims):
         assert torch.equal(t1[..., a], -rf(tg[..., a]))
     assert torch.equal(w1, rf(wp))
+
+
+def test_summary_compares_only_cases_where_both_starts_converge():
+    """Speed-ups, medians and the faster fraction are taken over the cases
+    where both starts reach the threshold; the converged counts cover all."""
+    from paper_2310_00810_amd.warmstart import summarize
+    res = [dict(cold_steps=1000, cold_s=1.0, warm_steps=500, warm_s=0.5, net_rel_l2_u=0.2, warm_cold_rel_l2=1e-3,
+                cold_r=5e-7, warm_r=8e-7),
+           dict(cold_steps=3000, cold_s=3.0, warm_steps=3000, warm_s=3.5, net_rel_l2_u=0.6, warm_cold_rel_l2=2e-3,
+                cold_r=9e-7, warm_r=9e-7),
+           dict(cold_steps=100000, cold_s=90.0, warm_steps=800, warm_s=0.8, net_rel_l2_u=1.0, warm_cold_rel_l2=5e-2,
+                cold_r=3e-6, warm_r=9e-7)]                     # cold start stopped at the cap: left out
+    s = summarize(res, 1e-6)
+    assert (s["cold_converged"], s["warm_converged"], s["both_converged"]) == (2, 3, 2)
+    assert s["speedup_median"] == pytest.approx((2.0 + 3.0 / 3.5) / 2)
+    assert s["speedup_mean"] == pytest.approx((2.0 + 3.0 / 3.5) / 2)
+    assert s["warm_faster_fraction"] == 0.5
+    assert (s["cold_steps_median"], s["warm_steps_median"]) == (2000.0, 1750.0)
+    assert s["net_rel_l2_u_median"] == pytest.approx(0.6) and s["net_rel_l2_u_mean"] == pytest.approx(0.6)
+    assert s["warm_cold_rel_l2_max"] == pytest.approx(2e-3)
+
+
+def test_periodic_axes_follow_the_boundary_kinds():
+    from paper_2310_00810_amd.warmstart import bc_of, periodic_axes
+    assert bc_of(2)[1] == "wall" and periodic_axes(2) == (0,)       # 2D: z (length 1) only
+    assert periodic_axes(3) == (1, 0)                                # 3D: y and z
